@@ -1,0 +1,222 @@
+"""Seeded synthetic Poisson time series standing in for the paper's dam-break matrices.
+
+The paper's experiments (Section 4) use matrices from a two-fluid dam-break simulation
+that are not available here.  These generators keep what matters for the method: a
+density jump of 1000 across a moving interface, a sparsity pattern fixed over a series
+of time steps, and SPD systems.  Everything is produced on the host in float64 so that
+every consumer sees identical bits.
+
+Conventions
+-----------
+* Cell (x, y, z) of an nx*ny*nz grid has row index x + nx*(y + ny*z) (x fastest).
+* Cell centres sit at ((x+1/2)/nx, (y+1/2)/ny, (z+1/2)/nz).
+* CSR rows list their columns in increasing order; int32 row pointers and columns.
+* Homogeneous Dirichlet closure by a ghost cell that carries the cell's own coefficient,
+  so a missing neighbour adds the cell's own face coefficient to the diagonal.
+* Seeds: numpy SeedSequence([2108, 2054, cfg_id, t, stream]).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SEED_ROOT = (2108, 2054)
+STREAM_RHS, STREAM_UT, STREAM_THETA, STREAM_CELLS, STREAM_LOGN, STREAM_DRIFT = range(6)
+
+
+def rng(cfg_id: int, t: int, stream: int) -> np.random.Generator:
+    """Independent generator for (configuration, time step, stream)."""
+    return np.random.default_rng(np.random.SeedSequence([*SEED_ROOT, cfg_id, t, stream]))
+
+
+# ----------------------------------------------------------------------------- patterns
+
+def _offsets(kind: str):
+    if kind == "7pt":
+        offs = [(0, 0, -1), (0, -1, 0), (-1, 0, 0), (0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    elif kind == "27pt":
+        offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    else:
+        raise ValueError(kind)
+    return offs
+
+
+def _shift(a: np.ndarray, dx: int, dy: int, dz: int):
+    """out[z,y,x] = a[z+dz, y+dy, x+dx] where in range, and the in-range mask."""
+    nz, ny, nx = a.shape
+    out = np.zeros_like(a)
+    mask = np.zeros(a.shape, dtype=bool)
+    zs = slice(max(0, -dz), nz - max(0, dz))
+    ys = slice(max(0, -dy), ny - max(0, dy))
+    xs = slice(max(0, -dx), nx - max(0, dx))
+    zt = slice(max(0, dz), nz - max(0, -dz))
+    yt = slice(max(0, dy), ny - max(0, -dy))
+    xt = slice(max(0, dx), nx - max(0, -dx))
+    out[zs, ys, xs] = a[zt, yt, xt]
+    mask[zs, ys, xs] = True
+    return out, mask
+
+
+def stencil_pattern(nx: int, ny: int, nz: int, kind: str = "7pt"):
+    """CSR pattern of a 7- or 27-point stencil.  Returns (row_ptr, col, mask) where
+    mask[n, n_offsets] marks which stencil entries exist (row-major over offsets, in
+    increasing column order), so dense per-offset values compress with ``v[mask]``."""
+    offs = _offsets(kind)
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64).reshape(nz, ny, nx)
+    cols = np.empty((n, len(offs)), dtype=np.int64)
+    mask = np.empty((n, len(offs)), dtype=bool)
+    for o, (dx, dy, dz) in enumerate(offs):
+        s, m = _shift(idx, dx, dy, dz)
+        cols[:, o] = s.reshape(-1)
+        mask[:, o] = m.reshape(-1)
+    counts = mask.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("pattern exceeds int32 indexing")
+    col = cols[mask].astype(np.int32)
+    return row_ptr.astype(np.int32), col, mask
+
+
+def pattern_7pt(nx, ny=None, nz=None):
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return stencil_pattern(nx, ny, nz, "7pt")
+
+
+def pattern_27pt(nx, ny=None, nz=None):
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    return stencil_pattern(nx, ny, nz, "27pt")
+
+
+def _assemble(coef: np.ndarray, kind: str, pair, ghost: bool = True):
+    """Values of a symmetric diffusion stencil from per-cell coefficients ``coef``
+    ([nz,ny,nx]).  ``pair(c, n)`` gives the face coefficient between a cell and a
+    neighbour; a_cn = -pair, a_cc = sum of pairs (+ own coefficient per missing
+    neighbour when ``ghost``)."""
+    nz, ny, nx = coef.shape
+    offs = _offsets(kind)
+    row_ptr, col, mask = stencil_pattern(nx, ny, nz, kind)
+    n = nx * ny * nz
+    dense = np.zeros((n, len(offs)), dtype=np.float64)
+    diag = np.zeros(coef.shape, dtype=np.float64)
+    n_missing = np.zeros(coef.shape, dtype=np.int64)
+    centre = offs.index((0, 0, 0))
+    for o, (dx, dy, dz) in enumerate(offs):
+        if o == centre:
+            continue
+        cn, m = _shift(coef, dx, dy, dz)
+        face = np.where(m, pair(coef, np.where(m, cn, coef)), 0.0)
+        dense[:, o] = -face.reshape(-1)
+        diag += face
+        n_missing += ~m
+    if ghost:
+        diag += n_missing * pair(coef, coef)
+    dense[:, centre] = diag.reshape(-1)
+    return row_ptr, col, dense[mask]
+
+
+# ----------------------------------------------------------------------------- C1-C3
+
+def front_c1(t: int) -> float:
+    """Interface position of the 32^3 series: x = 0.3 + 0.02 t."""
+    return 0.3 + 0.02 * t
+
+
+def front_moving(n_cells: int, t: int) -> float:
+    """Interface that advances one cell per step: x = 0.3 + t / N."""
+    return 0.3 + t / n_cells
+
+
+def two_fluid_7pt(N: int, front: float, rho_heavy: float = 1000.0, zcut: float = 0.6,
+                  ny: int | None = None, nz: int | None = None):
+    """Two-fluid pressure Poisson operator -div(1/rho grad p) on a 7-point stencil.
+
+    rho = rho_heavy inside the column x < front, z < zcut (no condition on y), else 1.
+    The face coefficient is the harmonic mean of 1/rho on both sides, 2/(rho_a+rho_b).
+    Returns (row_ptr int32, col int32, val float64)."""
+    nx = N
+    ny = N if ny is None else ny
+    nz = N if nz is None else nz
+    xc = (np.arange(nx) + 0.5) / nx
+    zc = (np.arange(nz) + 0.5) / nz
+    heavy = (xc[None, None, :] < front) & (zc[:, None, None] < zcut)
+    rho = np.where(np.broadcast_to(heavy, (nz, ny, nx)), rho_heavy, 1.0)
+    return _assemble(rho, "7pt", lambda a, b: 2.0 / (a + b))
+
+
+def neumann_7pt(N: int, seed: int = 0, sigma: float = 0.3):
+    """7-point operator with random positive face coefficients and no boundary terms:
+    every row sums to zero, so the constant vector is in the null space."""
+    g = np.random.default_rng(seed)
+    k = np.exp(g.normal(0.0, sigma, size=(N, N, N)))
+    return _assemble(k, "7pt", lambda a, b: 2.0 * a * b / (a + b), ghost=False)
+
+
+# ----------------------------------------------------------------------------- C5
+
+def lognormal_27pt(N: int, t: int, cfg_id: int = 5, sigma: float = 1.5,
+                   period: int = 40):
+    """27-point operator with lognormal coefficients drifting smoothly in time.
+
+    k_c^t = exp(sigma * g_c + d_t(x_c)), g_c ~ N(0,1) i.i.d. (fixed over the series),
+    d_t(x) = 0.5 sin(2 pi kappa.x + phi + 2 pi t / period), kappa in {1,2}^3 and
+    phi ~ U[0, 2 pi) drawn once.  Face coefficient 2 k_c k_n / (k_c + k_n) for all 26
+    neighbours; the pattern is fixed."""
+    g = rng(cfg_id, 0, STREAM_LOGN).standard_normal((N, N, N))
+    rd = rng(cfg_id, 0, STREAM_DRIFT)
+    kappa = rd.integers(1, 3, size=3)
+    phi = rd.uniform(0.0, 2.0 * np.pi)
+    c = (np.arange(N) + 0.5) / N
+    arg = (kappa[0] * c[None, None, :] + kappa[1] * c[None, :, None] + kappa[2] * c[:, None, None])
+    drift = 0.5 * np.sin(2.0 * np.pi * arg + phi + 2.0 * np.pi * t / period)
+    k = np.exp(sigma * g + drift)
+    return _assemble(k, "27pt", lambda a, b: 2.0 * a * b / (a + b))
+
+
+# ----------------------------------------------------------------------------- C4
+
+def logcoef_inputs(N: int, cfg_id: int = 4, n_cells: int = 16):
+    """Inputs of the differentiable solve: theta ~ N(0, 0.5^2) per cell, f ~ U[-1,1],
+    u_t ~ N(0,1), and ``n_cells`` distinct cells for the finite-difference check.
+    The operator values A(theta) are not built here (that is part of the method)."""
+    n = N ** 3
+    theta = rng(cfg_id, 0, STREAM_THETA).normal(0.0, 0.5, size=n)
+    f = rng(cfg_id, 0, STREAM_RHS).uniform(-1.0, 1.0, size=n)
+    u_t = rng(cfg_id, 0, STREAM_UT).standard_normal(n)
+    cells = rng(cfg_id, 0, STREAM_CELLS).choice(n, size=n_cells, replace=False)
+    return theta, f, u_t, np.sort(cells)
+
+
+def rhs_uniform(n: int, cfg_id: int, t: int) -> np.ndarray:
+    """Right-hand side of step t: U[-1, 1]."""
+    return rng(cfg_id, t, STREAM_RHS).uniform(-1.0, 1.0, size=n)
+
+
+# ----------------------------------------------------------------------------- presets
+
+CONFIGS = {
+    1: dict(name="two_fluid_7pt_32", N=32, steps=10, kind="two_fluid", front="c1",
+            eps_strong=0.08, precision="fp64"),
+    2: dict(name="two_fluid_7pt_128", N=128, steps=50, kind="two_fluid", front="moving",
+            eps_strong=0.08, precision="fp64"),
+    3: dict(name="two_fluid_7pt_192", N=192, steps=30, kind="two_fluid", front="moving",
+            eps_strong=0.08, precision="mixed"),
+    4: dict(name="logcoef_7pt", N=(64, 128), steps=1, kind="logcoef", eps_strong=0.08,
+            precision="fp64"),
+    5: dict(name="lognormal_27pt_160", N=160, steps=40, kind="lognormal27",
+            eps_strong=0.02, precision="mixed"),
+}
+
+
+def series_matrix(cfg_id: int, t: int, N: int | None = None):
+    """Matrix of step t of configuration ``cfg_id`` (C1, C2, C3, C5)."""
+    c = CONFIGS[cfg_id]
+    N = c["N"] if N is None else N
+    if c["kind"] == "two_fluid":
+        front = front_c1(t) if c["front"] == "c1" else front_moving(N, t)
+        return two_fluid_7pt(N, front)
+    if c["kind"] == "lognormal27":
+        return lognormal_27pt(N, t, cfg_id=cfg_id)
+    raise ValueError(f"configuration {cfg_id} has no matrix series")
