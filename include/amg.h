@@ -1,0 +1,194 @@
+/*
+ * amg.h -- C interface of the MI355X (gfx950) partial-reuse AMG library.
+ *
+ * The library solves A u = f for a sequence of sparse SPD matrices that share one
+ * sparsity pattern (a non-steady-state problem, one matrix per time step).  A smoothed-
+ * aggregation hierarchy is built once (Algorithm 1 of Demidov, "Partial Reuse AMG Setup
+ * Cost Amortization Strategy for the Solution of Non-Steady State Problems", Section 2).
+ * On later steps the transfer operators P_l and R_l = P_l^T are kept while every level's
+ * Galerkin operator A_{l+1} = R_l A_l P_l, smoother and the coarsest direct solver are
+ * rebuilt (Algorithm 4, Section 3); the Galerkin products reuse the sparsity pattern
+ * computed at setup, so only their numeric phase runs (the extension proposed in
+ * Section 5).  The solve is CG preconditioned by one V-cycle (Algorithm 2 and the last
+ * paragraph of Section 2).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are CSR with 0-based int32 row pointers and columns, columns sorted
+ *    ascending and unique within a row, a stored positive diagonal, a structurally
+ *    symmetric pattern and SPD values.
+ *  - Pointers are DEVICE pointers unless marked (host).  Inputs are borrowed for the
+ *    duration of the call; the library copies what it keeps.
+ *  - All device work is enqueued on the HIP stream given to amg_setup (NULL: the null
+ *    stream).  The caller's buffers must be ready on that stream.
+ *  - Every call returns an amg_status and never throws across the interface.  After a
+ *    HIP runtime error the context is unusable: later calls return AMG_ERR_STATE until
+ *    amg_destroy.  amg_last_error() describes the last failure of a context.
+ */
+#ifndef AMGMI_AMG_H
+#define AMGMI_AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amg_ctx amg_ctx;
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_ERR_ARG = -1,       /* invalid argument (NULL, size, unsorted/out-of-range columns) */
+    AMG_ERR_HIP = -2,       /* HIP runtime error */
+    AMG_ERR_OOM = -3,       /* device allocation failed */
+    AMG_ERR_PATTERN = -4,   /* pattern not structurally symmetric, or changed unexpectedly */
+    AMG_ERR_NOT_SPD = -5,   /* non-positive diagonal or coarse pivot */
+    AMG_ERR_BREAKDOWN = -6, /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
+    AMG_ERR_STATE = -7      /* context unusable after an earlier HIP error */
+} amg_status;
+
+/* How amg_rebuild_ex updates the hierarchy for new matrix values (same pattern). */
+typedef enum {
+    AMG_PARTIAL = 0,       /* Algorithm 4: keep P_l, R_l; rebuild A_{l+1}, smoothers, coarse solver */
+    AMG_FULL = 1,          /* Algorithm 1 from scratch (aggregation, P_l, patterns, everything) */
+    AMG_OPERATOR_ONLY = 2  /* Algorithm 3 (full reuse): only the Krylov operator changes */
+} amg_rebuild_mode;
+
+typedef struct {
+    int smoother;         /* 0: damped Jacobi m_i = omega/a_ii; 1: SPAI0 m_i = a_ii / sum_j a_ij^2 */
+    int aggregation;      /* 0: smoothed aggregation; 1: plain aggregation (P = tentative) */
+    double jacobi_omega;  /* Jacobi damping (0.72) */
+    double eps_strong;    /* strength threshold on level 0, halved per level (0.08) */
+    int coarse_enough;    /* stop coarsening at <= this many rows (128) */
+    int max_levels;       /* (12) */
+    int npre, npost;      /* Jacobi/SPAI0 sweeps before and after the coarse correction (1, 1) */
+    int precision;        /* 0: FP64 everywhere; 1: FP32 hierarchy and V-cycle under FP64 CG */
+    double rtol;          /* stop when ||f - A u||_2 / ||f||_2 <= rtol, true residual (1e-8) */
+    int maxiter;          /* (100) */
+    int flexible_cg;      /* 1: beta = r.(z - z_old) / rho_old (robust to an inexact B) */
+} amg_params;
+
+typedef struct {          /* host struct filled by amg_solve */
+    int iters;            /* CG iterations taken */
+    int converged;        /* 1 when the true relative residual reached rtol */
+    double rel_res_true;  /* ||f - A u|| / ||f|| of the returned u */
+} amg_solve_info;
+
+/* Fill *p (host) with the defaults listed above. */
+amg_status amg_params_default(amg_params* p);
+
+/* Algorithm 1 on the device.  n rows, nnz entries; row_ptr[n+1], col[nnz], val[nnz] are
+ * device arrays; p is a host struct (NULL: defaults).  Synchronises the stream (coarse
+ * sizes are needed on the host).  *out receives a new context on AMG_OK, NULL otherwise. */
+amg_status amg_setup(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                     const int32_t* col, const double* val, const amg_params* p, void* hip_stream);
+
+/* Algorithm 1 with prescribed transfer operators (test hook for closed-form Galerkin
+ * products): level l < nlev uses P_l with n_l rows, nc[l] columns and nnzP[l] entries
+ * (device CSR arrays P_ptr[l], P_col[l], P_val[l]; the pointer arrays and nc, nnzP are
+ * host arrays).  The level reached after them is the coarsest. */
+amg_status amg_setup_transfer(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                              const int32_t* col, const double* val, int nlev,
+                              const int32_t* const* P_ptr, const int32_t* const* P_col,
+                              const double* const* P_val, const int32_t* nc, const int64_t* nnzP,
+                              const amg_params* p, void* hip_stream);
+
+/* New values val[nnz] (device) for the current pattern.  pattern_changed == 0 runs
+ * Algorithm 4 (numeric Galerkin products on the cached patterns, smoothers, coarse
+ * inverse) without any host synchronisation.  pattern_changed != 0 is valid only after
+ * amg_set_pattern: with the same n the transfer operators are kept and the Galerkin
+ * patterns are recomputed before the partial update; with a different n a full setup runs
+ * (a size change, Section 3).  Non-zero without a pending pattern returns AMG_ERR_ARG. */
+amg_status amg_rebuild(amg_ctx* c, const double* val, int pattern_changed);
+
+/* Register a new pattern (device arrays) for the next amg_rebuild(..., 1). */
+amg_status amg_set_pattern(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                           const int32_t* col);
+
+/* New values with an explicit update mode (see amg_rebuild_mode). */
+amg_status amg_rebuild_ex(amg_ctx* c, const double* val, amg_rebuild_mode m);
+
+/* CG preconditioned by one V-cycle per iteration.  f[n] (device, read), u[n] (device,
+ * in: initial guess, out: solution).  info (host) may be NULL.  Returns after convergence
+ * or maxiter: one 16-byte device-to-host read per iteration decides the stop.  Not
+ * converging is not an error (info->converged = 0). */
+amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* info);
+
+/* One V-cycle z = B r from a zero initial guess (r, z: device, n entries). */
+amg_status amg_vcycle(amg_ctx* c, const double* r, double* z);
+
+amg_status amg_destroy(amg_ctx* c);
+
+/* Description of the last failure of c (or of the last failed amg_setup when c is NULL). */
+const char* amg_last_error(const amg_ctx* c);
+
+/* ---- introspection (tests and reports) ---- */
+amg_status amg_num_levels(const amg_ctx* c, int* L);
+
+/* dims[0..4] = { n_l, nnz(A_l), n_{l+1} (0 on the coarsest), nnz(P_l), nnz(A_l P_l) } */
+amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims);
+
+/* Copy level l to host arrays (any may be NULL).  agg[n_l], strong[nnz(A_l)] exist on
+ * aggregated levels; P on non-coarsest levels; m (smoother diagonal) on non-coarsest
+ * levels.  In mixed precision A_val/P_val/m are the FP32 values widened to FP64.
+ * Synchronises the stream. */
+amg_status amg_export_level(const amg_ctx* c, int l, int32_t* agg, uint8_t* strong, int32_t* A_ptr,
+                            int32_t* A_col, double* A_val, int32_t* P_ptr, int32_t* P_col,
+                            double* P_val, double* m);
+
+/* Dense inverse of the coarsest operator (host, n_L * n_L, row-major). */
+amg_status amg_export_coarse_inverse(const amg_ctx* c, double* inv);
+
+/* Milliseconds of the phases of the last setup or rebuild (host out[8]):
+ * {strength+aggregation, prolongator+transpose, symbolic Galerkin, numeric Galerkin,
+ *  smoother, coarse inverse, total, 0}.  Synchronises the stream. */
+amg_status amg_phase_times(const amg_ctx* c, double* out);
+
+/* ---- per-kernel timing (reports and roofline measurements) ---- */
+
+typedef enum {
+    AMG_K_GALERKIN_AP = 0,   /* numeric A_l P_l */
+    AMG_K_GALERKIN_RAP = 1,  /* numeric R_l (A_l P_l) */
+    AMG_K_SMOOTHER = 2,      /* smoother diagonal */
+    AMG_K_COARSE_INV = 3,    /* densify + inverse of the coarsest operator */
+    AMG_K_CG_PQ = 4,         /* p = z + beta p, q = A p, p.q (the Krylov operator SpMV) */
+    AMG_K_CG_UPDATE = 5,     /* x += alpha p, r -= alpha q, r.r */
+    AMG_K_CG_RZ = 6,         /* r.z */
+    AMG_K_CG_INIT = 7,       /* r = f - A x, r.r, f.f */
+    AMG_K_SMOOTH0_RES = 8,   /* first pre-smoothing sweep fused with the residual */
+    AMG_K_JACOBI = 9,        /* one smoothing sweep */
+    AMG_K_RESTRICT = 10,     /* f_{l+1} = R_l r_l */
+    AMG_K_PROLONG = 11,      /* u_l += P_l u_{l+1} */
+    AMG_K_COARSE_GEMV = 12,  /* u_L = A_L^{-1} f_L */
+    AMG_K_CAST = 13,         /* FP64 <-> FP32 conversions of the mixed-precision form */
+    AMG_K_COUNT = 16
+} amg_kernel_class;
+
+/* Bracket every launch of the kernel classes in `mask` (bit k = class k) on level `level`
+ * (-1: every level; the CG kernels count as level 0) with HIP events on the context's
+ * stream.  mask = 0 turns tracing off. */
+amg_status amg_trace(amg_ctx* c, unsigned mask, int level);
+
+/* Milliseconds and launch counts per class (host arrays of AMG_K_COUNT) accumulated since
+ * the previous read; resets them.  Synchronises the stream. */
+amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches);
+
+/* ---- differentiable form: 7-point operator with per-cell log-coefficients ---- */
+
+/* val[nnz] (device) = A(theta) on the sorted 7-point pattern of an nx*ny*nz grid (cell
+ * x + nx*(y + ny*z)): a_cj = -2 k_c k_j / (k_c + k_j) with k = exp(theta), and
+ * a_cc = sum_j 2 k_c k_j / (k_c + k_j) + (number of missing neighbours) * k_c. */
+amg_status amg_logcoef7_assemble(int32_t nx, int32_t ny, int32_t nz, const double* theta,
+                                 double* val, void* hip_stream);
+
+/* grad[c] (device) = -lambda^T (dA/dtheta_c) u for the operator above (the gradient of a
+ * loss L(u) when lambda = A^{-1} dL/du, A symmetric). */
+amg_status amg_logcoef7_adjoint(int32_t nx, int32_t ny, int32_t nz, const double* theta,
+                                const double* u, const double* lambda, double* grad,
+                                void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMGMI_AMG_H */

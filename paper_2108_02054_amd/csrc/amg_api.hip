@@ -1,0 +1,1029 @@
+// amg_api.hip -- hierarchy manager, update strategies, V-cycle / PCG orchestration, and
+// the exported C interface declared in include/amg.h.
+//
+// Strategies (Section 3 of the paper):
+//   full rebuild   (Algorithm 1)  build_hierarchy(): aggregation, P, R, patterns, values
+//   partial reuse  (Algorithm 4)  partial_rebuild(): numeric Galerkin chain on the cached
+//                                 patterns, smoothers, coarse inverse; no host sync
+//   full reuse     (Algorithm 3)  only the Krylov operator's values change
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <utility>
+
+#include "amg_internal.h"
+
+using namespace amgmi;
+
+namespace amgmi {
+
+[[noreturn]] void throw_hip(hipError_t e, const char* expr, const char* file, int line) {
+    (void)hipGetLastError();  // consume the error so later launch checks do not report it again
+    const amg_status st = (e == hipErrorOutOfMemory) ? AMG_ERR_OOM : AMG_ERR_HIP;
+    throw Fail{st, std::string(hipGetErrorString(e)) + " in " + expr + " (" + file + ":" + std::to_string(line) + ")"};
+}
+
+void* dalloc(size_t bytes, hipStream_t s) {
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes ? bytes : 8, s);
+    if (e == hipErrorOutOfMemory)
+        throw Fail{AMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    if (e != hipSuccess) throw_hip(e, "hipMallocAsync", __FILE__, __LINE__);
+    return p;
+}
+
+void dfree(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+int lane_group(double avg) {
+    int g = 2;
+    while (g < 64 && g < avg) g <<= 1;
+    return g;
+}
+
+}  // namespace amgmi
+
+namespace {
+
+thread_local std::string g_setup_err;
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------ memory bookkeeping
+
+template <typename T>
+T* halloc(amg_ctx* c, size_t n) {
+    T* p = dnew<T>(n, c->stream);
+    c->hier_allocs.push_back(p);
+    return p;
+}
+
+template <typename T>
+T* oalloc(amg_ctx* c, size_t n) {
+    T* p = dnew<T>(n, c->stream);
+    c->own_allocs.push_back(p);
+    return p;
+}
+
+void track(amg_ctx* c, const Csr& m) {
+    for (void* p : {(void*)m.ptr, (void*)m.col, (void*)m.val, (void*)m.val32})
+        if (p) c->hier_allocs.push_back(p);
+}
+
+void release(amg_ctx* c, void* p) {
+    if (!p) return;
+    for (auto& q : c->hier_allocs)
+        if (q == p) {
+            q = nullptr;
+            dfree(p, c->stream);
+            return;
+        }
+}
+
+void release_csr(amg_ctx* c, Csr& m) {
+    release(c, m.ptr);
+    release(c, m.col);
+    release(c, m.val);
+    release(c, m.val32);
+    m = Csr{};
+}
+
+void d2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes) HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+}
+
+bool mixed(const amg_ctx* c) { return c->prm.precision == 1; }
+
+// Brackets the launches inside its scope with events when the class is traced.
+struct Trace {
+    amg_ctx* c;
+    int cls;
+    hipEvent_t a = nullptr, b = nullptr;
+    static hipEvent_t take(amg_ctx* c) {
+        if (c->ev_pool.empty()) {
+            hipEvent_t e;
+            HIP_CHECK(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    Trace(amg_ctx* cc, int k, int level) : c(cc), cls(k) {
+        if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == level)) {
+            a = take(c);
+            b = take(c);
+            HIP_CHECK(hipEventRecord(a, c->stream));
+        }
+    }
+    ~Trace() {
+        if (a) {
+            (void)hipEventRecord(b, c->stream);
+            c->traced.push_back({cls, a, b});
+        }
+    }
+};
+
+void read_scalars(amg_ctx* c) {
+    HIP_CHECK(hipMemcpyAsync(c->h_scal, c->rs.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+void read_flags(amg_ctx* c) {
+    HIP_CHECK(hipMemcpyAsync(c->h_flags, c->d_flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+void clear_flags(amg_ctx* c) { HIP_CHECK(hipMemsetAsync(c->d_flags, 0, F_COUNT * sizeof(int), c->stream)); }
+
+// Pattern (and optionally values) checks of a CSR matrix on the device.
+void validate(amg_ctx* c, const Csr& A, int32_t* diag_pos, const char* what) {
+    clear_flags(c);
+    launch_validate(A, diag_pos, c->d_flags, c->stream);
+    read_flags(c);
+    if (c->h_flags[F_ARG])
+        throw Fail{AMG_ERR_ARG, std::string(what) + ": invalid CSR (pointers, unsorted/duplicate/out-of-range columns or non-finite values)"};
+    if (c->h_flags[F_NOT_SPD])
+        throw Fail{AMG_ERR_NOT_SPD, std::string(what) + ": missing or non-positive diagonal entry"};
+}
+
+void set_groups(Level& L) {
+    const double n = L.A.nrows > 0 ? (double)L.A.nrows : 1.0;
+    L.gA = lane_group((double)L.A.nnz / n);
+    if (L.P.nrows > 0) {
+        L.gP = lane_group((double)L.P.nnz / n);
+        L.gR = lane_group((double)L.R.nnz / (L.R.nrows > 0 ? (double)L.R.nrows : 1.0));
+        L.gAP = lane_group((double)L.AP.nnz / n);
+    }
+}
+
+// ------------------------------------------------------------------ Algorithm 4
+
+// Keep P_l, R_l and every cached pattern; recompute A_{l+1} = R_l (A_l P_l) level by
+// level, then the smoother diagonals, then the dense inverse of the coarsest operator.
+// All sizes are known, so nothing here waits for the device.
+template <typename T>
+void partial_rebuild(amg_ctx* c, const double* val) {
+    hipStream_t s = c->stream;
+    Level& L0 = c->lv[0];
+    HIP_CHECK(hipEventRecord(c->ev[0], s));
+    if (val != L0.A.val) d2d(L0.A.val, val, (size_t)L0.A.nnz * sizeof(double), s);
+    c->outer_val = L0.A.val;
+    if constexpr (std::is_same<T, float>::value) launch_cast_d2f(L0.A.nnz, L0.A.val, L0.A.val32, s);
+    const int nlev = (int)c->lv.size();
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const Level& L = c->lv[l];
+        {
+            Trace tr(c, AMG_K_GALERKIN_AP, l);
+            launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, s);
+        }
+        Trace tr(c, AMG_K_GALERKIN_RAP, l);
+        launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, s);
+    }
+    HIP_CHECK(hipEventRecord(c->ev[1], s));
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const Level& L = c->lv[l];
+        Trace tr(c, AMG_K_SMOOTHER, l);
+        launch_smoother_diag<T>(L.A, c->prm.smoother, c->prm.jacobi_omega, L.mv<T>(), s);
+    }
+    HIP_CHECK(hipEventRecord(c->ev[2], s));
+    {
+        Trace tr(c, AMG_K_COARSE_INV, nlev - 1);
+        launch_densify<T>(c->lv.back().A, c->cinv, s);
+        launch_dense_inverse(c->nL, c->cinv, c->rs.scal, s);
+    }
+    HIP_CHECK(hipEventRecord(c->ev[3], s));
+    c->phase_pending = true;
+}
+
+void partial_any(amg_ctx* c, const double* val) {
+    if (mixed(c))
+        partial_rebuild<float>(c, val);
+    else
+        partial_rebuild<double>(c, val);
+}
+
+template <typename T>
+void alloc_vectors(amg_ctx* c) {
+    for (Level& L : c->lv) {
+        const size_t n = (size_t)L.A.nrows;
+        L.u = halloc<T>(c, n);
+        L.f = halloc<T>(c, n);
+        L.r = halloc<T>(c, n);
+        L.t = halloc<T>(c, n);
+    }
+}
+
+// FP32 shadows of the hierarchy (mixed precision): every operator value array, and the
+// transfer operators cast once.
+void alloc_shadow(amg_ctx* c) {
+    hipStream_t s = c->stream;
+    for (Level& L : c->lv) {
+        L.A.val32 = halloc<float>(c, (size_t)L.A.nnz);
+        if (L.P.nrows > 0) {
+            L.P.val32 = halloc<float>(c, (size_t)L.P.nnz);
+            L.R.val32 = halloc<float>(c, (size_t)L.R.nnz);
+            L.AP.val32 = halloc<float>(c, (size_t)L.AP.nnz);
+            L.m32 = halloc<float>(c, (size_t)L.A.nrows);
+            launch_cast_d2f(L.P.nnz, L.P.val, L.P.val32, s);
+            launch_cast_d2f(L.R.nnz, L.R.val, L.R.val32, s);
+        }
+    }
+}
+
+void alloc_cg(amg_ctx* c) {
+    const size_t n = (size_t)c->lv[0].A.nrows;
+    c->x = halloc<double>(c, n);
+    c->r = halloc<double>(c, n);
+    c->z = halloc<double>(c, n);
+    c->zold = halloc<double>(c, n);
+    c->pa = halloc<double>(c, n);
+    c->pb = halloc<double>(c, n);
+    c->q = halloc<double>(c, n);
+}
+
+struct Transfer {
+    int nlev;
+    const int32_t* const* ptr;
+    const int32_t* const* col;
+    const double* const* val;
+    const int32_t* nc;
+    const int64_t* nnz;
+};
+
+// ------------------------------------------------------------------ Algorithm 1
+
+void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, const int32_t* col,
+                     const double* val, const Transfer* tr) {
+    hipStream_t s = c->stream;
+    const amg_params& p = c->prm;
+    const auto t_all = Clock::now();
+    double ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    // Copy the input first: it may be the current hierarchy's own level-0 arrays.
+    std::vector<void*> old = std::move(c->hier_allocs);
+    c->hier_allocs.clear();
+    Csr A0;
+    A0.nrows = A0.ncols = n;
+    A0.nnz = nnz;
+    A0.ptr = halloc<int32_t>(c, (size_t)n + 1);
+    A0.col = halloc<int32_t>(c, (size_t)nnz);
+    A0.val = halloc<double>(c, (size_t)nnz);
+    d2d(A0.ptr, ptr, ((size_t)n + 1) * sizeof(int32_t), s);
+    d2d(A0.col, col, (size_t)nnz * sizeof(int32_t), s);
+    d2d(A0.val, val, (size_t)nnz * sizeof(double), s);
+    for (void* q : old) dfree(q, s);
+    c->lv.clear();
+    c->outer_own = nullptr;
+    c->cinv = nullptr;
+    c->lv.emplace_back();
+    c->lv[0].A = A0;
+    c->outer_val = A0.val;
+    c->phase_pending = false;
+
+    for (int l = 0;; ++l) {
+        const Csr A = c->lv[(size_t)l].A;
+        const int32_t nl = A.nrows;
+        int32_t* diag_pos = dnew<int32_t>((size_t)nl, s);
+        validate(c, A, diag_pos, l == 0 ? "input matrix" : "coarse operator");
+        const bool stop = tr ? (l >= tr->nlev) : (nl <= p.coarse_enough || l >= p.max_levels - 1);
+        if (stop) {
+            dfree(diag_pos, s);
+            break;
+        }
+        Csr P;
+        auto t0 = Clock::now();
+        if (tr) {
+            P.nrows = nl;
+            P.ncols = tr->nc[l];
+            P.nnz = tr->nnz[l];
+            P.ptr = halloc<int32_t>(c, (size_t)nl + 1);
+            P.col = halloc<int32_t>(c, (size_t)P.nnz);
+            P.val = halloc<double>(c, (size_t)P.nnz);
+            d2d(P.ptr, tr->ptr[l], ((size_t)nl + 1) * sizeof(int32_t), s);
+            d2d(P.col, tr->col[l], (size_t)P.nnz * sizeof(int32_t), s);
+            d2d(P.val, tr->val[l], (size_t)P.nnz * sizeof(double), s);
+            validate(c, P, nullptr, "transfer operator");
+        } else {
+            uint8_t* strong = halloc<uint8_t>(c, (size_t)A.nnz);
+            int32_t* tpos = dnew<int32_t>((size_t)A.nnz, s);
+            uint8_t* iso = dnew<uint8_t>((size_t)nl, s);
+            uint8_t* state = dnew<uint8_t>((size_t)nl, s);
+            const double eps = std::ldexp(p.eps_strong, -l);
+            clear_flags(c);
+            launch_strength(A, diag_pos, eps * eps, strong, tpos, iso, c->d_flags, s);
+            read_flags(c);
+            if (c->h_flags[F_PATTERN]) throw Fail{AMG_ERR_PATTERN, "pattern is not structurally symmetric"};
+            run_mis2(A, strong, iso, state, c->d_flags, c->h_flags, s);
+            int32_t* agg = halloc<int32_t>(c, (size_t)nl);
+            const int32_t nc = run_aggregate(A, strong, tpos, state, agg, c->d_flags, c->h_flags, s);
+            c->lv[(size_t)l].agg = agg;
+            c->lv[(size_t)l].strong = strong;
+            dfree(tpos, s);
+            dfree(iso, s);
+            dfree(state, s);
+            ph[0] += ms_since(t0);
+            if (nc == 0 || nc >= nl) {
+                dfree(diag_pos, s);
+                break;
+            }
+            t0 = Clock::now();
+            build_prolongator(A, strong, diag_pos, agg, nc, p.aggregation, P, s);
+            track(c, P);
+        }
+        Csr R;
+        build_transpose(P, R, s);
+        track(c, R);
+        HIP_CHECK(hipStreamSynchronize(s));
+        ph[1] += ms_since(t0);
+        t0 = Clock::now();
+        Csr AP, Ac;
+        symbolic_spgemm(A, P, AP, s);
+        track(c, AP);
+        symbolic_spgemm(R, AP, Ac, s);
+        track(c, Ac);
+        AP.val = halloc<double>(c, (size_t)AP.nnz);
+        Ac.val = halloc<double>(c, (size_t)Ac.nnz);
+        Ac.ncols = Ac.nrows;
+        HIP_CHECK(hipStreamSynchronize(s));
+        ph[2] += ms_since(t0);
+        t0 = Clock::now();
+        {
+            Level& L = c->lv[(size_t)l];
+            L.P = P;
+            L.R = R;
+            L.AP = AP;
+            set_groups(L);
+        }
+        Level next;
+        next.A = Ac;
+        set_groups(next);
+        next.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
+        launch_galerkin_ap<double>(A, P, AP, c->lv[(size_t)l].gAP, s);
+        launch_galerkin_rap<double>(R, AP, Ac, next.gRAP, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        ph[3] += ms_since(t0);
+        dfree(diag_pos, s);
+        c->lv.push_back(next);
+    }
+    set_groups(c->lv.back());
+
+    auto t0 = Clock::now();
+    const int nlev = (int)c->lv.size();
+    for (int l = 0; l + 1 < nlev; ++l) {
+        Level& L = c->lv[(size_t)l];
+        L.m = halloc<double>(c, (size_t)L.A.nrows);
+        launch_smoother_diag<double>(L.A, p.smoother, p.jacobi_omega, L.m, s);
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    ph[4] += ms_since(t0);
+    t0 = Clock::now();
+    c->nL = c->lv.back().A.nrows;
+    if (c->nL > COARSE_GLOBAL_MAX)
+        throw Fail{AMG_ERR_ARG, "coarsest level has " + std::to_string(c->nL) + " rows; too many for a dense inverse"};
+    c->cinv = halloc<double>(c, (size_t)c->nL * c->nL);
+    launch_densify<double>(c->lv.back().A, c->cinv, s);
+    launch_dense_inverse(c->nL, c->cinv, c->rs.scal, s);
+    read_scalars(c);
+    if (c->h_scal[S_COARSE] != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
+    ph[5] += ms_since(t0);
+
+    if (mixed(c)) {
+        alloc_shadow(c);
+        partial_rebuild<float>(c, c->lv[0].A.val);
+        read_scalars(c);
+        if (c->h_scal[S_COARSE] != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest FP32 operator is not SPD"};
+        c->phase_pending = false;
+        alloc_vectors<float>(c);
+    } else {
+        alloc_vectors<double>(c);
+    }
+    alloc_cg(c);
+    HIP_CHECK(hipStreamSynchronize(s));
+    ph[6] = ms_since(t_all);
+    std::memcpy(c->phase_ms, ph, sizeof(ph));
+}
+
+// New pattern with the same number of rows: keep P_l and R_l, recompute the Galerkin
+// patterns level by level (values follow in the partial update).
+void repattern(amg_ctx* c) {
+    hipStream_t s = c->stream;
+    Level& L0 = c->lv[0];
+    Csr A;
+    A.nrows = A.ncols = c->pend_n;
+    A.nnz = c->pend_nnz;
+    A.ptr = halloc<int32_t>(c, (size_t)A.nrows + 1);
+    A.col = halloc<int32_t>(c, (size_t)A.nnz);
+    A.val = halloc<double>(c, (size_t)A.nnz);
+    d2d(A.ptr, c->pend_ptr, ((size_t)A.nrows + 1) * sizeof(int32_t), s);
+    d2d(A.col, c->pend_col, (size_t)A.nnz * sizeof(int32_t), s);
+    release_csr(c, L0.A);
+    release(c, c->outer_own);
+    c->outer_own = nullptr;
+    L0.A = A;
+    c->outer_val = L0.A.val;
+    dfree(c->pend_ptr, s);
+    dfree(c->pend_col, s);
+    c->pend_ptr = c->pend_col = nullptr;
+    c->pend_n = 0;
+    // structural checks only; the values are checked through the coarse factorisation
+    Csr pat = A;
+    pat.val = nullptr;
+    int32_t* diag_pos = dnew<int32_t>((size_t)A.nrows, s);
+    validate(c, pat, diag_pos, "new pattern");
+    dfree(diag_pos, s);
+    const int nlev = (int)c->lv.size();
+    for (int l = 0; l + 1 < nlev; ++l) {
+        Level& L = c->lv[(size_t)l];
+        Level& N = c->lv[(size_t)l + 1];
+        release_csr(c, L.AP);
+        Csr AP, Ac;
+        symbolic_spgemm(L.A, L.P, AP, s);
+        track(c, AP);
+        AP.val = halloc<double>(c, (size_t)AP.nnz);
+        if (mixed(c)) AP.val32 = halloc<float>(c, (size_t)AP.nnz);
+        symbolic_spgemm(L.R, AP, Ac, s);
+        track(c, Ac);
+        Ac.ncols = Ac.nrows;
+        Ac.val = halloc<double>(c, (size_t)Ac.nnz);
+        if (mixed(c)) Ac.val32 = halloc<float>(c, (size_t)Ac.nnz);
+        L.AP = AP;
+        release_csr(c, N.A);
+        N.A = Ac;
+        set_groups(L);
+        N.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
+    }
+    if (mixed(c)) L0.A.val32 = halloc<float>(c, (size_t)L0.A.nnz);
+    set_groups(c->lv.back());
+    // The strength flags were per entry of the old patterns; the aggregates stay (they
+    // still define the kept transfer operators).
+    for (Level& L : c->lv) {
+        release(c, L.strong);
+        L.strong = nullptr;
+    }
+}
+
+// ------------------------------------------------------------------ V-cycle
+
+// Algorithm 2 on level l from a zero initial guess; returns the buffer holding u_l.
+// At level 0 the last post-smoothing sweep writes directly into `out` when given.
+template <typename T>
+T* vcycle_level(amg_ctx* c, int l, const T* f, T* out) {
+    hipStream_t s = c->stream;
+    const Level& L = c->lv[(size_t)l];
+    const int nlev = (int)c->lv.size();
+    if (l == nlev - 1) {
+        T* u = out ? out : (T*)L.u;
+        Trace tr(c, AMG_K_COARSE_GEMV, l);
+        launch_coarse_gemv<T>(c->nL, c->cinv, f, u, s);
+        return u;
+    }
+    const amg_params& p = c->prm;
+    T* cur = (T*)L.u;
+    T* other = (T*)L.t;
+    T* r = (T*)L.r;
+    const T* m = L.mv<T>();
+    const T* rres = r;
+    if (p.npre == 0) {
+        HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)L.A.nrows * sizeof(T), s));
+        rres = f;
+    } else {
+        {
+            Trace tr(c, AMG_K_SMOOTH0_RES, l);
+            launch_smooth0_residual<T>(L.A, L.gA, m, f, cur, r, s);
+        }
+        for (int it = 1; it < p.npre; ++it) {
+            Trace tr(c, AMG_K_JACOBI, l);
+            launch_jacobi<T>(L.A, L.gA, m, f, cur, other, s);
+            std::swap(cur, other);
+        }
+        if (p.npre > 1) launch_residual<T>(L.A, L.gA, f, cur, r, s);
+    }
+    const Level& C = c->lv[(size_t)l + 1];
+    {
+        Trace tr(c, AMG_K_RESTRICT, l);
+        launch_spmv<T>(L.R, L.gR, rres, (T*)C.f, s);
+    }
+    const T* uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr);
+    {
+        Trace tr(c, AMG_K_PROLONG, l);
+        launch_prolong_add<T>(L.P, L.gP, uc, cur, s);
+    }
+    for (int it = 0; it < p.npost; ++it) {
+        T* dst = (out && it == p.npost - 1) ? out : other;
+        Trace tr(c, AMG_K_JACOBI, l);
+        launch_jacobi<T>(L.A, L.gA, m, f, cur, dst, s);
+        if (dst == other)
+            std::swap(cur, other);
+        else
+            cur = dst;
+    }
+    if (out && cur != out) {
+        d2d(out, cur, (size_t)L.A.nrows * sizeof(T), s);
+        cur = out;
+    }
+    return cur;
+}
+
+// z = B r with r, z in FP64; in mixed precision the cycle itself runs in FP32.
+void vcycle_apply(amg_ctx* c, const double* r, double* z) {
+    Level& L0 = c->lv[0];
+    if (mixed(c)) {
+        {
+            Trace tr(c, AMG_K_CAST, 0);
+            launch_cast_d2f(L0.A.nrows, r, (float*)L0.f, c->stream);
+        }
+        const float* res = vcycle_level<float>(c, 0, (const float*)L0.f, nullptr);
+        Trace tr(c, AMG_K_CAST, 0);
+        launch_cast_f2d(L0.A.nrows, res, z, c->stream);
+    } else {
+        vcycle_level<double>(c, 0, r, z);
+    }
+}
+
+// ------------------------------------------------------------------ PCG
+
+// CG preconditioned by one V-cycle; stops on the true relative residual.  Scalars stay on
+// the device; each iteration reads ||r||^2 and the breakdown flag back (one 64-byte copy).
+amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
+    hipStream_t s = c->stream;
+    const Level& L0 = c->lv[0];
+    const int n = L0.A.nrows;
+    const amg_params& p = c->prm;
+    amg_solve_info inf{0, 0, 0.0};
+    launch_copy(n, u, c->x, s);
+    {
+        Trace tr(c, AMG_K_CG_INIT, 0);
+        launch_cg_init(L0.A, c->outer_val, L0.gA, f, c->x, c->r, c->rs, s);
+    }
+    read_scalars(c);
+    if (c->h_scal[S_COARSE] != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
+    const double ff = c->h_scal[S_FF];
+    if (ff == 0.0) {
+        HIP_CHECK(hipMemsetAsync(u, 0, (size_t)n * sizeof(double), s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        inf.converged = 1;
+        if (info) *info = inf;
+        return AMG_OK;
+    }
+    const double nf = std::sqrt(ff);
+    double res = std::sqrt(c->h_scal[S_RR]) / nf;
+    if (res <= p.rtol) {
+        inf.converged = 1;
+        inf.rel_res_true = res;
+        if (info) *info = inf;
+        return AMG_OK;
+    }
+    vcycle_apply(c, c->r, c->z);
+    {
+        Trace tr(c, AMG_K_CG_RZ, 0);
+        launch_cg_rz(n, c->r, c->z, c->zold, p.flexible_cg, 1, c->rs, s);
+    }
+    double* pold = c->pa;
+    double* pnew = c->pb;
+    int it = 0;
+    bool converged = false;
+    while (it < p.maxiter) {
+        ++it;
+        {
+            Trace tr(c, AMG_K_CG_PQ, 0);
+            launch_cg_pq(L0.A, c->outer_val, L0.gA, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+        }
+        {
+            Trace tr(c, AMG_K_CG_UPDATE, 0);
+            launch_cg_update(n, pnew, c->q, c->x, c->r, c->rs, s);
+        }
+        read_scalars(c);
+        if (c->h_scal[S_FLAG] != 0.0) {
+            c->err = "CG breakdown (p.Ap <= 0 or a non-finite scalar)";
+            if (info) {
+                inf.iters = it;
+                *info = inf;
+            }
+            return AMG_ERR_BREAKDOWN;
+        }
+        res = std::sqrt(c->h_scal[S_RR]) / nf;
+        if (res <= p.rtol) {
+            launch_cg_init(L0.A, c->outer_val, L0.gA, f, c->x, c->r, c->rs, s);
+            read_scalars(c);
+            res = std::sqrt(c->h_scal[S_RR]) / nf;
+            if (res <= p.rtol) {
+                converged = true;
+                break;
+            }
+        }
+        if (p.flexible_cg) launch_copy(n, c->z, c->zold, s);
+        vcycle_apply(c, c->r, c->z);
+        {
+            Trace tr(c, AMG_K_CG_RZ, 0);
+            launch_cg_rz(n, c->r, c->z, c->zold, p.flexible_cg, 0, c->rs, s);
+        }
+        std::swap(pold, pnew);
+    }
+    if (!converged) {
+        launch_cg_init(L0.A, c->outer_val, L0.gA, f, c->x, c->r, c->rs, s);
+        read_scalars(c);
+        res = std::sqrt(c->h_scal[S_RR]) / nf;
+    }
+    launch_copy(n, c->x, u, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    inf.iters = it;
+    inf.converged = converged ? 1 : 0;
+    inf.rel_res_true = res;
+    if (info) *info = inf;
+    return AMG_OK;
+}
+
+// ------------------------------------------------------------------ context lifecycle
+
+amg_status check_params(const amg_params& p) {
+    if (p.smoother < 0 || p.smoother > 1 || p.aggregation < 0 || p.aggregation > 1 || p.precision < 0 ||
+        p.precision > 1 || p.npre < 0 || p.npre > 16 || p.npost < 0 || p.npost > 16 || p.coarse_enough < 1 ||
+        p.max_levels < 1 || p.max_levels > 64 || !(p.rtol > 0.0) || p.maxiter < 0 || !(p.eps_strong >= 0.0) ||
+        !(p.jacobi_omega > 0.0))
+        return AMG_ERR_ARG;
+    return AMG_OK;
+}
+
+void destroy_ctx(amg_ctx* c) {
+    if (!c) return;
+    hipStream_t s = c->stream;
+    (void)hipStreamSynchronize(s);
+    for (void* p : c->hier_allocs) dfree(p, s);
+    for (void* p : c->own_allocs) dfree(p, s);
+    dfree(c->pend_ptr, s);
+    dfree(c->pend_col, s);
+    (void)hipStreamSynchronize(s);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
+    for (hipEvent_t& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto& t : c->traced) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    delete c;
+}
+
+amg_ctx* create_ctx(const amg_params& p, void* stream) {
+    amg_ctx* c = new amg_ctx();
+    c->prm = p;
+    c->stream = (hipStream_t)stream;
+    try {
+        c->rs.part = oalloc<double>(c, (size_t)RED_MAXK * RED_BLOCKS);
+        c->rs.ticket = oalloc<unsigned>(c, 1);
+        c->rs.scal = oalloc<double>(c, S_COUNT);
+        c->d_flags = oalloc<int>(c, F_COUNT);
+        HIP_CHECK(hipMemsetAsync(c->rs.ticket, 0, sizeof(unsigned), c->stream));
+        HIP_CHECK(hipMemsetAsync(c->rs.scal, 0, S_COUNT * sizeof(double), c->stream));
+        HIP_CHECK(hipHostMalloc((void**)&c->h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault));
+        for (hipEvent_t& e : c->ev) HIP_CHECK(hipEventCreate(&e));
+    } catch (...) {
+        destroy_ctx(c);
+        throw;
+    }
+    return c;
+}
+
+template <typename F>
+amg_status guard(amg_ctx* c, F&& f) {
+    if (c && c->broken) return AMG_ERR_STATE;
+    try {
+        return f();
+    } catch (const Fail& e) {
+        if (c) {
+            c->err = e.msg;
+            if (e.st == AMG_ERR_HIP) c->broken = true;
+        } else {
+            g_setup_err = e.msg;
+        }
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return AMG_ERR_OOM;
+    } catch (...) {
+        if (c) c->err = "unexpected exception";
+        return AMG_ERR_HIP;
+    }
+}
+
+}  // namespace
+
+// ======================================================================= C interface
+extern "C" {
+
+amg_status amg_params_default(amg_params* p) {
+    if (!p) return AMG_ERR_ARG;
+    p->smoother = 0;
+    p->aggregation = 0;
+    p->jacobi_omega = 0.72;
+    p->eps_strong = 0.08;
+    p->coarse_enough = 128;
+    p->max_levels = 12;
+    p->npre = 1;
+    p->npost = 1;
+    p->precision = 0;
+    p->rtol = 1e-8;
+    p->maxiter = 100;
+    p->flexible_cg = 0;
+    return AMG_OK;
+}
+
+static amg_status setup_common(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                               const double* val, const amg_params* p, void* stream, const Transfer* tr) {
+    if (!out) return AMG_ERR_ARG;
+    *out = nullptr;
+    if (n <= 0 || nnz <= 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || !col || !val) {
+        g_setup_err = "amg_setup: invalid sizes or NULL arrays";
+        return AMG_ERR_ARG;
+    }
+    amg_params prm;
+    amg_params_default(&prm);
+    if (p) prm = *p;
+    if (check_params(prm) != AMG_OK) {
+        g_setup_err = "amg_setup: invalid parameters";
+        return AMG_ERR_ARG;
+    }
+    amg_ctx* c = nullptr;
+    amg_status st = guard(nullptr, [&] {
+        c = create_ctx(prm, stream);
+        return AMG_OK;
+    });
+    if (st != AMG_OK) return st;
+    c->transfer_given = tr != nullptr;
+    st = guard(c, [&] {
+        build_hierarchy(c, n, nnz, row_ptr, col, val, tr);
+        return AMG_OK;
+    });
+    if (st != AMG_OK) {
+        g_setup_err = c->err;
+        destroy_ctx(c);
+        return st;
+    }
+    *out = c;
+    return AMG_OK;
+}
+
+amg_status amg_setup(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                     const double* val, const amg_params* p, void* hip_stream) {
+    return setup_common(out, n, nnz, row_ptr, col, val, p, hip_stream, nullptr);
+}
+
+amg_status amg_setup_transfer(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                              const double* val, int nlev, const int32_t* const* P_ptr,
+                              const int32_t* const* P_col, const double* const* P_val, const int32_t* nc,
+                              const int64_t* nnzP, const amg_params* p, void* hip_stream) {
+    if (nlev < 0 || (nlev > 0 && (!P_ptr || !P_col || !P_val || !nc || !nnzP))) {
+        if (out) *out = nullptr;
+        g_setup_err = "amg_setup_transfer: invalid transfer arrays";
+        return AMG_ERR_ARG;
+    }
+    for (int l = 0; l < nlev; ++l)
+        if (nc[l] <= 0 || nnzP[l] < 0 || !P_ptr[l] || (nnzP[l] > 0 && (!P_col[l] || !P_val[l]))) {
+            if (out) *out = nullptr;
+            g_setup_err = "amg_setup_transfer: invalid transfer operator";
+            return AMG_ERR_ARG;
+        }
+    Transfer tr{nlev, P_ptr, P_col, P_val, nc, nnzP};
+    return setup_common(out, n, nnz, row_ptr, col, val, p, hip_stream, &tr);
+}
+
+amg_status amg_rebuild_ex(amg_ctx* c, const double* val, amg_rebuild_mode m) {
+    if (!c || !val) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        switch (m) {
+            case AMG_PARTIAL:
+                partial_any(c, val);
+                return AMG_OK;
+            case AMG_FULL: {
+                if (c->transfer_given) throw Fail{AMG_ERR_ARG, "full rebuild of a hierarchy with prescribed transfer operators"};
+                const Csr A = c->lv[0].A;
+                build_hierarchy(c, A.nrows, A.nnz, A.ptr, A.col, val, nullptr);
+                return AMG_OK;
+            }
+            case AMG_OPERATOR_ONLY: {
+                const Csr& A = c->lv[0].A;
+                if (!c->outer_own) c->outer_own = halloc<double>(c, (size_t)A.nnz);
+                d2d(c->outer_own, val, (size_t)A.nnz * sizeof(double), c->stream);
+                c->outer_val = c->outer_own;
+                return AMG_OK;
+            }
+        }
+        throw Fail{AMG_ERR_ARG, "unknown rebuild mode"};
+    });
+}
+
+amg_status amg_rebuild(amg_ctx* c, const double* val, int pattern_changed) {
+    if (!c || !val) return AMG_ERR_ARG;
+    if (!pattern_changed) return amg_rebuild_ex(c, val, AMG_PARTIAL);
+    return guard(c, [&] {
+        if (!c->pend_ptr) throw Fail{AMG_ERR_ARG, "pattern_changed without a pending amg_set_pattern"};
+        if (c->pend_n != c->lv[0].A.nrows || c->transfer_given) {
+            if (c->transfer_given) throw Fail{AMG_ERR_ARG, "size change of a hierarchy with prescribed transfer operators"};
+            const int32_t n = c->pend_n;
+            const int64_t nnz = c->pend_nnz;
+            int32_t* pp = c->pend_ptr;
+            int32_t* pc = c->pend_col;
+            c->pend_ptr = c->pend_col = nullptr;
+            c->pend_n = 0;
+            try {
+                build_hierarchy(c, n, nnz, pp, pc, val, nullptr);
+            } catch (...) {
+                dfree(pp, c->stream);
+                dfree(pc, c->stream);
+                throw;
+            }
+            dfree(pp, c->stream);
+            dfree(pc, c->stream);
+            return AMG_OK;
+        }
+        repattern(c);
+        partial_any(c, val);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_set_pattern(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col) {
+    if (!c || n <= 0 || nnz <= 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || !col) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        hipStream_t s = c->stream;
+        dfree(c->pend_ptr, s);
+        dfree(c->pend_col, s);
+        c->pend_ptr = c->pend_col = nullptr;
+        c->pend_ptr = dnew<int32_t>((size_t)n + 1, s);
+        c->pend_col = dnew<int32_t>((size_t)nnz, s);
+        d2d(c->pend_ptr, row_ptr, ((size_t)n + 1) * sizeof(int32_t), s);
+        d2d(c->pend_col, col, (size_t)nnz * sizeof(int32_t), s);
+        c->pend_n = n;
+        c->pend_nnz = nnz;
+        return AMG_OK;
+    });
+}
+
+amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
+    if (!c || !f || !u) return AMG_ERR_ARG;
+    return guard(c, [&] { return pcg(c, f, u, info); });
+}
+
+amg_status amg_vcycle(amg_ctx* c, const double* r, double* z) {
+    if (!c || !r || !z) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        vcycle_apply(c, r, z);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_destroy(amg_ctx* c) {
+    if (!c) return AMG_ERR_ARG;
+    destroy_ctx(c);
+    return AMG_OK;
+}
+
+const char* amg_last_error(const amg_ctx* c) { return c ? c->err.c_str() : g_setup_err.c_str(); }
+
+amg_status amg_num_levels(const amg_ctx* c, int* L) {
+    if (!c || !L) return AMG_ERR_ARG;
+    *L = (int)c->lv.size();
+    return AMG_OK;
+}
+
+amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims) {
+    if (!c || !dims || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
+    const Level& L = c->lv[(size_t)l];
+    dims[0] = L.A.nrows;
+    dims[1] = L.A.nnz;
+    dims[2] = L.P.ncols;
+    dims[3] = L.P.nnz;
+    dims[4] = L.AP.nnz;
+    return AMG_OK;
+}
+
+amg_status amg_export_level(const amg_ctx* cc, int l, int32_t* agg, uint8_t* strong, int32_t* A_ptr, int32_t* A_col,
+                            double* A_val, int32_t* P_ptr, int32_t* P_col, double* P_val, double* m) {
+    amg_ctx* c = const_cast<amg_ctx*>(cc);
+    if (!c || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        hipStream_t s = c->stream;
+        const Level& L = c->lv[(size_t)l];
+        const bool mx = mixed(c);
+        auto d2h = [&](void* dst, const void* src, size_t bytes) {
+            if (dst && src && bytes) HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+        };
+        auto vals = [&](double* dst, const double* v64, const float* v32, int64_t n) {
+            if (!dst || n == 0) return;
+            if (mx && v32) {
+                double* tmp = dnew<double>((size_t)n, s);
+                launch_cast_f2d(n, v32, tmp, s);
+                d2h(dst, tmp, (size_t)n * sizeof(double));
+                HIP_CHECK(hipStreamSynchronize(s));
+                dfree(tmp, s);
+            } else {
+                d2h(dst, v64, (size_t)n * sizeof(double));
+            }
+        };
+        const int32_t n = L.A.nrows;
+        d2h(agg, L.agg, (size_t)n * sizeof(int32_t));
+        d2h(strong, L.strong, (size_t)L.A.nnz);
+        d2h(A_ptr, L.A.ptr, ((size_t)n + 1) * sizeof(int32_t));
+        d2h(A_col, L.A.col, (size_t)L.A.nnz * sizeof(int32_t));
+        vals(A_val, L.A.val, L.A.val32, L.A.nnz);
+        if (L.P.nrows > 0) {
+            d2h(P_ptr, L.P.ptr, ((size_t)n + 1) * sizeof(int32_t));
+            d2h(P_col, L.P.col, (size_t)L.P.nnz * sizeof(int32_t));
+            vals(P_val, L.P.val, L.P.val32, L.P.nnz);
+            vals(m, L.m, L.m32, n);
+        }
+        HIP_CHECK(hipStreamSynchronize(s));
+        return AMG_OK;
+    });
+}
+
+amg_status amg_export_coarse_inverse(const amg_ctx* cc, double* inv) {
+    amg_ctx* c = const_cast<amg_ctx*>(cc);
+    if (!c || !inv) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        HIP_CHECK(hipMemcpyAsync(inv, c->cinv, (size_t)c->nL * c->nL * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIP_CHECK(hipStreamSynchronize(c->stream));
+        return AMG_OK;
+    });
+}
+
+amg_status amg_phase_times(const amg_ctx* cc, double* out) {
+    amg_ctx* c = const_cast<amg_ctx*>(cc);
+    if (!c || !out) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        if (c->phase_pending) {
+            HIP_CHECK(hipEventSynchronize(c->ev[3]));
+            float a = 0, b = 0, d = 0, t = 0;
+            HIP_CHECK(hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+            HIP_CHECK(hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
+            HIP_CHECK(hipEventElapsedTime(&d, c->ev[2], c->ev[3]));
+            HIP_CHECK(hipEventElapsedTime(&t, c->ev[0], c->ev[3]));
+            double ph[8] = {0, 0, 0, a, b, d, t, 0};
+            std::memcpy(c->phase_ms, ph, sizeof(ph));
+            c->phase_pending = false;
+        }
+        std::memcpy(out, c->phase_ms, sizeof(c->phase_ms));
+        return AMG_OK;
+    });
+}
+
+amg_status amg_trace(amg_ctx* c, unsigned mask, int level) {
+    if (!c) return AMG_ERR_ARG;
+    c->trace_mask = mask;
+    c->trace_level = level;
+    return AMG_OK;
+}
+
+amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        for (int k = 0; k < AMG_K_COUNT; ++k) {
+            ms[k] = 0.0;
+            launches[k] = 0;
+        }
+        HIP_CHECK(hipStreamSynchronize(c->stream));
+        for (auto& t : c->traced) {
+            float x = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&x, t.a, t.b));
+            if (t.cls >= 0 && t.cls < AMG_K_COUNT) {
+                ms[t.cls] += x;
+                launches[t.cls] += 1;
+            }
+            c->ev_pool.push_back(t.a);
+            c->ev_pool.push_back(t.b);
+        }
+        c->traced.clear();
+        return AMG_OK;
+    });
+}
+
+amg_status amg_logcoef7_assemble(int32_t nx, int32_t ny, int32_t nz, const double* theta, double* val,
+                                 void* hip_stream) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !theta || !val) return AMG_ERR_ARG;
+    return guard(nullptr, [&] {
+        launch_logcoef7_assemble(nx, ny, nz, theta, val, (hipStream_t)hip_stream);
+        return AMG_OK;
+    });
+}
+
+amg_status amg_logcoef7_adjoint(int32_t nx, int32_t ny, int32_t nz, const double* theta, const double* u,
+                                const double* lambda, double* grad, void* hip_stream) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !theta || !u || !lambda || !grad) return AMG_ERR_ARG;
+    return guard(nullptr, [&] {
+        launch_logcoef7_adjoint(nx, ny, nz, theta, u, lambda, grad, (hipStream_t)hip_stream);
+        return AMG_OK;
+    });
+}
+
+}  // extern "C"

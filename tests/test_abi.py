@@ -1,0 +1,56 @@
+"""The C interface: header compiles as C, the library exports every declared entry point,
+and argument checks that need no device reject bad input."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amg.h")
+LIB = os.path.join(ROOT, "paper_2108_02054_amd", "libamgmi.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(amg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_compiles_as_c(tmp_path):
+    f = tmp_path / "t.c"
+    f.write_text('#include "amg.h"\nint main(void){amg_params p; (void)p; return 0;}\n')
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-c", str(f),
+                    "-o", str(tmp_path / "t.o")], check=True)
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libamgmi.so not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB)
+    names = declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    from paper_2108_02054_amd import EXPORTED
+    assert sorted(EXPORTED) == names
+
+
+def test_host_side_argument_checks():
+    """Calls that fail before touching a device."""
+    from paper_2108_02054_amd import lib
+    from paper_2108_02054_amd.amg import AmgParams
+    L = lib()
+    assert L.amg_params_default(None) == -1
+    p = AmgParams()
+    assert L.amg_params_default(C.byref(p)) == 0
+    assert p.coarse_enough == 128 and p.npre == 1 and p.rtol == 1e-8
+    ctx = C.c_void_p()
+    assert L.amg_setup(C.byref(ctx), 0, 10, None, None, None, None, None) == -1
+    assert L.amg_setup(None, 10, 10, None, None, None, None, None) == -1
+    assert L.amg_rebuild(None, None, 0) == -1
+    assert L.amg_solve(None, None, None, None) == -1
+    assert L.amg_destroy(None) == -1
+    assert L.amg_logcoef7_assemble(0, 1, 1, None, None, None) == -1
+    assert b"invalid" in L.amg_last_error(None) or L.amg_last_error(None) is not None
