@@ -8,6 +8,7 @@
 //   full reuse     (Algorithm 3)  only the Krylov operator's values change
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <type_traits>
@@ -42,6 +43,21 @@ int lane_group(double avg) {
     int g = 2;
     while (g < 64 && g < avg) g <<= 1;
     return g;
+}
+
+// Largest power-of-two rows per block (<= RB_THREADS) whose blocks never hold more than
+// RB_CAP nonzeros; 0 when a single row is longer than that.
+int pick_rows_per_block(const int32_t* p, int32_t n) {
+    for (int rpb = RB_THREADS; rpb >= 1; rpb >>= 1) {
+        int64_t worst = 0;
+        for (int64_t r0 = 0; r0 < n; r0 += rpb) {
+            const int64_t r1 = r0 + rpb < n ? r0 + rpb : n;
+            const int64_t w = (int64_t)p[r1] - p[r0];
+            if (w > worst) worst = w;
+        }
+        if (worst <= RB_CAP) return rpb;
+    }
+    return 0;
 }
 
 }  // namespace amgmi
@@ -131,9 +147,21 @@ struct Trace {
     }
 };
 
-void read_scalars(amg_ctx* c) {
-    HIP_CHECK(hipMemcpyAsync(c->h_scal, c->rs.scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+// One device-to-host copy of the ||r||^2 and ||f||^2 partials and the scalar slots.
+void read_red(amg_ctx* c) {
+    HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.region(P_RR), (2 * RED_BLOCKS + S_COUNT) * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+double host_scal(const amg_ctx* c, int k) { return c->h_red[2 * RED_BLOCKS + k]; }
+
+// Sum of nb partials of the region read by read_red, in block order.
+double host_sum(const amg_ctx* c, int region, int nb) {
+    const double* p = c->h_red + (region - P_RR) * RED_BLOCKS;
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += p[i];
+    return s;
 }
 
 void read_flags(amg_ctx* c) {
@@ -154,13 +182,45 @@ void validate(amg_ctx* c, const Csr& A, int32_t* diag_pos, const char* what) {
         throw Fail{AMG_ERR_NOT_SPD, std::string(what) + ": missing or non-positive diagonal entry"};
 }
 
-void set_groups(Level& L) {
-    const double n = L.A.nrows > 0 ? (double)L.A.nrows : 1.0;
-    L.gA = lane_group((double)L.A.nnz / n);
+// AMGMI_ROW_KERNELS=lanes selects the lane-group kernels everywhere (used by the tests
+// to cover both kernel families); the default picks LDS-staged row blocks where they fit.
+bool lanes_only() {
+    const char* e = std::getenv("AMGMI_ROW_KERNELS");
+    return e != nullptr && std::strcmp(e, "lanes") == 0;
+}
+
+// Launch shapes of a matrix's row kernels (reads its row pointers back once).
+void configure(Csr& A, hipStream_t s) {
+    A.g = lane_group(A.nrows > 0 ? (double)A.nnz / A.nrows : 1.0);
+    std::vector<int32_t> hp((size_t)A.nrows + 1);
+    HIP_CHECK(hipMemcpyAsync(hp.data(), A.ptr, hp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    A.rpb = lanes_only() ? 0 : pick_rows_per_block(hp.data(), A.nrows);
+}
+
+template <typename T>
+std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
+    std::vector<T> h(n);
+    if (n) HIP_CHECK(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return h;
+}
+
+void set_groups(Level& L, hipStream_t s) {
+    configure(L.A, s);
     if (L.P.nrows > 0) {
-        L.gP = lane_group((double)L.P.nnz / n);
-        L.gR = lane_group((double)L.R.nnz / (L.R.nrows > 0 ? (double)L.R.nrows : 1.0));
-        L.gAP = lane_group((double)L.AP.nnz / n);
+        configure(L.P, s);
+        configure(L.R, s);
+        L.gAP = lane_group((double)L.AP.nnz / (L.A.nrows > 0 ? (double)L.A.nrows : 1.0));
+        // staged Galerkin blocks: A_l rows referencing P_l rows; R_l rows referencing AP rows
+        const auto Ap = to_host(L.A.ptr, (size_t)L.A.nrows + 1, s);
+        const auto Ac = to_host(L.A.col, (size_t)L.A.nnz, s);
+        const auto Pp = to_host(L.P.ptr, (size_t)L.P.nrows + 1, s);
+        L.rpbAP = lanes_only() ? 0 : pick_galerkin_rpb(Ap.data(), Ac.data(), L.A.nrows, Pp.data());
+        const auto Rp = to_host(L.R.ptr, (size_t)L.R.nrows + 1, s);
+        const auto Rc = to_host(L.R.col, (size_t)L.R.nnz, s);
+        const auto APp = to_host(L.AP.ptr, (size_t)L.AP.nrows + 1, s);
+        L.rpbRAP = lanes_only() ? 0 : pick_galerkin_rpb(Rp.data(), Rc.data(), L.R.nrows, APp.data());
     }
 }
 
@@ -174,21 +234,33 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     hipStream_t s = c->stream;
     Level& L0 = c->lv[0];
     HIP_CHECK(hipEventRecord(c->ev[0], s));
-    if (val != L0.A.val) d2d(L0.A.val, val, (size_t)L0.A.nnz * sizeof(double), s);
     c->outer_val = L0.A.val;
-    if constexpr (std::is_same<T, float>::value) launch_cast_d2f(L0.A.nnz, L0.A.val, L0.A.val32, s);
     const int nlev = (int)c->lv.size();
+    std::vector<char> smoothed((size_t)nlev, 0);
+    // Ingest: the level-0 staged A P kernel takes the new values straight from the caller's
+    // array and stores the hierarchy's copies (FP64, and FP32 in mixed precision) as it
+    // reads them; otherwise they are copied first.
+    bool ingested = false;
+    if (nlev == 1 || L0.rpbAP == 0) {
+        if (val != L0.A.val) d2d(L0.A.val, val, (size_t)L0.A.nnz * sizeof(double), s);
+        if constexpr (std::is_same<T, float>::value) launch_cast_d2f(L0.A.nnz, L0.A.val, L0.A.val32, s);
+        ingested = true;
+    }
     for (int l = 0; l + 1 < nlev; ++l) {
         const Level& L = c->lv[l];
         {
+            // the staged A P kernel also forms this level's smoother diagonal
             Trace tr(c, AMG_K_GALERKIN_AP, l);
-            launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, s);
+            smoothed[(size_t)l] = launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, L.rpbAP, c->prm.smoother,
+                                                        c->prm.jacobi_omega, L.mv<T>(),
+                                                        (l == 0 && !ingested) ? val : nullptr, s);
         }
         Trace tr(c, AMG_K_GALERKIN_RAP, l);
-        launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, s);
+        launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, L.rpbRAP, s);
     }
     HIP_CHECK(hipEventRecord(c->ev[1], s));
     for (int l = 0; l + 1 < nlev; ++l) {
+        if (smoothed[(size_t)l]) continue;
         const Level& L = c->lv[l];
         Trace tr(c, AMG_K_SMOOTHER, l);
         launch_smoother_diag<T>(L.A, c->prm.smoother, c->prm.jacobi_omega, L.mv<T>(), s);
@@ -197,7 +269,7 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     {
         Trace tr(c, AMG_K_COARSE_INV, nlev - 1);
         launch_densify<T>(c->lv.back().A, c->cinv, s);
-        launch_dense_inverse(c->nL, c->cinv, c->rs.scal, s);
+        launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), s);
     }
     HIP_CHECK(hipEventRecord(c->ev[3], s));
     c->phase_pending = true;
@@ -247,6 +319,16 @@ void alloc_cg(amg_ctx* c) {
     c->pa = halloc<double>(c, n);
     c->pb = halloc<double>(c, n);
     c->q = halloc<double>(c, n);
+}
+
+// Partial-sum scratch sized for the full grids of the level-0 kernels.
+void alloc_reduction(amg_ctx* c) {
+    const Csr& A = c->lv[0].A;
+    int cap = full_grid_rows(A.nrows, A.rpb, A.g);
+    if (cap < RED_BLOCKS) cap = RED_BLOCKS;
+    c->rs.cap = cap;
+    c->rs.part = halloc<double>(c, RedScratch::doubles(cap));
+    HIP_CHECK(hipMemsetAsync(c->rs.part, 0, RedScratch::doubles(cap) * sizeof(double), c->stream));
 }
 
 struct Transfer {
@@ -360,21 +442,23 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
             L.P = P;
             L.R = R;
             L.AP = AP;
-            set_groups(L);
+            set_groups(L, s);
         }
         Level next;
         next.A = Ac;
-        set_groups(next);
+        set_groups(next, s);
         next.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
-        launch_galerkin_ap<double>(A, P, AP, c->lv[(size_t)l].gAP, s);
-        launch_galerkin_rap<double>(R, AP, Ac, next.gRAP, s);
+        launch_galerkin_ap<double>(A, P, AP, c->lv[(size_t)l].gAP, c->lv[(size_t)l].rpbAP, 0, 0.0,
+                                   (double*)nullptr, nullptr, s);
+        launch_galerkin_rap<double>(R, AP, Ac, next.gRAP, c->lv[(size_t)l].rpbRAP, s);
         HIP_CHECK(hipStreamSynchronize(s));
         ph[3] += ms_since(t0);
         dfree(diag_pos, s);
         c->lv.push_back(next);
     }
-    set_groups(c->lv.back());
+    set_groups(c->lv.back(), s);
 
+    alloc_reduction(c);
     auto t0 = Clock::now();
     const int nlev = (int)c->lv.size();
     for (int l = 0; l + 1 < nlev; ++l) {
@@ -390,16 +474,16 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
         throw Fail{AMG_ERR_ARG, "coarsest level has " + std::to_string(c->nL) + " rows; too many for a dense inverse"};
     c->cinv = halloc<double>(c, (size_t)c->nL * c->nL);
     launch_densify<double>(c->lv.back().A, c->cinv, s);
-    launch_dense_inverse(c->nL, c->cinv, c->rs.scal, s);
-    read_scalars(c);
-    if (c->h_scal[S_COARSE] != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
+    launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), s);
+    read_red(c);
+    if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
     ph[5] += ms_since(t0);
 
     if (mixed(c)) {
         alloc_shadow(c);
         partial_rebuild<float>(c, c->lv[0].A.val);
-        read_scalars(c);
-        if (c->h_scal[S_COARSE] != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest FP32 operator is not SPD"};
+        read_red(c);
+        if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest FP32 operator is not SPD"};
         c->phase_pending = false;
         alloc_vectors<float>(c);
     } else {
@@ -457,11 +541,13 @@ void repattern(amg_ctx* c) {
         L.AP = AP;
         release_csr(c, N.A);
         N.A = Ac;
-        set_groups(L);
+        set_groups(L, s);
         N.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
     }
     if (mixed(c)) L0.A.val32 = halloc<float>(c, (size_t)L0.A.nnz);
-    set_groups(c->lv.back());
+    set_groups(c->lv.back(), s);
+    release(c, c->rs.part);
+    alloc_reduction(c);
     // The strength flags were per entry of the old patterns; the aggregates stay (they
     // still define the kept transfer operators).
     for (Level& L : c->lv) {
@@ -472,10 +558,19 @@ void repattern(amg_ctx* c) {
 
 // ------------------------------------------------------------------ V-cycle
 
+// CG dot products fused into the last step of the V-cycle (rho = r.z, beta).
+struct RzEpilogue {
+    int flexible;
+    mutable int nb;  // partials written (set by the kernel that formed r.z)
+};
+
 // Algorithm 2 on level l from a zero initial guess; returns the buffer holding u_l.
-// At level 0 the last post-smoothing sweep writes directly into `out` when given.
+// At level 0 the last post-smoothing sweep writes directly into `out` when given, and
+// with an epilogue (FP64) it also forms the CG partial sums of r.z from f (= the CG
+// residual) and z.  On coarser levels the restriction has already formed the first
+// smoothing sweep u = m f (`u_ready`).
 template <typename T>
-T* vcycle_level(amg_ctx* c, int l, const T* f, T* out) {
+T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, bool u_ready = false) {
     hipStream_t s = c->stream;
     const Level& L = c->lv[(size_t)l];
     const int nlev = (int)c->lv.size();
@@ -483,6 +578,11 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out) {
         T* u = out ? out : (T*)L.u;
         Trace tr(c, AMG_K_COARSE_GEMV, l);
         launch_coarse_gemv<T>(c->nL, c->cinv, f, u, s);
+        if (ep) {
+            Trace tr2(c, AMG_K_CG_RZ, 0);
+            if (ep->flexible) throw Fail{AMG_ERR_ARG, "flexible CG needs at least one post-smoothing sweep"};
+            ep->nb = launch_cg_rz(L.A.nrows, (const double*)f, (const double*)u, c->rs, s);
+        }
         return u;
     }
     const amg_params& p = c->prm;
@@ -495,31 +595,47 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out) {
         HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)L.A.nrows * sizeof(T), s));
         rres = f;
     } else {
-        {
+        if (u_ready) {
             Trace tr(c, AMG_K_SMOOTH0_RES, l);
-            launch_smooth0_residual<T>(L.A, L.gA, m, f, cur, r, s);
+            if (p.npre == 1) launch_residual<T>(L.A, f, cur, r, s);
+        } else {
+            Trace tr(c, AMG_K_SMOOTH0_RES, l);
+            launch_smooth0_residual<T>(L.A, m, f, cur, r, s);
         }
         for (int it = 1; it < p.npre; ++it) {
             Trace tr(c, AMG_K_JACOBI, l);
-            launch_jacobi<T>(L.A, L.gA, m, f, cur, other, s);
+            launch_jacobi<T>(L.A, m, f, cur, other, s);
             std::swap(cur, other);
         }
-        if (p.npre > 1) launch_residual<T>(L.A, L.gA, f, cur, r, s);
+        if (p.npre > 1) launch_residual<T>(L.A, f, cur, r, s);
     }
     const Level& C = c->lv[(size_t)l + 1];
+    // the next level's first sweep from zero is formed by the restriction
+    const bool c_smooths = (l + 2 < nlev) && p.npre > 0;
     {
         Trace tr(c, AMG_K_RESTRICT, l);
-        launch_spmv<T>(L.R, L.gR, rres, (T*)C.f, s);
+        launch_spmv<T>(L.R, rres, (T*)C.f, c_smooths ? C.mv<T>() : nullptr, c_smooths ? (T*)C.u : nullptr, s);
     }
-    const T* uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr);
+    const T* uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, c_smooths);
     {
         Trace tr(c, AMG_K_PROLONG, l);
-        launch_prolong_add<T>(L.P, L.gP, uc, cur, s);
+        launch_prolong_add<T>(L.P, uc, cur, s);
     }
+    bool fused = false;
     for (int it = 0; it < p.npost; ++it) {
-        T* dst = (out && it == p.npost - 1) ? out : other;
+        const bool last = it == p.npost - 1;
+        T* dst = (out && last) ? out : other;
         Trace tr(c, AMG_K_JACOBI, l);
-        launch_jacobi<T>(L.A, L.gA, m, f, cur, dst, s);
+        if constexpr (std::is_same<T, double>::value) {
+            if (last && ep && dst == out) {
+                ep->nb = launch_jacobi_rz(L.A, m, f, cur, dst, ep->flexible, c->rs, s);
+                fused = true;
+            } else {
+                launch_jacobi<T>(L.A, m, f, cur, dst, s);
+            }
+        } else {
+            launch_jacobi<T>(L.A, m, f, cur, dst, s);
+        }
         if (dst == other)
             std::swap(cur, other);
         else
@@ -529,11 +645,17 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out) {
         d2d(out, cur, (size_t)L.A.nrows * sizeof(T), s);
         cur = out;
     }
+    if (ep && !fused) {
+        if (ep->flexible) throw Fail{AMG_ERR_ARG, "flexible CG needs at least one post-smoothing sweep"};
+        Trace tr(c, AMG_K_CG_RZ, 0);
+        ep->nb = launch_cg_rz(L.A.nrows, (const double*)f, (const double*)cur, c->rs, s);
+    }
     return cur;
 }
 
-// z = B r with r, z in FP64; in mixed precision the cycle itself runs in FP32.
-void vcycle_apply(amg_ctx* c, const double* r, double* z) {
+// z = B r with r, z in FP64; in mixed precision the cycle itself runs in FP32.  With an
+// epilogue, the CG scalars rho (= r.z) and beta are formed in the same pass.
+void vcycle_apply(amg_ctx* c, const double* r, double* z, const RzEpilogue* ep = nullptr) {
     Level& L0 = c->lv[0];
     if (mixed(c)) {
         {
@@ -542,30 +664,39 @@ void vcycle_apply(amg_ctx* c, const double* r, double* z) {
         }
         const float* res = vcycle_level<float>(c, 0, (const float*)L0.f, nullptr);
         Trace tr(c, AMG_K_CAST, 0);
-        launch_cast_f2d(L0.A.nrows, res, z, c->stream);
+        if (ep)
+            ep->nb = launch_cast_rz(L0.A.nrows, res, r, z, ep->flexible, c->rs, c->stream);
+        else
+            launch_cast_f2d(L0.A.nrows, res, z, c->stream);
     } else {
-        vcycle_level<double>(c, 0, r, z);
+        vcycle_level<double>(c, 0, r, z, ep);
     }
 }
 
 // ------------------------------------------------------------------ PCG
 
 // CG preconditioned by one V-cycle; stops on the true relative residual.  Scalars stay on
-// the device; each iteration reads ||r||^2 and the breakdown flag back (one 64-byte copy).
+// the device (each kernel adds the partials it needs); each iteration reads the ||r||^2
+// partials and the breakdown flag back with one copy.
 amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
     hipStream_t s = c->stream;
     const Level& L0 = c->lv[0];
     const int n = L0.A.nrows;
     const amg_params& p = c->prm;
     amg_solve_info inf{0, 0, 0.0};
+    auto true_residual = [&]() {
+        int nb;
+        {
+            Trace tr(c, AMG_K_CG_INIT, 0);
+            nb = launch_cg_init(L0.A, c->outer_val, f, c->x, c->r, c->rs, s);
+        }
+        read_red(c);
+        return nb;
+    };
     launch_copy(n, u, c->x, s);
-    {
-        Trace tr(c, AMG_K_CG_INIT, 0);
-        launch_cg_init(L0.A, c->outer_val, L0.gA, f, c->x, c->r, c->rs, s);
-    }
-    read_scalars(c);
-    if (c->h_scal[S_COARSE] != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
-    const double ff = c->h_scal[S_FF];
+    int nb = true_residual();
+    if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
+    const double ff = host_sum(c, P_FF, nb);
     if (ff == 0.0) {
         HIP_CHECK(hipMemsetAsync(u, 0, (size_t)n * sizeof(double), s));
         HIP_CHECK(hipStreamSynchronize(s));
@@ -574,63 +705,71 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         return AMG_OK;
     }
     const double nf = std::sqrt(ff);
-    double res = std::sqrt(c->h_scal[S_RR]) / nf;
+    double res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
     if (res <= p.rtol) {
         inf.converged = 1;
         inf.rel_res_true = res;
         if (info) *info = inf;
         return AMG_OK;
     }
-    vcycle_apply(c, c->r, c->z);
-    {
-        Trace tr(c, AMG_K_CG_RZ, 0);
-        launch_cg_rz(n, c->r, c->z, c->zold, p.flexible_cg, 1, c->rs, s);
-    }
+    RzEpilogue ep{p.flexible_cg, 0};
+    auto precondition = [&](int first) {
+        vcycle_apply(c, c->r, c->z, &ep);
+        launch_fin_rz(ep.nb, p.flexible_cg, first, c->rs, s);
+    };
+    precondition(1);
     double* pold = c->pa;
     double* pnew = c->pb;
     int it = 0;
     bool converged = false;
     while (it < p.maxiter) {
         ++it;
+        int nb_pq;
         {
             Trace tr(c, AMG_K_CG_PQ, 0);
-            launch_cg_pq(L0.A, c->outer_val, L0.gA, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+            nb_pq = launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
         }
+        launch_fin_pq(nb_pq, c->rs, s);
         {
             Trace tr(c, AMG_K_CG_UPDATE, 0);
-            launch_cg_update(n, pnew, c->q, c->x, c->r, c->rs, s);
+            nb = launch_cg_update(n, pnew, c->q, c->x, c->r, c->rs, s);
         }
-        read_scalars(c);
-        if (c->h_scal[S_FLAG] != 0.0) {
+        // Read ||r||^2 back, but queue the next preconditioner application first so the
+        // device keeps working while the host decides; it is discarded on convergence.
+        HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.region(P_RR), (2 * RED_BLOCKS + S_COUNT) * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipEventRecord(c->ev_read, s));
+        // (not with flexible CG: its r.z_old term reads the z a speculative sweep overwrites)
+        const bool speculate = it < p.maxiter && !p.flexible_cg;
+        if (speculate) precondition(0);
+        HIP_CHECK(hipEventSynchronize(c->ev_read));
+        if (host_scal(c, S_FLAG) != 0.0) {
             c->err = "CG breakdown (p.Ap <= 0 or a non-finite scalar)";
+            HIP_CHECK(hipStreamSynchronize(s));
             if (info) {
                 inf.iters = it;
                 *info = inf;
             }
             return AMG_ERR_BREAKDOWN;
         }
-        res = std::sqrt(c->h_scal[S_RR]) / nf;
+        res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
         if (res <= p.rtol) {
-            launch_cg_init(L0.A, c->outer_val, L0.gA, f, c->x, c->r, c->rs, s);
-            read_scalars(c);
-            res = std::sqrt(c->h_scal[S_RR]) / nf;
+            nb = true_residual();
+            res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
             if (res <= p.rtol) {
                 converged = true;
                 break;
             }
-        }
-        if (p.flexible_cg) launch_copy(n, c->z, c->zold, s);
-        vcycle_apply(c, c->r, c->z);
-        {
-            Trace tr(c, AMG_K_CG_RZ, 0);
-            launch_cg_rz(n, c->r, c->z, c->zold, p.flexible_cg, 0, c->rs, s);
+            precondition(0);  // continue from the true residual
+        } else if (!speculate) {
+            if (it >= p.maxiter) break;
+            precondition(0);
         }
         std::swap(pold, pnew);
     }
     if (!converged) {
-        launch_cg_init(L0.A, c->outer_val, L0.gA, f, c->x, c->r, c->rs, s);
-        read_scalars(c);
-        res = std::sqrt(c->h_scal[S_RR]) / nf;
+        nb = true_residual();
+        res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
     }
     launch_copy(n, c->x, u, s);
     HIP_CHECK(hipStreamSynchronize(s));
@@ -661,11 +800,12 @@ void destroy_ctx(amg_ctx* c) {
     dfree(c->pend_ptr, s);
     dfree(c->pend_col, s);
     (void)hipStreamSynchronize(s);
-    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     for (hipEvent_t& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->ev_read) (void)hipEventDestroy(c->ev_read);
     for (auto& t : c->traced) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -678,15 +818,11 @@ amg_ctx* create_ctx(const amg_params& p, void* stream) {
     c->prm = p;
     c->stream = (hipStream_t)stream;
     try {
-        c->rs.part = oalloc<double>(c, (size_t)RED_MAXK * RED_BLOCKS);
-        c->rs.ticket = oalloc<unsigned>(c, 1);
-        c->rs.scal = oalloc<double>(c, S_COUNT);
         c->d_flags = oalloc<int>(c, F_COUNT);
-        HIP_CHECK(hipMemsetAsync(c->rs.ticket, 0, sizeof(unsigned), c->stream));
-        HIP_CHECK(hipMemsetAsync(c->rs.scal, 0, S_COUNT * sizeof(double), c->stream));
-        HIP_CHECK(hipHostMalloc((void**)&c->h_scal, S_COUNT * sizeof(double), hipHostMallocDefault));
+        HIP_CHECK(hipHostMalloc((void**)&c->h_red, (2 * RED_BLOCKS + S_COUNT) * sizeof(double), hipHostMallocDefault));
         HIP_CHECK(hipHostMalloc((void**)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault));
         for (hipEvent_t& e : c->ev) HIP_CHECK(hipEventCreate(&e));
+        HIP_CHECK(hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
     } catch (...) {
         destroy_ctx(c);
         throw;

@@ -49,6 +49,10 @@ struct Csr {
     int32_t* col = nullptr;
     double* val = nullptr;
     float* val32 = nullptr;
+    // Launch shape of the row kernels: rows per LDS-staged block (0: rows too long to
+    // stage, use lane groups) and the lane-group width.
+    int rpb = 0;
+    int g = 8;
     template <typename T>
     T* v() const;
 };
@@ -70,8 +74,10 @@ struct Level {
     void* f = nullptr;
     void* r = nullptr;
     void* t = nullptr;
-    // lane-group widths of the row kernels
-    int gA = 8, gP = 4, gR = 32, gAP = 8, gRAP = 32;
+    // Galerkin kernels: lane-group widths (A_l P_l rows; A_{l+1} rows) and rows per
+    // LDS-staged block (A_l rows for A_l P_l; R_l rows for R_l (A_l P_l); 0: lane groups)
+    int gAP = 8, gRAP = 32;
+    int rpbAP = 0, rpbRAP = 0;
     template <typename T>
     T* mv() const;
 };
@@ -80,67 +86,86 @@ inline double* Level::mv<double>() const { return m; }
 template <>
 inline float* Level::mv<float>() const { return m32; }
 
-// Device scalar slots used by the CG kernels.
+// Device scalar slots.
 enum Scal {
-    S_FF = 0,     // ||f||^2
-    S_RR = 1,     // ||r||^2
-    S_RHO = 2,    // r.z
-    S_PQ = 3,     // p.Ap
+    S_RHO = 0,    // r.z of the current iteration
+    S_PQ = 1,     // p.Ap
+    S_FLAG = 2,   // 1: CG breakdown
+    S_COARSE = 3, // coarse factorisation status: 0 ok, 1 not SPD
     S_BETA = 4,
-    S_FLAG = 5,   // 1: breakdown
-    S_RZOLD = 6,  // r.z_old (flexible CG)
-    S_COARSE = 7, // coarse factorisation status: 0 ok, 1 not SPD
+    S_ALPHA = 5,
+    S_RHO_USED = 6,  // the rho of the current iteration's alpha (beta's denominator)
     S_COUNT = 8
 };
 
-// Reductions run on a fixed grid so that every partial sum, and therefore the result,
-// is independent of scheduling: the last block to finish adds the partials in order.
-constexpr int RED_BLOCKS = 2048;
-constexpr int RED_THREADS = 256;
-constexpr int RED_MAXK = 2;
+// Reductions store one partial per block into a region; the consumer adds them in block
+// order.  Regions P_RZ, P_RZOLD, P_PQ hold up to `cap` partials (full grids of the level-0
+// kernels); P_RR, P_FF hold at most RED_BLOCKS (bounded grids) and sit right before the
+// scalars so the host reads them, and the scalars, with one copy.
+enum PartRegion { P_RZ = 0, P_RZOLD = 1, P_PQ = 2, P_RR = 3, P_FF = 4 };
+constexpr int RED_BLOCKS = 1024;
 
-int lane_group(double avg_per_row);  // power of two in [2, 64]
-
-// ------------------------------------------------------------------ solve kernels
 struct RedScratch {
-    double* part;      // RED_MAXK * RED_BLOCKS
-    unsigned* ticket;  // one counter
-    double* scal;      // S_COUNT device scalars
+    double* part = nullptr;  // 3 * cap + 2 * RED_BLOCKS + S_COUNT doubles
+    int cap = 0;
+    __host__ __device__ double* region(int k) const {
+        return k <= P_PQ ? part + (size_t)k * cap : part + 3 * (size_t)cap + (size_t)(k - P_RR) * RED_BLOCKS;
+    }
+    __host__ __device__ double* scal() const { return part + 3 * (size_t)cap + 2 * (size_t)RED_BLOCKS; }
+    static size_t doubles(int cap) { return 3 * (size_t)cap + 2 * (size_t)RED_BLOCKS + S_COUNT; }
 };
 
+// Row-block kernels: RB_THREADS threads, at most RB_CAP nonzeros staged in LDS per block.
+constexpr int RB_THREADS = 256;
+constexpr int RB_CAP = 2048;
+
+int lane_group(double avg_per_row);  // power of two in [2, 64]
+int pick_rows_per_block(const int32_t* host_ptr, int32_t nrows);  // 0: no row blocking
+int red_grid_rows(int nrows, int rpb, int g);
+int full_grid_rows(int nrows, int rpb, int g);
+int red_grid_elems(int64_t n);
+
+// ------------------------------------------------------------------ solve kernels
 template <typename T>
-void launch_spmv(const Csr& A, int g, const T* x, T* y, hipStream_t s);
+void launch_spmv(const Csr& A, const T* x, T* y, const T* m2, T* y2, hipStream_t s);
 template <typename T>
-void launch_residual(const Csr& A, int g, const T* f, const T* u, T* r, hipStream_t s);
+void launch_residual(const Csr& A, const T* f, const T* u, T* r, hipStream_t s);
 template <typename T>
-void launch_jacobi(const Csr& A, int g, const T* m, const T* f, const T* u, T* uout, hipStream_t s);
+void launch_jacobi(const Csr& A, const T* m, const T* f, const T* u, T* uout, hipStream_t s);
 template <typename T>
-void launch_smooth0_residual(const Csr& A, int g, const T* m, const T* f, T* u, T* r, hipStream_t s);
+void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, hipStream_t s);
 template <typename T>
-void launch_prolong_add(const Csr& P, int g, const T* uc, T* u, hipStream_t s);
+void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s);
 template <typename T>
 void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s);
 void launch_cast_d2f(int64_t n, const double* a, float* b, hipStream_t s);
 void launch_cast_f2d(int64_t n, const float* a, double* b, hipStream_t s);
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
 
-// CG pieces (FP64).  See amg_api.hip for the iteration they form.
-void launch_cg_init(const Csr& A, const double* outer_val, int g, const double* f, const double* x,
-                    double* r, const RedScratch& rs, hipStream_t s);
-void launch_cg_rz(int n, const double* r, const double* z, const double* zold, int flexible, int first,
-                  const RedScratch& rs, hipStream_t s);
-void launch_cg_pq(const Csr& A, const double* outer_val, int g, const double* z, const double* pold,
-                  double* pnew, double* q, int first, const RedScratch& rs, hipStream_t s);
-void launch_cg_update(int n, const double* p, const double* q, double* x, double* r, const RedScratch& rs,
-                      hipStream_t s);
+// CG pieces (FP64); each reducing launcher returns the number of partials it wrote.
+int launch_cg_init(const Csr& A, const double* val, const double* f, const double* x, double* r,
+                   const RedScratch& rs, hipStream_t s);
+int launch_jacobi_rz(const Csr& A, const double* m, const double* r, const double* u, double* z, int flexible,
+                     const RedScratch& rs, hipStream_t s);
+int launch_cast_rz(int n, const float* z32, const double* r, double* z, int flexible, const RedScratch& rs,
+                   hipStream_t s);
+int launch_cg_rz(int n, const double* r, const double* z, const RedScratch& rs, hipStream_t s);
+void launch_fin_rz(int nb, int flexible, int first, const RedScratch& rs, hipStream_t s);
+void launch_fin_pq(int nb, const RedScratch& rs, hipStream_t s);
+int launch_cg_pq(const Csr& A, const double* val, const double* z, const double* pold, double* pnew, double* q,
+                 int first, const RedScratch& rs, hipStream_t s);
+int launch_cg_update(int n, const double* p, const double* q, double* x, double* r, const RedScratch& rs,
+                     hipStream_t s);
 
 // ------------------------------------------------------------------ Galerkin / smoother
 template <typename T>
 void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_t s);
 template <typename T>
-void launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, hipStream_t s);
+bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, int rpb, int kind, double omega, T* m,
+                        const double* ain, hipStream_t s);
 template <typename T>
-void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, hipStream_t s);
+void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, int rpb, hipStream_t s);
+int pick_galerkin_rpb(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr);
 
 // ------------------------------------------------------------------ setup
 // flags: device int[8], see SetupFlag.
@@ -198,7 +223,7 @@ struct amg_ctx {
     double *x = nullptr, *r = nullptr, *z = nullptr, *zold = nullptr, *pa = nullptr, *pb = nullptr,
            *q = nullptr;
     amgmi::RedScratch rs{};
-    double* h_scal = nullptr;     // pinned host copy of the scalar slots
+    double* h_red = nullptr;      // pinned host copy of the P_RR, P_FF partials and the scalars
     int* d_flags = nullptr;       // setup flags
     int* h_flags = nullptr;       // pinned
     // pending pattern for amg_rebuild(..., pattern_changed)
@@ -214,6 +239,7 @@ struct amg_ctx {
     double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool phase_pending = false;   // partial rebuild: times still to be read from ev[]
     hipEvent_t ev[4]{};
+    hipEvent_t ev_read = nullptr;  // completion of the per-iteration scalar read
     // per-kernel tracing (amg_trace)
     unsigned trace_mask = 0;
     int trace_level = -1;

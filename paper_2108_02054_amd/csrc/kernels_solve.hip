@@ -1,15 +1,23 @@
 // kernels_solve.hip -- V-cycle (Algorithm 2) and preconditioned-CG kernels for gfx950.
 //
-// Row kernels give each CSR row a group of G lanes (G a power of two dividing the
-// 64-wide wavefront, picked per matrix from its mean row length): the G lanes read the
-// row's entries contiguously, gather x, and reduce with a butterfly of cross-lane
-// shuffles.  Every kernel is bandwidth bound (about 0.17 flop per byte), so the design
-// goals are coalesced CSR streams, few passes over the vectors, and XCD-local gathers.
+// Every kernel here is bandwidth bound (about 0.17 flop per byte).  The main form is the
+// row-block kernel: a workgroup owns `rpb` consecutive rows whose nonzeros (at most
+// RB_CAP, chosen per matrix at setup) are streamed with fully coalesced loads, multiplied
+// by the gathered vector entries and staged in LDS; one thread per row then adds its
+// row's products in column order and applies the kernel's epilogue.  Rows too long to
+// stage fall back to lane-group kernels (G lanes per row, cross-lane butterfly sums).
+//
+// Reductions never use fences or atomics (an agent-scope fence writes back and
+// invalidates the per-XCD L2 caches): each block stores one partial sum into a fixed slot
+// and the consumer -- the next kernel, or the host -- adds the slots in block order.  The
+// number of blocks is a fixed function of the size, so every result is bitwise
+// reproducible.
 #include "amg_internal.h"
 
 namespace amgmi {
 
 constexpr int TPB = 256;
+static_assert(RB_THREADS == TPB, "row-block kernels use one thread per staged row");
 
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T s) {
@@ -38,72 +46,218 @@ __device__ __forceinline__ T wave_sum(T s) {
         }                                                                   \
     } while (0)
 
-static inline unsigned row_blocks(int64_t rows, int G) {
-    int64_t b = (rows * G + TPB - 1) / TPB;
+static inline unsigned grid_for(int64_t items, int per_block) {
+    int64_t b = (items + per_block - 1) / per_block;
     return (unsigned)(b > 0 ? b : 1);
 }
 
-// Row handled by this lane group (XCD-local block order), and the lane within it.
+// ------------------------------------------------------------------ row-block staging
+
+// Loads ptr[row0 .. row1] into sptr, then val[k] * xget(col[k]) for the block's nonzeros
+// into sp.  Every thread of the block must call it.
+template <typename T, class X>
+__device__ __forceinline__ void rb_load(int row0, int row1, const int* __restrict__ ptr, const int* __restrict__ col,
+                                        const T* __restrict__ val, X xget, int* sptr, T* sp) {
+    const int nr = row1 - row0;
+    for (int i = threadIdx.x; i <= nr; i += RB_THREADS) sptr[i] = ptr[row0 + i];
+    __syncthreads();
+    const int k0 = sptr[0], k1 = min(sptr[nr], k0 + RB_CAP);  // blocks are sized within RB_CAP
+#pragma unroll
+    for (int it = 0; it < RB_CAP / RB_THREADS; ++it) {
+        const int k = k0 + it * RB_THREADS + (int)threadIdx.x;
+        if (k < k1) sp[k - k0] = val[k] * xget(col[k]);
+    }
+    __syncthreads();
+}
+
+// Threads per staged row: a block of rpb rows gives each row RB_THREADS / rpb threads
+// (at most a wavefront), which add strided subsets of the row and combine them with a
+// fixed butterfly; with one thread per row the sum is in plain column order.
+__device__ __forceinline__ int rb_tpr(int rpb) {
+    const int t = RB_THREADS / rpb;
+    return t > 64 ? 64 : t;
+}
+
+// Sum of row r (local) of the staged block; `lane` is the thread's index within the row.
+template <typename T>
+__device__ __forceinline__ T rb_rowsum(const int* sptr, const T* sp, int r, int lane, int tpr) {
+    const int k0 = sptr[0], e = sptr[r + 1] - k0;
+    T s = 0;
+    for (int q = sptr[r] - k0 + lane; q < e; q += tpr) s += sp[q];
+    for (int o = tpr >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, tpr);
+    return s;
+}
+
+// Contiguous range of row blocks handled by this (XCD-remapped) block of a bounded grid.
+__device__ __forceinline__ void rb_range(int nrb, int& rb0, int& rb1) {
+    const int per = (nrb + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int lb = xcd_block();
+    rb0 = lb * per;
+    rb1 = min(rb0 + per, nrb);
+}
+
+// Deterministic block sum of K values; thread 0 stores them at dst[q][slot].
+template <int K>
+__device__ __forceinline__ void block_store(double (&v)[K], double* const (&dst)[K], int slot) {
+    __shared__ double sm[K][RB_THREADS / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double x = wave_sum(v[q]);
+        if (lane == 0) sm[q][w] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double s = 0.0;
+            for (int i = 0; i < RB_THREADS / 64; ++i) s += sm[q][i];
+            dst[q][slot] = s;
+        }
+    }
+}
+
+// Sum of p[0..nb) by one block of FIN_THREADS threads in a fixed order (four independent
+// strided accumulators per thread, then a fixed tree); returned to every thread.
+constexpr int FIN_THREADS = 1024;
+__device__ __forceinline__ double block_sum(const double* __restrict__ p, int nb) {
+    __shared__ double sm[FIN_THREADS / 64];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 3 * FIN_THREADS < nb; i += 4 * FIN_THREADS) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] += p[i + u * FIN_THREADS];
+    }
+    for (int u = 0; i < nb; i += FIN_THREADS, ++u) a[u & 3] += p[i];
+    double s = (a[0] + a[1]) + (a[2] + a[3]);
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < FIN_THREADS / 64; ++k) t += sm[k];
+    __syncthreads();
+    return t;
+}
+
+// ------------------------------------------------------------------ V-cycle kernels
+
+// y = A x; with m2 given also y2 = m2 * y (the restriction forms the coarse level's first
+// smoothing sweep u = m f from zero at the same time).
+template <typename T>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_spmv(int n, int rpb, const int* __restrict__ ptr,
+                                                        const int* __restrict__ col, const T* __restrict__ val,
+                                                        const T* __restrict__ x, T* __restrict__ y,
+                                                        const T* __restrict__ m2, T* __restrict__ y2) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ T sp[RB_CAP];
+    const int row0 = xcd_block() * rpb;
+    if (row0 >= n) return;
+    const int row1 = min(row0 + rpb, n);
+    rb_load(row0, row1, ptr, col, val, [&](int j) { return x[j]; }, sptr, sp);
+    const int tpr = rb_tpr(rpb), r = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    if (r < row1 - row0) {
+        const T v = rb_rowsum(sptr, sp, r, lane, tpr);
+        if (lane == 0) {
+            y[row0 + r] = v;
+            if (m2 != nullptr) y2[row0 + r] = m2[row0 + r] * v;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_residual(int n, int rpb, const int* __restrict__ ptr,
+                                                            const int* __restrict__ col, const T* __restrict__ val,
+                                                            const T* __restrict__ f, const T* __restrict__ u,
+                                                            T* __restrict__ r) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ T sp[RB_CAP];
+    const int row0 = xcd_block() * rpb;
+    if (row0 >= n) return;
+    const int row1 = min(row0 + rpb, n);
+    rb_load(row0, row1, ptr, col, val, [&](int j) { return u[j]; }, sptr, sp);
+    const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    if (t < row1 - row0) {
+        const T v = rb_rowsum(sptr, sp, t, lane, tpr);
+        if (lane == 0) r[row0 + t] = f[row0 + t] - v;
+    }
+}
+
+// One damped-Jacobi / SPAI0 sweep: uout = u + m (f - A u)
+template <typename T>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_jacobi(int n, int rpb, const int* __restrict__ ptr,
+                                                          const int* __restrict__ col, const T* __restrict__ val,
+                                                          const T* __restrict__ m, const T* __restrict__ f,
+                                                          const T* __restrict__ u, T* __restrict__ uout) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ T sp[RB_CAP];
+    const int row0 = xcd_block() * rpb;
+    if (row0 >= n) return;
+    const int row1 = min(row0 + rpb, n);
+    rb_load(row0, row1, ptr, col, val, [&](int j) { return u[j]; }, sptr, sp);
+    const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    if (t < row1 - row0) {
+        const T v = rb_rowsum(sptr, sp, t, lane, tpr);
+        const int i = row0 + t;
+        if (lane == 0) uout[i] = u[i] + m[i] * (f[i] - v);
+    }
+}
+
+// First pre-smoothing sweep from u = 0 (u = m f) fused with the residual r = f - A u; the
+// neighbours' u_j = m_j f_j are formed from m and f.
+template <typename T>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_smooth0_residual(int n, int rpb, const int* __restrict__ ptr,
+                                                                    const int* __restrict__ col,
+                                                                    const T* __restrict__ val, const T* __restrict__ m,
+                                                                    const T* __restrict__ f, T* __restrict__ u,
+                                                                    T* __restrict__ r) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ T sp[RB_CAP];
+    const int row0 = xcd_block() * rpb;
+    if (row0 >= n) return;
+    const int row1 = min(row0 + rpb, n);
+    rb_load(row0, row1, ptr, col, val, [&](int j) { return m[j] * f[j]; }, sptr, sp);
+    const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    if (t < row1 - row0) {
+        const T v = rb_rowsum(sptr, sp, t, lane, tpr);
+        const int i = row0 + t;
+        if (lane == 0) {
+            const T fi = f[i];
+            u[i] = m[i] * fi;
+            r[i] = fi - v;
+        }
+    }
+}
+
+// u += P uc (coarse-grid correction)
+template <typename T>
+__global__ __launch_bounds__(RB_THREADS) void k_rb_prolong_add(int n, int rpb, const int* __restrict__ ptr,
+                                                               const int* __restrict__ col, const T* __restrict__ val,
+                                                               const T* __restrict__ uc, T* __restrict__ u) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ T sp[RB_CAP];
+    const int row0 = xcd_block() * rpb;
+    if (row0 >= n) return;
+    const int row1 = min(row0 + rpb, n);
+    rb_load(row0, row1, ptr, col, val, [&](int j) { return uc[j]; }, sptr, sp);
+    const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    if (t < row1 - row0) {
+        const T v = rb_rowsum(sptr, sp, t, lane, tpr);
+        if (lane == 0) u[row0 + t] += v;
+    }
+}
+
+// Lane-group fallbacks (rows longer than a staged block).
 template <int G>
 __device__ __forceinline__ int group_row(int& lane) {
     lane = threadIdx.x & (G - 1);
     return (xcd_block() * TPB + (int)threadIdx.x) / G;
 }
 
-// ------------------------------------------------------------------ SpMV family
-
-template <int G, typename T>
-__global__ __launch_bounds__(TPB) void k_spmv(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                                              const T* __restrict__ val, const T* __restrict__ x,
-                                              T* __restrict__ y) {
-    int lane;
-    const int row = group_row<G>(lane);
-    if (row >= n) return;
-    const int b = ptr[row], e = ptr[row + 1];
-    T s = 0;
-    for (int k = b + lane; k < e; k += G) s += val[k] * x[col[k]];
-    s = group_sum<G>(s);
-    if (lane == 0) y[row] = s;
-}
-
-// r = f - A u
-template <int G, typename T>
-__global__ __launch_bounds__(TPB) void k_residual(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                  const T* __restrict__ val, const T* __restrict__ f,
-                                                  const T* __restrict__ u, T* __restrict__ r) {
-    int lane;
-    const int row = group_row<G>(lane);
-    if (row >= n) return;
-    const int b = ptr[row], e = ptr[row + 1];
-    T s = 0;
-    for (int k = b + lane; k < e; k += G) s += val[k] * u[col[k]];
-    s = group_sum<G>(s);
-    if (lane == 0) r[row] = f[row] - s;
-}
-
-// One damped-Jacobi / SPAI0 sweep: uout = u + m (f - A u)
-template <int G, typename T>
-__global__ __launch_bounds__(TPB) void k_jacobi(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                const T* __restrict__ val, const T* __restrict__ m,
-                                                const T* __restrict__ f, const T* __restrict__ u,
-                                                T* __restrict__ uout) {
-    int lane;
-    const int row = group_row<G>(lane);
-    if (row >= n) return;
-    const int b = ptr[row], e = ptr[row + 1];
-    T s = 0;
-    for (int k = b + lane; k < e; k += G) s += val[k] * u[col[k]];
-    s = group_sum<G>(s);
-    if (lane == 0) uout[row] = u[row] + m[row] * (f[row] - s);
-}
-
-// First pre-smoothing sweep from u = 0 (u = m f) fused with the residual r = f - A u:
-// the neighbours' u_j = m_j f_j are recomputed from m and f instead of re-read.
-template <int G, typename T>
-__global__ __launch_bounds__(TPB) void k_smooth0_residual(int n, const int* __restrict__ ptr,
-                                                          const int* __restrict__ col, const T* __restrict__ val,
-                                                          const T* __restrict__ m, const T* __restrict__ f,
-                                                          T* __restrict__ u, T* __restrict__ r) {
+template <int G, typename T, int KIND>
+__global__ __launch_bounds__(TPB) void k_lg(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                            const T* __restrict__ val, const T* __restrict__ m,
+                                            const T* __restrict__ f, const T* __restrict__ x, T* __restrict__ y,
+                                            T* __restrict__ y2) {
     int lane;
     const int row = group_row<G>(lane);
     if (row >= n) return;
@@ -111,29 +265,21 @@ __global__ __launch_bounds__(TPB) void k_smooth0_residual(int n, const int* __re
     T s = 0;
     for (int k = b + lane; k < e; k += G) {
         const int j = col[k];
-        s += val[k] * (m[j] * f[j]);
+        s += val[k] * (KIND == 3 ? m[j] * f[j] : x[j]);
     }
     s = group_sum<G>(s);
-    if (lane == 0) {
-        const T fi = f[row];
-        u[row] = m[row] * fi;
-        r[row] = fi - s;
+    if (lane != 0) return;
+    if constexpr (KIND == 0) {                                            // y = A x (, y2 = m y)
+        y[row] = s;
+        if (m != nullptr) y2[row] = m[row] * s;
     }
-}
-
-// u += P uc (coarse-grid correction)
-template <int G, typename T>
-__global__ __launch_bounds__(TPB) void k_prolong_add(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                     const T* __restrict__ val, const T* __restrict__ uc,
-                                                     T* __restrict__ u) {
-    int lane;
-    const int row = group_row<G>(lane);
-    if (row >= n) return;
-    const int b = ptr[row], e = ptr[row + 1];
-    T s = 0;
-    for (int k = b + lane; k < e; k += G) s += val[k] * uc[col[k]];
-    s = group_sum<G>(s);
-    if (lane == 0) u[row] += s;
+    if constexpr (KIND == 1) y[row] = f[row] - s;                         // r = f - A x
+    if constexpr (KIND == 2) y[row] = x[row] + m[row] * (f[row] - s);     // Jacobi
+    if constexpr (KIND == 3) {                                            // first sweep + residual
+        y[row] = m[row] * f[row];
+        y2[row] = f[row] - s;
+    }
+    if constexpr (KIND == 4) y[row] += s;                                 // u += P uc
 }
 
 // u = A^{-1} f on the coarsest level: one wavefront per row of the dense FP64 inverse.
@@ -171,34 +317,45 @@ static inline unsigned ew_blocks(int64_t n) {
     return (unsigned)(b > 0 ? b : 1);
 }
 
+#define AMG_RB_OR_LG(A, RBCALL, KIND, ...)                                                              \
+    do {                                                                                                \
+        if ((A).rpb > 0) {                                                                              \
+            RBCALL;                                                                                     \
+        } else {                                                                                        \
+            AMG_WITH_G((A).g, (k_lg<G, T, KIND><<<grid_for((int64_t)(A).nrows * G, TPB), TPB, 0, s>>>(__VA_ARGS__))); \
+        }                                                                                               \
+        HIP_LAUNCH_CHECK();                                                                             \
+    } while (0)
+
 template <typename T>
-void launch_spmv(const Csr& A, int g, const T* x, T* y, hipStream_t s) {
-    AMG_WITH_G(g, k_spmv<G, T><<<row_blocks(A.nrows, G), TPB, 0, s>>>(A.nrows, A.ptr, A.col, A.v<T>(), x, y));
-    HIP_LAUNCH_CHECK();
+void launch_spmv(const Csr& A, const T* x, T* y, const T* m2, T* y2, hipStream_t s) {
+    AMG_RB_OR_LG(A, (k_rb_spmv<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), x, y, m2, y2)),
+                 0, A.nrows, A.ptr, A.col, A.v<T>(), m2, nullptr, x, y, y2);
 }
 template <typename T>
-void launch_residual(const Csr& A, int g, const T* f, const T* u, T* r, hipStream_t s) {
-    AMG_WITH_G(g, k_residual<G, T><<<row_blocks(A.nrows, G), TPB, 0, s>>>(A.nrows, A.ptr, A.col, A.v<T>(), f, u, r));
-    HIP_LAUNCH_CHECK();
+void launch_residual(const Csr& A, const T* f, const T* u, T* r, hipStream_t s) {
+    AMG_RB_OR_LG(A, (k_rb_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), f, u, r)),
+                 1, A.nrows, A.ptr, A.col, A.v<T>(), nullptr, f, u, r, nullptr);
 }
 template <typename T>
-void launch_jacobi(const Csr& A, int g, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
-    AMG_WITH_G(g, k_jacobi<G, T><<<row_blocks(A.nrows, G), TPB, 0, s>>>(A.nrows, A.ptr, A.col, A.v<T>(), m, f, u, uout));
-    HIP_LAUNCH_CHECK();
+void launch_jacobi(const Csr& A, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
+    AMG_RB_OR_LG(A, (k_rb_jacobi<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), m, f, u, uout)),
+                 2, A.nrows, A.ptr, A.col, A.v<T>(), m, f, u, uout, nullptr);
 }
 template <typename T>
-void launch_smooth0_residual(const Csr& A, int g, const T* m, const T* f, T* u, T* r, hipStream_t s) {
-    AMG_WITH_G(g, k_smooth0_residual<G, T><<<row_blocks(A.nrows, G), TPB, 0, s>>>(A.nrows, A.ptr, A.col, A.v<T>(), m, f, u, r));
-    HIP_LAUNCH_CHECK();
+void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, hipStream_t s) {
+    AMG_RB_OR_LG(A, (k_rb_smooth0_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), m, f, u, r)),
+                 3, A.nrows, A.ptr, A.col, A.v<T>(), m, f, nullptr, u, r);
 }
 template <typename T>
-void launch_prolong_add(const Csr& P, int g, const T* uc, T* u, hipStream_t s) {
-    AMG_WITH_G(g, k_prolong_add<G, T><<<row_blocks(P.nrows, G), TPB, 0, s>>>(P.nrows, P.ptr, P.col, P.v<T>(), uc, u));
-    HIP_LAUNCH_CHECK();
+void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s) {
+    const Csr& A = P;
+    AMG_RB_OR_LG(A, (k_rb_prolong_add<T><<<grid_for(P.nrows, P.rpb), RB_THREADS, 0, s>>>(P.nrows, P.rpb, P.ptr, P.col, P.v<T>(), uc, u)),
+                 4, P.nrows, P.ptr, P.col, P.v<T>(), nullptr, nullptr, uc, u, nullptr);
 }
 template <typename T>
 void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s) {
-    k_coarse_gemv<T><<<row_blocks(n, 64), TPB, 0, s>>>(n, inv, f, u);
+    k_coarse_gemv<T><<<grid_for((int64_t)n * 64, TPB), TPB, 0, s>>>(n, inv, f, u);
     HIP_LAUNCH_CHECK();
 }
 void launch_cast_d2f(int64_t n, const double* a, float* b, hipStream_t s) {
@@ -214,166 +371,238 @@ void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 
-#define AMG_INST(T)                                                                                      \
-    template void launch_spmv<T>(const Csr&, int, const T*, T*, hipStream_t);                            \
-    template void launch_residual<T>(const Csr&, int, const T*, const T*, T*, hipStream_t);              \
-    template void launch_jacobi<T>(const Csr&, int, const T*, const T*, const T*, T*, hipStream_t);      \
-    template void launch_smooth0_residual<T>(const Csr&, int, const T*, const T*, T*, T*, hipStream_t);  \
-    template void launch_prolong_add<T>(const Csr&, int, const T*, T*, hipStream_t);                     \
+#define AMG_INST(T)                                                                                 \
+    template void launch_spmv<T>(const Csr&, const T*, T*, const T*, T*, hipStream_t);              \
+    template void launch_residual<T>(const Csr&, const T*, const T*, T*, hipStream_t);              \
+    template void launch_jacobi<T>(const Csr&, const T*, const T*, const T*, T*, hipStream_t);      \
+    template void launch_smooth0_residual<T>(const Csr&, const T*, const T*, T*, T*, hipStream_t);  \
+    template void launch_prolong_add<T>(const Csr&, const T*, T*, hipStream_t);                     \
     template void launch_coarse_gemv<T>(int, const double*, const T*, T*, hipStream_t);
 AMG_INST(double)
 AMG_INST(float)
 #undef AMG_INST
 
-// ------------------------------------------------------------------ reductions
+// ------------------------------------------------------------------ CG kernels (FP64)
 //
-// Each kernel below runs on a grid of min(RED_BLOCKS, rows needed) blocks, fixed for a
-// given n.  A block sums its threads' partials in a fixed tree, writes one partial per
-// block, and the last block to arrive (ticket counter) adds the partials in block order.
-// The result is therefore bitwise reproducible run to run.
+// Scalars flow through partial sums: the kernels that form r.z and p.q write one partial
+// per block (full grids, indexed by logical block), a one-block finalize kernel adds them
+// in order and forms beta or alpha on the device; ||r||^2 and ||f||^2 come from bounded
+// grids (at most RED_BLOCKS partials) that the host adds after its one copy per iteration.
 
-template <int K>
-__device__ bool block_reduce_last(double (&v)[K], const RedScratch rs, double (&tot)[K]) {
-    __shared__ double sm[K][RED_THREADS / 64];
-    __shared__ int is_last;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        double x = wave_sum(v[q]);
-        if (lane == 0) sm[q][w] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < K; ++q) {
+int red_grid_elems(int64_t n) {
+    const int64_t b = (n + TPB - 1) / TPB;
+    return (int)(b < 1 ? 1 : (b > RED_BLOCKS ? RED_BLOCKS : b));
+}
+
+int full_grid_rows(int nrows, int rpb, int g) {
+    const int64_t b = rpb > 0 ? (nrows + (int64_t)rpb - 1) / rpb : ((int64_t)nrows * g + TPB - 1) / TPB;
+    return (int)(b < 1 ? 1 : b);
+}
+
+int red_grid_rows(int nrows, int rpb, int g) {
+    const int b = full_grid_rows(nrows, rpb, g);
+    return b > RED_BLOCKS ? RED_BLOCKS : b;
+}
+
+// r = f - A x, with ||r||^2 and ||f||^2 partials (bounded grid, host-summed).
+template <int G>
+__global__ __launch_bounds__(RB_THREADS) void k_cg_init(int n, int rpb, const int* __restrict__ ptr,
+                                                        const int* __restrict__ col, const double* __restrict__ val,
+                                                        const double* __restrict__ f, const double* __restrict__ x,
+                                                        double* __restrict__ r, RedScratch rs) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ double sp[RB_CAP];
+    double loc[2] = {0.0, 0.0};
+    if (rpb > 0) {
+        int rb0, rb1;
+        rb_range((n + rpb - 1) / rpb, rb0, rb1);
+        const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+        for (int rb = rb0; rb < rb1; ++rb) {
+            const int row0 = rb * rpb, row1 = min(row0 + rpb, n);
+            rb_load(row0, row1, ptr, col, val, [&](int j) { return x[j]; }, sptr, sp);
+            if (t < row1 - row0) {
+                const double v = rb_rowsum(sptr, sp, t, lane, tpr);
+                if (lane == 0) {
+                    const int i = row0 + t;
+                    const double fi = f[i], ri = fi - v;
+                    r[i] = ri;
+                    loc[0] += ri * ri;
+                    loc[1] += fi * fi;
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        const int lane = threadIdx.x & (G - 1);
+        const int groups = gridDim.x * (TPB / G);
+        for (int row = (blockIdx.x * TPB + (int)threadIdx.x) / G; row < n; row += groups) {
+            const int b = ptr[row], e = ptr[row + 1];
             double s = 0.0;
-            for (int i = 0; i < RED_THREADS / 64; ++i) s += sm[q][i];
-            rs.part[q * RED_BLOCKS + blockIdx.x] = s;
-        }
-        __threadfence();
-        const unsigned t = atomicAdd(rs.ticket, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-            s += __hip_atomic_load(&rs.part[q * RED_BLOCKS + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s = wave_sum(s);
-        __syncthreads();
-        if (lane == 0) sm[q][w] = s;
-        __syncthreads();
-        double t = 0.0;
-        for (int i = 0; i < RED_THREADS / 64; ++i) t += sm[q][i];
-        tot[q] = t;
-    }
-    if (threadIdx.x == 0) *rs.ticket = 0u;
-    return true;
-}
-
-static inline unsigned red_blocks(int64_t rows, int G) {
-    int64_t b = (rows * G + RED_THREADS - 1) / RED_THREADS;
-    if (b > RED_BLOCKS) b = RED_BLOCKS;
-    return (unsigned)(b > 0 ? b : 1);
-}
-
-// r = f - A x with ||r||^2 and ||f||^2.
-template <int G>
-__global__ __launch_bounds__(RED_THREADS) void k_cg_init(int n, const int* __restrict__ ptr,
-                                                         const int* __restrict__ col, const double* __restrict__ val,
-                                                         const double* __restrict__ f, const double* __restrict__ x,
-                                                         double* __restrict__ r, RedScratch rs) {
-    const int lane = threadIdx.x & (G - 1);
-    const int groups = gridDim.x * (RED_THREADS / G);
-    double loc[2] = {0.0, 0.0};
-    for (int row = (blockIdx.x * RED_THREADS + (int)threadIdx.x) / G; row < n; row += groups) {
-        const int b = ptr[row], e = ptr[row + 1];
-        double s = 0.0;
-        for (int k = b + lane; k < e; k += G) s += val[k] * x[col[k]];
-        s = group_sum<G>(s);
-        if (lane == 0) {
-            const double fi = f[row], ri = fi - s;
-            r[row] = ri;
-            loc[0] += ri * ri;
-            loc[1] += fi * fi;
-        }
-    }
-    double tot[2];
-    if (block_reduce_last<2>(loc, rs, tot) && threadIdx.x == 0) {
-        rs.scal[S_RR] = tot[0];
-        rs.scal[S_FF] = tot[1];
-    }
-}
-
-// rho_new = r.z (and r.z_old for flexible CG); beta = (rho_new [- r.z_old]) / rho_old.
-__global__ __launch_bounds__(RED_THREADS) void k_cg_rz(int n, const double* __restrict__ r,
-                                                       const double* __restrict__ z,
-                                                       const double* __restrict__ zold, int flexible, int first,
-                                                       RedScratch rs) {
-    double loc[2] = {0.0, 0.0};
-    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += gridDim.x * RED_THREADS) {
-        loc[0] += r[i] * z[i];
-        if (flexible) loc[1] += r[i] * zold[i];
-    }
-    double tot[2];
-    if (block_reduce_last<2>(loc, rs, tot) && threadIdx.x == 0) {
-        if (!first) {
-            const double num = flexible ? tot[0] - tot[1] : tot[0];
-            rs.scal[S_BETA] = num / rs.scal[S_RHO];
-        }
-        rs.scal[S_RHO] = tot[0];
-    }
-}
-
-// p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new, and p_new.q.
-// Neighbours' p_new entries are formed from z and p_old with the same fma as the owner
-// row, so q is exactly A applied to the stored p_new.
-template <int G>
-__global__ __launch_bounds__(RED_THREADS) void k_cg_pq(int n, const int* __restrict__ ptr,
-                                                       const int* __restrict__ col, const double* __restrict__ val,
-                                                       const double* __restrict__ z, const double* __restrict__ pold,
-                                                       double* __restrict__ pnew, double* __restrict__ q, int first,
-                                                       RedScratch rs) {
-    const int lane = threadIdx.x & (G - 1);
-    const int groups = gridDim.x * (RED_THREADS / G);
-    const double beta = first ? 0.0 : rs.scal[S_BETA];
-    double loc[1] = {0.0};
-    for (int row = (blockIdx.x * RED_THREADS + (int)threadIdx.x) / G; row < n; row += groups) {
-        const int b = ptr[row], e = ptr[row + 1];
-        double s = 0.0;
-        if (first) {
-            for (int k = b + lane; k < e; k += G) s += val[k] * z[col[k]];
-        } else {
-            for (int k = b + lane; k < e; k += G) {
-                const int j = col[k];
-                s += val[k] * __builtin_fma(beta, pold[j], z[j]);
+            for (int k = b + lane; k < e; k += G) s += val[k] * x[col[k]];
+            s = group_sum<G>(s);
+            if (lane == 0) {
+                const double fi = f[row], ri = fi - s;
+                r[row] = ri;
+                loc[0] += ri * ri;
+                loc[1] += fi * fi;
             }
         }
-        s = group_sum<G>(s);
-        if (lane == 0) {
-            const double pi = first ? z[row] : __builtin_fma(beta, pold[row], z[row]);
-            pnew[row] = pi;
-            q[row] = s;
-            loc[0] += pi * s;
-        }
     }
-    double tot[1];
-    if (block_reduce_last<1>(loc, rs, tot) && threadIdx.x == 0) rs.scal[S_PQ] = tot[0];
+    double* const dst[2] = {rs.region(P_RR), rs.region(P_FF)};
+    block_store<2>(loc, dst, blockIdx.x);
 }
 
-// alpha = rho / p.q; x += alpha p; r -= alpha q; ||r||^2.  On breakdown (p.q <= 0 or a
-// non-finite rho) nothing is updated and the flag is raised.
-__global__ __launch_bounds__(RED_THREADS) void k_cg_update(int n, const double* __restrict__ p,
-                                                           const double* __restrict__ q, double* __restrict__ x,
-                                                           double* __restrict__ r, RedScratch rs) {
-    const double rho = rs.scal[S_RHO], pq = rs.scal[S_PQ];
-    const bool bad = !(pq > 0.0) || !isfinite(rho);
-    const double alpha = bad ? 0.0 : rho / pq;
+// Last post-smoothing sweep of the level-0 V-cycle (FP64) fused with the CG dot products:
+// z = u + m (r - A u) (the level-0 right-hand side is the CG residual r), r.z and, for
+// flexible CG, r.z_old with z_old read from z before it is overwritten.  Full grid.
+template <int G>
+__global__ __launch_bounds__(RB_THREADS) void k_jacobi_rz(int n, int rpb, const int* __restrict__ ptr,
+                                                          const int* __restrict__ col, const double* __restrict__ val,
+                                                          const double* __restrict__ m, const double* __restrict__ r,
+                                                          const double* __restrict__ u, double* __restrict__ z,
+                                                          int flexible, RedScratch rs) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ double sp[RB_CAP];
+    double loc[2] = {0.0, 0.0};
+    auto emit = [&](int i, double s) {
+        const double ri = r[i];
+        const double zi = u[i] + m[i] * (ri - s);
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    };
+    const int lb = xcd_block();
+    if (rpb > 0) {
+        const int row0 = lb * rpb, row1 = min(row0 + rpb, n);
+        rb_load(row0, row1, ptr, col, val, [&](int j) { return u[j]; }, sptr, sp);
+        const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+        if (t < row1 - row0) {
+            const double v = rb_rowsum(sptr, sp, t, lane, tpr);
+            if (lane == 0) emit(row0 + t, v);
+        }
+    } else {
+        const int lane = threadIdx.x & (G - 1);
+        const int row = (lb * TPB + (int)threadIdx.x) / G;
+        if (row < n) {
+            const int b = ptr[row], e = ptr[row + 1];
+            double s = 0.0;
+            for (int k = b + lane; k < e; k += G) s += val[k] * u[col[k]];
+            s = group_sum<G>(s);
+            if (lane == 0) emit(row, s);
+        }
+    }
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, lb);
+}
+
+// Mixed precision: z = (double) z32 fused with the same dot products (bounded grid).
+__global__ __launch_bounds__(TPB) void k_cast_rz(int n, const float* __restrict__ z32, const double* __restrict__ r,
+                                                 double* __restrict__ z, int flexible, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+        const double ri = r[i];
+        const double zi = (double)z32[i];
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    }
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, blockIdx.x);
+}
+
+// r.z (used when the V-cycle has no post-smoothing sweep to fuse it into).
+__global__ __launch_bounds__(TPB) void k_cg_rz(int n, const double* __restrict__ r, const double* __restrict__ z,
+                                               RedScratch rs) {
     double loc[1] = {0.0};
-    for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += gridDim.x * RED_THREADS) {
+    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) loc[0] += r[i] * z[i];
+    double* const dst[1] = {rs.region(P_RZ)};
+    block_store<1>(loc, dst, blockIdx.x);
+}
+
+// rho_new = sum of the r.z partials; beta = (rho_new [- r.z_old]) / rho_old with rho_old
+// the rho of the last alpha (so re-running it after a restart is harmless); rho = rho_new.
+__global__ __launch_bounds__(FIN_THREADS) void k_fin_rz(int nb, int flexible, int first, RedScratch rs) {
+    const double rz = block_sum(rs.region(P_RZ), nb);
+    const double rzo = flexible ? block_sum(rs.region(P_RZOLD), nb) : 0.0;
+    if (threadIdx.x == 0) {
+        double* sc = rs.scal();
+        sc[S_BETA] = first ? 0.0 : (flexible ? rz - rzo : rz) / sc[S_RHO_USED];
+        sc[S_RHO] = rz;
+    }
+}
+
+// p.q = sum of its partials; alpha = rho / p.q, or the breakdown flag (p.q <= 0 or a
+// non-finite rho), in which case alpha = 0.
+__global__ __launch_bounds__(FIN_THREADS) void k_fin_pq(int nb, RedScratch rs) {
+    const double pq = block_sum(rs.region(P_PQ), nb);
+    if (threadIdx.x == 0) {
+        double* sc = rs.scal();
+        const double rho = sc[S_RHO];
+        const bool bad = !(pq > 0.0) || !isfinite(rho);
+        sc[S_RHO_USED] = rho;
+        sc[S_PQ] = pq;
+        sc[S_ALPHA] = bad ? 0.0 : rho / pq;
+        sc[S_FLAG] = bad ? 1.0 : 0.0;
+    }
+}
+
+// p_new = z + beta p_old (p_new = z on the first iteration), q = A p_new, p_new.q partials
+// (full grid).  Neighbours' p_new entries are formed with the same fma as the owner row,
+// so q is A applied to exactly the stored p_new.
+template <int G>
+__global__ __launch_bounds__(RB_THREADS) void k_cg_pq(int n, int rpb, const int* __restrict__ ptr,
+                                                      const int* __restrict__ col, const double* __restrict__ val,
+                                                      const double* __restrict__ z, const double* __restrict__ pold,
+                                                      double* __restrict__ pnew, double* __restrict__ q, int first,
+                                                      RedScratch rs) {
+    __shared__ int sptr[RB_THREADS + 1];
+    __shared__ double sp[RB_CAP];
+    const double beta = first ? 0.0 : rs.scal()[S_BETA];
+    auto pv = [&](int j) { return first ? z[j] : __builtin_fma(beta, pold[j], z[j]); };
+    double loc[1] = {0.0};
+    const int lb = xcd_block();
+    if (rpb > 0) {
+        const int row0 = lb * rpb, row1 = min(row0 + rpb, n);
+        rb_load(row0, row1, ptr, col, val, pv, sptr, sp);
+        const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+        if (t < row1 - row0) {
+            const double qi = rb_rowsum(sptr, sp, t, lane, tpr);
+            if (lane == 0) {
+                const int i = row0 + t;
+                const double pi = pv(i);
+                pnew[i] = pi;
+                q[i] = qi;
+                loc[0] += pi * qi;
+            }
+        }
+    } else {
+        const int lane = threadIdx.x & (G - 1);
+        const int row = (lb * TPB + (int)threadIdx.x) / G;
+        if (row < n) {
+            const int b = ptr[row], e = ptr[row + 1];
+            double s = 0.0;
+            for (int k = b + lane; k < e; k += G) s += val[k] * pv(col[k]);
+            s = group_sum<G>(s);
+            if (lane == 0) {
+                const double pi = pv(row);
+                pnew[row] = pi;
+                q[row] = s;
+                loc[0] += pi * s;
+            }
+        }
+    }
+    double* const dst[1] = {rs.region(P_PQ)};
+    block_store<1>(loc, dst, lb);
+}
+
+// x += alpha p; r -= alpha q; ||r||^2 partials (bounded grid).  On breakdown nothing moves.
+__global__ __launch_bounds__(TPB) void k_cg_update(int n, const double* __restrict__ p, const double* __restrict__ q,
+                                                   double* __restrict__ x, double* __restrict__ r, RedScratch rs) {
+    const double* sc = rs.scal();
+    const bool bad = sc[S_FLAG] != 0.0;
+    const double alpha = sc[S_ALPHA];
+    double loc[1] = {0.0};
+    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
         double ri = r[i];
         if (!bad) {
             x[i] += alpha * p[i];
@@ -382,32 +611,60 @@ __global__ __launch_bounds__(RED_THREADS) void k_cg_update(int n, const double* 
         }
         loc[0] += ri * ri;
     }
-    double tot[1];
-    if (block_reduce_last<1>(loc, rs, tot) && threadIdx.x == 0) {
-        rs.scal[S_RR] = tot[0];
-        rs.scal[S_FLAG] = bad ? 1.0 : 0.0;
-    }
+    double* const dst[1] = {rs.region(P_RR)};
+    block_store<1>(loc, dst, blockIdx.x);
 }
 
-void launch_cg_init(const Csr& A, const double* outer_val, int g, const double* f, const double* x, double* r,
-                    const RedScratch& rs, hipStream_t s) {
-    AMG_WITH_G(g, k_cg_init<G><<<red_blocks(A.nrows, G), RED_THREADS, 0, s>>>(A.nrows, A.ptr, A.col, outer_val, f, x, r, rs));
+int launch_cg_init(const Csr& A, const double* val, const double* f, const double* x, double* r, const RedScratch& rs,
+                   hipStream_t s) {
+    const int nb = red_grid_rows(A.nrows, A.rpb, A.g);
+    AMG_WITH_G(A.g, k_cg_init<G><<<nb, RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, val, f, x, r, rs));
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+int launch_jacobi_rz(const Csr& A, const double* m, const double* r, const double* u, double* z, int flexible,
+                     const RedScratch& rs, hipStream_t s) {
+    const int nb = full_grid_rows(A.nrows, A.rpb, A.g);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    AMG_WITH_G(A.g, k_jacobi_rz<G><<<nb, RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.val, m, r, u, z, flexible, rs));
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+int launch_cast_rz(int n, const float* z32, const double* r, double* z, int flexible, const RedScratch& rs,
+                   hipStream_t s) {
+    const int nb = red_grid_elems(n);
+    k_cast_rz<<<nb, TPB, 0, s>>>(n, z32, r, z, flexible, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+int launch_cg_rz(int n, const double* r, const double* z, const RedScratch& rs, hipStream_t s) {
+    const int nb = red_grid_elems(n);
+    k_cg_rz<<<nb, TPB, 0, s>>>(n, r, z, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+void launch_fin_rz(int nb, int flexible, int first, const RedScratch& rs, hipStream_t s) {
+    k_fin_rz<<<1, FIN_THREADS, 0, s>>>(nb, flexible, first, rs);
     HIP_LAUNCH_CHECK();
 }
-void launch_cg_rz(int n, const double* r, const double* z, const double* zold, int flexible, int first,
-                  const RedScratch& rs, hipStream_t s) {
-    k_cg_rz<<<red_blocks(n, 1), RED_THREADS, 0, s>>>(n, r, z, zold, flexible, first, rs);
+void launch_fin_pq(int nb, const RedScratch& rs, hipStream_t s) {
+    k_fin_pq<<<1, FIN_THREADS, 0, s>>>(nb, rs);
     HIP_LAUNCH_CHECK();
 }
-void launch_cg_pq(const Csr& A, const double* outer_val, int g, const double* z, const double* pold, double* pnew,
-                  double* q, int first, const RedScratch& rs, hipStream_t s) {
-    AMG_WITH_G(g, k_cg_pq<G><<<red_blocks(A.nrows, G), RED_THREADS, 0, s>>>(A.nrows, A.ptr, A.col, outer_val, z, pold, pnew, q, first, rs));
+int launch_cg_pq(const Csr& A, const double* val, const double* z, const double* pold, double* pnew, double* q,
+                 int first, const RedScratch& rs, hipStream_t s) {
+    const int nb = full_grid_rows(A.nrows, A.rpb, A.g);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    AMG_WITH_G(A.g, k_cg_pq<G><<<nb, RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, val, z, pold, pnew, q, first, rs));
     HIP_LAUNCH_CHECK();
+    return nb;
 }
-void launch_cg_update(int n, const double* p, const double* q, double* x, double* r, const RedScratch& rs,
-                      hipStream_t s) {
-    k_cg_update<<<red_blocks(n, 1), RED_THREADS, 0, s>>>(n, p, q, x, r, rs);
+int launch_cg_update(int n, const double* p, const double* q, double* x, double* r, const RedScratch& rs,
+                     hipStream_t s) {
+    const int nb = red_grid_elems(n);
+    k_cg_update<<<nb, TPB, 0, s>>>(n, p, q, x, r, rs);
     HIP_LAUNCH_CHECK();
+    return nb;
 }
 
 }  // namespace amgmi

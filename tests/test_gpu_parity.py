@@ -290,3 +290,21 @@ def test_zero_rhs_and_exact_guess():
     g, o = both(p, c, v, coarse_enough=30)
     u, info = g.solve(T(np.zeros(512)), T(np.ones(512)))
     assert info["iters"] == 0 and float(u.abs().max()) == 0.0
+
+
+def test_lane_group_kernels_parity(monkeypatch):
+    """The lane-group fallbacks (used where rows are too long to stage in LDS) give the
+    same hierarchy and solve as the staged kernels."""
+    monkeypatch.setenv("AMGMI_ROW_KERNELS", "lanes")
+    p, c, v0 = two_fluid_7pt(32, front_c1(0))
+    _, _, v1 = two_fluid_7pt(32, front_c1(5))
+    g, o = both(p, c, v0)
+    g.rebuild(T(v1))
+    o.rebuild(v1, 0)
+    compare_levels(g, o, tol=1e-10)
+    assert bitwise_levels(g, o) is None
+    f = rhs_uniform(32**3, 1, 5)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
