@@ -44,7 +44,23 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle partial steps in the CPU sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized FP64 buffer 3 times and exit: the known-size reference "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters of the other kernels")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain device copy of known size (read mib MiB, write mib MiB), three launches."""
+    import torch
+
+    x = torch.rand(mib * 131072, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy probe: {mib} MiB read + {mib} MiB written per launch, 3 launches")
 
 
 # ------------------------------------------------------------------ algorithmic bytes
@@ -78,9 +94,13 @@ def kernel_bytes(dims, sv_h, level_prec_bytes=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU row-block sharding is a design note, not implemented).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: runs on several GPUs "
+              f"(row-block sharding of every level) are not implemented.", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
 
     import numpy as np
     import torch

@@ -189,6 +189,24 @@ bool lanes_only() {
     return e != nullptr && std::strcmp(e, "lanes") == 0;
 }
 
+// Galerkin form override (AMGMI_GALERKIN = pos | pos16 | lanes, optionally ":G" for the
+// position-map form's lanes per row; pos16 forces two-byte positions); used to exercise
+// every form and launch shape.  Default: the shape picker's choice.
+struct GalForce {
+    int lanes = 0;  // 1: lane-group kernels
+    int wide = 0;   // 1: two-byte positions
+    int g = 0;
+};
+GalForce galerkin_force() {
+    GalForce f;
+    const char* e = std::getenv("AMGMI_GALERKIN");
+    if (e == nullptr) return f;
+    if (std::strncmp(e, "lanes", 5) == 0) f.lanes = 1;
+    if (std::strncmp(e, "pos16", 5) == 0) f.wide = 1;
+    if (const char* c = std::strchr(e, ':')) f.g = std::atoi(c + 1);
+    return f;
+}
+
 // Launch shapes of a matrix's row kernels (reads its row pointers back once).
 void configure(Csr& A, hipStream_t s) {
     A.g = lane_group(A.nrows > 0 ? (double)A.nnz / A.nrows : 1.0);
@@ -206,21 +224,46 @@ std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
     return h;
 }
 
-void set_groups(Level& L, hipStream_t s) {
+// The position map of C = L B for the shape gs (allocated with the hierarchy).
+void make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, GalShape& gs, hipStream_t s) {
+    if (gs.g == 0) return;
+    gs.off = halloc<int64_t>(c, (size_t)L.nrows + 1);
+    gs.terms = count_galerkin_terms(L, B, gs.off, s);
+    const size_t n = (size_t)std::max<int64_t>(gs.terms, 1);
+    gs.pos = gs.wide ? (void*)halloc<uint16_t>(c, n) : (void*)halloc<uint8_t>(c, n);
+    build_galerkin_posmap(L, B, C, gs, s);
+}
+
+void release_posmaps(amg_ctx* c, Level& L) {
+    for (GalShape* gs : {&L.galAP, &L.galRAP}) {
+        release(c, gs->pos);
+        release(c, gs->off);
+        *gs = GalShape{};
+    }
+}
+
+// Launch shapes of a level's row kernels and Galerkin kernels (Ac: the next level's
+// operator, whose pattern is the second Galerkin product's), with the position maps.
+void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
     configure(L.A, s);
-    if (L.P.nrows > 0) {
+    if (L.P.nrows > 0 && Ac != nullptr) {
         configure(L.P, s);
         configure(L.R, s);
         L.gAP = lane_group((double)L.AP.nnz / (L.A.nrows > 0 ? (double)L.A.nrows : 1.0));
-        // staged Galerkin blocks: A_l rows referencing P_l rows; R_l rows referencing AP rows
         const auto Ap = to_host(L.A.ptr, (size_t)L.A.nrows + 1, s);
-        const auto Ac = to_host(L.A.col, (size_t)L.A.nnz, s);
+        const auto Acl = to_host(L.A.col, (size_t)L.A.nnz, s);
         const auto Pp = to_host(L.P.ptr, (size_t)L.P.nrows + 1, s);
-        L.rpbAP = lanes_only() ? 0 : pick_galerkin_rpb(Ap.data(), Ac.data(), L.A.nrows, Pp.data());
+        const auto APp = to_host(L.AP.ptr, (size_t)L.AP.nrows + 1, s);
         const auto Rp = to_host(L.R.ptr, (size_t)L.R.nrows + 1, s);
         const auto Rc = to_host(L.R.col, (size_t)L.R.nnz, s);
-        const auto APp = to_host(L.AP.ptr, (size_t)L.AP.nrows + 1, s);
-        L.rpbRAP = lanes_only() ? 0 : pick_galerkin_rpb(Rp.data(), Rc.data(), L.R.nrows, APp.data());
+        const auto Cp = to_host(Ac->ptr, (size_t)Ac->nrows + 1, s);
+        const GalForce f = galerkin_force();
+        const bool lanes = lanes_only() || f.lanes;
+        L.galAP = lanes ? GalShape{} : pick_galerkin_shape(Ap.data(), Acl.data(), L.A.nrows, Pp.data(), APp.data(), f.g);
+        L.galRAP = lanes ? GalShape{} : pick_galerkin_shape(Rp.data(), Rc.data(), L.R.nrows, APp.data(), Cp.data(), f.g);
+        if (f.wide) L.galAP.wide = L.galRAP.wide = 1;
+        make_posmap(c, L.A, L.P, L.AP, L.galAP, s);
+        make_posmap(c, L.R, L.AP, *Ac, L.galRAP, s);
     }
 }
 
@@ -241,7 +284,7 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     // array and stores the hierarchy's copies (FP64, and FP32 in mixed precision) as it
     // reads them; otherwise they are copied first.
     bool ingested = false;
-    if (nlev == 1 || L0.rpbAP == 0) {
+    if (nlev == 1 || L0.galAP.g == 0) {
         if (val != L0.A.val) d2d(L0.A.val, val, (size_t)L0.A.nnz * sizeof(double), s);
         if constexpr (std::is_same<T, float>::value) launch_cast_d2f(L0.A.nnz, L0.A.val, L0.A.val32, s);
         ingested = true;
@@ -251,12 +294,12 @@ void partial_rebuild(amg_ctx* c, const double* val) {
         {
             // the staged A P kernel also forms this level's smoother diagonal
             Trace tr(c, AMG_K_GALERKIN_AP, l);
-            smoothed[(size_t)l] = launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, L.rpbAP, c->prm.smoother,
+            smoothed[(size_t)l] = launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, L.galAP, c->prm.smoother,
                                                         c->prm.jacobi_omega, L.mv<T>(),
                                                         (l == 0 && !ingested) ? val : nullptr, s);
         }
         Trace tr(c, AMG_K_GALERKIN_RAP, l);
-        launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, L.rpbRAP, s);
+        launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, L.galRAP, s);
     }
     HIP_CHECK(hipEventRecord(c->ev[1], s));
     for (int l = 0; l + 1 < nlev; ++l) {
@@ -442,21 +485,21 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
             L.P = P;
             L.R = R;
             L.AP = AP;
-            set_groups(L, s);
+            set_groups(c, L, &Ac, s);
         }
         Level next;
         next.A = Ac;
-        set_groups(next, s);
+        set_groups(c, next, nullptr, s);
         next.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
-        launch_galerkin_ap<double>(A, P, AP, c->lv[(size_t)l].gAP, c->lv[(size_t)l].rpbAP, 0, 0.0,
+        launch_galerkin_ap<double>(A, P, AP, c->lv[(size_t)l].gAP, c->lv[(size_t)l].galAP, 0, 0.0,
                                    (double*)nullptr, nullptr, s);
-        launch_galerkin_rap<double>(R, AP, Ac, next.gRAP, c->lv[(size_t)l].rpbRAP, s);
+        launch_galerkin_rap<double>(R, AP, Ac, next.gRAP, c->lv[(size_t)l].galRAP, s);
         HIP_CHECK(hipStreamSynchronize(s));
         ph[3] += ms_since(t0);
         dfree(diag_pos, s);
         c->lv.push_back(next);
     }
-    set_groups(c->lv.back(), s);
+    set_groups(c, c->lv.back(), nullptr, s);
 
     alloc_reduction(c);
     auto t0 = Clock::now();
@@ -541,11 +584,12 @@ void repattern(amg_ctx* c) {
         L.AP = AP;
         release_csr(c, N.A);
         N.A = Ac;
-        set_groups(L, s);
+        release_posmaps(c, L);
+        set_groups(c, L, &N.A, s);
         N.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
     }
     if (mixed(c)) L0.A.val32 = halloc<float>(c, (size_t)L0.A.nnz);
-    set_groups(c->lv.back(), s);
+    set_groups(c, c->lv.back(), nullptr, s);
     release(c, c->rs.part);
     alloc_reduction(c);
     // The strength flags were per entry of the old patterns; the aggregates stay (they

@@ -61,6 +61,20 @@ inline double* Csr::v<double>() const { return val; }
 template <>
 inline float* Csr::v<float>() const { return val32; }
 
+// A Galerkin product C = L B in the position-map form: lanes per output row g, LDS
+// accumulators per row cap, and the cached position map (for every product term l * b of
+// a C row, in the row-by-row product's order, the position of its column in the C row;
+// one byte each when every C row is shorter than 256, else two), with each row's first
+// term at off[row].  g == 0: the product uses the lane-group kernels.
+struct GalShape {
+    int g = 0;
+    int cap = 0;
+    int wide = 0;               // 1: two-byte positions
+    void* pos = nullptr;        // position map (device, owned by the hierarchy)
+    int64_t* off = nullptr;     // nrows + 1 term offsets (device, owned by the hierarchy)
+    int64_t terms = 0;
+};
+
 struct Level {
     Csr A;       // A_l
     Csr P, R;    // P_l and R_l = P_l^T (empty on the coarsest level)
@@ -74,10 +88,10 @@ struct Level {
     void* f = nullptr;
     void* r = nullptr;
     void* t = nullptr;
-    // Galerkin kernels: lane-group widths (A_l P_l rows; A_{l+1} rows) and rows per
-    // LDS-staged block (A_l rows for A_l P_l; R_l rows for R_l (A_l P_l); 0: lane groups)
+    // Galerkin kernels: lane-group widths (A_l P_l rows; A_{l+1} rows) and the gathered
+    // kernel's shapes for A_l P_l and R_l (A_l P_l)
     int gAP = 8, gRAP = 32;
-    int rpbAP = 0, rpbRAP = 0;
+    GalShape galAP, galRAP;
     template <typename T>
     T* mv() const;
 };
@@ -161,11 +175,16 @@ int launch_cg_update(int n, const double* p, const double* q, double* x, double*
 template <typename T>
 void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_t s);
 template <typename T>
-bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, int rpb, int kind, double omega, T* m,
+bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalShape gs, int kind, double omega, T* m,
                         const double* ain, hipStream_t s);
 template <typename T>
-void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, int rpb, hipStream_t s);
-int pick_galerkin_rpb(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr);
+void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s);
+GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr,
+                             const int32_t* Cptr, int gforce);
+// Fills gs.off (nrows + 1) and gs.pos (gs.terms entries, allocated by the caller between
+// the two calls): count_terms writes the offsets and returns the number of terms.
+int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, hipStream_t s);
+void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalShape& gs, hipStream_t s);
 
 // ------------------------------------------------------------------ setup
 // flags: device int[8], see SetupFlag.
@@ -184,6 +203,7 @@ void build_prolongator(const Csr& A, const uint8_t* strong, const int32_t* diag_
 void build_transpose(const Csr& P, Csr& R, hipStream_t s);
 void symbolic_spgemm(const Csr& A, const Csr& B, Csr& C, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------ coarse solve
 constexpr int COARSE_LDS_MAX = 128;      // dense FP64 inverse held in one workgroup's LDS

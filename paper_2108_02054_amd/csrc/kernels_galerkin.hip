@@ -7,6 +7,7 @@
 // along row i of the left factor, at most one matching entry per row of the right factor.
 // Products and sums are rounded separately (contraction off), so FP64 results are
 // bitwise reproducible and independent of the launch shape.
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -124,194 +125,250 @@ __global__ __launch_bounds__(TPB) void k_galerkin_rap(int nc, const int* __restr
     }
 }
 
-// ------------------------------------------------------------------ LDS-staged forms
+// ------------------------------------------------------------------ position-map form
 //
-// A workgroup owns `rpb` consecutive rows of the left factor (rows chosen at setup so the
-// staged data fits the caps below).  It stages the left factor's entries of those rows
-// and, for each entry, the whole row of the right factor it references, in LDS; lanes
-// then own output entries and add their terms from LDS in the fixed order above.
+// The terms of row i of C = L B are l_t * b_e for the L entries t of row i in order and,
+// for each, the entries e of B row Lcol[t] in order; this is the order in which a
+// row-by-row product adds them.  The column of each term and so its position in the
+// (cached, sorted) C row depend on the patterns alone: setup stores these positions once
+// (the position map), and each numeric product only multiplies, and adds each term into
+// its C entry, kept in LDS.  A group of G lanes per row of C walks the L entries in order;
+// for entry t the lanes take the terms of B row Lcol[t], G at a time.  Positions within one
+// B row are distinct, and the LDS operations of a wavefront complete in program order, so
+// every entry of C receives its terms in the row-by-row order.  Each lane holds two L
+// entries of a chunk (2G entries per chunk), and the terms of WF_AHEAD entries are loaded
+// before they are added.  For C = A P the group also forms the smoother diagonal (the
+// row's squares added in column order), and can take A's values from a new FP64 array,
+// storing the hierarchy's copies on the way.
 
-constexpr int GL_CAP_L = 512;   // staged entries of the left factor per block
-constexpr int GL_CAP_C = 2048;  // staged entries of the referenced right-factor rows
+constexpr int WF_AHEAD = 4;            // L entries whose terms are loaded together
+constexpr int WF_CAP_MAX = 4096;       // longest C row the form takes
+constexpr size_t WF_SMEM_MAX = 65536;  // LDS per block
 
-// Exclusive prefix sum of v[0..count) in place, v[count] = total (count <= GL_CAP_L).
-__device__ void block_exscan(int* v, int count, int* tmp) {
-    constexpr int PER = (GL_CAP_L + TPB - 1) / TPB;
-    const int t = threadIdx.x;
-    const int b = t * PER;
-    int loc = 0;
-    for (int q = 0; q < PER; ++q)
-        if (b + q < count) loc += v[b + q];
-    tmp[t] = loc;
-    __syncthreads();
-    for (int off = 1; off < TPB; off <<= 1) {  // inclusive scan of the per-thread sums
-        const int x = t >= off ? tmp[t - off] : 0;
-        __syncthreads();
-        tmp[t] += x;
-        __syncthreads();
+template <int G>
+__device__ __forceinline__ int group_exscan(int v, int g, int& total) {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        const int y = __shfl_up(x, o, G);
+        if (g >= o) x += y;
     }
-    int run = t > 0 ? tmp[t - 1] : 0;
-    for (int q = 0; q < PER; ++q)
-        if (b + q < count) {
-            const int x = v[b + q];
-            v[b + q] = run;
-            run += x;
-        }
-    if (t == TPB - 1) v[count] = tmp[TPB - 1];
-    __syncthreads();
+    total = __shfl(x, G - 1, G);
+    return x - v;
 }
 
-// Local row of a position given the staged row pointers (sorted, rows [0, nr)).
-__device__ __forceinline__ int local_row(const int* sptr, int nr, int pos) {
-    int lo = 0, hi = nr - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (sptr[mid] <= pos)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
-
-// Stages rows [row0, row1) of the left factor L and, for every entry (i, j), row j of the
-// right factor B.  Returns through shared arrays: lptr (row pointers, rebased), lval (L
-// values), lcol (L columns), boff (offset of each entry's B row in bcol/bval).
-// With `lin` given, the left factor's values are read from the caller's FP64 array
-// instead of Lval and copied to lout64 / loutT (either may be null) on the way: this is
-// how new matrix values enter the hierarchy without a separate copy pass.
-template <typename T>
-__device__ void stage_pair(int row0, int row1, const int* __restrict__ Lptr, const int* __restrict__ Lcol,
-                           const T* __restrict__ Lval, const int* __restrict__ Bptr, const int* __restrict__ Bcol,
-                           const T* __restrict__ Bval, int* lptr, int* lcol, T* lval, int* boff, int* bst, int* bcol,
-                           T* bval, int* tmp, const double* __restrict__ lin = nullptr,
-                           double* __restrict__ lout64 = nullptr, T* __restrict__ loutT = nullptr) {
-    const int nr = row1 - row0;
-    for (int i = threadIdx.x; i <= nr; i += TPB) lptr[i] = Lptr[row0 + i];
-    __syncthreads();
-    const int k0 = lptr[0];
-    const int nl = min(lptr[nr] - k0, GL_CAP_L);  // the host sizes blocks within the caps
-    for (int t = threadIdx.x; t < nl; t += TPB) {
-        const int j = Lcol[k0 + t];
-        lcol[t] = j;
-        if (lin != nullptr) {
-            const double a = lin[k0 + t];
-            if (lout64 != nullptr) lout64[k0 + t] = a;
-            if (loutT != nullptr) loutT[k0 + t] = (T)a;
-            lval[t] = (T)a;
-        } else {
-            lval[t] = Lval[k0 + t];
+template <typename T, int G, typename PT>
+__global__ __launch_bounds__(TPB) void k_galerkin_pos(
+    int nrows, int cap, const int* __restrict__ Lptr, const int* __restrict__ Lcol, const T* __restrict__ Lval,
+    const int* __restrict__ Bptr, const T* __restrict__ Bval, const int* __restrict__ Cptr, T* __restrict__ Cval,
+    const PT* __restrict__ pos, const int64_t* __restrict__ poff, int kind, T omega, T* __restrict__ m,
+    const double* __restrict__ lin, double* __restrict__ lout64, T* __restrict__ loutT) {
+    extern __shared__ __align__(16) unsigned char wf_smem[];
+    const int g = threadIdx.x & (G - 1);
+    T* sacc = reinterpret_cast<T*>(wf_smem) + (size_t)(threadIdx.x / G) * cap;
+    const int row = (xcd_block() * TPB + (int)threadIdx.x) / G;
+    if (row >= nrows) return;  // groups leave whole: G divides the wavefront
+    const int sb = Cptr[row];
+    const int len = min(Cptr[row + 1] - sb, cap);  // the host keeps every row within cap
+    for (int q = g; q < len; q += G) sacc[q] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T d = 0, ss = 0;
+    const int le = Lptr[row + 1];
+    const PT* prow = pos + poff[row];
+    int carry = 0;  // terms of the row's earlier chunks
+    for (int c0 = Lptr[row]; c0 < le; c0 += 2 * G) {
+        // lane g holds L entries c0 + g (h = 0) and c0 + G + g (h = 1)
+        int bst[2], blen[2], jj[2], toff[2];
+        T lv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int t = c0 + h * G + g;
+            bst[h] = 0;
+            blen[h] = 0;
+            jj[h] = -1;
+            lv[h] = 0;
+            if (t < le) {
+                const int j = Lcol[t];
+                jj[h] = j;
+                if (lin != nullptr) {
+                    const double x = lin[t];
+                    if (lout64 != nullptr) lout64[t] = x;
+                    if (loutT != nullptr) loutT[t] = (T)x;
+                    lv[h] = (T)x;
+                } else {
+                    lv[h] = Lval[t];
+                }
+                bst[h] = Bptr[j];
+                blen[h] = Bptr[j + 1] - bst[h];
+            }
         }
-        const int b = Bptr[j];
-        bst[t] = b;
-        boff[t] = Bptr[j + 1] - b;
-    }
-    __syncthreads();
-    block_exscan(boff, nl, tmp);
-    for (int t = threadIdx.x; t < nl; t += TPB) {
-        const int o = boff[t], b = bst[t];
-        const int len = min(boff[t + 1], GL_CAP_C) - o;
-        for (int q = 0; q < len; ++q) {
-            bcol[o + q] = Bcol[b + q];
-            bval[o + q] = Bval[b + q];
+        int tot0, tot1;
+        toff[0] = carry + group_exscan<G>(blen[0], g, tot0);
+        toff[1] = carry + tot0 + group_exscan<G>(blen[1], g, tot1);
+        carry += tot0 + tot1;
+        const int nt = min(2 * G, le - c0);  // uniform across the group
+        if (m != nullptr) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                for (int q = 0; q < G && h * G + q < nt; ++q) {  // the row's squares in column order
+                    const T a = __shfl(lv[h], q, G);
+                    if (__shfl(jj[h], q, G) == row) d = a;
+                    ss = ss + a * a;
+                }
         }
-    }
-    __syncthreads();
-}
-
-// AP = A P for rows [row0, row1) plus the smoother diagonal of those rows of A.
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_galerkin_ap_lds(int n, int rpb, const int* __restrict__ Aptr,
-                                                         const int* __restrict__ Acol, const T* __restrict__ Aval,
-                                                         const int* __restrict__ Pptr, const int* __restrict__ Pcol,
-                                                         const T* __restrict__ Pval, const int* __restrict__ APptr,
-                                                         const int* __restrict__ APcol, T* __restrict__ APval,
-                                                         int kind, T omega, T* __restrict__ m,
-                                                         const double* __restrict__ Ain, double* __restrict__ Aout64,
-                                                         T* __restrict__ AoutT) {
-    __shared__ int lptr[TPB + 1];
-    __shared__ int sptr[TPB + 1];
-    __shared__ int lcol[GL_CAP_L];
-    __shared__ T lval[GL_CAP_L];
-    __shared__ int boff[GL_CAP_L + 1];
-    __shared__ int bst[GL_CAP_L];
-    __shared__ int bcol[GL_CAP_C];
-    __shared__ T bval[GL_CAP_C];
-    __shared__ int tmp[TPB];
-    const int row0 = xcd_block() * rpb;
-    if (row0 >= n) return;
-    const int row1 = min(row0 + rpb, n), nr = row1 - row0;
-    stage_pair<T>(row0, row1, Aptr, Acol, Aval, Pptr, Pcol, Pval, lptr, lcol, lval, boff, bst, bcol, bval, tmp, Ain,
-                  Aout64, AoutT);
-    for (int i = threadIdx.x; i <= nr; i += TPB) sptr[i] = APptr[row0 + i];
-    __syncthreads();
-    const int k0 = lptr[0];
-    const int s0 = sptr[0], s1 = sptr[nr];
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += TPB) {
-        const int r = local_row(sptr, nr, s);
-        const int J = APcol[s];
-        T acc = 0;
-        for (int t = lptr[r] - k0; t < lptr[r + 1] - k0; ++t) {
-            for (int q = boff[t]; q < boff[t + 1]; ++q) {
-                const int c = bcol[q];
-                if (c >= J) {
-                    if (c == J) acc = acc + lval[t] * bval[q];
-                    break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            for (int u0 = 0; u0 < G && h * G + u0 < nt; u0 += WF_AHEAD) {
+                int ub[WF_AHEAD], ul[WF_AHEAD], uo[WF_AHEAD], up[WF_AHEAD];
+                T uv[WF_AHEAD], bv[WF_AHEAD];
+#pragma unroll
+                for (int i = 0; i < WF_AHEAD; ++i) {  // first G terms of each entry, in flight together
+                    const int u = u0 + i < G ? u0 + i : G - 1;
+                    ub[i] = __shfl(bst[h], u, G);
+                    ul[i] = (u0 + i < G && h * G + u0 + i < nt) ? __shfl(blen[h], u, G) : 0;
+                    uo[i] = __shfl(toff[h], u, G);
+                    uv[i] = __shfl(lv[h], u, G);
+                    if (g < ul[i]) {
+                        up[i] = (int)prow[uo[i] + g];
+                        bv[i] = Bval[ub[i] + g];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < WF_AHEAD; ++i) {
+                    if (g < ul[i] && up[i] < len) sacc[up[i]] = sacc[up[i]] + uv[i] * bv[i];
+                    for (int k = g + G; k < ul[i]; k += G) {  // rows of B longer than G
+                        const int p = (int)prow[uo[i] + k];
+                        const T b = Bval[ub[i] + k];
+                        if (p < len) sacc[p] = sacc[p] + uv[i] * b;
+                    }
                 }
             }
         }
-        APval[s] = acc;
     }
-    if (m != nullptr && (int)threadIdx.x < nr) {
-        const int r = threadIdx.x, i = row0 + r;
-        T d = 0, ss = 0;
-        for (int t = lptr[r] - k0; t < lptr[r + 1] - k0; ++t) {
-            const T a = lval[t];
-            if (lcol[t] == i) d = a;
-            ss = ss + a * a;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = g; q < len; q += G) Cval[sb + q] = sacc[q];
+    if (m != nullptr && g == 0) m[row] = (kind == 1) ? d / ss : omega / d;
+}
+
+// Terms per row of C = L B.
+__global__ __launch_bounds__(TPB) void k_count_terms(int nrows, const int* __restrict__ Lptr,
+                                                     const int* __restrict__ Lcol, const int* __restrict__ Bptr,
+                                                     int64_t* __restrict__ cnt) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i > nrows) return;
+    int64_t c = 0;
+    if (i < nrows)
+        for (int t = Lptr[i]; t < Lptr[i + 1]; ++t) c += Bptr[Lcol[t] + 1] - Bptr[Lcol[t]];
+    cnt[i] = c;  // cnt[nrows] = 0, so the exclusive scan ends with the total
+}
+
+// The position map: 8 lanes per row of C, the L entries in order, the B row's terms
+// across the lanes; each column is found in the sorted C row by binary search.  A column
+// missing from the C row (which a consistent cached pattern never has) maps to the row
+// length, which the numeric kernel skips.
+template <typename PT>
+__global__ __launch_bounds__(TPB) void k_posmap(int nrows, const int* __restrict__ Lptr,
+                                                const int* __restrict__ Lcol, const int* __restrict__ Bptr,
+                                                const int* __restrict__ Bcol, const int* __restrict__ Cptr,
+                                                const int* __restrict__ Ccol, const int64_t* __restrict__ poff,
+                                                PT* __restrict__ pos) {
+    constexpr int G = 8;
+    const int g = threadIdx.x & (G - 1);
+    const int row = (xcd_block() * TPB + (int)threadIdx.x) / G;
+    if (row >= nrows) return;
+    const int cb = Cptr[row], ce = Cptr[row + 1];
+    int64_t o = poff[row];
+    for (int t = Lptr[row]; t < Lptr[row + 1]; ++t) {
+        const int j = Lcol[t];
+        const int b0 = Bptr[j], b1 = Bptr[j + 1];
+        for (int e = b0 + g; e < b1; e += G) {
+            const int J = Bcol[e];
+            int lo = cb, hi = ce;  // lower bound of J in Ccol[cb, ce)
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (Ccol[mid] < J)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            const int p = (lo < ce && Ccol[lo] == J) ? lo - cb : ce - cb;
+            pos[o + (e - b0)] = (PT)p;
         }
-        m[i] = (kind == 1) ? d / ss : omega / d;
+        o += b1 - b0;
     }
 }
 
-// A_c = R (AP) for coarse rows [row0, row1).
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_galerkin_rap_lds(int nc, int rpb, const int* __restrict__ Rptr,
-                                                          const int* __restrict__ Rcol, const T* __restrict__ Rval,
-                                                          const int* __restrict__ APptr,
-                                                          const int* __restrict__ APcol,
-                                                          const T* __restrict__ APval, const int* __restrict__ Cptr,
-                                                          const int* __restrict__ Ccol, T* __restrict__ Cval) {
-    __shared__ int lptr[TPB + 1];
-    __shared__ int sptr[TPB + 1];
-    __shared__ int lcol[GL_CAP_L];
-    __shared__ T lval[GL_CAP_L];
-    __shared__ int boff[GL_CAP_L + 1];
-    __shared__ int bst[GL_CAP_L];
-    __shared__ int bcol[GL_CAP_C];
-    __shared__ T bval[GL_CAP_C];
-    __shared__ int tmp[TPB];
-    const int row0 = xcd_block() * rpb;
-    if (row0 >= nc) return;
-    const int row1 = min(row0 + rpb, nc), nr = row1 - row0;
-    stage_pair<T>(row0, row1, Rptr, Rcol, Rval, APptr, APcol, APval, lptr, lcol, lval, boff, bst, bcol, bval, tmp);
-    for (int i = threadIdx.x; i <= nr; i += TPB) sptr[i] = Cptr[row0 + i];
-    __syncthreads();
-    const int k0 = lptr[0];
-    const int s0 = sptr[0], s1 = sptr[nr];
-    for (int s = s0 + (int)threadIdx.x; s < s1; s += TPB) {
-        const int r = local_row(sptr, nr, s);
-        const int J = Ccol[s];
-        T acc = 0;
-        for (int t = lptr[r] - k0; t < lptr[r + 1] - k0; ++t) {
-            const int b = boff[t], e = boff[t + 1];
-            if (b == e) continue;
-            const int pos = find_sorted(bcol, b, e, J);
-            if (pos >= 0) acc = acc + lval[t] * bval[pos];
-        }
-        Cval[s] = acc;
-    }
+int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, hipStream_t s) {
+    int64_t* cnt = dnew<int64_t>((size_t)L.nrows + 1, s);
+    k_count_terms<<<row_blocks((int64_t)L.nrows + 1, 1), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, cnt);
+    HIP_LAUNCH_CHECK();
+    exclusive_scan_i64(cnt, off, (int64_t)L.nrows + 1, s);
+    dfree(cnt, s);
+    int64_t total = 0;
+    HIP_CHECK(hipMemcpyAsync(&total, off + L.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return total;
 }
+
+void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalShape& gs, hipStream_t s) {
+    if (gs.terms == 0) return;
+    if (gs.wide)
+        k_posmap<uint16_t><<<row_blocks(L.nrows, 8), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, B.col, C.ptr, C.col,
+                                                                   gs.off, (uint16_t*)gs.pos);
+    else
+        k_posmap<uint8_t><<<row_blocks(L.nrows, 8), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, B.col, C.ptr, C.col,
+                                                                  gs.off, (uint8_t*)gs.pos);
+    HIP_LAUNCH_CHECK();
+}
+
+#define AMG_WITH_GS1(g, ...)                                                \
+    do {                                                                    \
+        switch (g) {                                                        \
+            case 4: { constexpr int GG = 4; __VA_ARGS__; } break;           \
+            case 8: { constexpr int GG = 8; __VA_ARGS__; } break;           \
+            case 16: { constexpr int GG = 16; __VA_ARGS__; } break;         \
+            case 32: { constexpr int GG = 32; __VA_ARGS__; } break;         \
+            case 64: { constexpr int GG = 64; __VA_ARGS__; } break;         \
+            default: throw Fail{AMG_ERR_ARG, "unsupported Galerkin lane count"}; \
+        }                                                                   \
+    } while (0)
+
+// Launch shape of the position-map form for C = L B (host arrays): cap = the longest C
+// row rounded up to a multiple of 8, and G = the power of two in [4, 64] nearest above the
+// mean referenced B row length (so that most B rows take one pass of the group), raised
+// until a block's LDS (TPB / G rows of cap FP64 accumulators) is within WF_SMEM_MAX.
+// {0, ...}: the rows are too long for the form (lane-group kernels).  gforce forces G
+// where the LDS allows.  The position map itself is built by the caller.
+GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr,
+                             const int32_t* Cptr, int gforce) {
+    int maxlen = 0;
+    for (int32_t i = 0; i < nrows; ++i) maxlen = std::max(maxlen, Cptr[i + 1] - Cptr[i]);
+    if (maxlen > WF_CAP_MAX) return {};
+    double refs = 0.0, tot = 0.0;
+    for (int64_t k = 0; k < Lptr[nrows]; ++k) {
+        refs += 1.0;
+        tot += (double)(Bptr[Lcol[k] + 1] - Bptr[Lcol[k]]);
+    }
+    const double mean_b = refs > 0 ? tot / refs : 1.0;
+    const int cap = std::max(8, (maxlen + 7) / 8 * 8);
+    auto smem = [&](int G) { return (size_t)(TPB / G) * (size_t)cap * sizeof(double); };
+    int G = 4;
+    while (G < 64 && G < mean_b) G <<= 1;
+    if (gforce == 4 || gforce == 8 || gforce == 16 || gforce == 32 || gforce == 64) G = gforce;
+    while (G < 64 && smem(G) > WF_SMEM_MAX) G <<= 1;
+    if (smem(G) > WF_SMEM_MAX) return {};
+    GalShape gs;
+    gs.g = G;
+    gs.cap = cap;
+    gs.wide = maxlen > 255 ? 1 : 0;
+    return gs;
+}
+
+static size_t acc_smem(const GalShape& gs, size_t tsize) { return (size_t)(TPB / gs.g) * (size_t)gs.cap * tsize; }
 
 template <typename T>
 void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_t s) {
@@ -321,17 +378,23 @@ void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_
 
 // AP = A P; with m != nullptr also the smoother diagonal of A, and with ain != nullptr
 // the values of A are taken from ain (FP64) and stored into A's value arrays on the way.
-// Only the staged form fuses these; it returns true when it did (m and A written).
+// Only the position-map form fuses these; it returns true when it did (m and A written).
 template <typename T>
-bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, int rpb, int kind, double omega, T* m,
+bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalShape gs, int kind, double omega, T* m,
                         const double* ain, hipStream_t s) {
-    if (rpb > 0) {
+    if (gs.g > 0) {
         double* out64 = (ain != nullptr && ain != A.val) ? A.val : nullptr;
         T* outT = nullptr;
         if constexpr (!std::is_same<T, double>::value) outT = ain != nullptr ? A.v<T>() : nullptr;
-        k_galerkin_ap_lds<T><<<(unsigned)((A.nrows + rpb - 1) / rpb), TPB, 0, s>>>(
-            A.nrows, rpb, A.ptr, A.col, A.v<T>(), P.ptr, P.col, P.v<T>(), AP.ptr, AP.col, AP.v<T>(), kind, (T)omega, m,
-            ain, out64, outT);
+        const size_t sm = acc_smem(gs, sizeof(T));
+        if (gs.wide)
+            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint16_t><<<row_blocks(A.nrows, GG), TPB, sm, s>>>(
+                                   A.nrows, gs.cap, A.ptr, A.col, A.v<T>(), P.ptr, P.v<T>(), AP.ptr, AP.v<T>(),
+                                   (const uint16_t*)gs.pos, gs.off, kind, (T)omega, m, ain, out64, outT)));
+        else
+            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint8_t><<<row_blocks(A.nrows, GG), TPB, sm, s>>>(
+                                   A.nrows, gs.cap, A.ptr, A.col, A.v<T>(), P.ptr, P.v<T>(), AP.ptr, AP.v<T>(),
+                                   (const uint8_t*)gs.pos, gs.off, kind, (T)omega, m, ain, out64, outT)));
         HIP_LAUNCH_CHECK();
         return true;
     }
@@ -343,10 +406,19 @@ bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, int rp
 }
 
 template <typename T>
-void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, int rpb, hipStream_t s) {
-    if (rpb > 0) {
-        k_galerkin_rap_lds<T><<<(unsigned)((R.nrows + rpb - 1) / rpb), TPB, 0, s>>>(
-            R.nrows, rpb, R.ptr, R.col, R.v<T>(), AP.ptr, AP.col, AP.v<T>(), Ac.ptr, Ac.col, Ac.v<T>());
+void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s) {
+    if (gs.g > 0) {
+        const size_t sm = acc_smem(gs, sizeof(T));
+        if (gs.wide)
+            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint16_t><<<row_blocks(R.nrows, GG), TPB, sm, s>>>(
+                                   R.nrows, gs.cap, R.ptr, R.col, R.v<T>(), AP.ptr, AP.v<T>(), Ac.ptr, Ac.v<T>(),
+                                   (const uint16_t*)gs.pos, gs.off, 0, (T)0, (T*)nullptr, nullptr, nullptr,
+                                   (T*)nullptr)));
+        else
+            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint8_t><<<row_blocks(R.nrows, GG), TPB, sm, s>>>(
+                                   R.nrows, gs.cap, R.ptr, R.col, R.v<T>(), AP.ptr, AP.v<T>(), Ac.ptr, Ac.v<T>(),
+                                   (const uint8_t*)gs.pos, gs.off, 0, (T)0, (T*)nullptr, nullptr, nullptr,
+                                   (T*)nullptr)));
         HIP_LAUNCH_CHECK();
         return;
     }
@@ -355,34 +427,13 @@ void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, int 
     HIP_LAUNCH_CHECK();
 }
 
-// Rows per staged block for the product L B (0: the caps cannot be met, use lane groups):
-// the largest power of two <= TPB such that every block stages at most GL_CAP_L entries of
-// L and GL_CAP_C entries of the referenced B rows.  Host arrays.
-int pick_galerkin_rpb(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr) {
-    std::vector<int64_t> work((size_t)nrows + 1, 0);
-    for (int32_t i = 0; i < nrows; ++i) {
-        int64_t w = 0;
-        for (int32_t k = Lptr[i]; k < Lptr[i + 1]; ++k) w += Bptr[Lcol[k] + 1] - Bptr[Lcol[k]];
-        work[(size_t)i + 1] = work[i] + w;
-    }
-    for (int rpb = TPB; rpb >= 1; rpb >>= 1) {
-        bool ok = true;
-        for (int64_t r0 = 0; r0 < nrows && ok; r0 += rpb) {
-            const int64_t r1 = r0 + rpb < nrows ? r0 + rpb : nrows;
-            if ((int64_t)Lptr[r1] - Lptr[r0] > GL_CAP_L || work[r1] - work[r0] > GL_CAP_C) ok = false;
-        }
-        if (ok) return rpb;
-    }
-    return 0;
-}
-
+template bool launch_galerkin_ap<double>(const Csr&, const Csr&, const Csr&, int, GalShape, int, double, double*,
+                                         const double*, hipStream_t);
+template bool launch_galerkin_ap<float>(const Csr&, const Csr&, const Csr&, int, GalShape, int, double, float*,
+                                        const double*, hipStream_t);
+template void launch_galerkin_rap<double>(const Csr&, const Csr&, const Csr&, int, GalShape, hipStream_t);
+template void launch_galerkin_rap<float>(const Csr&, const Csr&, const Csr&, int, GalShape, hipStream_t);
 template void launch_smoother_diag<double>(const Csr&, int, double, double*, hipStream_t);
 template void launch_smoother_diag<float>(const Csr&, int, double, float*, hipStream_t);
-template bool launch_galerkin_ap<double>(const Csr&, const Csr&, const Csr&, int, int, int, double, double*,
-                                         const double*, hipStream_t);
-template bool launch_galerkin_ap<float>(const Csr&, const Csr&, const Csr&, int, int, int, double, float*,
-                                        const double*, hipStream_t);
-template void launch_galerkin_rap<double>(const Csr&, const Csr&, const Csr&, int, int, hipStream_t);
-template void launch_galerkin_rap<float>(const Csr&, const Csr&, const Csr&, int, int, hipStream_t);
 
 }  // namespace amgmi

@@ -280,6 +280,10 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
     scan_exclusive<int32_t, int32_t>(in, out, n, s);
 }
 
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+    scan_exclusive<int64_t, int64_t>(in, out, n, s);
+}
+
 int32_t run_aggregate(const Csr& A, const uint8_t* strong, const int32_t* tpos, const uint8_t* state, int32_t* agg,
                       int* flags, int* h_flags, hipStream_t s) {
     const int n = A.nrows;

@@ -308,3 +308,29 @@ def test_lane_group_kernels_parity(monkeypatch):
     uo, io = o.solve(f)
     assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+
+
+GALERKIN_FORMS = ["pos", "pos:4", "pos:16", "pos:64", "pos16", "lanes"]
+
+
+@pytest.mark.parametrize("form", GALERKIN_FORMS)
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_galerkin_forms_parity(monkeypatch, form, smoother):
+    """Every Galerkin form (the position-map form at several lanes per row and with one-
+    and two-byte positions, and the lane-group kernels) gives the oracle's FP64 hierarchy
+    bit for bit after a partial rebuild, with the fused value ingest and smoother
+    diagonal, on 7-point and 27-point patterns."""
+    monkeypatch.setenv("AMGMI_GALERKIN", form)
+    print(f"form {form} smoother {smoother}", flush=True)
+    p, c, v0 = two_fluid_7pt(32, front_c1(0))
+    _, _, v1 = two_fluid_7pt(32, front_c1(5))
+    g, o = both(p, c, v0, smoother=smoother)
+    g.rebuild(T(v1))
+    o.rebuild(v1, 0)
+    assert bitwise_levels(g, o) is None
+    p, c, v0 = lognormal_27pt(12, 0)
+    _, _, v1 = lognormal_27pt(12, 3)
+    g, o = both(p, c, v0, smoother=smoother, eps_strong=0.02, coarse_enough=16)
+    g.rebuild(T(v1))
+    o.rebuild(v1, 0)
+    assert bitwise_levels(g, o) is None
