@@ -161,6 +161,7 @@ typedef enum {
     AMG_K_PROLONG = 11,      /* u_l += P_l u_{l+1} */
     AMG_K_COARSE_GEMV = 12,  /* u_L = A_L^{-1} f_L */
     AMG_K_CAST = 13,         /* FP64 <-> FP32 conversions of the mixed-precision form */
+    AMG_K_TAIL = 14,         /* restriction into the coarse tail and Algorithm 2 on all its levels */
     AMG_K_COUNT = 16
 } amg_kernel_class;
 

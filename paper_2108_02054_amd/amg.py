@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libamgmi.so")
+LIB_PATH = os.environ.get("AMGMI_LIB") or os.path.join(HERE, "libamgmi.so")
 
 AMG_OK = 0
 STATUS = {0: "AMG_OK", -1: "AMG_ERR_ARG", -2: "AMG_ERR_HIP", -3: "AMG_ERR_OOM", -4: "AMG_ERR_PATTERN",
@@ -27,7 +27,7 @@ EXPORTED = [
     "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read",
 ]
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
-                  "cg_init", "smooth0_res", "jacobi", "restrict", "prolong", "coarse_gemv", "cast"]
+                  "cg_init", "smooth0_res", "jacobi", "restrict", "prolong", "coarse_gemv", "cast", "tail"]
 
 
 class AmgError(RuntimeError):

@@ -224,22 +224,34 @@ std::vector<T> to_host(const T* d, size_t n, hipStream_t s) {
     return h;
 }
 
-// The position map of C = L B for the shape gs (allocated with the hierarchy).
-void make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, GalShape& gs, hipStream_t s) {
-    if (gs.g == 0) return;
-    gs.off = halloc<int64_t>(c, (size_t)L.nrows + 1);
-    gs.terms = count_galerkin_terms(L, B, gs.off, s);
-    const size_t n = (size_t)std::max<int64_t>(gs.terms, 1);
-    gs.pos = gs.wide ? (void*)halloc<uint16_t>(c, n) : (void*)halloc<uint8_t>(c, n);
-    build_galerkin_posmap(L, B, C, gs, s);
+void release_posmap(amg_ctx* c, GalShape& gs) {
+    for (void* p : {gs.pos, (void*)gs.off, (void*)gs.bst, (void*)gs.tof, (void*)gs.dpos}) release(c, p);
+    gs = GalShape{};
 }
 
 void release_posmaps(amg_ctx* c, Level& L) {
-    for (GalShape* gs : {&L.galAP, &L.galRAP}) {
-        release(c, gs->pos);
-        release(c, gs->off);
-        *gs = GalShape{};
+    release_posmap(c, L.galAP);
+    release_posmap(c, L.galRAP);
+}
+
+// The position map of C = L B for the shape gs (allocated with the hierarchy); with
+// diag, also the diagonal index of every row of L (for the smoother).  Rows with more
+// terms than the form takes leave the product to the lane-group kernels.
+void make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, GalShape& gs, bool diag, hipStream_t s) {
+    if (gs.g == 0) return;
+    gs.off = halloc<int64_t>(c, (size_t)L.nrows + 1);
+    int64_t max_row = 0;
+    gs.terms = count_galerkin_terms(L, B, gs.off, &max_row, s);
+    if (!galerkin_terms_fit(max_row)) {
+        release_posmap(c, gs);
+        return;
     }
+    const size_t n = (size_t)std::max<int64_t>(gs.terms, 1);
+    gs.pos = gs.wide ? (void*)halloc<uint16_t>(c, n) : (void*)halloc<uint8_t>(c, n);
+    gs.bst = halloc<int32_t>(c, (size_t)std::max<int64_t>(L.nnz, 1));
+    gs.tof = halloc<uint16_t>(c, (size_t)std::max<int64_t>(L.nnz, 1));
+    if (diag) gs.dpos = halloc<int32_t>(c, (size_t)L.nrows + 1);
+    build_galerkin_posmap(L, B, C, gs, s);
 }
 
 // Launch shapes of a level's row kernels and Galerkin kernels (Ac: the next level's
@@ -262,8 +274,29 @@ void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
         L.galAP = lanes ? GalShape{} : pick_galerkin_shape(Ap.data(), Acl.data(), L.A.nrows, Pp.data(), APp.data(), f.g);
         L.galRAP = lanes ? GalShape{} : pick_galerkin_shape(Rp.data(), Rc.data(), L.R.nrows, APp.data(), Cp.data(), f.g);
         if (f.wide) L.galAP.wide = L.galRAP.wide = 1;
-        make_posmap(c, L.A, L.P, L.AP, L.galAP, s);
-        make_posmap(c, L.R, L.AP, *Ac, L.galRAP, s);
+        make_posmap(c, L.A, L.P, L.AP, L.galAP, true, s);
+        make_posmap(c, L.R, L.AP, *Ac, L.galRAP, false, s);
+    }
+}
+
+// The fused coarse tail starts at the first level t >= 1 from which every level down to
+// the coarsest fits the one-workgroup kernel: their rows together (LDS), their stored
+// entries together with the restriction into level t (a single CU reads them all, so
+// only the smallest levels gain from the fusion) and the level count.  0: no tail.
+void configure_tail(amg_ctx* c) {
+    const int nlev = (int)c->lv.size();
+    c->tail = 0;
+    if (nlev < 2 || std::getenv("AMGMI_NO_TAIL") != nullptr) return;
+    int64_t max_nnz = TAIL_MAX_NNZ;
+    if (const char* e = std::getenv("AMGMI_TAIL_NNZ")) max_nnz = std::atoll(e);
+    int64_t rows = 0, nnz = 0;
+    for (int t = nlev - 1; t >= 1; --t) {
+        const Level& L = c->lv[(size_t)t];
+        rows += L.A.nrows;
+        nnz += L.A.nnz + L.P.nnz + L.R.nnz;
+        const int64_t in = c->lv[(size_t)t - 1].R.nnz;
+        if (rows > TAIL_MAX_ROWS || nnz + in > max_nnz || nlev - t > TAIL_MAX_LEVELS) break;
+        c->tail = t;
     }
 }
 
@@ -533,6 +566,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
         alloc_vectors<double>(c);
     }
     alloc_cg(c);
+    configure_tail(c);
     HIP_CHECK(hipStreamSynchronize(s));
     ph[6] = ms_since(t_all);
     std::memcpy(c->phase_ms, ph, sizeof(ph));
@@ -592,6 +626,7 @@ void repattern(amg_ctx* c) {
     set_groups(c, c->lv.back(), nullptr, s);
     release(c, c->rs.part);
     alloc_reduction(c);
+    configure_tail(c);
     // The strength flags were per entry of the old patterns; the aggregates stay (they
     // still define the kept transfer operators).
     for (Level& L : c->lv) {
@@ -654,13 +689,51 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
         if (p.npre > 1) launch_residual<T>(L.A, f, cur, r, s);
     }
     const Level& C = c->lv[(size_t)l + 1];
-    // the next level's first sweep from zero is formed by the restriction
-    const bool c_smooths = (l + 2 < nlev) && p.npre > 0;
-    {
-        Trace tr(c, AMG_K_RESTRICT, l);
-        launch_spmv<T>(L.R, rres, (T*)C.f, c_smooths ? C.mv<T>() : nullptr, c_smooths ? (T*)C.u : nullptr, s);
+    const T* uc;
+    if (c->tail > 0 && l + 1 == c->tail) {
+        // restriction and levels tail .. L in one workgroup
+        TailArgs<T> ta;
+        ta.nlev = nlev - c->tail;
+        ta.npre = p.npre;
+        ta.npost = p.npost;
+        ta.rin_ptr = L.R.ptr;
+        ta.rin_col = L.R.col;
+        ta.rin_val = L.R.v<T>();
+        ta.rin = rres;
+        ta.uout = (T*)C.u;
+        ta.cinv = c->cinv;
+        int soff = 0;
+        for (int k = 0; k < ta.nlev; ++k) {
+            const Level& Lk = c->lv[(size_t)(c->tail + k)];
+            TailLevel<T>& tk = ta.lv[k];
+            tk.n = Lk.A.nrows;
+            tk.soff = soff;
+            soff += 3 * tk.n;
+            tk.Aptr = Lk.A.ptr;
+            tk.Acol = Lk.A.col;
+            tk.Aval = Lk.A.v<T>();
+            tk.m = Lk.mv<T>();
+            if (k + 1 < ta.nlev) {
+                tk.Rptr = Lk.R.ptr;
+                tk.Rcol = Lk.R.col;
+                tk.Rval = Lk.R.v<T>();
+                tk.Pptr = Lk.P.ptr;
+                tk.Pcol = Lk.P.col;
+                tk.Pval = Lk.P.v<T>();
+            }
+        }
+        Trace tr(c, AMG_K_TAIL, l + 1);
+        launch_vcycle_tail<T>(ta, s);
+        uc = (const T*)C.u;
+    } else {
+        // the next level's first sweep from zero is formed by the restriction
+        const bool c_smooths = (l + 2 < nlev) && p.npre > 0;
+        {
+            Trace tr(c, AMG_K_RESTRICT, l);
+            launch_spmv<T>(L.R, rres, (T*)C.f, c_smooths ? C.mv<T>() : nullptr, c_smooths ? (T*)C.u : nullptr, s);
+        }
+        uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, c_smooths);
     }
-    const T* uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, c_smooths);
     {
         Trace tr(c, AMG_K_PROLONG, l);
         launch_prolong_add<T>(L.P, uc, cur, s);

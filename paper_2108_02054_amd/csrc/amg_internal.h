@@ -69,9 +69,14 @@ inline float* Csr::v<float>() const { return val32; }
 struct GalShape {
     int g = 0;
     int cap = 0;
+    int epl = 2;                // L entries per lane per chunk
     int wide = 0;               // 1: two-byte positions
-    void* pos = nullptr;        // position map (device, owned by the hierarchy)
-    int64_t* off = nullptr;     // nrows + 1 term offsets (device, owned by the hierarchy)
+    // device arrays owned by the hierarchy
+    void* pos = nullptr;        // position map, one entry per term
+    int64_t* off = nullptr;     // nrows + 1 term offsets
+    int32_t* bst = nullptr;     // per L entry: start of its B row
+    uint16_t* tof = nullptr;    // per L entry: its first term's offset within the row
+    int32_t* dpos = nullptr;    // per L row: index of its diagonal entry (C = A P only)
     int64_t terms = 0;
 };
 
@@ -150,6 +155,42 @@ template <typename T>
 void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s);
+// The coarse tail of the V-cycle: the restriction into level t, then Algorithm 2 on levels
+// t .. L (the last one solved with the dense inverse) in one workgroup, writing u_t.
+constexpr int TAIL_MAX_LEVELS = 6;
+constexpr int TAIL_MAX_ROWS = 2048;        // rows of all tail levels together
+constexpr int64_t TAIL_MAX_NNZ = 16384;    // stored entries the tail reads (A, P, R and R_{t-1})
+constexpr size_t TAIL_SMEM_MAX = 3 * TAIL_MAX_ROWS * sizeof(double);
+template <typename T>
+struct TailLevel {
+    int n = 0;
+    int soff = 0;               // LDS offset (elements) of the level's f, u, w vectors
+    const int* Aptr = nullptr;
+    const int* Acol = nullptr;
+    const T* Aval = nullptr;
+    const T* m = nullptr;
+    const int* Rptr = nullptr;  // R_l and P_l: empty on the coarsest tail level
+    const int* Rcol = nullptr;
+    const T* Rval = nullptr;
+    const int* Pptr = nullptr;
+    const int* Pcol = nullptr;
+    const T* Pval = nullptr;
+};
+template <typename T>
+struct TailArgs {
+    int nlev = 0;
+    int npre = 1, npost = 1;
+    const int* rin_ptr = nullptr;  // R_{t-1} and r_{t-1}
+    const int* rin_col = nullptr;
+    const T* rin_val = nullptr;
+    const T* rin = nullptr;
+    T* uout = nullptr;             // u_t
+    const double* cinv = nullptr;  // dense inverse of the coarsest operator
+    TailLevel<T> lv[TAIL_MAX_LEVELS];
+};
+template <typename T>
+void launch_vcycle_tail(const TailArgs<T>& a, hipStream_t s);
+
 template <typename T>
 void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s);
 void launch_cast_d2f(int64_t n, const double* a, float* b, hipStream_t s);
@@ -181,9 +222,11 @@ template <typename T>
 void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s);
 GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr,
                              const int32_t* Cptr, int gforce);
-// Fills gs.off (nrows + 1) and gs.pos (gs.terms entries, allocated by the caller between
-// the two calls): count_terms writes the offsets and returns the number of terms.
-int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, hipStream_t s);
+// count_galerkin_terms writes the term offsets gs.off (nrows + 1) and returns the number
+// of terms (and the most in one row); build_galerkin_posmap fills gs.pos, gs.bst, gs.tof
+// and, if allocated, gs.dpos (all allocated by the caller in between).
+int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, int64_t* max_row, hipStream_t s);
+bool galerkin_terms_fit(int64_t max_row);
 void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalShape& gs, hipStream_t s);
 
 // ------------------------------------------------------------------ setup
@@ -238,6 +281,7 @@ struct amg_ctx {
     double* outer_val = nullptr;
     double* outer_own = nullptr;
     int32_t nL = 0;
+    int tail = 0;                 // first level of the fused coarse tail (0: none)
     double* cinv = nullptr;       // dense inverse of the coarsest operator (FP64)
     // CG state
     double *x = nullptr, *r = nullptr, *z = nullptr, *zold = nullptr, *pa = nullptr, *pb = nullptr,

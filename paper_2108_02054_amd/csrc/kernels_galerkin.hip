@@ -129,127 +129,129 @@ __global__ __launch_bounds__(TPB) void k_galerkin_rap(int nc, const int* __restr
 //
 // The terms of row i of C = L B are l_t * b_e for the L entries t of row i in order and,
 // for each, the entries e of B row Lcol[t] in order; this is the order in which a
-// row-by-row product adds them.  The column of each term and so its position in the
-// (cached, sorted) C row depend on the patterns alone: setup stores these positions once
-// (the position map), and each numeric product only multiplies, and adds each term into
-// its C entry, kept in LDS.  A group of G lanes per row of C walks the L entries in order;
-// for entry t the lanes take the terms of B row Lcol[t], G at a time.  Positions within one
-// B row are distinct, and the LDS operations of a wavefront complete in program order, so
-// every entry of C receives its terms in the row-by-row order.  Each lane holds two L
-// entries of a chunk (2G entries per chunk), and the terms of WF_AHEAD entries are loaded
-// before they are added.  For C = A P the group also forms the smoother diagonal (the
-// row's squares added in column order), and can take A's values from a new FP64 array,
-// storing the hierarchy's copies on the way.
+// row-by-row product adds them.  Which B entries a row's terms read, and the position of
+// each term's column in the (cached, sorted) C row, depend on the patterns alone, so setup
+// stores them once: for every L entry its B row start and the offset of its first term
+// within the row's terms, and for every term its position in the C row (the position
+// map).  Each numeric product then only multiplies, and adds each term into its C entry,
+// kept in LDS.  A group of G lanes per row of C loads a chunk of the row's L entries
+// (EPL per lane) into LDS, then walks them in order, WF_AHEAD at a time: the lanes load
+// those entries' terms (G per entry per pass) together, then add them entry by entry.
+// Positions within one B row are distinct, and the LDS operations of a wavefront complete
+// in program order, so every entry of C receives its terms in the row-by-row order.  For
+// C = A P the group also forms the smoother diagonal (the row's squares added in column
+// order), and can take A's values from a new FP64 array, storing the hierarchy's copies
+// on the way.
 
-constexpr int WF_AHEAD = 4;            // L entries whose terms are loaded together
+constexpr int WF_AHEAD = 8;            // L entries whose terms are loaded together
 constexpr int WF_CAP_MAX = 4096;       // longest C row the form takes
+constexpr int64_t WF_TERMS_MAX = 65535;  // most terms in one C row (two-byte term offsets)
 constexpr size_t WF_SMEM_MAX = 65536;  // LDS per block
 
-template <int G>
-__device__ __forceinline__ int group_exscan(int v, int g, int& total) {
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) {
-        const int y = __shfl_up(x, o, G);
-        if (g >= o) x += y;
-    }
-    total = __shfl(x, G - 1, G);
-    return x - v;
+// One staged L entry: its B row start, first term (within the row) and term count.
+struct alignas(16) WfEnt {
+    int bs, to, len, pad;
+};
+
+template <typename T, int G, int EPL>
+constexpr size_t wf_group_smem(int cap) {
+    return (size_t)cap * sizeof(T) + (size_t)EPL * G * (sizeof(T) + sizeof(WfEnt));
 }
 
-template <typename T, int G, typename PT>
+template <typename T, int G, typename PT, int EPL>
 __global__ __launch_bounds__(TPB) void k_galerkin_pos(
-    int nrows, int cap, const int* __restrict__ Lptr, const int* __restrict__ Lcol, const T* __restrict__ Lval,
-    const int* __restrict__ Bptr, const T* __restrict__ Bval, const int* __restrict__ Cptr, T* __restrict__ Cval,
-    const PT* __restrict__ pos, const int64_t* __restrict__ poff, int kind, T omega, T* __restrict__ m,
-    const double* __restrict__ lin, double* __restrict__ lout64, T* __restrict__ loutT) {
+    int nrows, int cap, const int* __restrict__ Lptr, const T* __restrict__ Lval, const int* __restrict__ Lbst,
+    const uint16_t* __restrict__ Ltof, const T* __restrict__ Bval, const int* __restrict__ Cptr,
+    T* __restrict__ Cval, const PT* __restrict__ pos, const int64_t* __restrict__ poff,
+    const int* __restrict__ dpos, int kind, T omega, T* __restrict__ m, const double* __restrict__ lin,
+    double* __restrict__ lout64, T* __restrict__ loutT) {
     extern __shared__ __align__(16) unsigned char wf_smem[];
+    constexpr int NE = EPL * G;  // L entries per chunk
     const int g = threadIdx.x & (G - 1);
-    T* sacc = reinterpret_cast<T*>(wf_smem) + (size_t)(threadIdx.x / G) * cap;
+    const int gi = threadIdx.x / G;
+    unsigned char* gbase = wf_smem + (size_t)gi * wf_group_smem<T, G, EPL>(cap);
+    T* sacc = reinterpret_cast<T*>(gbase);
+    T* elv = reinterpret_cast<T*>(gbase + (size_t)cap * sizeof(T));
+    WfEnt* ent = reinterpret_cast<WfEnt*>(gbase + (size_t)cap * sizeof(T) + (size_t)NE * sizeof(T));
     const int row = (xcd_block() * TPB + (int)threadIdx.x) / G;
     if (row >= nrows) return;  // groups leave whole: G divides the wavefront
     const int sb = Cptr[row];
     const int len = min(Cptr[row + 1] - sb, cap);  // the host keeps every row within cap
+    const int lb = Lptr[row], le = Lptr[row + 1];
+    const int64_t p0 = poff[row];
+    const int nterm = (int)(poff[row + 1] - p0);
+    const int dp = m != nullptr ? dpos[row] : -1;
+    const PT* prow = pos + p0;
     for (int q = g; q < len; q += G) sacc[q] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     T d = 0, ss = 0;
-    const int le = Lptr[row + 1];
-    const PT* prow = pos + poff[row];
-    int carry = 0;  // terms of the row's earlier chunks
-    for (int c0 = Lptr[row]; c0 < le; c0 += 2 * G) {
-        // lane g holds L entries c0 + g (h = 0) and c0 + G + g (h = 1)
-        int bst[2], blen[2], jj[2], toff[2];
-        T lv[2];
+    for (int c0 = lb; c0 < le; c0 += NE) {
+        const int nt = min(NE, le - c0);  // uniform across the group
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int t = c0 + h * G + g;
-            bst[h] = 0;
-            blen[h] = 0;
-            jj[h] = -1;
-            lv[h] = 0;
-            if (t < le) {
-                const int j = Lcol[t];
-                jj[h] = j;
+        for (int e = 0; e < EPL; ++e) {
+            const int u = e * G + g;
+            const int t = c0 + u;
+            if (u < nt) {
+                T lv;
                 if (lin != nullptr) {
                     const double x = lin[t];
                     if (lout64 != nullptr) lout64[t] = x;
                     if (loutT != nullptr) loutT[t] = (T)x;
-                    lv[h] = (T)x;
+                    lv = (T)x;
                 } else {
-                    lv[h] = Lval[t];
+                    lv = Lval[t];
                 }
-                bst[h] = Bptr[j];
-                blen[h] = Bptr[j + 1] - bst[h];
+                const int to = Ltof[t];
+                const int tn = t + 1 < le ? (int)Ltof[t + 1] : nterm;
+                elv[u] = lv;
+                WfEnt w;
+                w.bs = Lbst[t];
+                w.to = to;
+                w.len = tn - to;
+                w.pad = 0;
+                ent[u] = w;
             }
         }
-        int tot0, tot1;
-        toff[0] = carry + group_exscan<G>(blen[0], g, tot0);
-        toff[1] = carry + tot0 + group_exscan<G>(blen[1], g, tot1);
-        carry += tot0 + tot1;
-        const int nt = min(2 * G, le - c0);  // uniform across the group
-        if (m != nullptr) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (m != nullptr)
+            for (int u = 0; u < nt; ++u) {  // the row's squares in column order
+                const T a = elv[u];
+                if (c0 + u == dp) d = a;
+                ss = ss + a * a;
+            }
+        for (int u0 = 0; u0 < nt; u0 += WF_AHEAD) {
+            int up[WF_AHEAD], ul[WF_AHEAD];
+            T bv[WF_AHEAD];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                for (int q = 0; q < G && h * G + q < nt; ++q) {  // the row's squares in column order
-                    const T a = __shfl(lv[h], q, G);
-                    if (__shfl(jj[h], q, G) == row) d = a;
-                    ss = ss + a * a;
+            for (int i = 0; i < WF_AHEAD; ++i) {  // first G terms of each entry, in flight together
+                const int u = u0 + i < nt ? u0 + i : nt - 1;
+                const WfEnt w = ent[u];
+                ul[i] = u0 + i < nt ? w.len : 0;
+                if (g < ul[i]) {
+                    up[i] = (int)prow[w.to + g];
+                    bv[i] = Bval[w.bs + g];
                 }
-        }
+            }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            for (int u0 = 0; u0 < G && h * G + u0 < nt; u0 += WF_AHEAD) {
-                int ub[WF_AHEAD], ul[WF_AHEAD], uo[WF_AHEAD], up[WF_AHEAD];
-                T uv[WF_AHEAD], bv[WF_AHEAD];
-#pragma unroll
-                for (int i = 0; i < WF_AHEAD; ++i) {  // first G terms of each entry, in flight together
-                    const int u = u0 + i < G ? u0 + i : G - 1;
-                    ub[i] = __shfl(bst[h], u, G);
-                    ul[i] = (u0 + i < G && h * G + u0 + i < nt) ? __shfl(blen[h], u, G) : 0;
-                    uo[i] = __shfl(toff[h], u, G);
-                    uv[i] = __shfl(lv[h], u, G);
-                    if (g < ul[i]) {
-                        up[i] = (int)prow[uo[i] + g];
-                        bv[i] = Bval[ub[i] + g];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < WF_AHEAD; ++i) {
-                    if (g < ul[i] && up[i] < len) sacc[up[i]] = sacc[up[i]] + uv[i] * bv[i];
-                    for (int k = g + G; k < ul[i]; k += G) {  // rows of B longer than G
-                        const int p = (int)prow[uo[i] + k];
-                        const T b = Bval[ub[i] + k];
-                        if (p < len) sacc[p] = sacc[p] + uv[i] * b;
+            for (int i = 0; i < WF_AHEAD; ++i) {
+                if (ul[i] == 0) continue;  // uniform across the group
+                const T lv = elv[u0 + i];
+                if (g < ul[i] && up[i] < len) sacc[up[i]] = sacc[up[i]] + lv * bv[i];
+                if (ul[i] > G) {  // rows of B longer than G
+                    const WfEnt w = ent[u0 + i];
+                    for (int k = g + G; k < ul[i]; k += G) {
+                        const int p = (int)prow[w.to + k];
+                        const T b = Bval[w.bs + k];
+                        if (p < len) sacc[p] = sacc[p] + lv * b;
                     }
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int q = g; q < len; q += G) Cval[sb + q] = sacc[q];
     if (m != nullptr && g == 0) m[row] = (kind == 1) ? d / ss : omega / d;
 }
@@ -264,6 +266,37 @@ __global__ __launch_bounds__(TPB) void k_count_terms(int nrows, const int* __res
     if (i < nrows)
         for (int t = Lptr[i]; t < Lptr[i + 1]; ++t) c += Bptr[Lcol[t] + 1] - Bptr[Lcol[t]];
     cnt[i] = c;  // cnt[nrows] = 0, so the exclusive scan ends with the total
+}
+
+// Per L entry: its B row start and the offset of its first term within its row's terms.
+__global__ __launch_bounds__(TPB) void k_entry_meta(int nrows, const int* __restrict__ Lptr,
+                                                    const int* __restrict__ Lcol, const int* __restrict__ Bptr,
+                                                    int* __restrict__ bst, uint16_t* __restrict__ tof) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= nrows) return;
+    int o = 0;
+    for (int t = Lptr[i]; t < Lptr[i + 1]; ++t) {
+        const int b = Bptr[Lcol[t]];
+        bst[t] = b;
+        tof[t] = (uint16_t)o;
+        o += Bptr[Lcol[t] + 1] - b;
+    }
+}
+
+// Index of each row's diagonal entry (-1 if absent).
+__global__ __launch_bounds__(TPB) void k_diag_index(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                    int* __restrict__ dpos) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    int lo = ptr[i], hi = ptr[i + 1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    dpos[i] = (lo < ptr[i + 1] && col[lo] == i) ? lo : -1;
 }
 
 // The position map: 8 lanes per row of C, the L entries in order, the B row's terms
@@ -302,19 +335,34 @@ __global__ __launch_bounds__(TPB) void k_posmap(int nrows, const int* __restrict
     }
 }
 
-int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, hipStream_t s) {
+int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, int64_t* max_row, hipStream_t s) {
     int64_t* cnt = dnew<int64_t>((size_t)L.nrows + 1, s);
     k_count_terms<<<row_blocks((int64_t)L.nrows + 1, 1), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, cnt);
     HIP_LAUNCH_CHECK();
+    std::vector<int64_t> h((size_t)L.nrows + 1);
+    HIP_CHECK(hipMemcpyAsync(h.data(), cnt, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     exclusive_scan_i64(cnt, off, (int64_t)L.nrows + 1, s);
     dfree(cnt, s);
-    int64_t total = 0;
-    HIP_CHECK(hipMemcpyAsync(&total, off + L.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
+    int64_t total = 0, mx = 0;
+    for (int64_t v : h) {
+        total += v;
+        mx = std::max(mx, v);
+    }
+    *max_row = mx;
     return total;
 }
 
+bool galerkin_terms_fit(int64_t max_row) { return max_row <= WF_TERMS_MAX; }
+
 void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalShape& gs, hipStream_t s) {
+    if (L.nrows == 0) return;
+    k_entry_meta<<<row_blocks(L.nrows, 1), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, gs.bst, gs.tof);
+    HIP_LAUNCH_CHECK();
+    if (gs.dpos != nullptr) {
+        k_diag_index<<<row_blocks(L.nrows, 1), TPB, 0, s>>>(L.nrows, L.ptr, L.col, gs.dpos);
+        HIP_LAUNCH_CHECK();
+    }
     if (gs.terms == 0) return;
     if (gs.wide)
         k_posmap<uint16_t><<<row_blocks(L.nrows, 8), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, B.col, C.ptr, C.col,
@@ -339,8 +387,9 @@ void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalSh
 
 // Launch shape of the position-map form for C = L B (host arrays): cap = the longest C
 // row rounded up to a multiple of 8, and G = the power of two in [4, 64] nearest above the
-// mean referenced B row length (so that most B rows take one pass of the group), raised
-// until a block's LDS (TPB / G rows of cap FP64 accumulators) is within WF_SMEM_MAX.
+// mean referenced B row length (so that most B rows take one pass of the group), or at
+// least an eighth of the mean L row length, raised until a block's LDS (TPB / G rows of
+// cap FP64 accumulators and the staged L entries) is within WF_SMEM_MAX.
 // {0, ...}: the rows are too long for the form (lane-group kernels).  gforce forces G
 // where the LDS allows.  The position map itself is built by the caller.
 GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr,
@@ -355,20 +404,50 @@ GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t n
     }
     const double mean_b = refs > 0 ? tot / refs : 1.0;
     const int cap = std::max(8, (maxlen + 7) / 8 * 8);
-    auto smem = [&](int G) { return (size_t)(TPB / G) * (size_t)cap * sizeof(double); };
+    const double mean_l = nrows > 0 ? refs / (double)nrows : 1.0;
     int G = 4;
     while (G < 64 && G < mean_b) G <<= 1;
+    while (G < 64 && 8 * G <= mean_l) G <<= 1;  // long L rows: wider groups, fewer chunks
     if (gforce == 4 || gforce == 8 || gforce == 16 || gforce == 32 || gforce == 64) G = gforce;
+    const int epl = mean_l > 2.0 * G ? 4 : 2;
+    auto smem = [&](int g) {
+        return (size_t)(TPB / g) * ((size_t)cap * sizeof(double) + (size_t)epl * g * (sizeof(double) + sizeof(WfEnt)));
+    };
     while (G < 64 && smem(G) > WF_SMEM_MAX) G <<= 1;
     if (smem(G) > WF_SMEM_MAX) return {};
     GalShape gs;
     gs.g = G;
     gs.cap = cap;
+    gs.epl = epl;
     gs.wide = maxlen > 255 ? 1 : 0;
     return gs;
 }
 
-static size_t acc_smem(const GalShape& gs, size_t tsize) { return (size_t)(TPB / gs.g) * (size_t)gs.cap * tsize; }
+template <typename T>
+static size_t acc_smem(const GalShape& gs) {
+    return (size_t)(TPB / gs.g) * ((size_t)gs.cap * sizeof(T) + (size_t)gs.epl * gs.g * (sizeof(T) + sizeof(WfEnt)));
+}
+
+// Launches the position-map kernel for one product with the shape's template arguments.
+template <typename T>
+static void launch_pos(const Csr& L, const Csr& B, const Csr& C, const GalShape& gs, int kind, double omega, T* m,
+                       const double* lin, double* lout64, T* loutT, hipStream_t s) {
+    const size_t sm = acc_smem<T>(gs);
+    const int* dp = m != nullptr ? gs.dpos : nullptr;
+#define AMG_POS_LAUNCH(PT, EPL)                                                                           \
+    AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, PT, EPL><<<row_blocks(L.nrows, GG), TPB, sm, s>>>(           \
+                           L.nrows, gs.cap, L.ptr, L.v<T>(), gs.bst, gs.tof, B.v<T>(), C.ptr, C.v<T>(),     \
+                           (const PT*)gs.pos, gs.off, dp, kind, (T)omega, m, lin, lout64, loutT)))
+    if (gs.wide) {
+        if (gs.epl == 4) AMG_POS_LAUNCH(uint16_t, 4);
+        else AMG_POS_LAUNCH(uint16_t, 2);
+    } else {
+        if (gs.epl == 4) AMG_POS_LAUNCH(uint8_t, 4);
+        else AMG_POS_LAUNCH(uint8_t, 2);
+    }
+#undef AMG_POS_LAUNCH
+    HIP_LAUNCH_CHECK();
+}
 
 template <typename T>
 void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_t s) {
@@ -386,16 +465,7 @@ bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalSha
         double* out64 = (ain != nullptr && ain != A.val) ? A.val : nullptr;
         T* outT = nullptr;
         if constexpr (!std::is_same<T, double>::value) outT = ain != nullptr ? A.v<T>() : nullptr;
-        const size_t sm = acc_smem(gs, sizeof(T));
-        if (gs.wide)
-            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint16_t><<<row_blocks(A.nrows, GG), TPB, sm, s>>>(
-                                   A.nrows, gs.cap, A.ptr, A.col, A.v<T>(), P.ptr, P.v<T>(), AP.ptr, AP.v<T>(),
-                                   (const uint16_t*)gs.pos, gs.off, kind, (T)omega, m, ain, out64, outT)));
-        else
-            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint8_t><<<row_blocks(A.nrows, GG), TPB, sm, s>>>(
-                                   A.nrows, gs.cap, A.ptr, A.col, A.v<T>(), P.ptr, P.v<T>(), AP.ptr, AP.v<T>(),
-                                   (const uint8_t*)gs.pos, gs.off, kind, (T)omega, m, ain, out64, outT)));
-        HIP_LAUNCH_CHECK();
+        launch_pos<T>(A, P, AP, gs, kind, omega, m, ain, out64, outT, s);
         return true;
     }
     if (ain != nullptr) return false;  // the caller ingests the values first, then calls again
@@ -408,18 +478,7 @@ bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalSha
 template <typename T>
 void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s) {
     if (gs.g > 0) {
-        const size_t sm = acc_smem(gs, sizeof(T));
-        if (gs.wide)
-            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint16_t><<<row_blocks(R.nrows, GG), TPB, sm, s>>>(
-                                   R.nrows, gs.cap, R.ptr, R.col, R.v<T>(), AP.ptr, AP.v<T>(), Ac.ptr, Ac.v<T>(),
-                                   (const uint16_t*)gs.pos, gs.off, 0, (T)0, (T*)nullptr, nullptr, nullptr,
-                                   (T*)nullptr)));
-        else
-            AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, uint8_t><<<row_blocks(R.nrows, GG), TPB, sm, s>>>(
-                                   R.nrows, gs.cap, R.ptr, R.col, R.v<T>(), AP.ptr, AP.v<T>(), Ac.ptr, Ac.v<T>(),
-                                   (const uint8_t*)gs.pos, gs.off, 0, (T)0, (T*)nullptr, nullptr, nullptr,
-                                   (T*)nullptr)));
-        HIP_LAUNCH_CHECK();
+        launch_pos<T>(R, AP, Ac, gs, 0, 0.0, (T*)nullptr, nullptr, nullptr, (T*)nullptr, s);
         return;
     }
     AMG_WITH_G(g, k_galerkin_rap<G, T><<<row_blocks(R.nrows, G), TPB, 0, s>>>(

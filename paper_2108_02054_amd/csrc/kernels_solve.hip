@@ -371,13 +371,151 @@ void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ coarse tail
+//
+// The last levels of the V-cycle (Algorithm 2 from the level reached by a restriction down
+// to the direct solve and back up) are small, so one workgroup runs them all, with every
+// vector of those levels in LDS and __syncthreads() between the steps.  This replaces a
+// dozen launches, each of which would occupy a few CUs for a few microseconds, by one.
+// Rows: TAIL_G lanes each, adding their products and combining them with a butterfly.
+
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_G = 8;
+
+template <typename T>
+__device__ __forceinline__ T tail_row(const int* __restrict__ ptr, const int* __restrict__ col,
+                                      const T* __restrict__ val, const T* x, int i, int g) {
+    constexpr int U = 8;  // entries per lane loaded together
+    const int b = ptr[i], e = ptr[i + 1];
+    T s = 0;
+    for (int k0 = b + g; k0 < e; k0 += U * TAIL_G) {
+        int cc[U];
+        T vv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = k0 + j * TAIL_G;
+            if (k < e) {
+                cc[j] = col[k];
+                vv[j] = val[k];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (k0 + j * TAIL_G < e) s += vv[j] * x[cc[j]];
+    }
+    return group_sum<TAIL_G, T>(s);
+}
+
+// One smoothing sweep u <- u + m (f - A u) on a tail level (through w).
+template <typename T>
+__device__ __forceinline__ void tail_sweep(const TailLevel<T>& L, const T* f, T* u, T* w, int r0, int g) {
+    constexpr int RS = TAIL_THREADS / TAIL_G;
+    for (int i = r0; i < L.n; i += RS) {
+        const T au = tail_row<T>(L.Aptr, L.Acol, L.Aval, u, i, g);
+        if (g == 0) w[i] = u[i] + L.m[i] * (f[i] - au);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L.n; i += TAIL_THREADS) u[i] = w[i];
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(TAIL_THREADS) void k_vcycle_tail(TailArgs<T> a) {
+    extern __shared__ __align__(16) unsigned char tail_smem[];
+    T* sm = reinterpret_cast<T*>(tail_smem);  // level l: f, u, w at sm + a.lv[l].soff
+    const int g = threadIdx.x & (TAIL_G - 1);
+    const int r0 = threadIdx.x / TAIL_G;
+    constexpr int RS = TAIL_THREADS / TAIL_G;  // rows per pass
+    // restriction into the first tail level
+    {
+        T* f0 = sm + a.lv[0].soff;
+        for (int i = r0; i < a.lv[0].n; i += RS) {
+            const T v = tail_row<T>(a.rin_ptr, a.rin_col, a.rin_val, a.rin, i, g);
+            if (g == 0) f0[i] = v;
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < a.nlev; ++l) {
+        const TailLevel<T>& L = a.lv[l];
+        const int n = L.n;
+        T* f = sm + L.soff;
+        T* u = f + n;
+        T* w = u + n;
+        // pre-smoothing from u = 0: the first sweep is u = m f
+        for (int i = threadIdx.x; i < n; i += TAIL_THREADS) u[i] = a.npre > 0 ? L.m[i] * f[i] : (T)0;
+        __syncthreads();
+        for (int it = 1; it < a.npre; ++it) tail_sweep<T>(L, f, u, w, r0, g);
+        // residual into w, restricted to the next level
+        for (int i = r0; i < n; i += RS) {
+            const T au = tail_row<T>(L.Aptr, L.Acol, L.Aval, u, i, g);
+            if (g == 0) w[i] = f[i] - au;
+        }
+        __syncthreads();
+        T* fn = sm + a.lv[l + 1].soff;
+        for (int i = r0; i < a.lv[l + 1].n; i += RS) {
+            const T v = tail_row<T>(L.Rptr, L.Rcol, L.Rval, w, i, g);
+            if (g == 0) fn[i] = v;
+        }
+        __syncthreads();
+    }
+    {
+        // coarsest level: the dense inverse, applied in FP64
+        const TailLevel<T>& L = a.lv[a.nlev - 1];
+        const int nc = L.n;
+        const T* f = sm + L.soff;
+        T* u = sm + L.soff + nc;
+        for (int i = r0; i < nc; i += RS) {
+            double s = 0.0;
+            const double* row = a.cinv + (size_t)i * nc;
+            for (int j = g; j < nc; j += TAIL_G) s += row[j] * (double)f[j];
+            s = group_sum<TAIL_G, double>(s);
+            if (g == 0) u[i] = (T)s;
+        }
+        __syncthreads();
+    }
+    for (int l = a.nlev - 2; l >= 0; --l) {
+        const TailLevel<T>& L = a.lv[l];
+        const int n = L.n;
+        T* f = sm + L.soff;
+        T* u = f + n;
+        T* w = u + n;
+        const T* uc = sm + a.lv[l + 1].soff + a.lv[l + 1].n;
+        for (int i = r0; i < n; i += RS) {  // u_l += P_l u_{l+1}
+            const T v = tail_row<T>(L.Pptr, L.Pcol, L.Pval, uc, i, g);
+            if (g == 0) u[i] = u[i] + v;
+        }
+        __syncthreads();
+        for (int it = 0; it < a.npost; ++it) tail_sweep<T>(L, f, u, w, r0, g);
+    }
+    {
+        const T* u0 = sm + a.lv[0].soff + a.lv[0].n;
+        for (int i = threadIdx.x; i < a.lv[0].n; i += TAIL_THREADS) a.uout[i] = u0[i];
+    }
+}
+
+template <typename T>
+void launch_vcycle_tail(const TailArgs<T>& a, hipStream_t s) {
+    if (a.nlev < 1 || a.nlev > TAIL_MAX_LEVELS) throw Fail{AMG_ERR_ARG, "coarse tail: level count"};
+    // the LDS layout: level l's f, u, w at soff, soff + n, soff + 2n
+    size_t need = 0;
+    for (int l = 0; l < a.nlev; ++l) {
+        if ((size_t)a.lv[l].soff != need) throw Fail{AMG_ERR_ARG, "coarse tail: LDS layout"};
+        need += 3 * (size_t)a.lv[l].n;
+    }
+    const size_t sm = need * sizeof(T);
+    if (sm > TAIL_SMEM_MAX) throw Fail{AMG_ERR_ARG, "coarse tail too large"};
+    k_vcycle_tail<T><<<1, TAIL_THREADS, sm, s>>>(a);
+    HIP_LAUNCH_CHECK();
+}
+
 #define AMG_INST(T)                                                                                 \
     template void launch_spmv<T>(const Csr&, const T*, T*, const T*, T*, hipStream_t);              \
     template void launch_residual<T>(const Csr&, const T*, const T*, T*, hipStream_t);              \
     template void launch_jacobi<T>(const Csr&, const T*, const T*, const T*, T*, hipStream_t);      \
     template void launch_smooth0_residual<T>(const Csr&, const T*, const T*, T*, T*, hipStream_t);  \
     template void launch_prolong_add<T>(const Csr&, const T*, T*, hipStream_t);                     \
-    template void launch_coarse_gemv<T>(int, const double*, const T*, T*, hipStream_t);
+    template void launch_coarse_gemv<T>(int, const double*, const T*, T*, hipStream_t);             \
+    template void launch_vcycle_tail<T>(const TailArgs<T>&, hipStream_t);
 AMG_INST(double)
 AMG_INST(float)
 #undef AMG_INST

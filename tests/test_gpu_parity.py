@@ -334,3 +334,23 @@ def test_galerkin_forms_parity(monkeypatch, form, smoother):
     g.rebuild(T(v1))
     o.rebuild(v1, 0)
     assert bitwise_levels(g, o) is None
+
+
+@pytest.mark.parametrize("npre,npost,precision", [(1, 1, 0), (2, 2, 0), (0, 1, 0), (1, 1, 1)])
+def test_coarse_tail_matches_level_kernels(monkeypatch, npre, npost, precision):
+    """The one-workgroup coarse tail computes the same V-cycle as the per-level kernels
+    (Algorithm 2; the row sums differ only in their order), and both match the oracle."""
+    p, c, v = two_fluid_7pt(32, 0.5)
+    r = np.random.default_rng(7).standard_normal(32**3)
+    prm = dict(npre=npre, npost=npost, precision=precision)
+    g = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), **prm)
+    z_tail = g.vcycle(T(r)).cpu().numpy()
+    monkeypatch.setenv("AMGMI_NO_TAIL", "1")
+    h = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), **prm)
+    z_sep = h.vcycle(T(r)).cpu().numpy()
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert rel_fro(z_tail, z_sep) <= tol
+    if precision == 0:
+        import oracle
+        o = oracle.OracleHierarchy(p, c, v, npre=npre, npost=npost)
+        assert rel_fro(z_tail, o.vcycle(r)) <= 1e-12
