@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="grid size N (N^3 unknowns)")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle partial steps in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle partial steps in the CPU sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized FP64 buffer 3 times and exit: the known-size reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of the other kernels")
@@ -212,9 +212,23 @@ def main():
     log("kernel time per partial step (ms, launches), all levels: "
         + ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(breakdown_all.items(), key=lambda kv: -kv[1][0])))
 
-    def roof(name, achieved):
+    def roof(name, ms, launches, alg_bytes, traffic_rec=None):
+        """Roofline record of one kernel from its live HIP-event timing: algorithmic bytes per
+        launch over the average launch duration; traffic = measured HBM bytes per launch
+        (FETCH_SIZE + WRITE_SIZE, scaled by a known-size copy) when the stored counters were
+        taken on the current kernel source, else null."""
+        avg_us = ms * 1e3 / launches if launches else None
+        achieved = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
         return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None}
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": traffic_rec["traffic_bytes_per_launch"] if traffic_rec else None,
+                "algorithmic_bytes": alg_bytes, "avg_launch_us": avg_us, "launches": launches,
+                "traffic_source": (f"profiles/{os.path.basename(traffic_rec['_path'])}" if traffic_rec else None)}
+
+    from paper_2108_02054_amd.profiling import load_traffic
+    pq_traffic = load_traffic(os.path.join(ROOT, "profiles", "cg_pq_two_fluid_128_traffic.json"))
+    if pq_traffic is not None:
+        pq_traffic["_path"] = "cg_pq_two_fluid_128_traffic.json"
 
     result = {
         "metric": METRIC,
@@ -241,8 +255,10 @@ def main():
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
-        "roofline": roof("cg_pq (Krylov SpMV, level 0)", spmv_gbs),
-        "roofline_rap": roof("galerkin_ap+galerkin_rap (level 0)", rap_gbs),
+        "roofline": roof("k_cg_pq (Krylov operator SpMV with p = z + beta p and p.q, level 0)", pq_ms, pq_cnt,
+                         spmv_bytes / pq_cnt if pq_cnt else 0, pq_traffic if N == 128 else None),
+        "roofline_rap": roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
+                             kb["galerkin"]),
         "kernels_level0_ms": {k: v for k, v in breakdown_l0.items()},
         "kernels_all_levels_ms": {k: v for k, v in breakdown_all.items()},
     }
