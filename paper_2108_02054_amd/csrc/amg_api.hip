@@ -6,6 +6,7 @@
 //   partial reuse  (Algorithm 4)  partial_rebuild(): numeric Galerkin chain on the cached
 //                                 patterns, smoothers, coarse inverse; no host sync
 //   full reuse     (Algorithm 3)  only the Krylov operator's values change
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -234,24 +235,34 @@ void release_posmaps(amg_ctx* c, Level& L) {
     release_posmap(c, L.galRAP);
 }
 
-// The position map of C = L B for the shape gs (allocated with the hierarchy); with
+// The launch shape and position map of C = L B (allocated with the hierarchy); with
 // diag, also the diagonal index of every row of L (for the smoother).  Rows with more
-// terms than the form takes leave the product to the lane-group kernels.
-void make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, GalShape& gs, bool diag, hipStream_t s) {
-    if (gs.g == 0) return;
-    gs.off = halloc<int64_t>(c, (size_t)L.nrows + 1);
+// terms than the form takes, or C rows too long for it, leave the product to the
+// lane-group kernels.
+GalShape make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, bool diag, const GalForce& f,
+                     hipStream_t s) {
+    if (lanes_only() || f.lanes || L.nrows == 0) return {};
+    int64_t* off = halloc<int64_t>(c, (size_t)L.nrows + 1);
     int64_t max_row = 0;
-    gs.terms = count_galerkin_terms(L, B, gs.off, &max_row, s);
-    if (!galerkin_terms_fit(max_row)) {
-        release_posmap(c, gs);
-        return;
+    const int64_t terms = count_galerkin_terms(L, B, off, &max_row, s);
+    const auto Cp = to_host(C.ptr, (size_t)C.nrows + 1, s);
+    int maxlen = 0;
+    for (int32_t i = 0; i < C.nrows; ++i) maxlen = std::max(maxlen, Cp[(size_t)i + 1] - Cp[(size_t)i]);
+    GalShape gs = pick_galerkin_shape(L.nrows, L.nnz, terms, maxlen, f.g);
+    if (gs.g == 0 || !galerkin_terms_fit(max_row)) {
+        release(c, off);
+        return {};
     }
-    const size_t n = (size_t)std::max<int64_t>(gs.terms, 1);
+    if (f.wide) gs.wide = 1;
+    gs.off = off;
+    gs.terms = terms;
+    const size_t n = (size_t)std::max<int64_t>(terms, 1);
     gs.pos = gs.wide ? (void*)halloc<uint16_t>(c, n) : (void*)halloc<uint8_t>(c, n);
     gs.bst = halloc<int32_t>(c, (size_t)std::max<int64_t>(L.nnz, 1));
     gs.tof = halloc<uint16_t>(c, (size_t)std::max<int64_t>(L.nnz, 1));
     if (diag) gs.dpos = halloc<int32_t>(c, (size_t)L.nrows + 1);
     build_galerkin_posmap(L, B, C, gs, s);
+    return gs;
 }
 
 // Launch shapes of a level's row kernels and Galerkin kernels (Ac: the next level's
@@ -262,20 +273,9 @@ void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
         configure(L.P, s);
         configure(L.R, s);
         L.gAP = lane_group((double)L.AP.nnz / (L.A.nrows > 0 ? (double)L.A.nrows : 1.0));
-        const auto Ap = to_host(L.A.ptr, (size_t)L.A.nrows + 1, s);
-        const auto Acl = to_host(L.A.col, (size_t)L.A.nnz, s);
-        const auto Pp = to_host(L.P.ptr, (size_t)L.P.nrows + 1, s);
-        const auto APp = to_host(L.AP.ptr, (size_t)L.AP.nrows + 1, s);
-        const auto Rp = to_host(L.R.ptr, (size_t)L.R.nrows + 1, s);
-        const auto Rc = to_host(L.R.col, (size_t)L.R.nnz, s);
-        const auto Cp = to_host(Ac->ptr, (size_t)Ac->nrows + 1, s);
         const GalForce f = galerkin_force();
-        const bool lanes = lanes_only() || f.lanes;
-        L.galAP = lanes ? GalShape{} : pick_galerkin_shape(Ap.data(), Acl.data(), L.A.nrows, Pp.data(), APp.data(), f.g);
-        L.galRAP = lanes ? GalShape{} : pick_galerkin_shape(Rp.data(), Rc.data(), L.R.nrows, APp.data(), Cp.data(), f.g);
-        if (f.wide) L.galAP.wide = L.galRAP.wide = 1;
-        make_posmap(c, L.A, L.P, L.AP, L.galAP, true, s);
-        make_posmap(c, L.R, L.AP, *Ac, L.galRAP, false, s);
+        L.galAP = make_posmap(c, L.A, L.P, L.AP, true, f, s);
+        L.galRAP = make_posmap(c, L.R, L.AP, *Ac, false, f, s);
     }
 }
 
@@ -298,6 +298,49 @@ void configure_tail(amg_ctx* c) {
         if (rows > TAIL_MAX_ROWS || nnz + in > max_nnz || nlev - t > TAIL_MAX_LEVELS) break;
         c->tail = t;
     }
+}
+
+// Diagonal storage of A_0 when its pattern has at most DIA_MAX distinct column offsets
+// and they are well filled (a stencil: 7 or 27 offsets, nearly every row full).  The
+// hierarchy's CSR copy stays (the Galerkin product and the exports read it); the
+// diagonal copy is refreshed from it after every rebuild.  AMGMI_NO_DIA disables it.
+void release_dia(amg_ctx* c) {
+    release(c, c->dia.val);
+    release(c, c->dia.val32);
+    release(c, c->dia.slot);
+    c->dia = Dia{};
+}
+
+void refresh_dia(amg_ctx* c) {
+    if (c->dia.ndiag == 0) return;
+    const Level& L0 = c->lv[0];
+    launch_dia_scatter<double>(L0.A, c->dia, L0.A.val, c->dia.val, c->stream);
+    if (c->dia.val32) launch_dia_scatter<float>(L0.A, c->dia, L0.A.val, c->dia.val32, c->stream);
+}
+
+void configure_dia(amg_ctx* c) {
+    release_dia(c);
+    if (std::getenv("AMGMI_NO_DIA") != nullptr) return;
+    hipStream_t s = c->stream;
+    const Csr& A = c->lv[0].A;
+    if (A.nrows == 0) return;
+    const std::vector<int> offs = dia_offsets(A, s);
+    const int nd = (int)offs.size();
+    if (nd == 0 || (double)A.nnz < 0.75 * (double)nd * (double)A.nrows) return;  // not a well-filled stencil
+    Dia D;
+    D.ndiag = nd;
+    for (int d = 0; d < nd; ++d) D.off.off[d] = offs[(size_t)d];
+    D.slot = halloc<uint8_t>(c, (size_t)A.nnz);
+    launch_dia_slots(A, D, s);
+    const size_t nv = (size_t)nd * (size_t)A.nrows;
+    D.val = halloc<double>(c, nv);
+    HIP_CHECK(hipMemsetAsync(D.val, 0, nv * sizeof(double), s));
+    if (mixed(c)) {
+        D.val32 = halloc<float>(c, nv);
+        HIP_CHECK(hipMemsetAsync(D.val32, 0, nv * sizeof(float), s));
+    }
+    c->dia = D;
+    refresh_dia(c);
 }
 
 // ------------------------------------------------------------------ Algorithm 4
@@ -333,6 +376,10 @@ void partial_rebuild(amg_ctx* c, const double* val) {
         }
         Trace tr(c, AMG_K_GALERKIN_RAP, l);
         launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, L.galRAP, s);
+    }
+    {
+        Trace tr(c, AMG_K_CAST, 0);
+        refresh_dia(c);
     }
     HIP_CHECK(hipEventRecord(c->ev[1], s));
     for (int l = 0; l + 1 < nlev; ++l) {
@@ -441,6 +488,8 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     c->lv.clear();
     c->outer_own = nullptr;
     c->cinv = nullptr;
+    c->dia = Dia{};  // its arrays were hierarchy allocations
+    c->tail = 0;
     c->lv.emplace_back();
     c->lv[0].A = A0;
     c->outer_val = A0.val;
@@ -567,6 +616,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     }
     alloc_cg(c);
     configure_tail(c);
+    configure_dia(c);
     HIP_CHECK(hipStreamSynchronize(s));
     ph[6] = ms_since(t_all);
     std::memcpy(c->phase_ms, ph, sizeof(ph));
@@ -627,6 +677,7 @@ void repattern(amg_ctx* c) {
     release(c, c->rs.part);
     alloc_reduction(c);
     configure_tail(c);
+    configure_dia(c);
     // The strength flags were per entry of the old patterns; the aggregates stay (they
     // still define the kept transfer operators).
     for (Level& L : c->lv) {
@@ -670,23 +721,40 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
     T* r = (T*)L.r;
     const T* m = L.mv<T>();
     const T* rres = r;
+    const int n = L.A.nrows;
+    const bool dia = l == 0 && c->dia.ndiag > 0;  // level 0 in diagonal storage
+    auto residual = [&](const T* uu) {
+        if (dia)
+            launch_dia_residual<T>(n, c->dia, f, uu, r, s);
+        else
+            launch_residual<T>(L.A, f, uu, r, s);
+    };
+    auto sweep = [&](const T* uu, T* uout) {
+        if (dia)
+            launch_dia_jacobi<T>(n, c->dia, m, f, uu, uout, s);
+        else
+            launch_jacobi<T>(L.A, m, f, uu, uout, s);
+    };
     if (p.npre == 0) {
         HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)L.A.nrows * sizeof(T), s));
         rres = f;
     } else {
         if (u_ready) {
             Trace tr(c, AMG_K_SMOOTH0_RES, l);
-            if (p.npre == 1) launch_residual<T>(L.A, f, cur, r, s);
+            if (p.npre == 1) residual(cur);
         } else {
             Trace tr(c, AMG_K_SMOOTH0_RES, l);
-            launch_smooth0_residual<T>(L.A, m, f, cur, r, s);
+            if (dia)
+                launch_dia_smooth0_residual<T>(n, c->dia, m, f, cur, r, s);
+            else
+                launch_smooth0_residual<T>(L.A, m, f, cur, r, s);
         }
         for (int it = 1; it < p.npre; ++it) {
             Trace tr(c, AMG_K_JACOBI, l);
-            launch_jacobi<T>(L.A, m, f, cur, other, s);
+            sweep(cur, other);
             std::swap(cur, other);
         }
-        if (p.npre > 1) launch_residual<T>(L.A, f, cur, r, s);
+        if (p.npre > 1) residual(cur);
     }
     const Level& C = c->lv[(size_t)l + 1];
     const T* uc;
@@ -745,13 +813,14 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
         Trace tr(c, AMG_K_JACOBI, l);
         if constexpr (std::is_same<T, double>::value) {
             if (last && ep && dst == out) {
-                ep->nb = launch_jacobi_rz(L.A, m, f, cur, dst, ep->flexible, c->rs, s);
+                ep->nb = dia ? launch_dia_jacobi_rz(n, c->dia, m, f, cur, dst, ep->flexible, c->rs, s)
+                             : launch_jacobi_rz(L.A, m, f, cur, dst, ep->flexible, c->rs, s);
                 fused = true;
             } else {
-                launch_jacobi<T>(L.A, m, f, cur, dst, s);
+                sweep(cur, dst);
             }
         } else {
-            launch_jacobi<T>(L.A, m, f, cur, dst, s);
+            sweep(cur, dst);
         }
         if (dst == other)
             std::swap(cur, other);
@@ -844,7 +913,11 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         int nb_pq;
         {
             Trace tr(c, AMG_K_CG_PQ, 0);
-            nb_pq = launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+            // the diagonal storage holds the hierarchy's A_0, which is the Krylov operator
+            // except after an operator-only update (full reuse)
+            nb_pq = (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
+                        ? launch_dia_cg_pq(n, c->dia, c->z, pold, pnew, c->q, it == 1, c->rs, s)
+                        : launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
         }
         launch_fin_pq(nb_pq, c->rs, s);
         {

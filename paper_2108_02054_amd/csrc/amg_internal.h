@@ -155,6 +155,42 @@ template <typename T>
 void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s);
+// Diagonal storage of the finest operator when its pattern has few distinct column
+// offsets (a stencil): entry (i, i + off[d]) at val[d * n + i], absent entries 0.  The
+// level-0 solve kernels stream it without any index arrays.
+constexpr int DIA_MAX = 32;
+struct DiaOff {
+    int off[DIA_MAX];
+};
+struct Dia {
+    int ndiag = 0;              // 0: not used
+    DiaOff off{};
+    double* val = nullptr;      // FP64 values (Krylov operator and FP64 V-cycle)
+    float* val32 = nullptr;     // FP32 values (mixed-precision V-cycle)
+    uint8_t* slot = nullptr;    // diagonal of every stored entry of A_0
+    template <typename T>
+    const T* v() const;
+};
+template <>
+inline const double* Dia::v<double>() const { return val; }
+template <>
+inline const float* Dia::v<float>() const { return val32; }
+
+std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
+void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s);
+template <typename T>
+void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s);
+template <typename T>
+void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T* u, T* r, hipStream_t s);
+template <typename T>
+void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipStream_t s);
+template <typename T>
+void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, T* uout, hipStream_t s);
+int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
+                         int flexible, const RedScratch& rs, hipStream_t s);
+int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,
+                     const RedScratch& rs, hipStream_t s);
+
 // The coarse tail of the V-cycle: the restriction into level t, then Algorithm 2 on levels
 // t .. L (the last one solved with the dense inverse) in one workgroup, writing u_t.
 constexpr int TAIL_MAX_LEVELS = 6;
@@ -220,8 +256,7 @@ bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalSha
                         const double* ain, hipStream_t s);
 template <typename T>
 void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s);
-GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr,
-                             const int32_t* Cptr, int gforce);
+GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen_c, int gforce);
 // count_galerkin_terms writes the term offsets gs.off (nrows + 1) and returns the number
 // of terms (and the most in one row); build_galerkin_posmap fills gs.pos, gs.bst, gs.tof
 // and, if allocated, gs.dpos (all allocated by the caller in between).
@@ -247,6 +282,7 @@ void build_transpose(const Csr& P, Csr& R, hipStream_t s);
 void symbolic_spgemm(const Csr& A, const Csr& B, Csr& C, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+int64_t max_i64(const int64_t* in, int64_t n, hipStream_t s);  // synchronises
 
 // ------------------------------------------------------------------ coarse solve
 constexpr int COARSE_LDS_MAX = 128;      // dense FP64 inverse held in one workgroup's LDS
@@ -282,6 +318,7 @@ struct amg_ctx {
     double* outer_own = nullptr;
     int32_t nL = 0;
     int tail = 0;                 // first level of the fused coarse tail (0: none)
+    amgmi::Dia dia;               // diagonal storage of A_0 (ndiag 0: CSR kernels)
     double* cinv = nullptr;       // dense inverse of the coarsest operator (FP64)
     // CG state
     double *x = nullptr, *r = nullptr, *z = nullptr, *zold = nullptr, *pa = nullptr, *pb = nullptr,

@@ -339,17 +339,12 @@ int64_t count_galerkin_terms(const Csr& L, const Csr& B, int64_t* off, int64_t* 
     int64_t* cnt = dnew<int64_t>((size_t)L.nrows + 1, s);
     k_count_terms<<<row_blocks((int64_t)L.nrows + 1, 1), TPB, 0, s>>>(L.nrows, L.ptr, L.col, B.ptr, cnt);
     HIP_LAUNCH_CHECK();
-    std::vector<int64_t> h((size_t)L.nrows + 1);
-    HIP_CHECK(hipMemcpyAsync(h.data(), cnt, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     exclusive_scan_i64(cnt, off, (int64_t)L.nrows + 1, s);
+    *max_row = max_i64(cnt, (int64_t)L.nrows + 1, s);
     dfree(cnt, s);
+    int64_t total = 0;
+    HIP_CHECK(hipMemcpyAsync(&total, off + L.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    int64_t total = 0, mx = 0;
-    for (int64_t v : h) {
-        total += v;
-        mx = std::max(mx, v);
-    }
-    *max_row = mx;
     return total;
 }
 
@@ -385,26 +380,19 @@ void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalSh
         }                                                                   \
     } while (0)
 
-// Launch shape of the position-map form for C = L B (host arrays): cap = the longest C
-// row rounded up to a multiple of 8, and G = the power of two in [4, 64] nearest above the
-// mean referenced B row length (so that most B rows take one pass of the group), or at
+// Launch shape of the position-map form for C = L B from its sizes (rows and entries of L,
+// terms, the longest C row): cap = the longest C row rounded up to a multiple of 8, and
+// G = the power of two in [4, 64] nearest above the mean number of terms per L entry (the
+// mean referenced B row length, so that most B rows take one pass of the group), or at
 // least an eighth of the mean L row length, raised until a block's LDS (TPB / G rows of
 // cap FP64 accumulators and the staged L entries) is within WF_SMEM_MAX.
 // {0, ...}: the rows are too long for the form (lane-group kernels).  gforce forces G
 // where the LDS allows.  The position map itself is built by the caller.
-GalShape pick_galerkin_shape(const int32_t* Lptr, const int32_t* Lcol, int32_t nrows, const int32_t* Bptr,
-                             const int32_t* Cptr, int gforce) {
-    int maxlen = 0;
-    for (int32_t i = 0; i < nrows; ++i) maxlen = std::max(maxlen, Cptr[i + 1] - Cptr[i]);
+GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen, int gforce) {
     if (maxlen > WF_CAP_MAX) return {};
-    double refs = 0.0, tot = 0.0;
-    for (int64_t k = 0; k < Lptr[nrows]; ++k) {
-        refs += 1.0;
-        tot += (double)(Bptr[Lcol[k] + 1] - Bptr[Lcol[k]]);
-    }
-    const double mean_b = refs > 0 ? tot / refs : 1.0;
+    const double mean_b = nnzL > 0 ? (double)terms / (double)nnzL : 1.0;
     const int cap = std::max(8, (maxlen + 7) / 8 * 8);
-    const double mean_l = nrows > 0 ? refs / (double)nrows : 1.0;
+    const double mean_l = nrows > 0 ? (double)nnzL / (double)nrows : 1.0;
     int G = 4;
     while (G < 64 && G < mean_b) G <<= 1;
     while (G < 64 && 8 * G <= mean_l) G <<= 1;  // long L rows: wider groups, fewer chunks

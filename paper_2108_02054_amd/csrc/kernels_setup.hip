@@ -284,6 +284,20 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t 
     scan_exclusive<int64_t, int64_t>(in, out, n, s);
 }
 
+int64_t max_i64(const int64_t* in, int64_t n, hipStream_t s) {
+    int64_t* out = dnew<int64_t>(1, s);
+    size_t bytes = 0;
+    HIP_CHECK(hipcub::DeviceReduce::Max(nullptr, bytes, in, out, (int)n, s));
+    void* tmp = dalloc(bytes, s);
+    HIP_CHECK(hipcub::DeviceReduce::Max(tmp, bytes, in, out, (int)n, s));
+    int64_t h = 0;
+    HIP_CHECK(hipMemcpyAsync(&h, out, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    dfree(tmp, s);
+    dfree(out, s);
+    return h;
+}
+
 int32_t run_aggregate(const Csr& A, const uint8_t* strong, const int32_t* tpos, const uint8_t* state, int32_t* agg,
                       int* flags, int* h_flags, hipStream_t s) {
     const int n = A.nrows;

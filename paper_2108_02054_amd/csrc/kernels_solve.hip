@@ -12,6 +12,10 @@
 // and the consumer -- the next kernel, or the host -- adds the slots in block order.  The
 // number of blocks is a fixed function of the size, so every result is bitwise
 // reproducible.
+#include <algorithm>
+#include <climits>
+#include <vector>
+
 #include "amg_internal.h"
 
 namespace amgmi {
@@ -371,6 +375,232 @@ void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ diagonal storage
+//
+// Level-0 kernels on the diagonal storage of A_0: one thread per row, the row's
+// diagonals in increasing offset (that is, column) order, each product added into the
+// row sum; an absent entry is stored as 0 and adds nothing, a column outside [0, n) is
+// never read.  Values and vector entries are read with fully coalesced loads and no index
+// arrays.  Reductions write one partial per workgroup (logical block order).
+
+template <typename T, typename X>
+__device__ __forceinline__ T dia_row(int i, int n, int nd, const DiaOff& o, const T* __restrict__ v, X xget) {
+    T s = 0;
+#pragma unroll 8
+    for (int d = 0; d < nd; ++d) {
+        const int j = i + o.off[d];
+        const T a = v[(size_t)d * n + i];
+        if ((unsigned)j < (unsigned)n) s += a * xget(j);
+    }
+    return s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dia_scatter(int n, const int* __restrict__ ptr,
+                                                     const uint8_t* __restrict__ slot, const double* __restrict__ val,
+                                                     T* __restrict__ dval) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    for (int t = ptr[i]; t < ptr[i + 1]; ++t) dval[(size_t)slot[t] * n + i] = (T)val[t];
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dia_smooth0_residual(int n, int nd, DiaOff o, const T* __restrict__ v,
+                                                              const T* __restrict__ m, const T* __restrict__ f,
+                                                              T* __restrict__ u, T* __restrict__ r) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    const T s = dia_row(i, n, nd, o, v, [&](int j) { return m[j] * f[j]; });
+    const T fi = f[i];
+    u[i] = m[i] * fi;
+    r[i] = fi - s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dia_residual(int n, int nd, DiaOff o, const T* __restrict__ v,
+                                                      const T* __restrict__ f, const T* __restrict__ u,
+                                                      T* __restrict__ r) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    r[i] = f[i] - dia_row(i, n, nd, o, v, [&](int j) { return u[j]; });
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dia_jacobi(int n, int nd, DiaOff o, const T* __restrict__ v,
+                                                    const T* __restrict__ m, const T* __restrict__ f,
+                                                    const T* __restrict__ u, T* __restrict__ uout) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    const T s = dia_row(i, n, nd, o, v, [&](int j) { return u[j]; });
+    uout[i] = u[i] + m[i] * (f[i] - s);
+}
+
+__global__ __launch_bounds__(TPB) void k_dia_jacobi_rz(int n, int nd, DiaOff o, const double* __restrict__ v,
+                                                       const double* __restrict__ m, const double* __restrict__ r,
+                                                       const double* __restrict__ u, double* __restrict__ z,
+                                                       int flexible, RedScratch rs) {
+    const int lb = xcd_block();
+    const int i = lb * TPB + threadIdx.x;
+    double loc[2] = {0.0, 0.0};
+    if (i < n) {
+        const double s = dia_row(i, n, nd, o, v, [&](int j) { return u[j]; });
+        const double ri = r[i];
+        const double zi = u[i] + m[i] * (ri - s);
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    }
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, lb);
+}
+
+__global__ __launch_bounds__(TPB) void k_dia_cg_pq(int n, int nd, DiaOff o, const double* __restrict__ v,
+                                                   const double* __restrict__ z, const double* __restrict__ pold,
+                                                   double* __restrict__ pnew, double* __restrict__ q, int first,
+                                                   RedScratch rs) {
+    const double beta = first ? 0.0 : rs.scal()[S_BETA];
+    auto pv = [&](int j) { return first ? z[j] : __builtin_fma(beta, pold[j], z[j]); };
+    const int lb = xcd_block();
+    const int i = lb * TPB + threadIdx.x;
+    double loc[1] = {0.0};
+    if (i < n) {
+        const double qi = dia_row(i, n, nd, o, v, pv);
+        const double pi = pv(i);
+        pnew[i] = pi;
+        q[i] = qi;
+        loc[0] += pi * qi;
+    }
+    double* const dst[1] = {rs.region(P_PQ)};
+    block_store<1>(loc, dst, lb);
+}
+
+// The set of distinct column offsets (col - row) of a CSR pattern, in a 64-slot open-
+// addressing table (DIA_EMPTY: free).  Each workgroup first collects its rows' offsets in
+// LDS, then inserts them into the global table; flag[0] is set when the set outgrows
+// DIA_MAX.  Integer compare-and-swap only: the resulting set does not depend on order.
+constexpr int DIA_TAB = 64;
+constexpr int DIA_EMPTY = INT_MIN;
+
+__device__ __forceinline__ bool dia_insert(int* tab, int o) {
+    unsigned h = ((unsigned)o * 2654435761u) >> 26;  // 6 bits
+    for (int p = 0; p < DIA_TAB; ++p) {
+        int* slot = tab + ((h + p) & (DIA_TAB - 1));
+        const int cur = *slot;
+        if (cur == o) return true;
+        if (cur == DIA_EMPTY) {
+            const int prev = atomicCAS(slot, DIA_EMPTY, o);
+            if (prev == DIA_EMPTY || prev == o) return true;
+        }
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(TPB) void k_dia_offsets(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                     int* __restrict__ tab, int* __restrict__ flag) {
+    __shared__ int st[DIA_TAB];
+    __shared__ int over;
+    if (threadIdx.x < DIA_TAB) st[threadIdx.x] = DIA_EMPTY;
+    if (threadIdx.x == 0) over = 0;
+    __syncthreads();
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i < n)
+        for (int k = ptr[i]; k < ptr[i + 1]; ++k)
+            if (!dia_insert(st, col[k] - i)) {
+                over = 1;
+                break;
+            }
+    __syncthreads();
+    if (threadIdx.x < DIA_TAB && st[threadIdx.x] != DIA_EMPTY)
+        if (!dia_insert(tab, st[threadIdx.x])) over = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && over) flag[0] = 1;
+}
+
+// Diagonal index of every stored entry, given the sorted offsets.
+__global__ __launch_bounds__(TPB) void k_dia_slots(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                   int nd, DiaOff o, uint8_t* __restrict__ slot) {
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const int off = col[k] - i;
+        int lo = 0, hi = nd - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (o.off[mid] < off)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        slot[k] = (uint8_t)lo;
+    }
+}
+
+// The distinct offsets of A's pattern (sorted), or an empty list when there are more
+// than DIA_MAX of them.
+std::vector<int> dia_offsets(const Csr& A, hipStream_t s) {
+    int* buf = dnew<int>(DIA_TAB + 1, s);
+    std::vector<int> init(DIA_TAB + 1, DIA_EMPTY);
+    init[DIA_TAB] = 0;
+    HIP_CHECK(hipMemcpyAsync(buf, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    k_dia_offsets<<<(unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.ptr, A.col, buf, buf + DIA_TAB);
+    HIP_LAUNCH_CHECK();
+    std::vector<int> h(DIA_TAB + 1);
+    HIP_CHECK(hipMemcpyAsync(h.data(), buf, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    dfree(buf, s);
+    std::vector<int> offs;
+    if (h[DIA_TAB] != 0) return offs;
+    for (int q = 0; q < DIA_TAB; ++q)
+        if (h[q] != DIA_EMPTY) offs.push_back(h[q]);
+    if ((int)offs.size() > DIA_MAX) return {};
+    std::sort(offs.begin(), offs.end());
+    return offs;
+}
+
+void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s) {
+    k_dia_slots<<<(unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.ptr, A.col, D.ndiag, D.off, D.slot);
+    HIP_LAUNCH_CHECK();
+}
+
+static inline unsigned dia_blocks(int n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+template <typename T>
+void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s) {
+    k_dia_scatter<T><<<dia_blocks(A.nrows), TPB, 0, s>>>(A.nrows, A.ptr, D.slot, val, dval);
+    HIP_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T* u, T* r, hipStream_t s) {
+    k_dia_smooth0_residual<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, r);
+    HIP_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipStream_t s) {
+    k_dia_residual<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), f, u, r);
+    HIP_LAUNCH_CHECK();
+}
+template <typename T>
+void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
+    k_dia_jacobi<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, uout);
+    HIP_LAUNCH_CHECK();
+}
+int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
+                         int flexible, const RedScratch& rs, hipStream_t s) {
+    const int nb = (int)dia_blocks(n);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    k_dia_jacobi_rz<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,
+                     const RedScratch& rs, hipStream_t s) {
+    const int nb = (int)dia_blocks(n);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    k_dia_cg_pq<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, first, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+
 // ------------------------------------------------------------------ coarse tail
 //
 // The last levels of the V-cycle (Algorithm 2 from the level reached by a restriction down
@@ -515,7 +745,11 @@ void launch_vcycle_tail(const TailArgs<T>& a, hipStream_t s) {
     template void launch_smooth0_residual<T>(const Csr&, const T*, const T*, T*, T*, hipStream_t);  \
     template void launch_prolong_add<T>(const Csr&, const T*, T*, hipStream_t);                     \
     template void launch_coarse_gemv<T>(int, const double*, const T*, T*, hipStream_t);             \
-    template void launch_vcycle_tail<T>(const TailArgs<T>&, hipStream_t);
+    template void launch_vcycle_tail<T>(const TailArgs<T>&, hipStream_t);                          \
+    template void launch_dia_scatter<T>(const Csr&, const Dia&, const double*, T*, hipStream_t);    \
+    template void launch_dia_smooth0_residual<T>(int, const Dia&, const T*, const T*, T*, T*, hipStream_t); \
+    template void launch_dia_residual<T>(int, const Dia&, const T*, const T*, T*, hipStream_t);     \
+    template void launch_dia_jacobi<T>(int, const Dia&, const T*, const T*, const T*, T*, hipStream_t);
 AMG_INST(double)
 AMG_INST(float)
 #undef AMG_INST

@@ -354,3 +354,45 @@ def test_coarse_tail_matches_level_kernels(monkeypatch, npre, npost, precision):
         import oracle
         o = oracle.OracleHierarchy(p, c, v, npre=npre, npost=npost)
         assert rel_fro(z_tail, o.vcycle(r)) <= 1e-12
+
+
+@pytest.mark.parametrize("case,precision", [("tf32", 0), ("tf32", 1), ("ln27", 0), ("box", 0)])
+def test_diagonal_storage_matches_csr(monkeypatch, case, precision):
+    """The level-0 kernels on the diagonal storage of a stencil operator compute the same
+    V-cycle and solve as the CSR kernels (row sums in a different order only)."""
+    from paper_2108_02054_amd import AMG
+
+    if case == "tf32":
+        p, c, v0 = two_fluid_7pt(32, front_c1(0))
+        v1 = two_fluid_7pt(32, front_c1(4))[2]
+        prm = dict()
+    elif case == "ln27":
+        p, c, v0 = lognormal_27pt(16, 0)
+        v1 = lognormal_27pt(16, 2)[2]
+        prm = dict(eps_strong=0.02)
+    else:
+        p, c, v0 = two_fluid_7pt(33, 0.4, ny=17, nz=9)
+        v1 = two_fluid_7pt(33, 0.45, ny=17, nz=9)[2]
+        prm = dict()
+    prm["precision"] = precision
+    n = len(p) - 1
+    r = np.random.default_rng(11).standard_normal(n)
+    f = rhs_uniform(n, 1, 3)
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), **prm)
+        g.rebuild(T(v1))
+        z = g.vcycle(T(r)).cpu().numpy()
+        u, info = g.solve(T(f))
+        out = (z, u.cpu().numpy(), info)
+        g.close()
+        return out
+
+    zd, ud, idia = run()
+    monkeypatch.setenv("AMGMI_NO_DIA", "1")
+    zc, uc, icsr = run()
+    tol = 1e-12 if precision == 0 else 1e-5
+    assert rel_fro(zd, zc) <= tol
+    assert idia["converged"] and icsr["converged"]
+    assert abs(idia["iters"] - icsr["iters"]) <= 1
+    assert rel_fro(ud, uc) <= 1e-7
