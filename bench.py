@@ -40,7 +40,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed time steps")
     ap.add_argument("--warmup", type=int, default=3, help="untimed time steps before the timed ones")
-    ap.add_argument("--n", type=int, default=128, help="grid size N (N^3 unknowns)")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5],
+                    help="matrix series: 2 = two-fluid 7-point 128^3 FP64 (the headline), 3 = two-fluid "
+                         "7-point 192^3, 5 = lognormal 27-point 160^3 with the FP32 hierarchy")
+    ap.add_argument("--n", type=int, default=0, help="grid size N (N^3 unknowns); 0: the series' own")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle partial steps in the CPU sample")
@@ -48,6 +51,15 @@ def parse():
                     help="only copy a MIB-sized FP64 buffer 3 times and exit: the known-size reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of the other kernels")
     return ap.parse_args()
+
+
+def workload_name(cfg_id, N, n, nnz):
+    series = {2: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
+              3: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
+              5: "27-point lognormal-coefficient Poisson (sigma 1.5) with smooth drift per step"}[cfg_id]
+    form = ("FP32 hierarchy and V-cycle under FP64 CG" if cfg_id == 5 else "FP64")
+    return (f"{series}, {N}^3 (n={n}, nnz={nnz}); partial reuse (numeric-only cached RAP + smoother), "
+            f"{form}, PCG to 1e-8 true rel res")
 
 
 def copy_probe(mib):
@@ -65,21 +77,23 @@ def copy_probe(mib):
 
 # ------------------------------------------------------------------ algorithmic bytes
 
-def kernel_bytes(dims, sv_h, level_prec_bytes=None):
+def kernel_bytes(dims, sv_h, ndiag=0):
     """Algorithmic bytes per launch of the level-0 kernels: each operand read once, each
-    output written once, vector gathers counted once.  CSR: 4-byte indices.  sv_h is the
-    value size of the hierarchy (8 FP64, 4 FP32); the CG kernels are always FP64."""
+    output written once, vector gathers counted once.  CSR: 4-byte indices; an operator
+    in diagonal storage (ndiag > 0) needs no index arrays, so its bytes are its values.
+    sv_h is the value size of the hierarchy (8 FP64, 4 FP32); the CG kernels are FP64."""
     n, nnzA, nc, nnzP, nnzAP = dims[0]
     nnzAc = dims[1][1]
     ind = lambda rows, nnz: 4 * (rows + 1) + 4 * nnz  # noqa: E731
+    ind0 = (lambda rows, nnz: 0) if ndiag > 0 else ind  # noqa: E731
     b = {}
     # Krylov operator SpMV fused with p = z + beta p and p.q: A, z, p_old read; p_new, q written
-    b["cg_pq"] = ind(n, nnzA) + 8 * nnzA + 8 * 4 * n
+    b["cg_pq"] = ind0(n, nnzA) + 8 * nnzA + 8 * 4 * n
     b["cg_update"] = 8 * 6 * n          # p, q, x, r read; x, r written
     b["cg_rz"] = 8 * 2 * n
     b["cg_init"] = ind(n, nnzA) + 8 * nnzA + 8 * 3 * n
-    b["smooth0_res"] = ind(n, nnzA) + sv_h * nnzA + sv_h * 4 * n   # m, f read; u, r written
-    b["jacobi"] = ind(n, nnzA) + sv_h * nnzA + sv_h * 4 * n        # m, f, u read; u' written
+    b["smooth0_res"] = ind0(n, nnzA) + sv_h * nnzA + sv_h * 4 * n   # m, f read; u, r written
+    b["jacobi"] = ind0(n, nnzA) + sv_h * nnzA + sv_h * 4 * n        # m, f, u read; u' written
     b["restrict"] = ind(nc, nnzP) + sv_h * nnzP + sv_h * (n + nc)
     b["prolong"] = ind(n, nnzP) + sv_h * nnzP + sv_h * (nc + 2 * n)
     b["smoother"] = ind(n, nnzA) + sv_h * nnzA + sv_h * n
@@ -106,33 +120,41 @@ def main():
     import torch
 
     from paper_2108_02054_amd import AMG, FULL, OPERATOR_ONLY
-    from workloads import front_moving, rhs_uniform, two_fluid_7pt
+    from workloads import CONFIGS, rhs_uniform, series_matrix
 
     dev = torch.device("cuda:0")
-    N, K, W = args.n, args.steps, args.warmup
+    cfg_id = args.config
+    cfg = CONFIGS[cfg_id]
+    N = args.n or cfg["N"]
+    K, W = args.steps, args.warmup
     n = N**3
     nsteps = W + K + 1
-    cfg_id = 2
+    # the series' own precision for the headline line: FP64, or the FP32 hierarchy under
+    # FP64 CG for the 27-point series
+    head_prec = 1 if cfg_id == 5 else 0
+    amg_params = dict(eps_strong=cfg["eps_strong"])
 
     # ---------------------------------------------------------------- inputs in HBM
     t0 = time.time()
     vals, rhs = [], []
     for t in range(nsteps):
-        p, c, v = two_fluid_7pt(N, front_moving(N, t))
+        p, c, v = series_matrix(cfg_id, t, N)
         if t == 0:
             ptr = torch.from_numpy(p).to(dev)
             col = torch.from_numpy(c).to(dev)
         vals.append(torch.from_numpy(v).to(dev))
         rhs.append(torch.from_numpy(rhs_uniform(n, cfg_id, t)).to(dev))
+        del p, c, v
     torch.cuda.synchronize()
     nnz = int(col.numel())
-    log(f"inputs: {nsteps} steps of {N}^3 (n={n}, nnz={nnz}) generated and uploaded in {time.time() - t0:.1f}s")
+    log(f"inputs: {nsteps} steps of {cfg['name']} at {N}^3 (n={n}, nnz={nnz}) generated and uploaded in "
+        f"{time.time() - t0:.1f}s")
 
     u = torch.zeros(n, dtype=torch.float64, device=dev)
 
     def series(mode, precision=0, trace=None):
         """Setup at t=0 (untimed), W warm-up steps, K timed steps."""
-        amg = AMG(ptr, col, vals[0], precision=precision)
+        amg = AMG(ptr, col, vals[0], precision=precision, **amg_params)
         info_log = {"iters": [], "rebuilds": 0, "converged": True, "rel_res_max": 0.0}
 
         def step(t, record):
@@ -174,9 +196,10 @@ def main():
 
     # ---------------------------------------------------------------- partial reuse (headline)
     traced = ["cg_pq", "galerkin_ap", "galerkin_rap"]
-    amg, ms_partial, info_p, kt = series("partial", trace=traced)
+    amg, ms_partial, info_p, kt = series("partial", precision=head_prec, trace=traced)
     L = amg.num_levels
     dims = [amg.dims(l) for l in range(L)]
+    ndiag = amg.level_format(0)
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
     log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
     ph = amg.phase_times()
@@ -197,7 +220,7 @@ def main():
     amg.trace([], level=0)
     amg.close()
 
-    kb = kernel_bytes(dims, 8)
+    kb = kernel_bytes(dims, 8, ndiag)
     # live measurement over the timed region
     pq_ms, pq_cnt = kt.get("cg_pq", (0.0, 0))
     n_solves = K
@@ -241,13 +264,12 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head_prec == 0 else "f32 hierarchy and V-cycle, f64 CG",
         "data": "synthetic",
-        "config": {"workload": f"two-fluid 7-point Poisson {N}^3 (n={n}, nnz={nnz}), rho ratio 1000, "
-                               f"interface +1 cell/step, partial reuse (numeric-only cached RAP + smoother), "
-                               f"PCG to 1e-8 true rel res",
+        "config": {"workload": workload_name(cfg_id, N, n, nnz),
                    "grid": N, "n": n, "nnz": nnz, "levels": L, "level_rows": [d[0] for d in dims],
-                   "level_nnz": [d[1] for d in dims], "parallelism": "single GPU"},
+                   "level_nnz": [d[1] for d in dims], "level0_storage": (f"{ndiag} diagonals" if ndiag else "CSR"),
+                   "parallelism": "single GPU"},
         "iters_partial": info_p["iters"],
         "converged_all": info_p["converged"],
         "rel_res_max": info_p["rel_res_max"],
@@ -255,8 +277,10 @@ def main():
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
-        "roofline": roof("k_cg_pq (Krylov operator SpMV with p = z + beta p and p.q, level 0)", pq_ms, pq_cnt,
-                         spmv_bytes / pq_cnt if pq_cnt else 0, pq_traffic if N == 128 else None),
+        "roofline": roof(("k_dia_cg_pq" if ndiag else "k_cg_pq")
+                         + " (Krylov operator SpMV with p = z + beta p and p.q, level 0)", pq_ms, pq_cnt,
+                         spmv_bytes / pq_cnt if pq_cnt else 0,
+                         pq_traffic if (cfg_id == 2 and N == 128 and ndiag > 0) else None),
         "roofline_rap": roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
                              kb["galerkin"]),
         "kernels_level0_ms": {k: v for k, v in breakdown_l0.items()},
@@ -265,40 +289,53 @@ def main():
 
     # ---------------------------------------------------------------- comparators
     if not args.no_compare:
-        _, ms_full, info_f, _ = series("full")
-        log(f"full rebuild: {ms_full:.3f} ms/step, iters {info_f['iters']}")
-        _, ms_reuse, info_r, _ = series("reuse")
-        log(f"full reuse: {ms_reuse:.3f} ms/step, iters {info_r['iters']}, rebuilds {info_r['rebuilds']}")
-        _, ms_mixed, info_m, _ = series("partial", precision=1)
-        log(f"mixed partial: {ms_mixed:.3f} ms/step, iters {info_m['iters']}")
-        result.update({
-            "full_rebuild_ms_per_step": ms_full,
-            "full_reuse_ms_per_step": ms_reuse,
-            "mixed_partial_ms_per_step": ms_mixed,
-            "iters_full_rebuild": info_f["iters"],
-            "iters_full_reuse": info_r["iters"],
-            "full_reuse_rebuilds": info_r["rebuilds"],
-            "iters_mixed": info_m["iters"],
-            "converged_all": bool(info_p["converged"] and info_f["converged"] and info_r["converged"]
-                                  and info_m["converged"]),
+        runs = {}
+        if cfg_id == 5:
+            plan = [("full", "full", 1), ("fp64_partial", "partial", 0)]
+        elif cfg_id == 3:
+            plan = [("mixed", "partial", 1), ("full", "full", 0)]
+        else:
+            plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1)]
+        for name, mode, prec in plan:
+            _, ms_x, info_x, _ = series(mode, precision=prec)
+            runs[name] = (ms_x, info_x)
+            extra = f", rebuilds {info_x['rebuilds']}" if mode == "reuse" else ""
+            log(f"{name}: {ms_x:.3f} ms/step, iters {info_x['iters']}{extra}")
+        conv = info_p["converged"]
+        for name, (ms_x, info_x) in runs.items():
+            conv = conv and bool(info_x["converged"])
+        if "full" in runs:
+            result["full_rebuild_ms_per_step"] = runs["full"][0]
+            result["iters_full_rebuild"] = runs["full"][1]["iters"]
             # the paper's speedup form: (t_base / t - 1) * 100
-            "total_speedup_vs_full_rebuild_pct": (ms_full / ms_partial - 1.0) * 100.0,
-            "mixed_speedup_vs_fp64_pct": (ms_partial / ms_mixed - 1.0) * 100.0,
-        })
+            result["total_speedup_vs_full_rebuild_pct"] = (runs["full"][0] / ms_partial - 1.0) * 100.0
+        if "reuse" in runs:
+            result["full_reuse_ms_per_step"] = runs["reuse"][0]
+            result["iters_full_reuse"] = runs["reuse"][1]["iters"]
+            result["full_reuse_rebuilds"] = runs["reuse"][1]["rebuilds"]
+        if "mixed" in runs:
+            result["mixed_partial_ms_per_step"] = runs["mixed"][0]
+            result["iters_mixed"] = runs["mixed"][1]["iters"]
+            result["mixed_speedup_vs_fp64_pct"] = (ms_partial / runs["mixed"][0] - 1.0) * 100.0
+        if "fp64_partial" in runs:
+            result["fp64_partial_ms_per_step"] = runs["fp64_partial"][0]
+            result["iters_fp64"] = runs["fp64_partial"][1]["iters"]
+            result["mixed_speedup_vs_fp64_pct"] = (runs["fp64_partial"][0] / ms_partial - 1.0) * 100.0
+        result["converged_all"] = conv
 
     # ---------------------------------------------------------------- CPU oracle sample
     if not args.no_cpu:
         import oracle
         nthr = oracle.num_threads()
-        p, c, v0 = two_fluid_7pt(N, front_moving(N, 0))
+        p, c, v0 = series_matrix(cfg_id, 0, N)
         t0 = time.time()
-        h = oracle.OracleHierarchy(p, c, v0)
+        h = oracle.OracleHierarchy(p, c, v0, **amg_params)
         t_setup = time.time() - t0
-        ks = max(1, args.cpu_steps)
+        ks = max(1, args.cpu_steps if cfg_id == 2 else 1)
         elapsed = 0.0
         its = []
         for t in range(1, ks + 1):
-            _, _, vt = two_fluid_7pt(N, front_moving(N, t))
+            _, _, vt = series_matrix(cfg_id, t, N)
             ft = rhs_uniform(n, cfg_id, t)
             ts = time.perf_counter()  # the step's inputs are generated outside the timing
             h.rebuild(vt, 0)
@@ -309,9 +346,9 @@ def main():
         h.close()
         log(f"oracle: setup {t_setup:.1f}s, partial step {cpu_ms:.0f} ms ({nthr} threads), iters {its}")
         result["cpu_baseline"] = {"value": cpu_ms, "unit": "ms/step", "cores": nthr, "kind": "oracle",
-                                  "sample": f"oracle partial rebuild + PCG solve to 1e-8, {N}^3 two-fluid steps "
-                                            f"t=1..{ks} after an untimed setup at t=0 (full setup took "
-                                            f"{t_setup:.1f}s); iterations {its}"}
+                                  "sample": f"oracle (FP64) partial rebuild + PCG solve to 1e-8 of {cfg['name']} at "
+                                            f"{N}^3, steps t=1..{ks} after an untimed setup at t=0 (full setup "
+                                            f"took {t_setup:.1f}s); iterations {its}"}
     print(json.dumps(result), flush=True)
 
 

@@ -128,6 +128,13 @@ amg_status amg_num_levels(const amg_ctx* c, int* L);
 /* dims[0..4] = { n_l, nnz(A_l), n_{l+1} (0 on the coarsest), nnz(P_l), nnz(A_l P_l) } */
 amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims);
 
+/* Storage of level l's operator in the solve kernels: *ndiag (host) receives the number of
+ * stored diagonals when the level is kept in diagonal storage (the finest level of a
+ * stencil operator: at most 32 distinct column offsets, well filled; the values are
+ * refreshed from the CSR copy after every rebuild), or 0 when the CSR kernels are used.
+ * Errors: AMG_ERR_ARG for a NULL argument or l out of range. */
+amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag);
+
 /* Copy level l to host arrays (any may be NULL).  agg[n_l], strong[nnz(A_l)] exist on
  * aggregated levels; P on non-coarsest levels; m (smoother diagonal) on non-coarsest
  * levels.  In mixed precision A_val/P_val/m are the FP32 values widened to FP64.

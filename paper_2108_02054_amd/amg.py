@@ -23,7 +23,7 @@ PARTIAL, FULL, OPERATOR_ONLY = 0, 1, 2
 EXPORTED = [
     "amg_params_default", "amg_setup", "amg_setup_transfer", "amg_rebuild", "amg_set_pattern",
     "amg_rebuild_ex", "amg_solve", "amg_vcycle", "amg_destroy", "amg_last_error", "amg_num_levels",
-    "amg_level_dims", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
+    "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
     "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read",
 ]
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
@@ -83,6 +83,7 @@ def lib():
         L.amg_last_error.restype = C.c_char_p
         L.amg_num_levels.argtypes = [V, C.POINTER(I)]
         L.amg_level_dims.argtypes = [V, I, C.POINTER(I64)]
+        L.amg_level_format.argtypes = [V, I, C.POINTER(I)]
         L.amg_export_level.argtypes = [V, I] + [V] * 9
         L.amg_export_coarse_inverse.argtypes = [V, V]
         L.amg_phase_times.argtypes = [V, C.POINTER(D)]
@@ -220,6 +221,12 @@ class AMG:
         d = (C.c_int64 * 5)()
         self._check(lib().amg_level_dims(self.ctx, l, d))
         return [int(x) for x in d]
+
+    def level_format(self, l: int) -> int:
+        """Diagonals of level l's diagonal storage (0: CSR kernels)."""
+        nd = C.c_int()
+        self._check(lib().amg_level_format(self.ctx, l, C.byref(nd)))
+        return nd.value
 
     def level(self, l: int):
         """Host copies of level l: dict with A (ptr, col, val), P (ptr, col, val, nc) or

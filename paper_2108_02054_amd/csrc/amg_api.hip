@@ -1233,6 +1233,12 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims) {
     return AMG_OK;
 }
 
+amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag) {
+    if (!c || !ndiag || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
+    *ndiag = l == 0 ? c->dia.ndiag : 0;
+    return AMG_OK;
+}
+
 amg_status amg_export_level(const amg_ctx* cc, int l, int32_t* agg, uint8_t* strong, int32_t* A_ptr, int32_t* A_col,
                             double* A_val, int32_t* P_ptr, int32_t* P_col, double* P_val, double* m) {
     amg_ctx* c = const_cast<amg_ctx*>(cc);

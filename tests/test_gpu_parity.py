@@ -396,3 +396,27 @@ def test_diagonal_storage_matches_csr(monkeypatch, case, precision):
     assert idia["converged"] and icsr["converged"]
     assert abs(idia["iters"] - icsr["iters"]) <= 1
     assert rel_fro(ud, uc) <= 1e-7
+
+
+def test_full_size_128_partial_rebuild_and_solve():
+    """At the benchmark's full size (two-fluid 128^3, the configuration bench.py times,
+    with the diagonal storage and the default launch shapes): after a partial rebuild to a
+    later step, every level's aggregates and patterns match the oracle's bit for bit and
+    its FP64 values too (summed in the oracle's order); the solve converges to 1e-8 in the
+    oracle's iteration count +-1 with a solution within 1e-6."""
+    N = 128
+    p, c, v0 = two_fluid_7pt(N, front_moving(N, 0))
+    v5 = two_fluid_7pt(N, front_moving(N, 5))[2]
+    print("case two-fluid 128^3 step 0 -> 5", flush=True)
+    g, o = both(p, c, v0)
+    assert g.level_format(0) == 7
+    g.rebuild(T(v5))
+    o.rebuild(v5, 0)
+    compare_levels(g, o, tol=1e-10)
+    assert bitwise_levels(g, o) is None
+    f = rhs_uniform(N**3, 2, 5)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and info["rel_res_true"] <= 1e-8
+    assert abs(info["iters"] - io["iters"]) <= 1
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
