@@ -148,18 +148,25 @@ struct Trace {
     }
 };
 
-// One device-to-host copy of the ||r||^2 and ||f||^2 partials and the scalar slots.
+// One device-to-host copy of the scalar slots and the ||r||^2 and ||f||^2 partials.
 void read_red(amg_ctx* c) {
-    HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.region(P_RR), (2 * RED_BLOCKS + S_COUNT) * sizeof(double),
+    HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.scal(), RedScratch::host_doubles(c->rs.cap) * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
 }
 
-double host_scal(const amg_ctx* c, int k) { return c->h_red[2 * RED_BLOCKS + k]; }
+// Queue the copy of the scalar slots and the first nrr ||r||^2 partials (the CG loop's
+// per-iteration read).
+void queue_read_rr(amg_ctx* c, int nrr) {
+    HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.scal(), (S_COUNT + (size_t)nrr) * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+}
 
-// Sum of nb partials of the region read by read_red, in block order.
+double host_scal(const amg_ctx* c, int k) { return c->h_red[k]; }
+
+// Sum of nb partials of P_RR or P_FF as last copied to the host, in block order.
 double host_sum(const amg_ctx* c, int region, int nb) {
-    const double* p = c->h_red + (region - P_RR) * RED_BLOCKS;
+    const double* p = c->h_red + S_COUNT + (region == P_RR ? 0 : (size_t)c->rs.cap);
     double s = 0.0;
     for (int i = 0; i < nb; ++i) s += p[i];
     return s;
@@ -437,6 +444,7 @@ void alloc_cg(amg_ctx* c) {
     const size_t n = (size_t)c->lv[0].A.nrows;
     c->x = halloc<double>(c, n);
     c->r = halloc<double>(c, n);
+    c->r2 = halloc<double>(c, n);
     c->z = halloc<double>(c, n);
     c->zold = halloc<double>(c, n);
     c->pa = halloc<double>(c, n);
@@ -452,6 +460,19 @@ void alloc_reduction(amg_ctx* c) {
     c->rs.cap = cap;
     c->rs.part = halloc<double>(c, RedScratch::doubles(cap));
     HIP_CHECK(hipMemsetAsync(c->rs.part, 0, RedScratch::doubles(cap) * sizeof(double), c->stream));
+    if (c->h_red) {
+        HIP_CHECK(hipStreamSynchronize(c->stream));
+        HIP_CHECK(hipHostFree(c->h_red));
+        c->h_red = nullptr;
+    }
+    HIP_CHECK(hipHostMalloc((void**)&c->h_red, RedScratch::host_doubles(cap) * sizeof(double),
+                            hipHostMallocMapped | hipHostMallocCoherent));
+    c->rs.host = nullptr;
+    if (std::getenv("AMGMI_NO_HOST_WRITE") == nullptr) {
+        void* dptr = nullptr;
+        HIP_CHECK(hipHostGetDevicePointer(&dptr, c->h_red, 0));
+        c->rs.host = (double*)dptr;
+    }
 }
 
 struct Transfer {
@@ -697,10 +718,11 @@ struct RzEpilogue {
 // Algorithm 2 on level l from a zero initial guess; returns the buffer holding u_l.
 // At level 0 the last post-smoothing sweep writes directly into `out` when given, and
 // with an epilogue (FP64) it also forms the CG partial sums of r.z from f (= the CG
-// residual) and z.  On coarser levels the restriction has already formed the first
-// smoothing sweep u = m f (`u_ready`).
+// residual) and z.  `ready` = 1: the first smoothing sweep u = m f is already in the
+// level's u (the restriction forms it on coarser levels); 2: so is the residual f - A u
+// in the level's r (the fused CG update forms both on level 0; one pre-sweep only).
 template <typename T>
-T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, bool u_ready = false) {
+T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, int ready = 0) {
     hipStream_t s = c->stream;
     const Level& L = c->lv[(size_t)l];
     const int nlev = (int)c->lv.size();
@@ -739,7 +761,9 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
         HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)L.A.nrows * sizeof(T), s));
         rres = f;
     } else {
-        if (u_ready) {
+        if (ready == 2) {
+            if (p.npre != 1) throw Fail{AMG_ERR_ARG, "a fused first sweep needs exactly one pre-sweep"};
+        } else if (ready == 1) {
             Trace tr(c, AMG_K_SMOOTH0_RES, l);
             if (p.npre == 1) residual(cur);
         } else {
@@ -800,7 +824,7 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
             Trace tr(c, AMG_K_RESTRICT, l);
             launch_spmv<T>(L.R, rres, (T*)C.f, c_smooths ? C.mv<T>() : nullptr, c_smooths ? (T*)C.u : nullptr, s);
         }
-        uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, c_smooths);
+        uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, c_smooths ? 1 : 0);
     }
     {
         Trace tr(c, AMG_K_PROLONG, l);
@@ -840,11 +864,13 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
 }
 
 // z = B r with r, z in FP64; in mixed precision the cycle itself runs in FP32.  With an
-// epilogue, the CG scalars rho (= r.z) and beta are formed in the same pass.
-void vcycle_apply(amg_ctx* c, const double* r, double* z, const RzEpilogue* ep = nullptr) {
+// epilogue, the CG scalars rho (= r.z) and beta are formed in the same pass.  `ready`:
+// what the CG update already formed -- FP64: 2 = level 0's first sweep and residual;
+// mixed: 1 = r in FP32 in level 0's f.
+void vcycle_apply(amg_ctx* c, const double* r, double* z, const RzEpilogue* ep = nullptr, int ready = 0) {
     Level& L0 = c->lv[0];
     if (mixed(c)) {
-        {
+        if (ready != 1) {
             Trace tr(c, AMG_K_CAST, 0);
             launch_cast_d2f(L0.A.nrows, r, (float*)L0.f, c->stream);
         }
@@ -855,7 +881,7 @@ void vcycle_apply(amg_ctx* c, const double* r, double* z, const RzEpilogue* ep =
         else
             launch_cast_f2d(L0.A.nrows, res, z, c->stream);
     } else {
-        vcycle_level<double>(c, 0, r, z, ep);
+        vcycle_level<double>(c, 0, r, z, ep, ready);
     }
 }
 
@@ -870,11 +896,14 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
     const int n = L0.A.nrows;
     const amg_params& p = c->prm;
     amg_solve_info inf{0, 0, 0.0};
+    // the CG residual; the fused update writes the new one to the other buffer
+    double* rc = c->r;
+    double* ra = c->r2;
     auto true_residual = [&]() {
         int nb;
         {
             Trace tr(c, AMG_K_CG_INIT, 0);
-            nb = launch_cg_init(L0.A, c->outer_val, f, c->x, c->r, c->rs, s);
+            nb = launch_cg_init(L0.A, c->outer_val, f, c->x, rc, c->rs, s);
         }
         read_red(c);
         return nb;
@@ -899,11 +928,16 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         return AMG_OK;
     }
     RzEpilogue ep{p.flexible_cg, 0};
-    auto precondition = [&](int first) {
-        vcycle_apply(c, c->r, c->z, &ep);
+    auto precondition = [&](int first, int ready) {
+        vcycle_apply(c, rc, c->z, &ep, ready);
         launch_fin_rz(ep.nb, p.flexible_cg, first, c->rs, s);
     };
-    precondition(1);
+    // The x, r update can start the next preconditioner application: on a level-0
+    // diagonal storage (FP64) it also forms the first V-cycle sweep and its residual; in
+    // mixed precision it stores r in FP32 for the V-cycle.
+    const bool fuse_dia = !mixed(c) && c->dia.ndiag > 0 && p.npre == 1 && c->lv.size() > 1;
+    const bool fuse_cast = mixed(c);
+    precondition(1, 0);
     double* pold = c->pa;
     double* pnew = c->pb;
     int it = 0;
@@ -920,18 +954,30 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
                         : launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
         }
         launch_fin_pq(nb_pq, c->rs, s);
+        int ready = 0;
         {
             Trace tr(c, AMG_K_CG_UPDATE, 0);
-            nb = launch_cg_update(n, pnew, c->q, c->x, c->r, c->rs, s);
+            if (fuse_dia) {
+                nb = launch_dia_update_smooth0(n, c->dia, pnew, c->q, c->x, rc, ra, L0.m, (double*)L0.u,
+                                               (double*)L0.r, c->rs, s);
+                std::swap(rc, ra);
+                ready = 2;
+            } else if (fuse_cast) {
+                nb = launch_cg_update_cast(n, pnew, c->q, c->x, rc, (float*)L0.f, c->rs, s);
+                ready = 1;
+            } else {
+                nb = launch_cg_update(n, pnew, c->q, c->x, rc, c->rs, s);
+            }
         }
         // Read ||r||^2 back, but queue the next preconditioner application first so the
         // device keeps working while the host decides; it is discarded on convergence.
-        HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.region(P_RR), (2 * RED_BLOCKS + S_COUNT) * sizeof(double),
-                                 hipMemcpyDeviceToHost, s));
+        // the update kernel wrote the ||r||^2 partials and the breakdown flag straight into
+        // the host mirror; otherwise they are copied there
+        if (c->rs.host == nullptr) queue_read_rr(c, nb);
         HIP_CHECK(hipEventRecord(c->ev_read, s));
         // (not with flexible CG: its r.z_old term reads the z a speculative sweep overwrites)
         const bool speculate = it < p.maxiter && !p.flexible_cg;
-        if (speculate) precondition(0);
+        if (speculate) precondition(0, ready);
         HIP_CHECK(hipEventSynchronize(c->ev_read));
         if (host_scal(c, S_FLAG) != 0.0) {
             c->err = "CG breakdown (p.Ap <= 0 or a non-finite scalar)";
@@ -950,10 +996,10 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
                 converged = true;
                 break;
             }
-            precondition(0);  // continue from the true residual
+            precondition(0, 0);  // continue from the true residual
         } else if (!speculate) {
             if (it >= p.maxiter) break;
-            precondition(0);
+            precondition(0, ready);
         }
         std::swap(pold, pnew);
     }
@@ -1009,7 +1055,6 @@ amg_ctx* create_ctx(const amg_params& p, void* stream) {
     c->stream = (hipStream_t)stream;
     try {
         c->d_flags = oalloc<int>(c, F_COUNT);
-        HIP_CHECK(hipHostMalloc((void**)&c->h_red, (2 * RED_BLOCKS + S_COUNT) * sizeof(double), hipHostMallocDefault));
         HIP_CHECK(hipHostMalloc((void**)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault));
         for (hipEvent_t& e : c->ev) HIP_CHECK(hipEventCreate(&e));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));

@@ -125,13 +125,22 @@ enum PartRegion { P_RZ = 0, P_RZOLD = 1, P_PQ = 2, P_RR = 3, P_FF = 4 };
 constexpr int RED_BLOCKS = 1024;
 
 struct RedScratch {
-    double* part = nullptr;  // 3 * cap + 2 * RED_BLOCKS + S_COUNT doubles
+    // [P_RZ cap][P_RZOLD cap][P_PQ cap][scalars S_COUNT][P_RR cap][P_FF RED_BLOCKS]: the
+    // scalars and the ||r||^2 partials are adjacent, so one copy brings both to the host
+    double* part = nullptr;
     int cap = 0;
+    // device address of the host mirror (mapped, coherent pinned memory): the CG update
+    // kernels write their ||r||^2 partials and the breakdown flag there directly
+    double* host = nullptr;
     __host__ __device__ double* region(int k) const {
-        return k <= P_PQ ? part + (size_t)k * cap : part + 3 * (size_t)cap + (size_t)(k - P_RR) * RED_BLOCKS;
+        if (k <= P_PQ) return part + (size_t)k * cap;
+        if (k == P_RR) return part + 3 * (size_t)cap + S_COUNT;
+        return part + 4 * (size_t)cap + S_COUNT;
     }
-    __host__ __device__ double* scal() const { return part + 3 * (size_t)cap + 2 * (size_t)RED_BLOCKS; }
-    static size_t doubles(int cap) { return 3 * (size_t)cap + 2 * (size_t)RED_BLOCKS + S_COUNT; }
+    __host__ __device__ double* scal() const { return part + 3 * (size_t)cap; }
+    static size_t doubles(int cap) { return 4 * (size_t)cap + S_COUNT + (size_t)RED_BLOCKS; }
+    // the host mirror of [scalars, P_RR, P_FF]
+    static size_t host_doubles(int cap) { return S_COUNT + (size_t)cap + (size_t)RED_BLOCKS; }
 };
 
 // Row-block kernels: RB_THREADS threads, at most RB_CAP nonzeros staged in LDS per block.
@@ -186,6 +195,11 @@ template <typename T>
 void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipStream_t s);
 template <typename T>
 void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, T* uout, hipStream_t s);
+int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double* q, double* x, const double* r,
+                              double* rn, const double* m, double* u, double* rv, const RedScratch& rs,
+                              hipStream_t s);
+int launch_cg_update_cast(int n, const double* p, const double* q, double* x, double* r, float* r32,
+                          const RedScratch& rs, hipStream_t s);
 int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
                          int flexible, const RedScratch& rs, hipStream_t s);
 int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,
@@ -321,10 +335,10 @@ struct amg_ctx {
     amgmi::Dia dia;               // diagonal storage of A_0 (ndiag 0: CSR kernels)
     double* cinv = nullptr;       // dense inverse of the coarsest operator (FP64)
     // CG state
-    double *x = nullptr, *r = nullptr, *z = nullptr, *zold = nullptr, *pa = nullptr, *pb = nullptr,
+    double *x = nullptr, *r = nullptr, *r2 = nullptr, *z = nullptr, *zold = nullptr, *pa = nullptr, *pb = nullptr,
            *q = nullptr;
     amgmi::RedScratch rs{};
-    double* h_red = nullptr;      // pinned host copy of the P_RR, P_FF partials and the scalars
+    double* h_red = nullptr;      // pinned host mirror of the scalars and the P_RR, P_FF partials
     int* d_flags = nullptr;       // setup flags
     int* h_flags = nullptr;       // pinned
     // pending pattern for amg_rebuild(..., pattern_changed)

@@ -143,6 +143,14 @@ __device__ __forceinline__ double block_sum(const double* __restrict__ p, int nb
     return t;
 }
 
+// Where the CG update kernels put their ||r||^2 partials: straight into the host mirror
+// when there is one (workgroup 0 also copies the breakdown flag there), else P_RR.
+__device__ __forceinline__ double* rr_dest(const RedScratch& rs, bool bad) {
+    if (rs.host == nullptr) return rs.region(P_RR);
+    if (blockIdx.x == 0 && threadIdx.x == 0) rs.host[S_FLAG] = bad ? 1.0 : 0.0;
+    return rs.host + S_COUNT;
+}
+
 // ------------------------------------------------------------------ V-cycle kernels
 
 // y = A x; with m2 given also y2 = m2 * y (the restriction forms the coarse level's first
@@ -562,6 +570,37 @@ void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 
+// The CG update x += alpha p, r_new = r - alpha q (nothing moves on breakdown) fused with
+// the first V-cycle sweep from zero on level 0 and its residual: u = m r_new and
+// rv = r_new - A u, where every neighbour's r_new is formed from r and q with the same
+// operation as its owner row uses (so r is read, and r_new written to another buffer);
+// ||r_new||^2 partials, one per workgroup.
+__global__ __launch_bounds__(TPB) void k_dia_update_smooth0(int n, int nd, DiaOff o, const double* __restrict__ v,
+                                                            const double* __restrict__ p,
+                                                            const double* __restrict__ q, double* __restrict__ x,
+                                                            const double* __restrict__ r, double* __restrict__ rn,
+                                                            const double* __restrict__ m, double* __restrict__ u,
+                                                            double* __restrict__ rv, RedScratch rs) {
+    const double* sc = rs.scal();
+    const bool bad = sc[S_FLAG] != 0.0;
+    const double alpha = sc[S_ALPHA];
+    auto rnew = [&](int j) { return bad ? r[j] : __builtin_fma(-alpha, q[j], r[j]); };
+    const int lb = xcd_block();
+    const int i = lb * TPB + threadIdx.x;
+    double loc[1] = {0.0};
+    if (i < n) {
+        const double s = dia_row(i, n, nd, o, v, [&](int j) { return m[j] * rnew(j); });
+        const double ri = rnew(i);
+        if (!bad) x[i] = __builtin_fma(alpha, p[i], x[i]);
+        rn[i] = ri;
+        u[i] = m[i] * ri;
+        rv[i] = ri - s;
+        loc[0] = ri * ri;
+    }
+    double* const dst[1] = {rr_dest(rs, bad)};
+    block_store<1>(loc, dst, lb);
+}
+
 static inline unsigned dia_blocks(int n) { return (unsigned)((n + TPB - 1) / TPB); }
 
 template <typename T>
@@ -597,6 +636,16 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     k_dia_cg_pq<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, first, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+
+int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double* q, double* x, const double* r,
+                              double* rn, const double* m, double* u, double* rv, const RedScratch& rs,
+                              hipStream_t s) {
+    const int nb = (int)dia_blocks(n);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    k_dia_update_smooth0<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
     HIP_LAUNCH_CHECK();
     return nb;
 }
@@ -977,13 +1026,36 @@ __global__ __launch_bounds__(TPB) void k_cg_update(int n, const double* __restri
     for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
         double ri = r[i];
         if (!bad) {
-            x[i] += alpha * p[i];
-            ri -= alpha * q[i];
+            x[i] = __builtin_fma(alpha, p[i], x[i]);
+            ri = __builtin_fma(-alpha, q[i], ri);
             r[i] = ri;
         }
         loc[0] += ri * ri;
     }
-    double* const dst[1] = {rs.region(P_RR)};
+    double* const dst[1] = {rr_dest(rs, bad)};
+    block_store<1>(loc, dst, blockIdx.x);
+}
+
+// The same update, also storing r in FP32 for the mixed-precision V-cycle (bounded grid).
+__global__ __launch_bounds__(TPB) void k_cg_update_cast(int n, const double* __restrict__ p,
+                                                        const double* __restrict__ q, double* __restrict__ x,
+                                                        double* __restrict__ r, float* __restrict__ r32,
+                                                        RedScratch rs) {
+    const double* sc = rs.scal();
+    const bool bad = sc[S_FLAG] != 0.0;
+    const double alpha = sc[S_ALPHA];
+    double loc[1] = {0.0};
+    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+        double ri = r[i];
+        if (!bad) {
+            x[i] = __builtin_fma(alpha, p[i], x[i]);
+            ri = __builtin_fma(-alpha, q[i], ri);
+            r[i] = ri;
+        }
+        r32[i] = (float)ri;
+        loc[0] += ri * ri;
+    }
+    double* const dst[1] = {rr_dest(rs, bad)};
     block_store<1>(loc, dst, blockIdx.x);
 }
 
@@ -1035,6 +1107,13 @@ int launch_cg_update(int n, const double* p, const double* q, double* x, double*
                      hipStream_t s) {
     const int nb = red_grid_elems(n);
     k_cg_update<<<nb, TPB, 0, s>>>(n, p, q, x, r, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+int launch_cg_update_cast(int n, const double* p, const double* q, double* x, double* r, float* r32,
+                          const RedScratch& rs, hipStream_t s) {
+    const int nb = red_grid_elems(n);
+    k_cg_update_cast<<<nb, TPB, 0, s>>>(n, p, q, x, r, r32, rs);
     HIP_LAUNCH_CHECK();
     return nb;
 }

@@ -420,3 +420,31 @@ def test_full_size_128_partial_rebuild_and_solve():
     assert info["converged"] and info["rel_res_true"] <= 1e-8
     assert abs(info["iters"] - io["iters"]) <= 1
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+
+
+@pytest.mark.parametrize("precision,flexible", [(0, 0), (1, 0), (0, 1)])
+def test_host_mirror_matches_copy(monkeypatch, precision, flexible):
+    """The CG update kernels write the ||r||^2 partials and the breakdown flag straight into
+    mapped host memory; the solve then takes exactly the decisions, iterations and iterates
+    it takes when they are copied back after the kernel (over several solves and rebuilds)."""
+    from paper_2108_02054_amd import AMG
+
+    p, c, v0 = two_fluid_7pt(32, front_c1(0))
+    vals = [two_fluid_7pt(32, front_c1(t))[2] for t in (1, 2, 3)]
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), precision=precision, flexible_cg=flexible)
+        out = []
+        for t, vt in enumerate(vals):
+            g.rebuild(T(vt))
+            u, info = g.solve(T(rhs_uniform(32**3, 1, t)))
+            out.append((info["iters"], info["converged"], u.cpu().numpy()))
+        g.close()
+        return out
+
+    mapped = run()
+    monkeypatch.setenv("AMGMI_NO_HOST_WRITE", "1")
+    copied = run()
+    for (im, cm, um), (ic, cc, uc) in zip(mapped, copied):
+        assert cm and cc and im == ic
+        assert np.array_equal(um, uc)
