@@ -310,17 +310,21 @@ def test_lane_group_kernels_parity(monkeypatch):
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
 
 
-GALERKIN_FORMS = ["pos", "pos:4", "pos:16", "pos:64", "pos16", "lanes"]
+GALERKIN_FORMS = ["pos", "pos:4", "pos:16", "pos:64", "pos16", "lanes", "nodia"]
 
 
 @pytest.mark.parametrize("form", GALERKIN_FORMS)
 @pytest.mark.parametrize("smoother", [0, 1])
 def test_galerkin_forms_parity(monkeypatch, form, smoother):
     """Every Galerkin form (the position-map form at several lanes per row and with one-
-    and two-byte positions, and the lane-group kernels) gives the oracle's FP64 hierarchy
-    bit for bit after a partial rebuild, with the fused value ingest and smoother
-    diagonal, on 7-point and 27-point patterns."""
-    monkeypatch.setenv("AMGMI_GALERKIN", form)
+    and two-byte positions, the lane-group kernels, and with level 0 in CSR rather than
+    diagonal storage) gives the oracle's FP64 hierarchy bit for bit after a partial
+    rebuild, with the fused value ingest and smoother diagonal, on 7-point and 27-point
+    patterns."""
+    if form == "nodia":  # level 0 in CSR
+        monkeypatch.setenv("AMGMI_NO_DIA", "1")
+    else:
+        monkeypatch.setenv("AMGMI_GALERKIN", form)
     print(f"form {form} smoother {smoother}", flush=True)
     p, c, v0 = two_fluid_7pt(32, front_c1(0))
     _, _, v1 = two_fluid_7pt(32, front_c1(5))
