@@ -942,6 +942,7 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
     double* pnew = c->pb;
     int it = 0;
     bool converged = false;
+    double rate = 1.0, rate_last = 1.0;  // recent per-iteration residual reduction
     while (it < p.maxiter) {
         ++it;
         int nb_pq;
@@ -976,7 +977,11 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         if (c->rs.host == nullptr) queue_read_rr(c, nb);
         HIP_CHECK(hipEventRecord(c->ev_read, s));
         // (not with flexible CG: its r.z_old term reads the z a speculative sweep overwrites)
-        const bool speculate = it < p.maxiter && !p.flexible_cg;
+        // ... except when this update is likely the last one: the residual reduction of the
+        // last two iterations predicts whether it reaches the tolerance, and a speculative
+        // application after the final update would only delay the end of the solve.
+        const double predicted = res * rate;
+        const bool speculate = it < p.maxiter && !p.flexible_cg && !(it > 2 && predicted <= 3.0 * p.rtol);
         if (speculate) precondition(0, ready);
         HIP_CHECK(hipEventSynchronize(c->ev_read));
         if (host_scal(c, S_FLAG) != 0.0) {
@@ -988,7 +993,11 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
             }
             return AMG_ERR_BREAKDOWN;
         }
+        const double res_prev = res;
         res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
+        const double ratio = res_prev > 0.0 ? res / res_prev : 1.0;
+        rate = it == 1 ? ratio : std::sqrt(rate_last * ratio);  // geometric mean of the last two
+        rate_last = ratio;
         if (res <= p.rtol) {
             nb = true_residual();
             res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
