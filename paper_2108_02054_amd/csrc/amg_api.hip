@@ -56,7 +56,12 @@ int pick_rows_per_block(const int32_t* p, int32_t n) {
             const int64_t w = (int64_t)p[r1] - p[r0];
             if (w > worst) worst = w;
         }
-        if (worst <= RB_CAP) return rpb;
+        if (worst <= RB_CAP) {
+            // small matrices: fewer rows per workgroup, so that about RB_MIN_BLOCKS
+            // workgroups (four per CU) share the latency of their dependent loads
+            while (rpb > 1 && ((int64_t)n + rpb - 1) / rpb < RB_MIN_BLOCKS) rpb >>= 1;
+            return rpb;
+        }
     }
     return 0;
 }

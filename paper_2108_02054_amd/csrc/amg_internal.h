@@ -146,6 +146,7 @@ struct RedScratch {
 // Row-block kernels: RB_THREADS threads, at most RB_CAP nonzeros staged in LDS per block.
 constexpr int RB_THREADS = 256;
 constexpr int RB_CAP = 2048;
+constexpr int RB_MIN_BLOCKS = 1024;
 
 int lane_group(double avg_per_row);  // power of two in [2, 64]
 int pick_rows_per_block(const int32_t* host_ptr, int32_t nrows);  // 0: no row blocking
