@@ -908,7 +908,9 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         int nb;
         {
             Trace tr(c, AMG_K_CG_INIT, 0);
-            nb = launch_cg_init(L0.A, c->outer_val, f, c->x, rc, c->rs, s);
+            nb = (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
+                     ? launch_dia_cg_init(n, c->dia, f, c->x, rc, c->rs, s)
+                     : launch_cg_init(L0.A, c->outer_val, f, c->x, rc, c->rs, s);
         }
         read_red(c);
         return nb;

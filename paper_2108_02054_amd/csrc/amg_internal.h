@@ -201,6 +201,8 @@ int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double
                               hipStream_t s);
 int launch_cg_update_cast(int n, const double* p, const double* q, double* x, double* r, float* r32,
                           const RedScratch& rs, hipStream_t s);
+int launch_dia_cg_init(int n, const Dia& D, const double* f, const double* x, double* r, const RedScratch& rs,
+                       hipStream_t s);
 int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
                          int flexible, const RedScratch& rs, hipStream_t s);
 int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,

@@ -220,19 +220,27 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
                 if (c0 + u == dp) d = a;
                 ss = ss + a * a;
             }
-        for (int u0 = 0; u0 < nt; u0 += WF_AHEAD) {
-            int up[WF_AHEAD], ul[WF_AHEAD];
-            T bv[WF_AHEAD];
+        // Batches of WF_AHEAD entries, double-buffered: the terms of the next batch are
+        // loaded before the current batch is added.
+        int up[WF_AHEAD], ul[WF_AHEAD];
+        T bv[WF_AHEAD];
+        auto load = [&](int u0, int (&qp)[WF_AHEAD], int (&ql)[WF_AHEAD], T (&qv)[WF_AHEAD]) {
 #pragma unroll
             for (int i = 0; i < WF_AHEAD; ++i) {  // first G terms of each entry, in flight together
                 const int u = u0 + i < nt ? u0 + i : nt - 1;
                 const WfEnt w = ent[u];
-                ul[i] = u0 + i < nt ? w.len : 0;
-                if (g < ul[i]) {
-                    up[i] = (int)prow[w.to + g];
-                    bv[i] = Bval[w.bs + g];
+                ql[i] = u0 + i < nt ? w.len : 0;
+                if (g < ql[i]) {
+                    qp[i] = (int)prow[w.to + g];
+                    qv[i] = Bval[w.bs + g];
                 }
             }
+        };
+        load(0, up, ul, bv);
+        for (int u0 = 0; u0 < nt; u0 += WF_AHEAD) {
+            int up2[WF_AHEAD], ul2[WF_AHEAD];
+            T bv2[WF_AHEAD];
+            if (u0 + WF_AHEAD < nt) load(u0 + WF_AHEAD, up2, ul2, bv2);  // uniform across the group
 #pragma unroll
             for (int i = 0; i < WF_AHEAD; ++i) {
                 if (ul[i] == 0) continue;  // uniform across the group
@@ -246,6 +254,12 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
                         if (p < len) sacc[p] = sacc[p] + lv * b;
                     }
                 }
+            }
+#pragma unroll
+            for (int i = 0; i < WF_AHEAD; ++i) {
+                up[i] = up2[i];
+                ul[i] = ul2[i];
+                bv[i] = bv2[i];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

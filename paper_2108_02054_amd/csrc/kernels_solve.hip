@@ -601,6 +601,23 @@ __global__ __launch_bounds__(TPB) void k_dia_update_smooth0(int n, int nd, DiaOf
     block_store<1>(loc, dst, lb);
 }
 
+// r = f - A x on the diagonal storage, with ||r||^2 and ||f||^2 partials (bounded grid,
+// host-summed).
+__global__ __launch_bounds__(TPB) void k_dia_cg_init(int n, int nd, DiaOff o, const double* __restrict__ v,
+                                                     const double* __restrict__ f, const double* __restrict__ x,
+                                                     double* __restrict__ r, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+        const double fi = f[i];
+        const double ri = fi - dia_row(i, n, nd, o, v, [&](int j) { return x[j]; });
+        r[i] = ri;
+        loc[0] += ri * ri;
+        loc[1] += fi * fi;
+    }
+    double* const dst[2] = {rs.region(P_RR), rs.region(P_FF)};
+    block_store<2>(loc, dst, blockIdx.x);
+}
+
 static inline unsigned dia_blocks(int n) { return (unsigned)((n + TPB - 1) / TPB); }
 
 template <typename T>
@@ -622,6 +639,13 @@ template <typename T>
 void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
     k_dia_jacobi<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, uout);
     HIP_LAUNCH_CHECK();
+}
+int launch_dia_cg_init(int n, const Dia& D, const double* f, const double* x, double* r, const RedScratch& rs,
+                       hipStream_t s) {
+    const int nb = red_grid_elems(n);
+    k_dia_cg_init<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, f, x, r, rs);
+    HIP_LAUNCH_CHECK();
+    return nb;
 }
 int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
                          int flexible, const RedScratch& rs, hipStream_t s) {
