@@ -77,23 +77,25 @@ def copy_probe(mib):
 
 # ------------------------------------------------------------------ algorithmic bytes
 
-def kernel_bytes(dims, sv_h, ndiag=0):
+def kernel_bytes(dims, sv_h, ndiag=0, sym=False):
     """Algorithmic bytes per launch of the level-0 kernels: each operand read once, each
     output written once, vector gathers counted once.  CSR: 4-byte indices; an operator
-    in diagonal storage (ndiag > 0) needs no index arrays, so its bytes are its values.
+    in diagonal storage (ndiag > 0) needs no index arrays, so its bytes are its values,
+    and with symmetric values (sym) only the main diagonal and the entries above it.
     sv_h is the value size of the hierarchy (8 FP64, 4 FP32); the CG kernels are FP64."""
     n, nnzA, nc, nnzP, nnzAP = dims[0]
     nnzAc = dims[1][1]
     ind = lambda rows, nnz: 4 * (rows + 1) + 4 * nnz  # noqa: E731
     ind0 = (lambda rows, nnz: 0) if ndiag > 0 else ind  # noqa: E731
+    a0 = (nnzA + n) // 2 if (ndiag > 0 and sym) else nnzA  # level-0 matrix entries read
     b = {}
     # Krylov operator SpMV fused with p = z + beta p and p.q: A, z, p_old read; p_new, q written
-    b["cg_pq"] = ind0(n, nnzA) + 8 * nnzA + 8 * 4 * n
+    b["cg_pq"] = ind0(n, nnzA) + 8 * a0 + 8 * 4 * n
     b["cg_update"] = 8 * 6 * n          # p, q, x, r read; x, r written
     b["cg_rz"] = 8 * 2 * n
     b["cg_init"] = ind(n, nnzA) + 8 * nnzA + 8 * 3 * n
-    b["smooth0_res"] = ind0(n, nnzA) + sv_h * nnzA + sv_h * 4 * n   # m, f read; u, r written
-    b["jacobi"] = ind0(n, nnzA) + sv_h * nnzA + sv_h * 4 * n        # m, f, u read; u' written
+    b["smooth0_res"] = ind0(n, nnzA) + sv_h * a0 + sv_h * 4 * n   # m, f read; u, r written
+    b["jacobi"] = ind0(n, nnzA) + sv_h * a0 + sv_h * 4 * n        # m, f, u read; u' written
     b["restrict"] = ind(nc, nnzP) + sv_h * nnzP + sv_h * (n + nc)
     b["prolong"] = ind(n, nnzP) + sv_h * nnzP + sv_h * (nc + 2 * n)
     b["smoother"] = ind(n, nnzA) + sv_h * nnzA + sv_h * n
@@ -200,6 +202,7 @@ def main():
     L = amg.num_levels
     dims = [amg.dims(l) for l in range(L)]
     ndiag = amg.level_format(0)
+    nread = amg.diagonals_read(0)
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
     log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
     ph = amg.phase_times()
@@ -220,7 +223,7 @@ def main():
     amg.trace([], level=0)
     amg.close()
 
-    kb = kernel_bytes(dims, 8, ndiag)
+    kb = kernel_bytes(dims, 8, ndiag, sym=0 < nread < ndiag)
     # live measurement over the timed region
     pq_ms, pq_cnt = kt.get("cg_pq", (0.0, 0))
     n_solves = K
@@ -268,7 +271,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(cfg_id, N, n, nnz),
                    "grid": N, "n": n, "nnz": nnz, "levels": L, "level_rows": [d[0] for d in dims],
-                   "level_nnz": [d[1] for d in dims], "level0_storage": (f"{ndiag} diagonals" if ndiag else "CSR"),
+                   "level_nnz": [d[1] for d in dims], "level0_storage": (f"{ndiag} diagonals, {nread} read per row" if ndiag else "CSR"),
                    "parallelism": "single GPU"},
         "iters_partial": info_p["iters"],
         "converged_all": info_p["converged"],

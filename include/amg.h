@@ -132,8 +132,12 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims);
  * stored diagonals when the level is kept in diagonal storage (the finest level of a
  * stencil operator: at most 32 distinct column offsets, well filled; the values are
  * refreshed from the CSR copy after every rebuild), or 0 when the CSR kernels are used.
- * Errors: AMG_ERR_ARG for a NULL argument or l out of range. */
-amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag);
+ * *nread (host, may be NULL) receives the number of diagonals the solve kernels read per
+ * row: (ndiag+1)/2 when the offsets are symmetric and the values last refreshed were
+ * found symmetric (the solve reads each sub-diagonal entry as its mirror; known from the
+ * first solve after a rebuild on), else ndiag.
+ * Errors: AMG_ERR_ARG for a NULL ndiag or l out of range. */
+amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread);
 
 /* Copy level l to host arrays (any may be NULL).  agg[n_l], strong[nnz(A_l)] exist on
  * aggregated levels; P on non-coarsest levels; m (smoother diagonal) on non-coarsest

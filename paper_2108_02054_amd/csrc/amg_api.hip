@@ -323,11 +323,23 @@ void release_dia(amg_ctx* c) {
     c->dia = Dia{};
 }
 
+// The full set of diagonals is always written; when the offsets are symmetric the values
+// are checked on the device, and the solve switches to the symmetric read (half the
+// diagonals) once it has seen the result (c->dia.off.sym, set in the CG's first
+// residual read-back).
 void refresh_dia(amg_ctx* c) {
     if (c->dia.ndiag == 0) return;
     const Level& L0 = c->lv[0];
     launch_dia_scatter<double>(L0.A, c->dia, L0.A.val, c->dia.val, c->stream);
     if (c->dia.val32) launch_dia_scatter<float>(L0.A, c->dia, L0.A.val, c->dia.val32, c->stream);
+    c->dia.off.sym = 0;
+    if (c->dia.symoff) launch_dia_symcheck(L0.A.nrows, c->dia, c->rs.scal(), c->stream);
+}
+
+// After a read-back of the scalar slots: use the symmetric read when the last refresh
+// found symmetric values.
+void note_dia_symmetry(amg_ctx* c) {
+    if (c->dia.ndiag > 0 && c->dia.symoff) c->dia.off.sym = host_scal(c, S_ASYM) == 0.0 ? 1 : 0;
 }
 
 void configure_dia(amg_ctx* c) {
@@ -342,6 +354,16 @@ void configure_dia(amg_ctx* c) {
     Dia D;
     D.ndiag = nd;
     for (int d = 0; d < nd; ++d) D.off.off[d] = offs[(size_t)d];
+    D.symoff = (nd & 1) == 1 && offs[(size_t)nd / 2] == 0;
+    for (int d = 0; d < nd / 2 && D.symoff; ++d) D.symoff = offs[(size_t)d] == -offs[(size_t)(nd - 1 - d)];
+    // the 7-point marching kernels: offsets -a, -b, -1, 0, 1, b, a
+    const bool seven = nd == 7 && offs[2] == -1 && offs[3] == 0 && offs[4] == 1 && offs[1] == -offs[5] &&
+                       offs[0] == -offs[6];
+    if (seven && std::getenv("AMGMI_NO_MARCH") == nullptr && march_blocks(A.nrows, offs[6]) <= c->rs.cap) {
+        D.march_a = offs[6];
+        D.march_b = offs[5];
+    }
+    if (std::getenv("AMGMI_NO_DIA_SYM") != nullptr) D.symoff = false;
     D.slot = halloc<uint8_t>(c, (size_t)A.nnz);
     launch_dia_slots(A, D, s);
     const size_t nv = (size_t)nd * (size_t)A.nrows;
@@ -913,6 +935,7 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
                      : launch_cg_init(L0.A, c->outer_val, f, c->x, rc, c->rs, s);
         }
         read_red(c);
+        note_dia_symmetry(c);
         return nb;
     };
     launch_copy(n, u, c->x, s);
@@ -1294,9 +1317,10 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims) {
     return AMG_OK;
 }
 
-amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag) {
+amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread) {
     if (!c || !ndiag || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
     *ndiag = l == 0 ? c->dia.ndiag : 0;
+    if (nread) *nread = (l == 0 && c->dia.off.sym) ? (c->dia.ndiag + 1) / 2 : *ndiag;
     return AMG_OK;
 }
 

@@ -114,6 +114,7 @@ enum Scal {
     S_BETA = 4,
     S_ALPHA = 5,
     S_RHO_USED = 6,  // the rho of the current iteration's alpha (beta's denominator)
+    S_ASYM = 7,      // diagonal storage: 0 when the last refreshed values are symmetric
     S_COUNT = 8
 };
 
@@ -171,10 +172,16 @@ void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s);
 constexpr int DIA_MAX = 32;
 struct DiaOff {
     int off[DIA_MAX];
+    // 1: the values are symmetric, so the solve kernels read each sub-diagonal entry
+    // A(i, j) as the super-diagonal entry A(j, i) and never touch the lower diagonals
+    int sym;
 };
 struct Dia {
     int ndiag = 0;              // 0: not used
     DiaOff off{};
+    bool symoff = false;        // the offsets are -k..k-symmetric and include 0
+    // 7-point marching kernels: offsets -a, -b, -1, 0, 1, b, a; march_a == 0: not used
+    int march_a = 0, march_b = 0;
     double* val = nullptr;      // FP64 values (Krylov operator and FP64 V-cycle)
     float* val32 = nullptr;     // FP32 values (mixed-precision V-cycle)
     uint8_t* slot = nullptr;    // diagonal of every stored entry of A_0
@@ -187,9 +194,14 @@ template <>
 inline const float* Dia::v<float>() const { return val32; }
 
 std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
+// Workgroups of the 7-point marching kernels for n rows with plane stride a.
+int march_blocks(int n, int a);
 void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s);
 template <typename T>
 void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s);
+// scal[S_ASYM] = 0 when every stored sub-diagonal entry equals its mirror (bit for bit), 1
+// otherwise; needs D.symoff and the FP64 values just scattered.
+void launch_dia_symcheck(int n, const Dia& D, double* scal, hipStream_t s);
 template <typename T>
 void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T* u, T* r, hipStream_t s);
 template <typename T>

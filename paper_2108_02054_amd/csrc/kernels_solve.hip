@@ -16,6 +16,8 @@
 #include <climits>
 #include <vector>
 
+#include <type_traits>
+
 #include "amg_internal.h"
 
 namespace amgmi {
@@ -391,16 +393,63 @@ void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
 // never read.  Values and vector entries are read with fully coalesced loads and no index
 // arrays.  Reductions write one partial per workgroup (logical block order).
 
-template <typename T, typename X>
-__device__ __forceinline__ T dia_row(int i, int n, int nd, const DiaOff& o, const T* __restrict__ v, X xget) {
+//
+// Symmetric values (o.sym): the offsets are -k..k around a main diagonal in the middle,
+// and the entry on diagonal d < nd/2 of row i is read as the entry on the mirrored
+// diagonal nd-1-d of row j = i + off[d]; that is the same number, so the sum (same terms,
+// same order) is the same to the bit, and only the main and upper diagonals are read.
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+    if constexpr (std::is_same<T, double>::value)
+        return __builtin_fma(a, b, c);
+    else
+        return __builtin_fmaf(a, b, c);
+}
+
+// ND > 0: the diagonal count as a compile-time constant (the loops unroll fully).  Every
+// load is issued unconditionally (a column outside [0, n) reads row i's own entries
+// instead) and an out-of-range term is dropped with a select, not a branch, so that all
+// of a row's loads are in flight together.
+template <int ND, typename T, typename X>
+__device__ __forceinline__ T dia_row(int i, int n, int nd_rt, const DiaOff& o, const T* __restrict__ v, X xget) {
+    const int nd = ND > 0 ? ND : nd_rt;
     T s = 0;
-#pragma unroll 8
+    if (o.sym) {
+        const int h = nd >> 1;
+#pragma unroll
+        for (int d = 0; d < h; ++d) {
+            const int j = i + o.off[d];
+            const bool in = (unsigned)j < (unsigned)n;
+            const int jj = in ? j : i;
+            const T t = fmadd(v[(size_t)(nd - 1 - d) * n + jj], xget(jj), s);
+            s = in ? t : s;
+        }
+#pragma unroll
+        for (int d = h; d < nd; ++d) {
+            const int j = i + o.off[d];
+            const bool in = (unsigned)j < (unsigned)n;
+            const T t = fmadd(v[(size_t)d * n + i], xget(in ? j : i), s);
+            s = in ? t : s;
+        }
+        return s;
+    }
+#pragma unroll
     for (int d = 0; d < nd; ++d) {
         const int j = i + o.off[d];
-        const T a = v[(size_t)d * n + i];
-        if ((unsigned)j < (unsigned)n) s += a * xget(j);
+        const bool in = (unsigned)j < (unsigned)n;
+        const T t = fmadd(v[(size_t)d * n + i], xget(in ? j : i), s);
+        s = in ? t : s;
     }
     return s;
+}
+
+// Calls f(std::integral_constant<int, ND>) with ND = 7 for the 7-point stencil, else 0.
+template <typename F>
+inline void dia_nd(int nd, F&& f) {
+    if (nd == 7)
+        f(std::integral_constant<int, 7>{});
+    else
+        f(std::integral_constant<int, 0>{});
 }
 
 template <typename T>
@@ -412,37 +461,59 @@ __global__ __launch_bounds__(TPB) void k_dia_scatter(int n, const int* __restric
     for (int t = ptr[i]; t < ptr[i + 1]; ++t) dval[(size_t)slot[t] * n + i] = (T)val[t];
 }
 
-template <typename T>
+// Compares every sub-diagonal value with its mirror (absent entries are stored zeros, so
+// the pattern is compared too).  k_dia_clear zeroes the flag in a launch of its own first;
+// the check only ever stores 1, so the order of its stores does not matter.
+__global__ void k_dia_clear(double* __restrict__ flag) {
+    if (threadIdx.x == 0) flag[0] = 0.0;
+}
+
+__global__ __launch_bounds__(TPB) void k_dia_symcheck(int n, int nd, DiaOff o, const double* __restrict__ v,
+                                                      double* __restrict__ flag) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    bool bad = false;
+    for (int d = 0; d < (nd >> 1); ++d) {
+        const int j = i + o.off[d];
+        if ((unsigned)j < (unsigned)n)
+            bad |= __double_as_longlong(v[(size_t)d * n + i]) !=
+                   __double_as_longlong(v[(size_t)(nd - 1 - d) * n + j]);
+    }
+    if (bad) flag[0] = 1.0;
+}
+
+template <typename T, int ND>
 __global__ __launch_bounds__(TPB) void k_dia_smooth0_residual(int n, int nd, DiaOff o, const T* __restrict__ v,
                                                               const T* __restrict__ m, const T* __restrict__ f,
                                                               T* __restrict__ u, T* __restrict__ r) {
     const int i = xcd_block() * TPB + threadIdx.x;
     if (i >= n) return;
-    const T s = dia_row(i, n, nd, o, v, [&](int j) { return m[j] * f[j]; });
+    const T s = dia_row<ND>(i, n, nd, o, v, [&](int j) { return m[j] * f[j]; });
     const T fi = f[i];
     u[i] = m[i] * fi;
     r[i] = fi - s;
 }
 
-template <typename T>
+template <typename T, int ND>
 __global__ __launch_bounds__(TPB) void k_dia_residual(int n, int nd, DiaOff o, const T* __restrict__ v,
                                                       const T* __restrict__ f, const T* __restrict__ u,
                                                       T* __restrict__ r) {
     const int i = xcd_block() * TPB + threadIdx.x;
     if (i >= n) return;
-    r[i] = f[i] - dia_row(i, n, nd, o, v, [&](int j) { return u[j]; });
+    r[i] = f[i] - dia_row<ND>(i, n, nd, o, v, [&](int j) { return u[j]; });
 }
 
-template <typename T>
+template <typename T, int ND>
 __global__ __launch_bounds__(TPB) void k_dia_jacobi(int n, int nd, DiaOff o, const T* __restrict__ v,
                                                     const T* __restrict__ m, const T* __restrict__ f,
                                                     const T* __restrict__ u, T* __restrict__ uout) {
     const int i = xcd_block() * TPB + threadIdx.x;
     if (i >= n) return;
-    const T s = dia_row(i, n, nd, o, v, [&](int j) { return u[j]; });
+    const T s = dia_row<ND>(i, n, nd, o, v, [&](int j) { return u[j]; });
     uout[i] = u[i] + m[i] * (f[i] - s);
 }
 
+template <int ND>
 __global__ __launch_bounds__(TPB) void k_dia_jacobi_rz(int n, int nd, DiaOff o, const double* __restrict__ v,
                                                        const double* __restrict__ m, const double* __restrict__ r,
                                                        const double* __restrict__ u, double* __restrict__ z,
@@ -451,7 +522,7 @@ __global__ __launch_bounds__(TPB) void k_dia_jacobi_rz(int n, int nd, DiaOff o, 
     const int i = lb * TPB + threadIdx.x;
     double loc[2] = {0.0, 0.0};
     if (i < n) {
-        const double s = dia_row(i, n, nd, o, v, [&](int j) { return u[j]; });
+        const double s = dia_row<ND>(i, n, nd, o, v, [&](int j) { return u[j]; });
         const double ri = r[i];
         const double zi = u[i] + m[i] * (ri - s);
         if (flexible) loc[1] += ri * z[i];
@@ -462,17 +533,18 @@ __global__ __launch_bounds__(TPB) void k_dia_jacobi_rz(int n, int nd, DiaOff o, 
     block_store<2>(loc, dst, lb);
 }
 
+template <int ND, bool FIRST>
 __global__ __launch_bounds__(TPB) void k_dia_cg_pq(int n, int nd, DiaOff o, const double* __restrict__ v,
                                                    const double* __restrict__ z, const double* __restrict__ pold,
-                                                   double* __restrict__ pnew, double* __restrict__ q, int first,
+                                                   double* __restrict__ pnew, double* __restrict__ q,
                                                    RedScratch rs) {
-    const double beta = first ? 0.0 : rs.scal()[S_BETA];
-    auto pv = [&](int j) { return first ? z[j] : __builtin_fma(beta, pold[j], z[j]); };
+    const double beta = FIRST ? 0.0 : rs.scal()[S_BETA];
+    auto pv = [&](int j) { return FIRST ? z[j] : __builtin_fma(beta, pold[j], z[j]); };
     const int lb = xcd_block();
     const int i = lb * TPB + threadIdx.x;
     double loc[1] = {0.0};
     if (i < n) {
-        const double qi = dia_row(i, n, nd, o, v, pv);
+        const double qi = dia_row<ND>(i, n, nd, o, v, pv);
         const double pi = pv(i);
         pnew[i] = pi;
         q[i] = qi;
@@ -570,11 +642,12 @@ void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 
-// The CG update x += alpha p, r_new = r - alpha q (nothing moves on breakdown) fused with
+// The CG update x += alpha p, r_new = r - alpha q (x does not move on breakdown) fused with
 // the first V-cycle sweep from zero on level 0 and its residual: u = m r_new and
 // rv = r_new - A u, where every neighbour's r_new is formed from r and q with the same
 // operation as its owner row uses (so r is read, and r_new written to another buffer);
 // ||r_new||^2 partials, one per workgroup.
+template <int ND>
 __global__ __launch_bounds__(TPB) void k_dia_update_smooth0(int n, int nd, DiaOff o, const double* __restrict__ v,
                                                             const double* __restrict__ p,
                                                             const double* __restrict__ q, double* __restrict__ x,
@@ -584,12 +657,14 @@ __global__ __launch_bounds__(TPB) void k_dia_update_smooth0(int n, int nd, DiaOf
     const double* sc = rs.scal();
     const bool bad = sc[S_FLAG] != 0.0;
     const double alpha = sc[S_ALPHA];
-    auto rnew = [&](int j) { return bad ? r[j] : __builtin_fma(-alpha, q[j], r[j]); };
+    // on breakdown r_new = r - 0 q (r up to the sign of a zero entry; the solve stops there)
+    const double step = bad ? 0.0 : alpha;
+    auto rnew = [&](int j) { return __builtin_fma(-step, q[j], r[j]); };
     const int lb = xcd_block();
     const int i = lb * TPB + threadIdx.x;
     double loc[1] = {0.0};
     if (i < n) {
-        const double s = dia_row(i, n, nd, o, v, [&](int j) { return m[j] * rnew(j); });
+        const double s = dia_row<ND>(i, n, nd, o, v, [&](int j) { return m[j] * rnew(j); });
         const double ri = rnew(i);
         if (!bad) x[i] = __builtin_fma(alpha, p[i], x[i]);
         rn[i] = ri;
@@ -603,13 +678,14 @@ __global__ __launch_bounds__(TPB) void k_dia_update_smooth0(int n, int nd, DiaOf
 
 // r = f - A x on the diagonal storage, with ||r||^2 and ||f||^2 partials (bounded grid,
 // host-summed).
+template <int ND>
 __global__ __launch_bounds__(TPB) void k_dia_cg_init(int n, int nd, DiaOff o, const double* __restrict__ v,
                                                      const double* __restrict__ f, const double* __restrict__ x,
                                                      double* __restrict__ r, RedScratch rs) {
     double loc[2] = {0.0, 0.0};
     for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
         const double fi = f[i];
-        const double ri = fi - dia_row(i, n, nd, o, v, [&](int j) { return x[j]; });
+        const double ri = fi - dia_row<ND>(i, n, nd, o, v, [&](int j) { return x[j]; });
         r[i] = ri;
         loc[0] += ri * ri;
         loc[1] += fi * fi;
@@ -620,46 +696,323 @@ __global__ __launch_bounds__(TPB) void k_dia_cg_init(int n, int nd, DiaOff o, co
 
 static inline unsigned dia_blocks(int n) { return (unsigned)((n + TPB - 1) / TPB); }
 
+// ------------------------------------------------------------------ 7-point marching form
+//
+// Level-0 kernels for a 7-point operator whose diagonals have the offsets -a, -b, -1, 0,
+// 1, b, a (1 < b < a: a stencil on a grid of planes of a rows and lines of b rows).  The
+// one-row-per-thread kernels above load the vector at all seven columns of a row and
+// every load goes through the vector memory path on its own; here a workgroup owns TPB
+// consecutive positions r of a plane and MZ consecutive planes (rows i = plane * a + r)
+// and every vector entry is loaded about once: x(i -+ a) is the thread's own x of the
+// planes before and after, x(i -+ 1) and x(i -+ b) are read from an LDS copy of the
+// plane's segment (from global memory where they fall outside it), and with symmetric
+// values the sub-diagonal entries U_1(i - 1), U_b(i - b) come from LDS copies of those
+// diagonals, U_a(i - a) from the previous plane.  All global loads of the MZ planes are
+// issued before the first is used.  Each row adds the same terms in the same order with
+// the same fused multiply-adds as dia_row, so the row results equal the one-row-per-thread
+// kernels' bit for bit; reduction partials are one per workgroup.
+constexpr int MZ = 2;
+
+int march_blocks(int n, int a) {
+    const int64_t nseg = (a + TPB - 1) / TPB;
+    const int64_t planes = ((int64_t)n + a - 1) / a;
+    return (int)(nseg * ((planes + MZ - 1) / MZ));
+}
+
+template <bool SYM, typename T, typename XG, typename EP>
+__device__ __forceinline__ void march7(int n, int a, int b, const T* __restrict__ v, XG xget, EP epi) {
+    __shared__ T Xs[2][TPB];
+    __shared__ T U1s[SYM ? 2 : 1][SYM ? TPB : 1], Ubs[SYM ? 2 : 1][SYM ? TPB : 1];
+    const int nseg = (a + TPB - 1) / TPB;
+    const int lb = xcd_block();
+    const int t = threadIdx.x;
+    const int r = (lb % nseg) * TPB + t;
+    const bool own = r < a;  // positions past the plane only supply their x to neighbours
+    const int64_t ib = (int64_t)(lb / nseg) * MZ * a + r;
+    auto cl = [n](int64_t j) { return (j >= 0 && j < n) ? (int)j : 0; };  // loads stay in [0, n)
+    const size_t sn = (size_t)n;
+    const T* dm = v + 3 * sn;  // offset 0
+    const T* d1 = v + 4 * sn;  // +1
+    const T* db = v + 5 * sn;  // +b
+    const T* da = v + 6 * sn;  // +a
+    T X[MZ + 2], A0[MZ], A1[MZ], AB[MZ], AA[MZ + 1], LA[MZ], LB[MZ], L1[MZ];
+    T XMB[MZ], AMB[MZ], XPB[MZ], XM1[MZ], AM1[MZ], XP1[MZ];
+    const bool mb_out = t < b, pb_out = t + b >= TPB;
+    AA[0] = SYM ? da[cl(ib - a)] : T(0);
+#pragma unroll
+    for (int k = 0; k < MZ + 2; ++k) X[k] = xget(cl(ib + (int64_t)(k - 1) * a));
+#pragma unroll
+    for (int k = 0; k < MZ; ++k) {
+        const int64_t i = ib + (int64_t)k * a;
+        const int ic = cl(i);
+        A0[k] = dm[ic];
+        A1[k] = d1[ic];
+        AB[k] = db[ic];
+        AA[k + 1] = da[ic];
+        if constexpr (!SYM) {
+            LA[k] = v[ic];
+            LB[k] = v[sn + ic];
+            L1[k] = v[2 * sn + ic];
+        }
+        XMB[k] = AMB[k] = XPB[k] = XM1[k] = AM1[k] = XP1[k] = T(0);
+        if (mb_out) {
+            const int jj = cl(i - b);
+            XMB[k] = xget(jj);
+            if constexpr (SYM) AMB[k] = db[jj];
+        }
+        if (pb_out) XPB[k] = xget(cl(i + b));
+        if (t == 0) {
+            const int jj = cl(i - 1);
+            XM1[k] = xget(jj);
+            if constexpr (SYM) AM1[k] = d1[jj];
+        }
+        if (t == TPB - 1) XP1[k] = xget(cl(i + 1));
+    }
+    const int tm1 = t > 0 ? t - 1 : t, tp1 = t < TPB - 1 ? t + 1 : t;
+    const int tmb = mb_out ? t : t - b, tpb = pb_out ? t : t + b;
+#pragma unroll
+    for (int k = 0; k < MZ; ++k) {
+        const int64_t i = ib + (int64_t)k * a;
+        const int bf = k & 1;
+        Xs[bf][t] = X[k + 1];
+        if constexpr (SYM) {
+            U1s[bf][t] = A1[k];
+            Ubs[bf][t] = AB[k];
+        }
+        __syncthreads();
+        const T x_m1 = t > 0 ? Xs[bf][tm1] : XM1[k];
+        const T x_p1 = t < TPB - 1 ? Xs[bf][tp1] : XP1[k];
+        const T x_mb = mb_out ? XMB[k] : Xs[bf][tmb];
+        const T x_pb = pb_out ? XPB[k] : Xs[bf][tpb];
+        T c_ma, c_mb, c_m1;
+        if constexpr (SYM) {
+            c_ma = AA[k];
+            c_mb = mb_out ? AMB[k] : Ubs[bf][tmb];
+            c_m1 = t > 0 ? U1s[bf][tm1] : AM1[k];
+        } else {
+            c_ma = LA[k];
+            c_mb = LB[k];
+            c_m1 = L1[k];
+        }
+        if (own && i < n) {
+            T s = 0;
+            s = i - a >= 0 ? fmadd(c_ma, X[k], s) : s;
+            s = i - b >= 0 ? fmadd(c_mb, x_mb, s) : s;
+            s = i - 1 >= 0 ? fmadd(c_m1, x_m1, s) : s;
+            s = fmadd(A0[k], X[k + 1], s);
+            s = i + 1 < n ? fmadd(A1[k], x_p1, s) : s;
+            s = i + b < n ? fmadd(AB[k], x_pb, s) : s;
+            s = i + a < n ? fmadd(AA[k + 1], X[k + 2], s) : s;
+            epi((int)i, s, X[k + 1]);
+        }
+    }
+}
+
+template <bool SYM, typename T>
+__global__ __launch_bounds__(TPB) void k_m7_smooth0_residual(int n, int a, int b, const T* __restrict__ v,
+                                                             const T* __restrict__ m, const T* __restrict__ f,
+                                                             T* __restrict__ u, T* __restrict__ r) {
+    march7<SYM, T>(n, a, b, v, [&](int j) { return m[j] * f[j]; }, [&](int i, T s, T xc) {
+        u[i] = xc;
+        r[i] = f[i] - s;
+    });
+}
+
+template <bool SYM, typename T>
+__global__ __launch_bounds__(TPB) void k_m7_residual(int n, int a, int b, const T* __restrict__ v,
+                                                     const T* __restrict__ f, const T* __restrict__ u,
+                                                     T* __restrict__ r) {
+    march7<SYM, T>(n, a, b, v, [&](int j) { return u[j]; }, [&](int i, T s, T) { r[i] = f[i] - s; });
+}
+
+template <bool SYM, typename T>
+__global__ __launch_bounds__(TPB) void k_m7_jacobi(int n, int a, int b, const T* __restrict__ v,
+                                                   const T* __restrict__ m, const T* __restrict__ f,
+                                                   const T* __restrict__ u, T* __restrict__ uout) {
+    march7<SYM, T>(n, a, b, v, [&](int j) { return u[j]; },
+                   [&](int i, T s, T xc) { uout[i] = xc + m[i] * (f[i] - s); });
+}
+
+template <bool SYM>
+__global__ __launch_bounds__(TPB) void k_m7_jacobi_rz(int n, int a, int b, const double* __restrict__ v,
+                                                      const double* __restrict__ m, const double* __restrict__ r,
+                                                      const double* __restrict__ u, double* __restrict__ z,
+                                                      int flexible, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    march7<SYM, double>(n, a, b, v, [&](int j) { return u[j]; }, [&](int i, double s, double xc) {
+        const double ri = r[i];
+        const double zi = xc + m[i] * (ri - s);
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    });
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, xcd_block());
+}
+
+template <bool SYM, bool FIRST>
+__global__ __launch_bounds__(TPB) void k_m7_cg_pq(int n, int a, int b, const double* __restrict__ v,
+                                                  const double* __restrict__ z, const double* __restrict__ pold,
+                                                  double* __restrict__ pnew, double* __restrict__ q, RedScratch rs) {
+    const double beta = FIRST ? 0.0 : rs.scal()[S_BETA];
+    double loc[1] = {0.0};
+    march7<SYM, double>(
+        n, a, b, v, [&](int j) { return FIRST ? z[j] : __builtin_fma(beta, pold[j], z[j]); },
+        [&](int i, double s, double xc) {
+            pnew[i] = xc;
+            q[i] = s;
+            loc[0] += xc * s;
+        });
+    double* const dst[1] = {rs.region(P_PQ)};
+    block_store<1>(loc, dst, xcd_block());
+}
+
+template <bool SYM>
+__global__ __launch_bounds__(TPB) void k_m7_update_smooth0(int n, int a, int b, const double* __restrict__ v,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q, double* __restrict__ x,
+                                                           const double* __restrict__ r, double* __restrict__ rn,
+                                                           const double* __restrict__ m, double* __restrict__ u,
+                                                           double* __restrict__ rv, RedScratch rs) {
+    const double* sc = rs.scal();
+    const bool bad = sc[S_FLAG] != 0.0;
+    const double alpha = sc[S_ALPHA];
+    const double step = bad ? 0.0 : alpha;
+    double loc[1] = {0.0};
+    march7<SYM, double>(
+        n, a, b, v, [&](int j) { return m[j] * __builtin_fma(-step, q[j], r[j]); },
+        [&](int i, double s, double xc) {
+            const double ri = __builtin_fma(-step, q[i], r[i]);
+            if (!bad) x[i] = __builtin_fma(alpha, p[i], x[i]);
+            rn[i] = ri;
+            u[i] = xc;
+            rv[i] = ri - s;
+            loc[0] += ri * ri;
+        });
+    double* const dst[1] = {rr_dest(rs, bad)};
+    block_store<1>(loc, dst, xcd_block());
+}
+
+// Runs f(std::bool_constant<SYM>) for the marching form when D has one.
+template <typename F>
+inline bool march_call(const Dia& D, F&& f) {
+    if (D.march_a == 0) return false;
+    if (D.off.sym)
+        f(std::true_type{});
+    else
+        f(std::false_type{});
+    return true;
+}
+
+
 template <typename T>
 void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s) {
     k_dia_scatter<T><<<dia_blocks(A.nrows), TPB, 0, s>>>(A.nrows, A.ptr, D.slot, val, dval);
     HIP_LAUNCH_CHECK();
 }
+
+void launch_dia_symcheck(int n, const Dia& D, double* scal, hipStream_t s) {
+    k_dia_clear<<<1, 64, 0, s>>>(scal + S_ASYM);
+    HIP_LAUNCH_CHECK();
+    if (n == 0) return;
+    k_dia_symcheck<<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.val, scal + S_ASYM);
+    HIP_LAUNCH_CHECK();
+}
+
 template <typename T>
 void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T* u, T* r, hipStream_t s) {
-    k_dia_smooth0_residual<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, r);
+    if (march_call(D, [&](auto S) {
+            k_m7_smooth0_residual<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
+                n, D.march_a, D.march_b, D.v<T>(), m, f, u, r);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return;
+    }
+    dia_nd(D.ndiag, [&](auto K) {
+        k_dia_smooth0_residual<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, r);
+    });
     HIP_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipStream_t s) {
-    k_dia_residual<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), f, u, r);
+    if (march_call(D, [&](auto S) {
+            k_m7_residual<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
+                n, D.march_a, D.march_b, D.v<T>(), f, u, r);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return;
+    }
+    dia_nd(D.ndiag, [&](auto K) {
+        k_dia_residual<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), f, u, r);
+    });
     HIP_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
-    k_dia_jacobi<T><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, uout);
+    if (march_call(D, [&](auto S) {
+            k_m7_jacobi<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
+                n, D.march_a, D.march_b, D.v<T>(), m, f, u, uout);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return;
+    }
+    dia_nd(D.ndiag, [&](auto K) {
+        k_dia_jacobi<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, uout);
+    });
     HIP_LAUNCH_CHECK();
 }
 int launch_dia_cg_init(int n, const Dia& D, const double* f, const double* x, double* r, const RedScratch& rs,
                        hipStream_t s) {
     const int nb = red_grid_elems(n);
-    k_dia_cg_init<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, f, x, r, rs);
+    dia_nd(D.ndiag, [&](auto K) {
+        k_dia_cg_init<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, f, x, r, rs);
+    });
     HIP_LAUNCH_CHECK();
     return nb;
 }
 int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
                          int flexible, const RedScratch& rs, hipStream_t s) {
+    if (D.march_a > 0) {
+        const int nb = march_blocks(n, D.march_a);
+        if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+        march_call(D, [&](auto S) {
+            k_m7_jacobi_rz<decltype(S)::value><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, m, r, u, z,
+                                                                   flexible, rs);
+        });
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    k_dia_jacobi_rz<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
+    dia_nd(D.ndiag, [&](auto K) {
+        k_dia_jacobi_rz<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
+    });
     HIP_LAUNCH_CHECK();
     return nb;
 }
 int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,
                      const RedScratch& rs, hipStream_t s) {
+    if (D.march_a > 0) {
+        const int nb = march_blocks(n, D.march_a);
+        if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+        march_call(D, [&](auto S) {
+            constexpr bool SYM = decltype(S)::value;
+            if (first)
+                k_m7_cg_pq<SYM, true><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, z, pold, pnew, q, rs);
+            else
+                k_m7_cg_pq<SYM, false><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, z, pold, pnew, q, rs);
+        });
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    k_dia_cg_pq<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, first, rs);
+    dia_nd(D.ndiag, [&](auto K) {
+        if (first)
+            k_dia_cg_pq<decltype(K)::value, true><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, rs);
+        else
+            k_dia_cg_pq<decltype(K)::value, false><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, rs);
+    });
     HIP_LAUNCH_CHECK();
     return nb;
 }
@@ -667,9 +1020,21 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
 int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double* q, double* x, const double* r,
                               double* rn, const double* m, double* u, double* rv, const RedScratch& rs,
                               hipStream_t s) {
+    if (D.march_a > 0) {
+        const int nb = march_blocks(n, D.march_a);
+        if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+        march_call(D, [&](auto S) {
+            k_m7_update_smooth0<decltype(S)::value><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, p, q, x, r,
+                                                                        rn, m, u, rv, rs);
+        });
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    k_dia_update_smooth0<<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
+    dia_nd(D.ndiag, [&](auto K) {
+        k_dia_update_smooth0<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
+    });
     HIP_LAUNCH_CHECK();
     return nb;
 }

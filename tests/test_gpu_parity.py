@@ -402,6 +402,101 @@ def test_diagonal_storage_matches_csr(monkeypatch, case, precision):
     assert rel_fro(ud, uc) <= 1e-7
 
 
+@pytest.mark.parametrize("case", ["tf32", "ln27", "aniso"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_symmetric_diagonal_read_is_exact(monkeypatch, case, precision):
+    """Once a solve has seen symmetric values, the level-0 kernels read each sub-diagonal
+    entry of the diagonal storage as its mirror on the super-diagonal: the same numbers in
+    the same order, so V-cycles, iterates and iteration counts equal those of the full read
+    bit for bit.  Values made unsymmetric in one entry are caught at the rebuild and read in
+    full."""
+    from paper_2108_02054_amd import AMG
+
+    if case == "tf32":
+        p, c, v0 = two_fluid_7pt(32, front_c1(0))
+        v1 = two_fluid_7pt(32, front_c1(4))[2]
+        prm, nd = dict(), 7
+    elif case == "ln27":
+        p, c, v0 = lognormal_27pt(16, 0)
+        v1 = lognormal_27pt(16, 2)[2]
+        prm, nd = dict(eps_strong=0.02), 27
+    else:
+        p, c, v0 = two_fluid_7pt(33, 0.4, ny=17, nz=9)
+        v1 = two_fluid_7pt(33, 0.45, ny=17, nz=9)[2]
+        prm, nd = dict(), 7
+    prm["precision"] = precision
+    n = len(p) - 1
+    r = np.random.default_rng(12).standard_normal(n)
+    f1, f2 = rhs_uniform(n, 1, 3), rhs_uniform(n, 2, 4)
+    # one off-diagonal entry of a middle row scaled: the pattern stays, the values are not
+    # symmetric any more
+    row = n // 2
+    k = next(t for t in range(p[row], p[row + 1]) if c[t] != row)
+    v1_bad = v1.copy()
+    v1_bad[k] *= 1.0 + 1e-6
+
+    def run(vals):
+        g = AMG(T(p), T(c), T(v0), **prm)
+        assert g.level_format(0) == nd
+        g.rebuild(T(vals))
+        u1, i1 = g.solve(T(f1))
+        z = g.vcycle(T(r)).cpu().numpy()
+        u2, i2 = g.solve(T(f2))
+        out = (g.diagonals_read(0), z, u1.cpu().numpy(), u2.cpu().numpy(), i1["iters"], i2["iters"])
+        g.close()
+        return out
+
+    sym = run(v1)
+    bad = run(v1_bad)
+    monkeypatch.setenv("AMGMI_NO_DIA_SYM", "1")
+    full = run(v1)
+    full_bad = run(v1_bad)
+    assert sym[0] == (nd + 1) // 2 and full[0] == nd
+    assert bad[0] == nd and full_bad[0] == nd
+    for a, b in ((sym, full), (bad, full_bad)):
+        for x, y in zip(a[1:4], b[1:4]):
+            assert np.array_equal(x, y)
+        assert a[4:] == b[4:]
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (33, 17, 9), (260, 3, 5), (5, 6, 40)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_marching_kernels_match_row_kernels(monkeypatch, shape, precision):
+    """The 7-point marching kernels (a workgroup walks planes of the grid, neighbours from
+    registers and LDS) give every row the same result as the one-row-per-thread kernels:
+    V-cycles agree bit for bit; solves, whose dot products are grouped differently, agree
+    in iterations and to the solver tolerance.  Shapes: whole segments; a plane that is
+    not a whole number of segments with an odd last chunk of planes; lines longer than a
+    workgroup (every -+b neighbour from global memory); planes shorter than a workgroup."""
+    from paper_2108_02054_amd import AMG
+
+    nx, ny, nz = shape
+    p, c, v0 = two_fluid_7pt(nx, 0.4, ny=ny, nz=nz)
+    v1 = two_fluid_7pt(nx, 0.47, ny=ny, nz=nz)[2]
+    n = len(p) - 1
+    r = np.random.default_rng(13).standard_normal(n)
+    f = rhs_uniform(n, 1, 3)
+    print(f"case {shape} precision {precision}", flush=True)
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), precision=precision)
+        assert g.level_format(0) == 7
+        g.rebuild(T(v1))
+        u1, i1 = g.solve(T(f))
+        z = g.vcycle(T(r)).cpu().numpy()
+        out = (z, u1.cpu().numpy(), i1)
+        g.close()
+        return out
+
+    zm, um, im = run()
+    monkeypatch.setenv("AMGMI_NO_MARCH", "1")
+    zr, ur, ir = run()
+    assert np.array_equal(zm, zr)
+    assert im["converged"] and ir["converged"]
+    assert abs(im["iters"] - ir["iters"]) <= 1
+    assert rel_fro(um, ur) <= 1e-7
+
+
 def test_full_size_128_partial_rebuild_and_solve():
     """At the benchmark's full size (two-fluid 128^3, the configuration bench.py times,
     with the diagonal storage and the default launch shapes): after a partial rebuild to a
