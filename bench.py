@@ -203,6 +203,8 @@ def main():
     dims = [amg.dims(l) for l in range(L)]
     ndiag = amg.level_format(0)
     nread = amg.diagonals_read(0)
+    plane = amg.march_plane(0)
+    pq_kernel = "k_m7_cg_pq" if plane else ("k_dia_cg_pq" if ndiag else "k_cg_pq")
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
     log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
     ph = amg.phase_times()
@@ -271,7 +273,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name(cfg_id, N, n, nnz),
                    "grid": N, "n": n, "nnz": nnz, "levels": L, "level_rows": [d[0] for d in dims],
-                   "level_nnz": [d[1] for d in dims], "level0_storage": (f"{ndiag} diagonals, {nread} read per row" if ndiag else "CSR"),
+                   "level_nnz": [d[1] for d in dims], "level0_storage": ((f"{ndiag} diagonals, {nread} read per row"
+                                      + (f", marching planes of {plane} rows" if plane else "")) if ndiag else "CSR"),
                    "parallelism": "single GPU"},
         "iters_partial": info_p["iters"],
         "converged_all": info_p["converged"],
@@ -280,10 +283,10 @@ def main():
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
-        "roofline": roof(("k_dia_cg_pq" if ndiag else "k_cg_pq")
-                         + " (Krylov operator SpMV with p = z + beta p and p.q, level 0)", pq_ms, pq_cnt,
+        "roofline": roof(pq_kernel + " (Krylov operator SpMV with p = z + beta p and p.q, level 0)", pq_ms, pq_cnt,
                          spmv_bytes / pq_cnt if pq_cnt else 0,
-                         pq_traffic if (cfg_id == 2 and N == 128 and ndiag > 0) else None),
+                         pq_traffic if (cfg_id == 2 and N == 128 and pq_traffic is not None
+                                        and pq_traffic["kernel"] == pq_kernel) else None),
         "roofline_rap": roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
                              kb["galerkin"]),
         "kernels_level0_ms": {k: v for k, v in breakdown_l0.items()},

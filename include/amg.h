@@ -135,9 +135,12 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims);
  * *nread (host, may be NULL) receives the number of diagonals the solve kernels read per
  * row: (ndiag+1)/2 when the offsets are symmetric and the values last refreshed were
  * found symmetric (the solve reads each sub-diagonal entry as its mirror; known from the
- * first solve after a rebuild on), else ndiag.
+ * first solve after a rebuild on), else ndiag.  *plane (host, may be NULL) receives the
+ * plane stride a when the level-0 kernels of a 7-point operator (offsets -a, -b, -1, 0,
+ * 1, b, a) walk the grid plane by plane (two planes per workgroup, neighbours within a
+ * plane from LDS), else 0.
  * Errors: AMG_ERR_ARG for a NULL ndiag or l out of range. */
-amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread);
+amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread, int* plane);
 
 /* Copy level l to host arrays (any may be NULL).  agg[n_l], strong[nnz(A_l)] exist on
  * aggregated levels; P on non-coarsest levels; m (smoother diagonal) on non-coarsest

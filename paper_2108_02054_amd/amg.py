@@ -83,7 +83,7 @@ def lib():
         L.amg_last_error.restype = C.c_char_p
         L.amg_num_levels.argtypes = [V, C.POINTER(I)]
         L.amg_level_dims.argtypes = [V, I, C.POINTER(I64)]
-        L.amg_level_format.argtypes = [V, I, C.POINTER(I), C.POINTER(I)]
+        L.amg_level_format.argtypes = [V, I, C.POINTER(I), C.POINTER(I), C.POINTER(I)]
         L.amg_export_level.argtypes = [V, I] + [V] * 9
         L.amg_export_coarse_inverse.argtypes = [V, V]
         L.amg_phase_times.argtypes = [V, C.POINTER(D)]
@@ -225,15 +225,21 @@ class AMG:
     def level_format(self, l: int) -> int:
         """Diagonals of level l's diagonal storage (0: CSR kernels)."""
         nd = C.c_int()
-        self._check(lib().amg_level_format(self.ctx, l, C.byref(nd), None))
+        self._check(lib().amg_level_format(self.ctx, l, C.byref(nd), None, None))
         return nd.value
 
     def diagonals_read(self, l: int) -> int:
         """Diagonals the solve kernels read per row of level l's diagonal storage: half of
         them (plus the main one) once a solve has seen symmetric values."""
         nd, nr = C.c_int(), C.c_int()
-        self._check(lib().amg_level_format(self.ctx, l, C.byref(nd), C.byref(nr)))
+        self._check(lib().amg_level_format(self.ctx, l, C.byref(nd), C.byref(nr), None))
         return nr.value
+
+    def march_plane(self, l: int) -> int:
+        """Plane stride of the 7-point marching kernels on level l (0: not used)."""
+        nd, pl = C.c_int(), C.c_int()
+        self._check(lib().amg_level_format(self.ctx, l, C.byref(nd), None, C.byref(pl)))
+        return pl.value
 
     def level(self, l: int):
         """Host copies of level l: dict with A (ptr, col, val), P (ptr, col, val, nc) or

@@ -138,18 +138,31 @@ struct Trace {
         c->ev_pool.pop_back();
         return e;
     }
+    // The Krylov SpMV (one launch) records its own events at launch, which time the kernel
+    // alone; every other class is bracketed by events recorded on the stream around it.
+    bool own = false;
     Trace(amg_ctx* cc, int k, int level) : c(cc), cls(k) {
         if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == level)) {
             a = take(c);
             b = take(c);
-            HIP_CHECK(hipEventRecord(a, c->stream));
+            if (k == AMG_K_CG_PQ) {
+                own = true;
+                g_kernel_events = KernelEvents{a, b};
+            } else {
+                HIP_CHECK(hipEventRecord(a, c->stream));
+            }
         }
     }
     ~Trace() {
-        if (a) {
+        if (!a) return;
+        if (!own) {
             (void)hipEventRecord(b, c->stream);
-            c->traced.push_back({cls, a, b});
+        } else if (g_kernel_events.start == a) {  // no timed launch took them (not expected)
+            g_kernel_events = KernelEvents{};
+            (void)hipEventRecord(a, c->stream);
+            (void)hipEventRecord(b, c->stream);
         }
+        c->traced.push_back({cls, a, b});
     }
 };
 
@@ -1317,10 +1330,11 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims) {
     return AMG_OK;
 }
 
-amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread) {
+amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread, int* plane) {
     if (!c || !ndiag || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
     *ndiag = l == 0 ? c->dia.ndiag : 0;
     if (nread) *nread = (l == 0 && c->dia.off.sym) ? (c->dia.ndiag + 1) / 2 : *ndiag;
+    if (plane) *plane = l == 0 ? c->dia.march_a : 0;
     return AMG_OK;
 }
 

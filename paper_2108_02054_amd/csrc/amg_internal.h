@@ -193,6 +193,13 @@ inline const double* Dia::v<double>() const { return val; }
 template <>
 inline const float* Dia::v<float>() const { return val32; }
 
+// Start and stop events that the next launch of a timed kernel (the Krylov SpMV) records
+// itself, set by the host's kernel trace and cleared by the launch.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelEvents g_kernel_events;
+
 std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
 // Workgroups of the 7-point marching kernels for n rows with plane stride a.
 int march_blocks(int n, int a);

@@ -18,6 +18,8 @@
 
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "amg_internal.h"
 
 namespace amgmi {
@@ -51,6 +53,22 @@ __device__ __forceinline__ T wave_sum(T s) {
             default: throw Fail{AMG_ERR_ARG, "unsupported lane group"};     \
         }                                                                   \
     } while (0)
+
+thread_local KernelEvents g_kernel_events;
+
+// Launches kernel k; when the host's trace asked for this kernel's own timing, the launch
+// records its start and stop events itself (hipExtLaunchKernel), so that they bracket the
+// kernel's execution and not the dispatch gap before it.
+template <typename F, typename... Args>
+void timed_launch(F k, unsigned grid, unsigned block, hipStream_t s, Args... args) {
+    if (g_kernel_events.start != nullptr) {
+        const KernelEvents e = g_kernel_events;
+        g_kernel_events = KernelEvents{};
+        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, e.start, e.stop, 0, args...);
+    } else {
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, args...);
+    }
+}
 
 static inline unsigned grid_for(int64_t items, int per_block) {
     int64_t b = (items + per_block - 1) / per_block;
@@ -998,9 +1016,11 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
         march_call(D, [&](auto S) {
             constexpr bool SYM = decltype(S)::value;
             if (first)
-                k_m7_cg_pq<SYM, true><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, z, pold, pnew, q, rs);
+                timed_launch(k_m7_cg_pq<SYM, true>, nb, TPB, s, n, D.march_a, D.march_b, (const double*)D.val, z,
+                             pold, pnew, q, rs);
             else
-                k_m7_cg_pq<SYM, false><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, z, pold, pnew, q, rs);
+                timed_launch(k_m7_cg_pq<SYM, false>, nb, TPB, s, n, D.march_a, D.march_b, (const double*)D.val, z,
+                             pold, pnew, q, rs);
         });
         HIP_LAUNCH_CHECK();
         return nb;
@@ -1009,9 +1029,11 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     dia_nd(D.ndiag, [&](auto K) {
         if (first)
-            k_dia_cg_pq<decltype(K)::value, true><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, rs);
+            timed_launch(k_dia_cg_pq<decltype(K)::value, true>, nb, TPB, s, n, D.ndiag, D.off, (const double*)D.val,
+                         z, pold, pnew, q, rs);
         else
-            k_dia_cg_pq<decltype(K)::value, false><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, z, pold, pnew, q, rs);
+            timed_launch(k_dia_cg_pq<decltype(K)::value, false>, nb, TPB, s, n, D.ndiag, D.off, (const double*)D.val,
+                         z, pold, pnew, q, rs);
     });
     HIP_LAUNCH_CHECK();
     return nb;
@@ -1488,7 +1510,8 @@ int launch_cg_pq(const Csr& A, const double* val, const double* z, const double*
                  int first, const RedScratch& rs, hipStream_t s) {
     const int nb = full_grid_rows(A.nrows, A.rpb, A.g);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    AMG_WITH_G(A.g, k_cg_pq<G><<<nb, RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, val, z, pold, pnew, q, first, rs));
+    AMG_WITH_G(A.g, timed_launch(k_cg_pq<G>, nb, RB_THREADS, s, A.nrows, A.rpb, (const int*)A.ptr, (const int*)A.col,
+                                 val, z, pold, pnew, q, first, rs));
     HIP_LAUNCH_CHECK();
     return nb;
 }
