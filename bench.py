@@ -122,6 +122,8 @@ def main():
     import torch
 
     from paper_2108_02054_amd import AMG, FULL, OPERATOR_ONLY
+    from paper_2108_02054_amd.amg import PARTIAL, policy
+    POLICY = policy(PARTIAL, every=10)  # an occasional full setup between partial updates (Section 3)
     from workloads import CONFIGS, rhs_uniform, series_matrix
 
     dev = torch.device("cuda:0")
@@ -162,6 +164,9 @@ def main():
         def step(t, record):
             if mode == "partial":
                 amg.rebuild(vals[t])
+            elif mode == "policy":
+                if amg.rebuild_auto(vals[t], POLICY) == FULL and record:
+                    info_log["rebuilds"] += 1
             elif mode == "full":
                 amg.rebuild_ex(vals[t], FULL)
             else:
@@ -301,11 +306,11 @@ def main():
         elif cfg_id == 3:
             plan = [("mixed", "partial", 1), ("full", "full", 0)]
         else:
-            plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1)]
+            plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1), ("policy", "policy", 0)]
         for name, mode, prec in plan:
             _, ms_x, info_x, _ = series(mode, precision=prec)
             runs[name] = (ms_x, info_x)
-            extra = f", rebuilds {info_x['rebuilds']}" if mode == "reuse" else ""
+            extra = f", full setups {info_x['rebuilds']}" if mode in ("reuse", "policy") else ""
             log(f"{name}: {ms_x:.3f} ms/step, iters {info_x['iters']}{extra}")
         conv = info_p["converged"]
         for name, (ms_x, info_x) in runs.items():
@@ -323,6 +328,11 @@ def main():
             result["mixed_partial_ms_per_step"] = runs["mixed"][0]
             result["iters_mixed"] = runs["mixed"][1]["iters"]
             result["mixed_speedup_vs_fp64_pct"] = (ms_partial / runs["mixed"][0] - 1.0) * 100.0
+        if "policy" in runs:
+            result["policy_every_ms_per_step"] = runs["policy"][0]
+            result["policy"] = f"partial reuse with a full setup every {POLICY.every}th step"
+            result["iters_policy"] = runs["policy"][1]["iters"]
+            result["policy_full_setups"] = runs["policy"][1]["rebuilds"]
         if "fp64_partial" in runs:
             result["fp64_partial_ms_per_step"] = runs["fp64_partial"][0]
             result["iters_fp64"] = runs["fp64_partial"][1]["iters"]

@@ -108,6 +108,32 @@ amg_status amg_set_pattern(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ro
 /* New values with an explicit update mode (see amg_rebuild_mode). */
 amg_status amg_rebuild_ex(amg_ctx* c, const double* val, amg_rebuild_mode m);
 
+/* Rebuild policy layered on amg_rebuild_ex (Section 3: full reuse until a solve misses the
+ * iteration limit, Algorithm 3; an occasional full rebuild between partial updates).
+ *   base:   AMG_PARTIAL or AMG_OPERATOR_ONLY, the mode used when no trigger fires;
+ *   every:  > 0: a full setup as the every-th update after the last full setup (0: off);
+ *   growth: > 0: a full setup when the last solve took more than growth times the
+ *           iterations of the first solve after the last full setup (0: off).
+ * With the AMG_OPERATOR_ONLY base a solve that did not converge also triggers one. */
+typedef struct {
+    amg_rebuild_mode base;
+    int every;
+    double growth;
+} amg_policy;
+
+/* The mode the policy p (host) picks, host logic only: updates = updates since the last
+ * full setup (0 right after it), iters_ref = iterations of the first solve after it (0:
+ * none yet), last_iters / last_converged = the last solve (last_iters 0: none yet).
+ * *mode (host) receives AMG_FULL or p->base.  Errors: AMG_ERR_ARG for NULL pointers, a
+ * base other than AMG_PARTIAL / AMG_OPERATOR_ONLY, every < 0 or growth < 0 (or NaN). */
+amg_status amg_policy_pick(const amg_policy* p, int updates, int iters_ref, int last_iters, int last_converged,
+                           amg_rebuild_mode* mode);
+
+/* amg_rebuild_ex(c, val, m) with m = amg_policy_pick(p, ...) on c's history (updates since
+ * its last full setup, the first and the last solve's iterations); *taken (host, may be
+ * NULL) receives m.  Errors: those of amg_policy_pick and amg_rebuild_ex. */
+amg_status amg_rebuild_auto(amg_ctx* c, const double* val, const amg_policy* p, amg_rebuild_mode* taken);
+
 /* CG preconditioned by one V-cycle per iteration.  f[n] (device, read), u[n] (device,
  * in: initial guess, out: solution).  info (host) may be NULL.  Returns after convergence
  * or maxiter: one 16-byte device-to-host read per iteration decides the stop.  Not

@@ -24,8 +24,10 @@ EXPORTED = [
     "amg_params_default", "amg_setup", "amg_setup_transfer", "amg_rebuild", "amg_set_pattern",
     "amg_rebuild_ex", "amg_solve", "amg_vcycle", "amg_destroy", "amg_last_error", "amg_num_levels",
     "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
-    "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read",
+    "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read", "amg_policy_pick",
+    "amg_rebuild_auto",
 ]
+MODE_NAMES = {PARTIAL: "partial", FULL: "full", OPERATOR_ONLY: "operator_only"}
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
                   "cg_init", "smooth0_res", "jacobi", "restrict", "prolong", "coarse_gemv", "cast", "tail"]
 
@@ -51,6 +53,24 @@ class AmgParams(C.Structure):
         ("maxiter", C.c_int),
         ("flexible_cg", C.c_int),
     ]
+
+
+class AmgPolicy(C.Structure):
+    _fields_ = [("base", C.c_int), ("every", C.c_int), ("growth", C.c_double)]
+
+
+def policy(base: int = PARTIAL, every: int = 0, growth: float = 0.0) -> AmgPolicy:
+    return AmgPolicy(int(base), int(every), float(growth))
+
+
+def policy_pick(pol: AmgPolicy, updates: int, iters_ref: int, last_iters: int, last_converged: int) -> int:
+    """The mode the rebuild policy picks for a history (host logic of the library)."""
+    m = C.c_int(-1)
+    code = lib().amg_policy_pick(C.byref(pol), int(updates), int(iters_ref), int(last_iters),
+                                 int(last_converged), C.byref(m))
+    if code != AMG_OK:
+        raise AmgError(code, "invalid rebuild policy")
+    return m.value
 
 
 class AmgSolveInfo(C.Structure):
@@ -91,6 +111,8 @@ def lib():
         L.amg_logcoef7_adjoint.argtypes = [I32, I32, I32, V, V, V, V, V]
         L.amg_trace.argtypes = [V, C.c_uint, I]
         L.amg_trace_read.argtypes = [V, C.POINTER(D), C.POINTER(I64)]
+        L.amg_policy_pick.argtypes = [C.POINTER(AmgPolicy), I, I, I, I, C.POINTER(I)]
+        L.amg_rebuild_auto.argtypes = [V, V, C.POINTER(AmgPolicy), C.POINTER(I)]
         for name in EXPORTED:
             getattr(L, name).restype = C.c_int if name != "amg_last_error" else C.c_char_p
         _lib = L
@@ -186,6 +208,15 @@ class AMG:
         _dev(val, torch.float64, "val")
         self._values_token = None
         self._check(lib().amg_rebuild_ex(self.ctx, _ptr(val), int(mode)))
+
+    def rebuild_auto(self, val: torch.Tensor, pol: AmgPolicy) -> int:
+        """New values with the mode the rebuild policy picks from this hierarchy's history
+        (updates since its last full setup, first and last solve's iterations); returns it."""
+        _dev(val, torch.float64, "val")
+        self._values_token = None
+        m = C.c_int(-1)
+        self._check(lib().amg_rebuild_auto(self.ctx, _ptr(val), C.byref(pol), C.byref(m)))
+        return m.value
 
     def set_pattern(self, row_ptr: torch.Tensor, col: torch.Tensor):
         _dev(row_ptr, torch.int32, "row_ptr")

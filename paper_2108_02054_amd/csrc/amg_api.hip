@@ -528,6 +528,10 @@ struct Transfer {
 
 void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, const int32_t* col,
                      const double* val, const Transfer* tr) {
+    c->pol_updates = 0;
+    c->pol_iters_ref = 0;
+    c->pol_last_iters = 0;
+    c->pol_last_conv = 0;
     hipStream_t s = c->stream;
     const amg_params& p = c->prm;
     const auto t_all = Clock::now();
@@ -1226,6 +1230,7 @@ amg_status amg_rebuild_ex(amg_ctx* c, const double* val, amg_rebuild_mode m) {
         switch (m) {
             case AMG_PARTIAL:
                 partial_any(c, val);
+                ++c->pol_updates;
                 return AMG_OK;
             case AMG_FULL: {
                 if (c->transfer_given) throw Fail{AMG_ERR_ARG, "full rebuild of a hierarchy with prescribed transfer operators"};
@@ -1238,11 +1243,34 @@ amg_status amg_rebuild_ex(amg_ctx* c, const double* val, amg_rebuild_mode m) {
                 if (!c->outer_own) c->outer_own = halloc<double>(c, (size_t)A.nnz);
                 d2d(c->outer_own, val, (size_t)A.nnz * sizeof(double), c->stream);
                 c->outer_val = c->outer_own;
+                ++c->pol_updates;
                 return AMG_OK;
             }
         }
         throw Fail{AMG_ERR_ARG, "unknown rebuild mode"};
     });
+}
+
+amg_status amg_policy_pick(const amg_policy* p, int updates, int iters_ref, int last_iters, int last_converged,
+                           amg_rebuild_mode* mode) {
+    if (!p || !mode || (p->base != AMG_PARTIAL && p->base != AMG_OPERATOR_ONLY) || p->every < 0 ||
+        !(p->growth >= 0.0))
+        return AMG_ERR_ARG;
+    bool full = p->every > 0 && updates + 1 >= p->every;
+    if (p->growth > 0.0 && iters_ref > 0 && last_iters > 0 && (double)last_iters > p->growth * (double)iters_ref)
+        full = true;
+    if (p->base == AMG_OPERATOR_ONLY && last_iters > 0 && !last_converged) full = true;
+    *mode = full ? AMG_FULL : p->base;
+    return AMG_OK;
+}
+
+amg_status amg_rebuild_auto(amg_ctx* c, const double* val, const amg_policy* p, amg_rebuild_mode* taken) {
+    if (!c || !val) return AMG_ERR_ARG;
+    amg_rebuild_mode m;
+    const amg_status st = amg_policy_pick(p, c->pol_updates, c->pol_iters_ref, c->pol_last_iters, c->pol_last_conv, &m);
+    if (st != AMG_OK) return st;
+    if (taken) *taken = m;
+    return amg_rebuild_ex(c, val, m);
 }
 
 amg_status amg_rebuild(amg_ctx* c, const double* val, int pattern_changed) {
@@ -1294,7 +1322,13 @@ amg_status amg_set_pattern(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ro
 
 amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
     if (!c || !f || !u) return AMG_ERR_ARG;
-    return guard(c, [&] { return pcg(c, f, u, info); });
+    amg_solve_info inf{0, 0, 0.0};
+    const amg_status st = guard(c, [&] { return pcg(c, f, u, &inf); });
+    c->pol_last_iters = st == AMG_OK ? (inf.iters > 0 ? inf.iters : 1) : (c->prm.maxiter > 0 ? c->prm.maxiter : 1);
+    c->pol_last_conv = st == AMG_OK ? inf.converged : 0;
+    if (c->pol_iters_ref == 0 && st == AMG_OK) c->pol_iters_ref = c->pol_last_iters;
+    if (info) *info = inf;
+    return st;
 }
 
 amg_status amg_vcycle(amg_ctx* c, const double* r, double* z) {

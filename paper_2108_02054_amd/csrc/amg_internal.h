@@ -369,6 +369,9 @@ struct amg_ctx {
     int32_t* pend_ptr = nullptr;
     int32_t* pend_col = nullptr;
     bool transfer_given = false;
+    // rebuild-policy history: updates since the last full setup, iterations of the first
+    // solve after it (0: not yet), the last solve's iterations and convergence
+    int pol_updates = 0, pol_iters_ref = 0, pol_last_iters = 0, pol_last_conv = 0;
     // allocations: the hierarchy (released by a full rebuild) and the context's own
     std::vector<void*> hier_allocs;
     std::vector<void*> own_allocs;

@@ -54,3 +54,35 @@ def test_host_side_argument_checks():
     assert L.amg_destroy(None) == -1
     assert L.amg_logcoef7_assemble(0, 1, 1, None, None, None) == -1
     assert b"invalid" in L.amg_last_error(None) or L.amg_last_error(None) is not None
+
+
+def test_rebuild_policy_decisions():
+    """The rebuild policy's choice (host logic): an every-th full setup, iteration growth
+    against the first solve after the last full setup, and a missed convergence under full
+    reuse; invalid policies are rejected."""
+    import math
+
+    from paper_2108_02054_amd import lib
+    from paper_2108_02054_amd.amg import FULL, OPERATOR_ONLY, PARTIAL, AmgError, policy, policy_pick
+
+    every3 = policy(PARTIAL, every=3)
+    assert [policy_pick(every3, u, 0, 0, 0) for u in range(6)] == [PARTIAL, PARTIAL, FULL, FULL, FULL, FULL]
+    grow = policy(PARTIAL, growth=1.5)
+    assert policy_pick(grow, 4, 10, 15, 1) == PARTIAL     # 15 is not more than 1.5 * 10
+    assert policy_pick(grow, 4, 10, 16, 1) == FULL
+    assert policy_pick(grow, 4, 0, 16, 1) == PARTIAL      # no reference solve yet
+    assert policy_pick(grow, 4, 10, 0, 0) == PARTIAL      # no solve since the update
+    reuse = policy(OPERATOR_ONLY)
+    assert policy_pick(reuse, 7, 30, 100, 0) == FULL      # the last solve missed the limit
+    assert policy_pick(reuse, 7, 30, 100, 1) == OPERATOR_ONLY
+    assert policy_pick(reuse, 7, 30, 0, 0) == OPERATOR_ONLY
+    plain = policy(PARTIAL)
+    assert all(policy_pick(plain, u, 10, 99, 0) == PARTIAL for u in range(50))
+    for bad in (policy(FULL), policy(PARTIAL, every=-1), policy(PARTIAL, growth=-1.0),
+                policy(PARTIAL, growth=math.nan)):
+        with pytest.raises(AmgError):
+            policy_pick(bad, 0, 0, 0, 0)
+    m = C.c_int()
+    assert lib().amg_policy_pick(None, 0, 0, 0, 0, C.byref(m)) == -1
+    assert lib().amg_policy_pick(C.byref(plain), 0, 0, 0, 0, None) == -1
+    assert lib().amg_rebuild_auto(None, None, C.byref(plain), None) == -1
