@@ -15,11 +15,12 @@
  *     reuse: P_l, R_l kept; smoothers, Galerkin operators and the coarse solver rebuilt).
  * The transfer operators are smoothed aggregation (Vanek, Mandel, Brezina 1996); the
  * paper's own runs use plain aggregation, available here as an option.  The Krylov
- * method is preconditioned CG (the paper uses BiCGStab on non-symmetric systems; the
- * systems here are SPD).  Details the paper leaves open are fixed as follows and
- * documented per function: strength test, distance-2 maximal independent set with a
- * fixed hash priority, aggregate assembly, prolongator smoothing, Jacobi/SPAI0 diagonal,
- * dense Cholesky on the coarsest level.
+ * methods are preconditioned CG for SPD systems and BiCGStab (the paper's method, for its
+ * non-symmetric systems; van der Vorst 1992, the V-cycle applied on the right).  Details
+ * the paper leaves open are fixed as follows and documented per function: strength test,
+ * distance-2 maximal independent set with a fixed hash priority, aggregate assembly,
+ * prolongator smoothing, Jacobi/SPAI0 diagonal, dense Cholesky on the coarsest level
+ * when A_0 is symmetric and dense LU without pivoting otherwise.
  *
  * Semantics are sequential.  Row loops may run under OpenMP; rows are independent and
  * every reduction (dot products, norms, sums along a row) is taken in index order by
@@ -486,6 +487,55 @@ void cholesky_solve(const std::vector<double>& L, int32_t n, const double* b, do
     }
 }
 
+/* Dense LU A = L U without pivoting (Doolittle: L unit lower, U upper, packed row-major
+ * into one matrix) of a non-symmetric coarsest operator.  A non-positive or non-finite
+ * pivot is rejected, as for the Cholesky pivots (the operators here are M-matrices whose
+ * elimination pivots are positive). */
+int lu_nopivot(const Csr& A, std::vector<double>& LU) {
+    const int32_t n = A.n_rows;
+    LU.assign((size_t)n * n, 0.0);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) LU[(size_t)i * n + A.col[k]] = A.val[k];
+    for (int32_t k = 0; k < n; ++k) {
+        const double piv = LU[(size_t)k * n + k];
+        if (!(piv > 0.0) || !std::isfinite(piv)) return fail(ORA_ERR_NOT_SPD, "non-positive pivot in the coarse LU");
+        for (int32_t i = k + 1; i < n; ++i) {
+            const double lik = LU[(size_t)i * n + k] / piv;
+            LU[(size_t)i * n + k] = lik;
+            for (int32_t j = k + 1; j < n; ++j) LU[(size_t)i * n + j] -= lik * LU[(size_t)k * n + j];
+        }
+    }
+    return ORA_OK;
+}
+
+/* x = (L U)^-1 b by forward (unit L) then backward substitution. */
+void lu_solve(const std::vector<double>& LU, int32_t n, const double* b, double* x) {
+    std::vector<double> y((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int32_t j = 0; j < i; ++j) s -= LU[(size_t)i * n + j] * y[j];
+        y[i] = s;
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int32_t j = i + 1; j < n; ++j) s -= LU[(size_t)i * n + j] * x[j];
+        x[i] = s / LU[(size_t)i * n + i];
+    }
+}
+
+/* True when every stored a_ij equals a_ji (same pattern assumed structurally symmetric). */
+bool symmetric_values(const Csr& A) {
+    for (int32_t i = 0; i < A.n_rows; ++i)
+        for (int32_t k = A.ptr[i]; k < A.ptr[(size_t)i + 1]; ++k) {
+            const int32_t j = A.col[k];
+            const int32_t* b = A.col.data() + A.ptr[j];
+            const int32_t* e = A.col.data() + A.ptr[(size_t)j + 1];
+            const int32_t* q = std::lower_bound(b, e, i);
+            if (q == e || *q != i || A.val[(size_t)(q - A.col.data())] != A.val[k]) return false;
+        }
+    return true;
+}
+
 /* --------------------------------------------------------------------- hierarchy */
 
 struct Level {
@@ -500,7 +550,8 @@ struct Hierarchy {
     ora_params prm{};
     std::vector<Level> lv;
     Csr A_outer;            // the operator the Krylov solver iterates with
-    std::vector<double> L;  // Cholesky factor of the coarsest operator
+    std::vector<double> L;  // Cholesky factor of the coarsest operator, or its packed LU
+    bool coarse_lu = false; // A_0 is not symmetric: L holds the coarsest operator's L U
     bool transfer_given = false;
 };
 
@@ -518,7 +569,9 @@ int finish_levels(Hierarchy& h) {
         l.r.assign((size_t)l.A.n_rows, 0.0);
         l.t.assign((size_t)l.A.n_rows, 0.0);
     }
-    return cholesky(c.A, h.L);
+    // Galerkin operators of a symmetric A_0 are symmetric up to rounding: Cholesky then
+    h.coarse_lu = !symmetric_values(h.lv[0].A);
+    return h.coarse_lu ? lu_nopivot(c.A, h.L) : cholesky(c.A, h.L);
 }
 
 /* Algorithm 1: build the hierarchy from A. */
@@ -576,7 +629,10 @@ void vcycle_level(Hierarchy& h, size_t l) {
     Level& L = h.lv[l];
     const int32_t n = L.A.n_rows;
     if (l + 1 == h.lv.size()) {
-        cholesky_solve(h.L, n, L.f.data(), L.u.data());
+        if (h.coarse_lu)
+            lu_solve(h.L, n, L.f.data(), L.u.data());
+        else
+            cholesky_solve(h.L, n, L.f.data(), L.u.data());
         return;
     }
     const ora_params& p = h.prm;
@@ -664,6 +720,108 @@ int pcg(Hierarchy& h, const double* fin, double* uin, ora_info* info) {
         }
         rho = rho_new;
         for (size_t i = 0; i < n; ++i) pv[i] = z[i] + beta * pv[i];
+    }
+    if (!info->converged) {
+        residual(A, f.data(), x.data(), r.data());
+        res = norm2(r) / nf;
+    }
+    info->iters = it;
+    info->rel_res_true = res;
+    std::copy(x.begin(), x.end(), uin);
+    return ORA_OK;
+}
+
+/* BiCGStab (van der Vorst 1992) with one V-cycle M applied on the right, the paper's
+ * Krylov method for its non-symmetric systems.  With r^ = r_0 fixed: rho = r^.r;
+ * beta = (rho / rho_prev)(alpha / omega); p = r + beta (p - omega v) (p = r at the first
+ * step); p^ = M p; v = A p^; alpha = rho / r^.v; s = r - alpha v; s^ = M s; t = A s^;
+ * omega = t.s / t.t; x += alpha p^ + omega s^; r = s - omega t.  When ||s|| or ||r||
+ * reaches rtol the true residual f - A x is formed; if it is not small enough the method
+ * restarts from it (r^ = r, p = v = 0).  A zero or non-finite rho, r^.v, t.t or omega is
+ * a breakdown. */
+int bicgstab(Hierarchy& h, const double* fin, double* uin, ora_info* info) {
+    const Csr& A = h.A_outer;
+    const size_t n = (size_t)A.n_rows;
+    const ora_params& prm = h.prm;
+    std::vector<double> f(fin, fin + n), x(uin, uin + n), r(n), rh(n), p(n, 0.0), v(n, 0.0), ph(n), s(n), sh(n),
+        t(n);
+    info->iters = 0;
+    info->converged = 0;
+    info->rel_res_true = 0.0;
+    const double nf = norm2(f);
+    if (nf == 0.0) {
+        std::fill(uin, uin + n, 0.0);
+        info->converged = 1;
+        return ORA_OK;
+    }
+    residual(A, f.data(), x.data(), r.data());
+    double res = norm2(r) / nf;
+    if (res <= prm.rtol) {
+        info->converged = 1;
+        info->rel_res_true = res;
+        return ORA_OK;
+    }
+    rh = r;
+    double rho_prev = 1.0, alpha = 1.0, omega = 1.0;
+    bool fresh = true;  // the first step after the start or a restart: p = r
+    int it = 0;
+    auto breakdown = [&](const char* what) {
+        info->iters = it;
+        return fail(ORA_ERR_BREAKDOWN, std::string("BiCGStab breakdown: ") + what);
+    };
+    // true residual; true (converged) or restart from it
+    auto settle = [&]() {
+        residual(A, f.data(), x.data(), r.data());
+        res = norm2(r) / nf;
+        if (res <= prm.rtol) return true;
+        rh = r;
+        std::fill(p.begin(), p.end(), 0.0);
+        std::fill(v.begin(), v.end(), 0.0);
+        rho_prev = alpha = omega = 1.0;
+        fresh = true;
+        return false;
+    };
+    while (it < prm.maxiter) {
+        ++it;
+        const double rho = dot(rh, r);
+        if (rho == 0.0 || !std::isfinite(rho)) return breakdown("r^.r = 0");
+        if (fresh) {
+            p = r;
+            fresh = false;
+        } else {
+            const double beta = (rho / rho_prev) * (alpha / omega);
+            for (size_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        vcycle(h, p.data(), ph.data());
+        spmv(A, ph.data(), v.data());
+        const double rv = dot(rh, v);
+        if (rv == 0.0 || !std::isfinite(rv)) return breakdown("r^.v = 0");
+        alpha = rho / rv;
+        for (size_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        if (norm2(s) / nf <= prm.rtol) {
+            for (size_t i = 0; i < n; ++i) x[i] += alpha * ph[i];
+            if (settle()) {
+                info->converged = 1;
+                break;
+            }
+            continue;
+        }
+        vcycle(h, s.data(), sh.data());
+        spmv(A, sh.data(), t.data());
+        const double tt = dot(t, t);
+        if (tt == 0.0 || !std::isfinite(tt)) return breakdown("t.t = 0");
+        omega = dot(t, s) / tt;
+        for (size_t i = 0; i < n; ++i) x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+        for (size_t i = 0; i < n; ++i) r[i] = s[i] - omega * t[i];
+        rho_prev = rho;
+        if (norm2(r) / nf <= prm.rtol) {
+            if (settle()) {
+                info->converged = 1;
+                break;
+            }
+            continue;
+        }
+        if (omega == 0.0 || !std::isfinite(omega)) return breakdown("omega = 0");
     }
     if (!info->converged) {
         residual(A, f.data(), x.data(), r.data());
@@ -842,6 +1000,12 @@ int ora_solve(void* hp, const double* f, double* u, ora_info* info) {
     Hierarchy* h = (Hierarchy*)hp;
     if (!h || !f || !u || !info) return fail(ORA_ERR_ARG, "bad argument");
     return pcg(*h, f, u, info);
+}
+
+int ora_solve_bicgstab(void* hp, const double* f, double* u, ora_info* info) {
+    Hierarchy* h = (Hierarchy*)hp;
+    if (!h || !f || !u || !info) return fail(ORA_ERR_ARG, "bad argument");
+    return bicgstab(*h, f, u, info);
 }
 
 int ora_vcycle(void* hp, const double* r, double* z) {

@@ -75,6 +75,7 @@ def lib():
                                          C.POINTER(OracleParams)]
         L.ora_rebuild.argtypes = [P, pd, C.c_int]
         L.ora_solve.argtypes = [P, pd, pd, C.POINTER(OracleInfo)]
+        L.ora_solve_bicgstab.argtypes = [P, pd, pd, C.POINTER(OracleInfo)]
         L.ora_vcycle.argtypes = [P, pd, pd]
         L.ora_num_levels.argtypes = [P]
         L.ora_level_dims.argtypes = [P, C.c_int, pi64]
@@ -204,6 +205,14 @@ class OracleHierarchy:
         u = np.zeros(self.n) if u is None else np.array(u, dtype=np.float64, copy=True)
         info = OracleInfo()
         _check(lib().ora_solve(self.h, _p(f, C.c_double), _p(u, C.c_double), C.byref(info)))
+        return u, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true)
+
+    def solve_bicgstab(self, f, u=None):
+        """BiCGStab with the V-cycle on the right (the paper's Krylov method)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        u = np.zeros(self.n) if u is None else np.array(u, dtype=np.float64, copy=True)
+        info = OracleInfo()
+        _check(lib().ora_solve_bicgstab(self.h, _p(f, C.c_double), _p(u, C.c_double), C.byref(info)))
         return u, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true)
 
     def vcycle(self, r):

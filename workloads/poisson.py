@@ -220,3 +220,54 @@ def series_matrix(cfg_id: int, t: int, N: int | None = None):
     if c["kind"] == "lognormal27":
         return lognormal_27pt(N, t, cfg_id=cfg_id)
     raise ValueError(f"configuration {cfg_id} has no matrix series")
+
+
+# ----------------------------------------------------------------------------- C6 (non-symmetric)
+
+STREAM_FLOW = 6
+
+
+def convdiff_velocity(N: int, t: int, peclet: float = 1.0, period: int = 40, nz: int | None = None):
+    """Cell velocities of the convection-diffusion series, shape [nz, 3]: a flow turning in
+    the x-y plane with period ``period`` steps, w = peclet*N*(1 + 0.5 sin(2 pi z)) *
+    (cos phi_t, sin phi_t, 0.25), phi_t = 2 pi t / period (constant in x and y)."""
+    nz = N if nz is None else nz
+    zc = (np.arange(nz) + 0.5) / nz
+    phi = 2.0 * np.pi * t / period
+    amp = peclet * N * (1.0 + 0.5 * np.sin(2.0 * np.pi * zc))
+    return amp[:, None] * np.array([np.cos(phi), np.sin(phi), 0.25])[None, :]
+
+
+def convdiff_7pt(N: int, t: int, peclet: float = 1.0, period: int = 40, ny: int | None = None,
+                 nz: int | None = None):
+    """Non-symmetric 7-point convection-diffusion operator -lap u + w.grad u on the unit
+    cube (h = 1/N), first-order upwind convection, scaled by h^2: row c has diagonal
+    6 + h(|w_x| + |w_y| + |w_z|) and, towards the neighbour in direction -+e_d, the entry
+    -1 - h max(+-w_d, 0) (the upwind side carries the convection); homogeneous Dirichlet
+    closure (a missing neighbour's entry is dropped, the diagonal keeps its 6).  A
+    diagonally dominant M-matrix with the 7-point pattern; at peclet = 0 it is the
+    constant-coefficient Laplacian of two_fluid_7pt with rho_heavy = 1.  Returns
+    (row_ptr int32, col int32, val float64)."""
+    nx = N
+    ny = N if ny is None else ny
+    nz = N if nz is None else nz
+    h = 1.0 / N
+    w = convdiff_velocity(N, t, peclet, period, nz)           # [nz, 3]
+    wz = np.broadcast_to(w[:, None, None, :], (nz, ny, nx, 3))
+    offs = _offsets("7pt")
+    row_ptr, col, mask = stencil_pattern(nx, ny, nz, "7pt")
+    n = nx * ny * nz
+    dense = np.zeros((n, len(offs)), dtype=np.float64)
+    centre = offs.index((0, 0, 0))
+    diag = np.full((nz, ny, nx), 6.0)
+    for d in range(3):
+        diag = diag + h * np.abs(wz[..., d])
+    for o, e in enumerate(offs):
+        if o == centre:
+            continue
+        d = int(np.flatnonzero(e)[0])
+        sgn = e[d]                                            # -1: neighbour behind, +1: ahead
+        conv = h * np.maximum(-sgn * wz[..., d], 0.0)         # upwind side only
+        dense[:, o] = (-1.0 - conv).reshape(-1)
+    dense[:, centre] = diag.reshape(-1)
+    return row_ptr, col, dense[mask]
