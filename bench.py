@@ -40,9 +40,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed time steps")
     ap.add_argument("--warmup", type=int, default=3, help="untimed time steps before the timed ones")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5, 6],
                     help="matrix series: 2 = two-fluid 7-point 128^3 FP64 (the headline), 3 = two-fluid "
-                         "7-point 192^3, 5 = lognormal 27-point 160^3 with the FP32 hierarchy")
+                         "7-point 192^3, 5 = lognormal 27-point 160^3 with the FP32 hierarchy, 6 = non-symmetric "
+                         "convection-diffusion 7-point 128^3 solved by BiCGStab")
     ap.add_argument("--n", type=int, default=0, help="grid size N (N^3 unknowns); 0: the series' own")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -56,10 +57,12 @@ def parse():
 def workload_name(cfg_id, N, n, nnz):
     series = {2: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               3: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
-              5: "27-point lognormal-coefficient Poisson (sigma 1.5) with smooth drift per step"}[cfg_id]
+              5: "27-point lognormal-coefficient Poisson (sigma 1.5) with smooth drift per step",
+              6: "non-symmetric upwind convection-diffusion 7-point, flow turning 9 degrees per step"}[cfg_id]
     form = ("FP32 hierarchy and V-cycle under FP64 CG" if cfg_id == 5 else "FP64")
+    krylov = "BiCGStab" if cfg_id == 6 else "PCG"
     return (f"{series}, {N}^3 (n={n}, nnz={nnz}); partial reuse (numeric-only cached RAP + smoother), "
-            f"{form}, PCG to 1e-8 true rel res")
+            f"{form}, {krylov} to 1e-8 true rel res")
 
 
 def copy_probe(mib):
@@ -91,6 +94,7 @@ def kernel_bytes(dims, sv_h, ndiag=0, sym=False):
     b = {}
     # Krylov operator SpMV fused with p = z + beta p and p.q: A, z, p_old read; p_new, q written
     b["cg_pq"] = ind0(n, nnzA) + 8 * a0 + 8 * 4 * n
+    b["krylov_spmv"] = ind(n, nnzA) + 8 * nnzA + 8 * 2 * n   # CSR y = A x: A, x read, y written
     b["cg_update"] = 8 * 6 * n          # p, q, x, r read; x, r written
     b["cg_rz"] = 8 * 2 * n
     b["cg_init"] = ind(n, nnzA) + 8 * nnzA + 8 * 3 * n
@@ -136,6 +140,10 @@ def main():
     # the series' own precision for the headline line: FP64, or the FP32 hierarchy under
     # FP64 CG for the 27-point series
     head_prec = 1 if cfg_id == 5 else 0
+    bicg = cfg_id == 6  # the non-symmetric series: BiCGStab, the paper's Krylov method
+
+    def solve(amg, f, x):
+        return amg.solve_bicgstab(f, x) if bicg else amg.solve(f, x)
     amg_params = dict(eps_strong=cfg["eps_strong"])
 
     # ---------------------------------------------------------------- inputs in HBM
@@ -172,12 +180,12 @@ def main():
             else:
                 amg.rebuild_ex(vals[t], OPERATOR_ONLY)
             u.zero_()
-            _, info = amg.solve(rhs[t], u)
+            _, info = solve(amg, rhs[t], u)
             its = info["iters"]
             if mode == "reuse" and not info["converged"]:
                 amg.rebuild_ex(vals[t], FULL)
                 u.zero_()
-                _, info = amg.solve(rhs[t], u)
+                _, info = solve(amg, rhs[t], u)
                 its += info["iters"]
                 if record:
                     info_log["rebuilds"] += 1
@@ -202,14 +210,16 @@ def main():
         return amg, (te - ts) * 1e3 / K, info_log, kt
 
     # ---------------------------------------------------------------- partial reuse (headline)
-    traced = ["cg_pq", "galerkin_ap", "galerkin_rap"]
+    spmv_cls = "bicg_spmv" if bicg else "cg_pq"
+    traced = [spmv_cls, "galerkin_ap", "galerkin_rap"]
     amg, ms_partial, info_p, kt = series("partial", precision=head_prec, trace=traced)
     L = amg.num_levels
     dims = [amg.dims(l) for l in range(L)]
     ndiag = amg.level_format(0)
     nread = amg.diagonals_read(0)
     plane = amg.march_plane(0)
-    pq_kernel = "k_m7_cg_pq" if plane else ("k_dia_cg_pq" if ndiag else "k_cg_pq")
+    pq_kernel = ("k_rb_spmv" if bicg else
+                 "k_m7_cg_pq" if plane else ("k_dia_cg_pq" if ndiag else "k_cg_pq"))
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
     log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
     ph = amg.phase_times()
@@ -220,21 +230,24 @@ def main():
     amg.trace_read()
     amg.rebuild(vals[W + 1])
     u.zero_()
-    amg.solve(rhs[W + 1], u)
+    solve(amg, rhs[W + 1], u)
     breakdown_all = amg.trace_read()
     amg.trace(KERNEL_CLASSES, level=0)
     amg.rebuild(vals[W + 1])
     u.zero_()
-    amg.solve(rhs[W + 1], u)
+    solve(amg, rhs[W + 1], u)
     breakdown_l0 = amg.trace_read()
     amg.trace([], level=0)
     amg.close()
 
     kb = kernel_bytes(dims, 8, ndiag, sym=0 < nread < ndiag)
     # live measurement over the timed region
-    pq_ms, pq_cnt = kt.get("cg_pq", (0.0, 0))
+    pq_ms, pq_cnt = kt.get(spmv_cls, (0.0, 0))
     n_solves = K
-    spmv_bytes = pq_cnt * kb["cg_pq"] - n_solves * 8 * n  # first iteration reads no p_old
+    if bicg:
+        spmv_bytes = pq_cnt * kb["krylov_spmv"]
+    else:
+        spmv_bytes = pq_cnt * kb["cg_pq"] - n_solves * 8 * n  # first iteration reads no p_old
     spmv_gbs = spmv_bytes / (pq_ms * 1e-3) / 1e9 if pq_ms > 0 else None
     g_ms = kt.get("galerkin_ap", (0.0, 0))[0] + kt.get("galerkin_rap", (0.0, 0))[0]
     g_cnt = kt.get("galerkin_rap", (0.0, 0))[1]
@@ -288,7 +301,9 @@ def main():
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
-        "roofline": roof(pq_kernel + " (Krylov operator SpMV with p = z + beta p and p.q, level 0)", pq_ms, pq_cnt,
+        "roofline": roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, CSR, level 0)"
+                                      if bicg else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
+                         pq_ms, pq_cnt,
                          spmv_bytes / pq_cnt if pq_cnt else 0,
                          pq_traffic if (cfg_id == 2 and N == 128 and pq_traffic is not None
                                         and pq_traffic["kernel"] == pq_kernel) else None),
@@ -305,6 +320,8 @@ def main():
             plan = [("full", "full", 1), ("fp64_partial", "partial", 0)]
         elif cfg_id == 3:
             plan = [("mixed", "partial", 1), ("full", "full", 0)]
+        elif cfg_id == 6:
+            plan = [("full", "full", 0), ("mixed", "partial", 1)]
         else:
             plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1), ("policy", "policy", 0)]
         for name, mode, prec in plan:
@@ -355,14 +372,15 @@ def main():
             ft = rhs_uniform(n, cfg_id, t)
             ts = time.perf_counter()  # the step's inputs are generated outside the timing
             h.rebuild(vt, 0)
-            _, io = h.solve(ft)
+            _, io = h.solve_bicgstab(ft) if bicg else h.solve(ft)
             elapsed += time.perf_counter() - ts
             its.append(io["iters"])
         cpu_ms = elapsed * 1e3 / ks
         h.close()
         log(f"oracle: setup {t_setup:.1f}s, partial step {cpu_ms:.0f} ms ({nthr} threads), iters {its}")
         result["cpu_baseline"] = {"value": cpu_ms, "unit": "ms/step", "cores": nthr, "kind": "oracle",
-                                  "sample": f"oracle (FP64) partial rebuild + PCG solve to 1e-8 of {cfg['name']} at "
+                                  "sample": f"oracle (FP64) partial rebuild + {'BiCGStab' if bicg else 'PCG'} solve "
+                                            f"to 1e-8 of {cfg['name']} at "
                                             f"{N}^3, steps t=1..{ks} after an untimed setup at t=0 (full setup "
                                             f"took {t_setup:.1f}s); iterations {its}"}
     print(json.dumps(result), flush=True)

@@ -140,6 +140,16 @@ amg_status amg_rebuild_auto(amg_ctx* c, const double* val, const amg_policy* p, 
  * converging is not an error (info->converged = 0). */
 amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* info);
 
+/* BiCGStab (van der Vorst) with one V-cycle applied on the right per half step: the
+ * paper's Krylov method, for non-symmetric operators (Section 4).  Arguments, stopping
+ * rule (true relative residual, maxiter, restart from the true residual when the
+ * recursive one reached rtol but the true one did not) and info as for amg_solve; each
+ * iteration applies the V-cycle and the Krylov operator twice and reads dot-product
+ * partials back three times.  A zero or non-finite r^.r, r^.v, t.t or omega returns
+ * AMG_ERR_BREAKDOWN.  The coarsest level's inverse is formed without pivoting and needs
+ * positive elimination pivots (diagonally dominant M-matrices have them). */
+amg_status amg_solve_bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info);
+
 /* One V-cycle z = B r from a zero initial guess (r, z: device, n entries). */
 amg_status amg_vcycle(amg_ctx* c, const double* r, double* z);
 
@@ -202,6 +212,7 @@ typedef enum {
     AMG_K_COARSE_GEMV = 12,  /* u_L = A_L^{-1} f_L */
     AMG_K_CAST = 13,         /* FP64 <-> FP32 conversions of the mixed-precision form */
     AMG_K_TAIL = 14,         /* restriction into the coarse tail and Algorithm 2 on all its levels */
+    AMG_K_BICG_SPMV = 15,    /* BiCGStab's products with the Krylov operator (v = A p^, t = A s^) */
     AMG_K_COUNT = 16
 } amg_kernel_class;
 

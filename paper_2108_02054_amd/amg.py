@@ -25,11 +25,12 @@ EXPORTED = [
     "amg_rebuild_ex", "amg_solve", "amg_vcycle", "amg_destroy", "amg_last_error", "amg_num_levels",
     "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
     "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read", "amg_policy_pick",
-    "amg_rebuild_auto",
+    "amg_rebuild_auto", "amg_solve_bicgstab",
 ]
 MODE_NAMES = {PARTIAL: "partial", FULL: "full", OPERATOR_ONLY: "operator_only"}
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
-                  "cg_init", "smooth0_res", "jacobi", "restrict", "prolong", "coarse_gemv", "cast", "tail"]
+                  "cg_init", "smooth0_res", "jacobi", "restrict", "prolong", "coarse_gemv", "cast", "tail",
+                  "bicg_spmv"]
 
 
 class AmgError(RuntimeError):
@@ -97,6 +98,7 @@ def lib():
         L.amg_set_pattern.argtypes = [V, I32, I64, V, V]
         L.amg_rebuild_ex.argtypes = [V, V, I]
         L.amg_solve.argtypes = [V, V, V, C.POINTER(AmgSolveInfo)]
+        L.amg_solve_bicgstab.argtypes = [V, V, V, C.POINTER(AmgSolveInfo)]
         L.amg_vcycle.argtypes = [V, V, V]
         L.amg_destroy.argtypes = [V]
         L.amg_last_error.argtypes = [V]
@@ -233,6 +235,17 @@ class AMG:
             _dev(u, torch.float64, "u")
         info = AmgSolveInfo()
         self._check(lib().amg_solve(self.ctx, _ptr(f), _ptr(u), C.byref(info)))
+        return u, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true)
+
+    def solve_bicgstab(self, f: torch.Tensor, u: torch.Tensor | None = None):
+        """BiCGStab with the V-cycle on the right (non-symmetric operators).  Returns (u, info)."""
+        _dev(f, torch.float64, "f")
+        if u is None:
+            u = torch.zeros_like(f)
+        else:
+            _dev(u, torch.float64, "u")
+        info = AmgSolveInfo()
+        self._check(lib().amg_solve_bicgstab(self.ctx, _ptr(f), _ptr(u), C.byref(info)))
         return u, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true)
 
     def vcycle(self, r: torch.Tensor) -> torch.Tensor:

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libamgmi.so")
 SOURCES = ["amg_api.hip", "kernels_solve.hip", "kernels_galerkin.hip", "kernels_setup.hip",
-           "kernels_logcoef.hip"]
+           "kernels_logcoef.hip", "kernels_krylov.hip"]
 ARCH = os.environ.get("AMGMI_ARCH", "gfx950")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -532,6 +532,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     c->pol_iters_ref = 0;
     c->pol_last_iters = 0;
     c->pol_last_conv = 0;
+    c->bi_t = nullptr;  // a hierarchy allocation: released with the old hierarchy
     hipStream_t s = c->stream;
     const amg_params& p = c->prm;
     const auto t_all = Clock::now();
@@ -1072,6 +1073,153 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
     return AMG_OK;
 }
 
+// ------------------------------------------------------------------ BiCGStab
+
+// BiCGStab (van der Vorst) with one V-cycle applied on the right: the paper's Krylov
+// method for its non-symmetric systems (Section 4), with the CG's stopping rule (true
+// relative residual; when the recursive ||s|| or ||r|| reaches rtol the true residual is
+// formed and, if it is not small enough, the method restarts from it with r^ = r).  Per
+// iteration: two V-cycles, two products with the Krylov operator, and three host reads
+// of dot-product partials (r^.v for alpha, ||s||, t.s and t.t for omega; r^.r and ||r||
+// come with the update).  Scalars are formed on the host from partials added in
+// workgroup order.
+amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
+    hipStream_t s = c->stream;
+    const Level& L0 = c->lv[0];
+    const int n = L0.A.nrows;
+    const amg_params& prm = c->prm;
+    if (!c->bi_t) c->bi_t = halloc<double>(c, (size_t)n);
+    if (!c->h_bi) {
+        HIP_CHECK(hipHostMalloc((void**)&c->h_bi, 2 * (size_t)RED_BLOCKS * sizeof(double),
+                                hipHostMallocMapped | hipHostMallocCoherent));
+        void* dptr = nullptr;
+        HIP_CHECK(hipHostGetDevicePointer(&dptr, c->h_bi, 0));
+        c->d_bi = (double*)dptr;
+    }
+    Csr Aout = L0.A;  // the Krylov operator: the hierarchy's pattern, the outer values
+    Aout.val = c->outer_val;
+    double *x = c->x, *r = c->r, *rh = c->r2, *p = c->pa, *v = c->q, *ph = c->z, *sv = c->zold, *sh = c->pb,
+           *t = c->bi_t;
+    const int nb = bi_grid(n);
+    double* part = c->d_bi;
+    const double* hp = c->h_bi;
+    auto sum = [&](int q) {
+        double a = 0.0;
+        for (int i = 0; i < nb; ++i) a += hp[(size_t)q * nb + i];
+        return a;
+    };
+    auto wait = [&]() { HIP_CHECK(hipStreamSynchronize(s)); };
+    auto true_residual = [&]() {  // r = f - A x; partials ||r||^2, ||f||^2
+        launch_spmv<double>(Aout, x, t, nullptr, nullptr, s);
+        launch_bi_residual(n, f, t, r, part, nb, s);
+        wait();
+        return sum(0);
+    };
+    amg_solve_info inf{0, 0, 0.0};
+    launch_copy(n, u, x, s);
+    double rr = true_residual();
+    const double ff = sum(1);
+    if (ff == 0.0) {
+        HIP_CHECK(hipMemsetAsync(u, 0, (size_t)n * sizeof(double), s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        inf.converged = 1;
+        if (info) *info = inf;
+        return AMG_OK;
+    }
+    const double nf = std::sqrt(ff);
+    double res = std::sqrt(rr) / nf;
+    if (res <= prm.rtol) {
+        inf.converged = 1;
+        inf.rel_res_true = res;
+        if (info) *info = inf;
+        return AMG_OK;
+    }
+    d2d(rh, r, (size_t)n * sizeof(double), s);
+    double rho = rr, rho_prev = 1.0, alpha = 1.0, omega = 1.0;  // rho = r^.r of the coming step
+    bool fresh = true;
+    int it = 0;
+    bool converged = false;
+    auto settle = [&]() {  // true residual; converged, or restart from it
+        rr = true_residual();
+        res = std::sqrt(rr) / nf;
+        if (res <= prm.rtol) return true;
+        d2d(rh, r, (size_t)n * sizeof(double), s);
+        rho = rr;
+        rho_prev = alpha = omega = 1.0;
+        fresh = true;
+        return false;
+    };
+    auto breakdown = [&](const char* what) {
+        c->err = std::string("BiCGStab breakdown: ") + what;
+        HIP_CHECK(hipStreamSynchronize(s));
+        if (info) {
+            inf.iters = it;
+            *info = inf;
+        }
+        return AMG_ERR_BREAKDOWN;
+    };
+    while (it < prm.maxiter) {
+        ++it;
+        if (rho == 0.0 || !std::isfinite(rho)) return breakdown("r^.r = 0");
+        const double beta = fresh ? 0.0 : (rho / rho_prev) * (alpha / omega);
+        launch_bi_direction(n, r, v, beta, omega, fresh ? 1 : 0, p, s);
+        fresh = false;
+        vcycle_apply(c, p, ph);
+        {
+            Trace tr(c, AMG_K_BICG_SPMV, 0);
+            launch_spmv<double>(Aout, ph, v, nullptr, nullptr, s);
+        }
+        launch_bi_dots(n, rh, v, nullptr, nullptr, part, nb, s);
+        wait();
+        const double rv = sum(0);
+        if (rv == 0.0 || !std::isfinite(rv)) return breakdown("r^.v = 0");
+        alpha = rho / rv;
+        launch_bi_half(n, r, v, alpha, sv, part, nb, s);
+        wait();
+        if (std::sqrt(sum(0)) / nf <= prm.rtol) {
+            launch_bi_xhalf(n, ph, alpha, x, s);
+            if (settle()) {
+                converged = true;
+                break;
+            }
+            continue;
+        }
+        vcycle_apply(c, sv, sh);
+        {
+            Trace tr(c, AMG_K_BICG_SPMV, 0);
+            launch_spmv<double>(Aout, sh, t, nullptr, nullptr, s);
+        }
+        launch_bi_dots(n, t, sv, t, t, part, nb, s);
+        wait();
+        const double ts = sum(0), tt = sum(1);
+        if (tt == 0.0 || !std::isfinite(tt)) return breakdown("t.t = 0");
+        omega = ts / tt;
+        launch_bi_update(n, ph, sh, sv, t, rh, alpha, omega, x, r, part, nb, s);
+        wait();
+        rho_prev = rho;
+        rho = sum(0);
+        if (std::sqrt(sum(1)) / nf <= prm.rtol) {
+            if (settle()) {
+                converged = true;
+                break;
+            }
+            continue;
+        }
+        if (omega == 0.0 || !std::isfinite(omega)) return breakdown("omega = 0");
+    }
+    if (!converged) {
+        rr = true_residual();
+        res = std::sqrt(rr) / nf;
+    }
+    launch_copy(n, x, u, s);
+    HIP_CHECK(hipStreamSynchronize(s));
+    inf.iters = it;
+    inf.converged = converged ? 1 : 0;
+    inf.rel_res_true = res;
+    if (info) *info = inf;
+    return AMG_OK;
+}
+
 // ------------------------------------------------------------------ context lifecycle
 
 amg_status check_params(const amg_params& p) {
@@ -1093,6 +1241,7 @@ void destroy_ctx(amg_ctx* c) {
     dfree(c->pend_col, s);
     (void)hipStreamSynchronize(s);
     if (c->h_red) (void)hipHostFree(c->h_red);
+    if (c->h_bi) (void)hipHostFree(c->h_bi);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     for (hipEvent_t& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -1324,6 +1473,17 @@ amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* inf
     if (!c || !f || !u) return AMG_ERR_ARG;
     amg_solve_info inf{0, 0, 0.0};
     const amg_status st = guard(c, [&] { return pcg(c, f, u, &inf); });
+    c->pol_last_iters = st == AMG_OK ? (inf.iters > 0 ? inf.iters : 1) : (c->prm.maxiter > 0 ? c->prm.maxiter : 1);
+    c->pol_last_conv = st == AMG_OK ? inf.converged : 0;
+    if (c->pol_iters_ref == 0 && st == AMG_OK) c->pol_iters_ref = c->pol_last_iters;
+    if (info) *info = inf;
+    return st;
+}
+
+amg_status amg_solve_bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
+    if (!c || !f || !u) return AMG_ERR_ARG;
+    amg_solve_info inf{0, 0, 0.0};
+    const amg_status st = guard(c, [&] { return bicgstab(c, f, u, &inf); });
     c->pol_last_iters = st == AMG_OK ? (inf.iters > 0 ? inf.iters : 1) : (c->prm.maxiter > 0 ? c->prm.maxiter : 1);
     c->pol_last_conv = st == AMG_OK ? inf.converged : 0;
     if (c->pol_iters_ref == 0 && st == AMG_OK) c->pol_iters_ref = c->pol_last_iters;

@@ -203,6 +203,20 @@ extern thread_local KernelEvents g_kernel_events;
 std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
 // Workgroups of the 7-point marching kernels for n rows with plane stride a.
 int march_blocks(int n, int a);
+
+// BiCGStab vector kernels (kernels_krylov.hip).  Partials: part[q * nb + workgroup].
+int bi_grid(int64_t n);
+void launch_bi_residual(int64_t n, const double* f, const double* y, double* r, double* part, int nb, hipStream_t s);
+void launch_bi_dots(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
+                    int nb, hipStream_t s);
+void launch_bi_direction(int64_t n, const double* r, const double* v, double beta, double omega, int first, double* p,
+                         hipStream_t s);
+void launch_bi_half(int64_t n, const double* r, const double* v, double alpha, double* sv, double* part, int nb,
+                    hipStream_t s);
+void launch_bi_xhalf(int64_t n, const double* ph, double alpha, double* x, hipStream_t s);
+void launch_bi_update(int64_t n, const double* ph, const double* sh, const double* sv, const double* t,
+                      const double* rh, double alpha, double omega, double* x, double* r, double* part, int nb,
+                      hipStream_t s);
 void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s);
 template <typename T>
 void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s);
@@ -361,6 +375,10 @@ struct amg_ctx {
            *q = nullptr;
     amgmi::RedScratch rs{};
     double* h_red = nullptr;      // pinned host mirror of the scalars and the P_RR, P_FF partials
+    // BiCGStab: one more vector (the hierarchy's) and mapped host memory for its partials
+    double* bi_t = nullptr;
+    double* h_bi = nullptr;
+    double* d_bi = nullptr;
     int* d_flags = nullptr;       // setup flags
     int* h_flags = nullptr;       // pinned
     // pending pattern for amg_rebuild(..., pattern_changed)

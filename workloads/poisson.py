@@ -207,11 +207,13 @@ CONFIGS = {
             precision="fp64"),
     5: dict(name="lognormal_27pt_160", N=160, steps=40, kind="lognormal27",
             eps_strong=0.02, precision="mixed"),
+    6: dict(name="convdiff_7pt_128", N=128, steps=40, kind="convdiff", eps_strong=0.08,
+            precision="fp64"),
 }
 
 
 def series_matrix(cfg_id: int, t: int, N: int | None = None):
-    """Matrix of step t of configuration ``cfg_id`` (C1, C2, C3, C5)."""
+    """Matrix of step t of configuration ``cfg_id`` (C1, C2, C3, C5, C6)."""
     c = CONFIGS[cfg_id]
     N = c["N"] if N is None else N
     if c["kind"] == "two_fluid":
@@ -219,13 +221,12 @@ def series_matrix(cfg_id: int, t: int, N: int | None = None):
         return two_fluid_7pt(N, front)
     if c["kind"] == "lognormal27":
         return lognormal_27pt(N, t, cfg_id=cfg_id)
+    if c["kind"] == "convdiff":
+        return convdiff_7pt(N, t)
     raise ValueError(f"configuration {cfg_id} has no matrix series")
 
 
 # ----------------------------------------------------------------------------- C6 (non-symmetric)
-
-STREAM_FLOW = 6
-
 
 def convdiff_velocity(N: int, t: int, peclet: float = 1.0, period: int = 40, nz: int | None = None):
     """Cell velocities of the convection-diffusion series, shape [nz, 3]: a flow turning in
