@@ -218,8 +218,8 @@ def main():
     ndiag = amg.level_format(0)
     nread = amg.diagonals_read(0)
     plane = amg.march_plane(0)
-    pq_kernel = ("k_rb_spmv" if bicg else
-                 "k_m7_cg_pq" if plane else ("k_dia_cg_pq" if ndiag else "k_cg_pq"))
+    pq_kernel = ("k_rb_spmv" if bicg else "k_m7_cg_pq" if plane else
+                 ("k_w_cg_pq" if 0 < ndiag != 7 else "k_dia_cg_pq") if ndiag else "k_cg_pq")
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
     log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
     ph = amg.phase_times()

@@ -376,6 +376,12 @@ void configure_dia(amg_ctx* c) {
         D.march_a = offs[6];
         D.march_b = offs[5];
     }
+    // windowed kernels for other stencils (the kernels that read several FP64 vectors per
+    // neighbour; every windowed kernel with AMGMI_WIN_ALL)
+    if (D.march_a == 0 && std::getenv("AMGMI_NO_WIN") == nullptr) {
+        D.win = win_plan(offs);
+        D.win.all = std::getenv("AMGMI_WIN_ALL") != nullptr;
+    }
     if (std::getenv("AMGMI_NO_DIA_SYM") != nullptr) D.symoff = false;
     D.slot = halloc<uint8_t>(c, (size_t)A.nnz);
     launch_dia_slots(A, D, s);

@@ -176,12 +176,27 @@ struct DiaOff {
     // A(i, j) as the super-diagonal entry A(j, i) and never touch the lower diagonals
     int sym;
 };
+// Windowed form of the diagonal-storage kernels: the offsets fall into at most
+// WIN_MAX_CL clusters (a stencil's planes); a workgroup of TPB rows stages, per cluster,
+// the vector entries of rows [i0 + lo, i0 + TPB + lo + span) in LDS.
+constexpr int WIN_MAX_CL = 4;
+constexpr int WIN_CAP = 4096;   // LDS entries per workgroup (all windows)
+struct WinPlan {
+    int ncl = 0;                // 0: not used
+    int lo[WIN_MAX_CL] = {0, 0, 0, 0};    // smallest offset of the cluster
+    int len[WIN_MAX_CL] = {0, 0, 0, 0};   // window length: TPB + span of the cluster
+    int base[WIN_MAX_CL] = {0, 0, 0, 0};  // start of the window in LDS
+    int total = 0;                        // LDS entries of all windows
+    bool all = false;                     // also the V-cycle kernels (else the Krylov SpMV only)
+    unsigned char cl[DIA_MAX] = {};       // cluster of each diagonal
+};
 struct Dia {
     int ndiag = 0;              // 0: not used
     DiaOff off{};
     bool symoff = false;        // the offsets are -k..k-symmetric and include 0
     // 7-point marching kernels: offsets -a, -b, -1, 0, 1, b, a; march_a == 0: not used
     int march_a = 0, march_b = 0;
+    WinPlan win;                // windowed kernels for other stencils (ncl == 0: not used)
     double* val = nullptr;      // FP64 values (Krylov operator and FP64 V-cycle)
     float* val32 = nullptr;     // FP32 values (mixed-precision V-cycle)
     uint8_t* slot = nullptr;    // diagonal of every stored entry of A_0
@@ -203,6 +218,9 @@ extern thread_local KernelEvents g_kernel_events;
 std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
 // Workgroups of the 7-point marching kernels for n rows with plane stride a.
 int march_blocks(int n, int a);
+// Window plan for the sorted offsets (clusters split at gaps wider than a workgroup), or
+// ncl = 0 when they need more clusters or LDS than the windowed kernels have.
+WinPlan win_plan(const std::vector<int>& offs);
 
 // BiCGStab vector kernels (kernels_krylov.hip).  Partials: part[q * nb + workgroup].
 int bi_grid(int64_t n);

@@ -60,13 +60,13 @@ thread_local KernelEvents g_kernel_events;
 // records its start and stop events itself (hipExtLaunchKernel), so that they bracket the
 // kernel's execution and not the dispatch gap before it.
 template <typename F, typename... Args>
-void timed_launch(F k, unsigned grid, unsigned block, hipStream_t s, Args... args) {
+void timed_launch(F k, unsigned grid, unsigned block, unsigned shmem, hipStream_t s, Args... args) {
     if (g_kernel_events.start != nullptr) {
         const KernelEvents e = g_kernel_events;
         g_kernel_events = KernelEvents{};
-        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, e.start, e.stop, 0, args...);
+        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, e.start, e.stop, 0, args...);
     } else {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, args...);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, args...);
     }
 }
 
@@ -911,6 +911,206 @@ __global__ __launch_bounds__(TPB) void k_m7_update_smooth0(int n, int a, int b, 
     block_store<1>(loc, dst, xcd_block());
 }
 
+// ------------------------------------------------------------------ windowed form
+//
+// Level-0 kernels for other stencils in diagonal storage (the 27-point operator): the
+// offsets fall into a few clusters (the grid planes below, at and above a row), and a
+// workgroup of TPB consecutive rows stages, per cluster, the vector entries its rows
+// reach through that cluster (rows [i0 + lo, i0 + TPB + lo + span)) in LDS with
+// coalesced loads, so each vector entry is loaded about (TPB + span) / TPB times per
+// cluster instead of once per diagonal.  The matrix entries are loaded as in dia_row
+// (all before the barrier), and each row adds the same terms in the same order with the
+// same fused multiply-adds, so its result is the one-row-per-thread kernels' bit for bit.
+
+WinPlan win_plan(const std::vector<int>& offs) {
+    WinPlan w;
+    const int nd = (int)offs.size();
+    if (nd == 0 || nd > DIA_MAX) return w;
+    int k = 0, start = 0, total = 0;
+    for (int d = 0; d <= nd; ++d) {
+        if (d == nd || (d > start && offs[(size_t)d] - offs[(size_t)d - 1] > TPB)) {
+            if (k == WIN_MAX_CL) return WinPlan{};
+            w.lo[k] = offs[(size_t)start];
+            w.len[k] = TPB + (offs[(size_t)d - 1] - offs[(size_t)start]);
+            w.base[k] = total;
+            total += w.len[k];
+            for (int q = start; q < d; ++q) w.cl[q] = (unsigned char)k;
+            ++k;
+            start = d;
+        }
+    }
+    if (total > WIN_CAP) return WinPlan{};
+    w.ncl = k;
+    w.total = total;
+    return w;
+}
+
+template <int ND, bool SYM, typename T, typename XG, typename EP>
+__device__ __forceinline__ void win_rows(int n, int nd_rt, const DiaOff& o, const WinPlan& w,
+                                         const T* __restrict__ v, XG xget, EP epi) {
+    extern __shared__ __align__(16) unsigned char win_smem[];  // w.total entries, sized at launch
+    T* X = reinterpret_cast<T*>(win_smem);
+    const int nd = ND > 0 ? ND : nd_rt;
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)xcd_block() * TPB;
+    for (int k = 0; k < w.ncl; ++k)
+        for (int e = t; e < w.len[k]; e += TPB) {
+            const int64_t j = i0 + w.lo[k] + e;
+            X[w.base[k] + e] = (j >= 0 && j < n) ? xget((int)j) : T(0);
+        }
+    const int64_t i = i0 + t;
+    const bool row = i < n;
+    const int ii = row ? (int)i : 0;
+    const size_t sn = (size_t)n;
+    // the row's matrix entries (one-row-per-thread order; mirrored reads when symmetric)
+    auto coef = [&](int d) {
+        const int off = o.off[d];
+        const int64_t j = i + off;
+        const int jj = (j >= 0 && j < n) ? (int)j : ii;
+        return (SYM && off < 0) ? v[(size_t)(nd - 1 - d) * sn + jj] : v[(size_t)d * sn + ii];
+    };
+    constexpr int NA = ND > 0 ? ND : 1;
+    T A[NA];
+    if constexpr (ND > 0) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) A[d] = coef(d);
+    }
+    __syncthreads();
+    if (!row) return;
+    T s = 0, xc = 0;
+#pragma unroll
+    for (int d = 0; d < (ND > 0 ? ND : DIA_MAX); ++d) {
+        if (ND == 0 && d >= nd) break;
+        const int off = o.off[d];
+        const int k = w.cl[d];
+        const T x = X[w.base[k] + (off - w.lo[k]) + t];
+        if (off == 0) xc = x;
+        const int64_t j = i + off;
+        const bool in = j >= 0 && j < n;
+        T a;
+        if constexpr (ND > 0)
+            a = A[d];
+        else
+            a = coef(d);
+        s = in ? fmadd(a, x, s) : s;
+    }
+    epi((int)i, s, xc);
+}
+
+template <int ND, bool SYM, typename T>
+__global__ __launch_bounds__(TPB) void k_w_smooth0_residual(int n, int nd, DiaOff o, WinPlan w,
+                                                            const T* __restrict__ v, const T* __restrict__ m,
+                                                            const T* __restrict__ f, T* __restrict__ u,
+                                                            T* __restrict__ r) {
+    win_rows<ND, SYM, T>(n, nd, o, w, v, [&](int j) { return m[j] * f[j]; }, [&](int i, T s, T xc) {
+        u[i] = xc;
+        r[i] = f[i] - s;
+    });
+}
+
+template <int ND, bool SYM, typename T>
+__global__ __launch_bounds__(TPB) void k_w_residual(int n, int nd, DiaOff o, WinPlan w, const T* __restrict__ v,
+                                                    const T* __restrict__ f, const T* __restrict__ u,
+                                                    T* __restrict__ r) {
+    win_rows<ND, SYM, T>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, T s, T) { r[i] = f[i] - s; });
+}
+
+template <int ND, bool SYM, typename T>
+__global__ __launch_bounds__(TPB) void k_w_jacobi(int n, int nd, DiaOff o, WinPlan w, const T* __restrict__ v,
+                                                  const T* __restrict__ m, const T* __restrict__ f,
+                                                  const T* __restrict__ u, T* __restrict__ uout) {
+    win_rows<ND, SYM, T>(n, nd, o, w, v, [&](int j) { return u[j]; },
+                         [&](int i, T s, T xc) { uout[i] = xc + m[i] * (f[i] - s); });
+}
+
+template <int ND, bool SYM>
+__global__ __launch_bounds__(TPB) void k_w_jacobi_rz(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
+                                                     const double* __restrict__ m, const double* __restrict__ r,
+                                                     const double* __restrict__ u, double* __restrict__ z,
+                                                     int flexible, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    win_rows<ND, SYM, double>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, double s, double xc) {
+        const double ri = r[i];
+        const double zi = xc + m[i] * (ri - s);
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    });
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, xcd_block());
+}
+
+template <int ND, bool SYM, bool FIRST>
+__global__ __launch_bounds__(TPB) void k_w_cg_pq(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
+                                                 const double* __restrict__ z, const double* __restrict__ pold,
+                                                 double* __restrict__ pnew, double* __restrict__ q, RedScratch rs) {
+    const double beta = FIRST ? 0.0 : rs.scal()[S_BETA];
+    double loc[1] = {0.0};
+    win_rows<ND, SYM, double>(
+        n, nd, o, w, v, [&](int j) { return FIRST ? z[j] : __builtin_fma(beta, pold[j], z[j]); },
+        [&](int i, double s, double xc) {
+            pnew[i] = xc;
+            q[i] = s;
+            loc[0] += xc * s;
+        });
+    double* const dst[1] = {rs.region(P_PQ)};
+    block_store<1>(loc, dst, xcd_block());
+}
+
+template <int ND, bool SYM>
+__global__ __launch_bounds__(TPB) void k_w_update_smooth0(int n, int nd, DiaOff o, WinPlan w,
+                                                          const double* __restrict__ v, const double* __restrict__ p,
+                                                          const double* __restrict__ q, double* __restrict__ x,
+                                                          const double* __restrict__ r, double* __restrict__ rn,
+                                                          const double* __restrict__ m, double* __restrict__ u,
+                                                          double* __restrict__ rv, RedScratch rs) {
+    const double* sc = rs.scal();
+    const bool bad = sc[S_FLAG] != 0.0;
+    const double alpha = sc[S_ALPHA];
+    const double step = bad ? 0.0 : alpha;
+    double loc[1] = {0.0};
+    win_rows<ND, SYM, double>(
+        n, nd, o, w, v, [&](int j) { return m[j] * __builtin_fma(-step, q[j], r[j]); },
+        [&](int i, double s, double xc) {
+            const double ri = __builtin_fma(-step, q[i], r[i]);
+            if (!bad) x[i] = __builtin_fma(alpha, p[i], x[i]);
+            rn[i] = ri;
+            u[i] = xc;
+            rv[i] = ri - s;
+            loc[0] += ri * ri;
+        });
+    double* const dst[1] = {rr_dest(rs, bad)};
+    block_store<1>(loc, dst, xcd_block());
+}
+
+template <typename T>
+inline unsigned win_bytes(const Dia& D) {
+    return (unsigned)((size_t)D.win.total * sizeof(T));
+}
+
+// Runs f(std::integral_constant<int, ND>, std::bool_constant<SYM>) for the windowed form
+// when D has one (ND = 27 for the 27-point stencil, else 0).
+// `gains`: the kernel reads two or more FP64 vectors per neighbour (the Krylov SpMV, the
+// CG update fused with the first sweep, the FP64 first sweep): the windows win there; the
+// sweeps that read one vector per neighbour, and the FP32 ones, measured faster with one
+// row per thread (27-point, 160^3: last sweep 176 against 231 us), so they use the
+// windows only when D.win.all is set.
+template <typename F>
+inline bool win_call(const Dia& D, F&& f, bool gains = false) {
+    if (D.win.ncl == 0 || !(gains || D.win.all)) return false;
+    auto with_nd = [&](auto S) {
+        if (D.ndiag == 27)
+            f(std::integral_constant<int, 27>{}, S);
+        else
+            f(std::integral_constant<int, 0>{}, S);
+    };
+    if (D.off.sym)
+        with_nd(std::true_type{});
+    else
+        with_nd(std::false_type{});
+    return true;
+}
+
 // Runs f(std::bool_constant<SYM>) for the marching form when D has one.
 template <typename F>
 inline bool march_call(const Dia& D, F&& f) {
@@ -946,6 +1146,13 @@ void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T*
         HIP_LAUNCH_CHECK();
         return;
     }
+    if (win_call(D, [&](auto K, auto S) {
+            k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, T>
+                <<<dia_blocks(n), TPB, win_bytes<T>(D), s>>>(n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
+        }, std::is_same<T, double>::value)) {
+        HIP_LAUNCH_CHECK();
+        return;
+    }
     dia_nd(D.ndiag, [&](auto K) {
         k_dia_smooth0_residual<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, r);
     });
@@ -960,6 +1167,13 @@ void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipS
         HIP_LAUNCH_CHECK();
         return;
     }
+    if (win_call(D, [&](auto K, auto S) {
+            k_w_residual<decltype(K)::value, decltype(S)::value, T>
+                <<<dia_blocks(n), TPB, win_bytes<T>(D), s>>>(n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return;
+    }
     dia_nd(D.ndiag, [&](auto K) {
         k_dia_residual<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), f, u, r);
     });
@@ -970,6 +1184,13 @@ void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, 
     if (march_call(D, [&](auto S) {
             k_m7_jacobi<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
                 n, D.march_a, D.march_b, D.v<T>(), m, f, u, uout);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return;
+    }
+    if (win_call(D, [&](auto K, auto S) {
+            k_w_jacobi<decltype(K)::value, decltype(S)::value, T>
+                <<<dia_blocks(n), TPB, win_bytes<T>(D), s>>>(n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
         })) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1002,6 +1223,13 @@ int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, 
     }
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    if (win_call(D, [&](auto K, auto S) {
+            k_w_jacobi_rz<decltype(K)::value, decltype(S)::value>
+                <<<nb, TPB, win_bytes<double>(D), s>>>(n, D.ndiag, D.off, D.win, D.val, m, r, u, z, flexible, rs);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
     dia_nd(D.ndiag, [&](auto K) {
         k_dia_jacobi_rz<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
     });
@@ -1016,10 +1244,10 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
         march_call(D, [&](auto S) {
             constexpr bool SYM = decltype(S)::value;
             if (first)
-                timed_launch(k_m7_cg_pq<SYM, true>, nb, TPB, s, n, D.march_a, D.march_b, (const double*)D.val, z,
+                timed_launch(k_m7_cg_pq<SYM, true>, nb, TPB, 0, s, n, D.march_a, D.march_b, (const double*)D.val, z,
                              pold, pnew, q, rs);
             else
-                timed_launch(k_m7_cg_pq<SYM, false>, nb, TPB, s, n, D.march_a, D.march_b, (const double*)D.val, z,
+                timed_launch(k_m7_cg_pq<SYM, false>, nb, TPB, 0, s, n, D.march_a, D.march_b, (const double*)D.val, z,
                              pold, pnew, q, rs);
         });
         HIP_LAUNCH_CHECK();
@@ -1027,12 +1255,25 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
     }
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    if (win_call(D, [&](auto K, auto S) {
+            constexpr int NDK = decltype(K)::value;
+            constexpr bool SYM = decltype(S)::value;
+            if (first)
+                timed_launch(k_w_cg_pq<NDK, SYM, true>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, (const double*)D.val,
+                             z, pold, pnew, q, rs);
+            else
+                timed_launch(k_w_cg_pq<NDK, SYM, false>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, (const double*)D.val,
+                             z, pold, pnew, q, rs);
+        }, true)) {
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
     dia_nd(D.ndiag, [&](auto K) {
         if (first)
-            timed_launch(k_dia_cg_pq<decltype(K)::value, true>, nb, TPB, s, n, D.ndiag, D.off, (const double*)D.val,
+            timed_launch(k_dia_cg_pq<decltype(K)::value, true>, nb, TPB, 0, s, n, D.ndiag, D.off, (const double*)D.val,
                          z, pold, pnew, q, rs);
         else
-            timed_launch(k_dia_cg_pq<decltype(K)::value, false>, nb, TPB, s, n, D.ndiag, D.off, (const double*)D.val,
+            timed_launch(k_dia_cg_pq<decltype(K)::value, false>, nb, TPB, 0, s, n, D.ndiag, D.off, (const double*)D.val,
                          z, pold, pnew, q, rs);
     });
     HIP_LAUNCH_CHECK();
@@ -1054,6 +1295,13 @@ int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double
     }
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    if (win_call(D, [&](auto K, auto S) {
+            k_w_update_smooth0<decltype(K)::value, decltype(S)::value>
+                <<<nb, TPB, win_bytes<double>(D), s>>>(n, D.ndiag, D.off, D.win, D.val, p, q, x, r, rn, m, u, rv, rs);
+        }, true)) {
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
     dia_nd(D.ndiag, [&](auto K) {
         k_dia_update_smooth0<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
     });
@@ -1510,7 +1758,7 @@ int launch_cg_pq(const Csr& A, const double* val, const double* z, const double*
                  int first, const RedScratch& rs, hipStream_t s) {
     const int nb = full_grid_rows(A.nrows, A.rpb, A.g);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    AMG_WITH_G(A.g, timed_launch(k_cg_pq<G>, nb, RB_THREADS, s, A.nrows, A.rpb, (const int*)A.ptr, (const int*)A.col,
+    AMG_WITH_G(A.g, timed_launch(k_cg_pq<G>, nb, RB_THREADS, 0, s, A.nrows, A.rpb, (const int*)A.ptr, (const int*)A.col,
                                  val, z, pold, pnew, q, first, rs));
     HIP_LAUNCH_CHECK();
     return nb;

@@ -497,6 +497,50 @@ def test_marching_kernels_match_row_kernels(monkeypatch, shape, precision):
     assert rel_fro(um, ur) <= 1e-7
 
 
+@pytest.mark.parametrize("case", ["ln27_16", "ln27_20", "tf7_nomarch"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_windowed_kernels_match_row_kernels(monkeypatch, case, precision):
+    """The windowed diagonal-storage kernels (vector entries of each offset cluster staged
+    in LDS per workgroup) give every row the one-row-per-thread result bit for bit: the
+    27-point operator on grids whose plane is and is not a multiple of a workgroup, and a
+    7-point operator with the marching kernels switched off."""
+    from paper_2108_02054_amd import AMG
+
+    if case.startswith("ln27"):
+        N = int(case.split("_")[1])
+        p, c, v0 = lognormal_27pt(N, 0)
+        v1 = lognormal_27pt(N, 2)[2]
+        prm = dict(eps_strong=0.02)
+    else:
+        monkeypatch.setenv("AMGMI_NO_MARCH", "1")
+        p, c, v0 = two_fluid_7pt(33, 0.4, ny=17, nz=9)
+        v1 = two_fluid_7pt(33, 0.45, ny=17, nz=9)[2]
+        prm = dict()
+    prm["precision"] = precision
+    monkeypatch.setenv("AMGMI_WIN_ALL", "1")  # the V-cycle kernels too
+    n = len(p) - 1
+    r = np.random.default_rng(14).standard_normal(n)
+    f = rhs_uniform(n, 1, 3)
+    print(f"case {case} precision {precision}", flush=True)
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), **prm)
+        g.rebuild(T(v1))
+        u1, i1 = g.solve(T(f))
+        z = g.vcycle(T(r)).cpu().numpy()
+        out = (z, u1.cpu().numpy(), i1)
+        g.close()
+        return out
+
+    zw, uw, iw = run()
+    monkeypatch.setenv("AMGMI_NO_WIN", "1")
+    zr, ur, ir = run()
+    assert np.array_equal(zw, zr)
+    assert iw["converged"] and ir["converged"]
+    assert abs(iw["iters"] - ir["iters"]) <= 1
+    assert rel_fro(uw, ur) <= 1e-7
+
+
 def test_full_size_128_partial_rebuild_and_solve():
     """At the benchmark's full size (two-fluid 128^3, the configuration bench.py times,
     with the diagonal storage and the default launch shapes): after a partial rebuild to a
