@@ -94,7 +94,7 @@ def kernel_bytes(dims, sv_h, ndiag=0, sym=False):
     b = {}
     # Krylov operator SpMV fused with p = z + beta p and p.q: A, z, p_old read; p_new, q written
     b["cg_pq"] = ind0(n, nnzA) + 8 * a0 + 8 * 4 * n
-    b["krylov_spmv"] = ind(n, nnzA) + 8 * nnzA + 8 * 2 * n   # CSR y = A x: A, x read, y written
+    b["krylov_spmv"] = ind0(n, nnzA) + 8 * a0 + 8 * 2 * n   # y = A x: A, x read, y written
     b["cg_update"] = 8 * 6 * n          # p, q, x, r read; x, r written
     b["cg_rz"] = 8 * 2 * n
     b["cg_init"] = ind(n, nnzA) + 8 * nnzA + 8 * 3 * n
@@ -218,8 +218,12 @@ def main():
     ndiag = amg.level_format(0)
     nread = amg.diagonals_read(0)
     plane = amg.march_plane(0)
-    pq_kernel = ("k_rb_spmv" if bicg else "k_m7_cg_pq" if plane else
-                 ("k_w_cg_pq" if 0 < ndiag != 7 else "k_dia_cg_pq") if ndiag else "k_cg_pq")
+    if plane:
+        pq_kernel = "k_m7_cg_pq"
+    elif ndiag:
+        pq_kernel = "k_w_cg_pq" if ndiag != 7 else "k_dia_cg_pq"
+    else:
+        pq_kernel = "k_rb_spmv" if bicg else "k_cg_pq"
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
     log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
     ph = amg.phase_times()
@@ -301,7 +305,7 @@ def main():
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
-        "roofline": roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, CSR, level 0)"
+        "roofline": roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, level 0)"
                                       if bicg else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
                          pq_ms, pq_cnt,
                          spmv_bytes / pq_cnt if pq_cnt else 0,

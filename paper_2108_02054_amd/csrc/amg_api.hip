@@ -538,7 +538,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     c->pol_iters_ref = 0;
     c->pol_last_iters = 0;
     c->pol_last_conv = 0;
-    c->bi_t = nullptr;  // a hierarchy allocation: released with the old hierarchy
+    c->bi_t = c->bi_w = nullptr;  // hierarchy allocations: released with the old hierarchy
     hipStream_t s = c->stream;
     const amg_params& p = c->prm;
     const auto t_all = Clock::now();
@@ -1104,6 +1104,16 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
     }
     Csr Aout = L0.A;  // the Krylov operator: the hierarchy's pattern, the outer values
     Aout.val = c->outer_val;
+    // y = A x: on the diagonal storage when it holds the Krylov operator (the Krylov SpMV
+    // kernel with beta = 0 also copies x to bi_w and adds x.y partials, both unused)
+    const bool on_dia = c->dia.ndiag > 0 && c->outer_val == L0.A.val;
+    if (on_dia && !c->bi_w) c->bi_w = halloc<double>(c, (size_t)n);
+    auto apply_A = [&](const double* xin, double* yout) {
+        if (on_dia)
+            launch_dia_cg_pq(n, c->dia, xin, xin, c->bi_w, yout, 1, c->rs, s);
+        else
+            launch_spmv<double>(Aout, xin, yout, nullptr, nullptr, s);
+    };
     double *x = c->x, *r = c->r, *rh = c->r2, *p = c->pa, *v = c->q, *ph = c->z, *sv = c->zold, *sh = c->pb,
            *t = c->bi_t;
     const int nb = bi_grid(n);
@@ -1116,7 +1126,7 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
     };
     auto wait = [&]() { HIP_CHECK(hipStreamSynchronize(s)); };
     auto true_residual = [&]() {  // r = f - A x; partials ||r||^2, ||f||^2
-        launch_spmv<double>(Aout, x, t, nullptr, nullptr, s);
+        apply_A(x, t);
         launch_bi_residual(n, f, t, r, part, nb, s);
         wait();
         return sum(0);
@@ -1173,7 +1183,7 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
         vcycle_apply(c, p, ph);
         {
             Trace tr(c, AMG_K_BICG_SPMV, 0);
-            launch_spmv<double>(Aout, ph, v, nullptr, nullptr, s);
+            apply_A(ph, v);
         }
         launch_bi_dots(n, rh, v, nullptr, nullptr, part, nb, s);
         wait();
@@ -1193,7 +1203,7 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
         vcycle_apply(c, sv, sh);
         {
             Trace tr(c, AMG_K_BICG_SPMV, 0);
-            launch_spmv<double>(Aout, sh, t, nullptr, nullptr, s);
+            apply_A(sh, t);
         }
         launch_bi_dots(n, t, sv, t, t, part, nb, s);
         wait();

@@ -395,6 +395,7 @@ struct amg_ctx {
     double* h_red = nullptr;      // pinned host mirror of the scalars and the P_RR, P_FF partials
     // BiCGStab: one more vector (the hierarchy's) and mapped host memory for its partials
     double* bi_t = nullptr;
+    double* bi_w = nullptr;       // the p copy the diagonal-storage SpMV writes (unused here)
     double* h_bi = nullptr;
     double* d_bi = nullptr;
     int* d_flags = nullptr;       // setup flags
