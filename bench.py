@@ -279,6 +279,9 @@ def main():
     pq_traffic = load_traffic(os.path.join(ROOT, "profiles", "cg_pq_two_fluid_128_traffic.json"))
     if pq_traffic is not None:
         pq_traffic["_path"] = "cg_pq_two_fluid_128_traffic.json"
+    rap_traffic = load_traffic(os.path.join(ROOT, "profiles", "galerkin_two_fluid_128_traffic.json"))
+    if rap_traffic is not None:
+        rap_traffic["_path"] = "galerkin_two_fluid_128_traffic.json"
 
     result = {
         "metric": METRIC,
@@ -312,7 +315,8 @@ def main():
                          pq_traffic if (cfg_id == 2 and N == 128 and pq_traffic is not None
                                         and pq_traffic["kernel"] == pq_kernel) else None),
         "roofline_rap": roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
-                             kb["galerkin"]),
+                             kb["galerkin"],
+                             rap_traffic if (cfg_id == 2 and N == 128 and head_prec == 0) else None),
         "kernels_level0_ms": {k: v for k, v in breakdown_l0.items()},
         "kernels_all_levels_ms": {k: v for k, v in breakdown_all.items()},
     }

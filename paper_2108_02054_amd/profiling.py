@@ -12,7 +12,8 @@ Usage (after the rocprofv3 runs):
   python -m paper_2108_02054_amd.profiling stats <kernel_stats.csv> <out.txt> --command "..." --workload "..."
   python -m paper_2108_02054_amd.profiling traffic --kernel k_cg_pq --source csrc/kernels_solve.hip \\
       --fetch <dir>/run_counter_collection.csv --write <dir>/run_counter_collection.csv \\
-      --copy-fetch <dir> --copy-write <dir> --copy-mib 256 --command "..." --out profiles/x.json
+      --copy-fetch <dir> --copy-write <dir> --copy-mib 256 --command "..." --out profiles/x.json \\
+      [--part REGEX:GRID ...]   (several kernels per unit, e.g. the Galerkin products of level 0)
 """
 from __future__ import annotations
 
@@ -72,12 +73,14 @@ def write_stats(csv_path: str, out_txt: str, command: str, workload: str, top: i
         f.write("\n".join(lines) + "\n")
 
 
-def counter_per_dispatch(csv_path: str, counter: str, kernel_re: str) -> list[float]:
-    """Counter value (KiB) of every dispatch whose kernel name matches kernel_re."""
+def counter_per_dispatch(csv_path: str, counter: str, kernel_re: str, grid: int | None = None) -> list[float]:
+    """Counter value (KiB) of every dispatch whose kernel name matches kernel_re (and whose
+    grid size is ``grid`` when given)."""
     vals = []
     for r in csv.DictReader(open(csv_path)):
         if r["Counter_Name"] == counter and re.search(kernel_re, r["Kernel_Name"]):
-            vals.append(float(r["Counter_Value"]))
+            if grid is None or int(r["Grid_Size"]) == grid:
+                vals.append(float(r["Counter_Value"]))
     return vals
 
 
@@ -91,21 +94,28 @@ def copy_kib(run_dir: str, counter: str) -> float:
 
 
 def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, copy_fetch_dir: str, copy_write_dir: str,
-            copy_mib: int, command: str) -> dict:
+            copy_mib: int, command: str, parts: list[tuple[str, int]] | None = None) -> dict:
+    """HBM bytes per launch of ``kernel``; with ``parts`` (kernel regex, grid size) the
+    per-dispatch averages of each part are added (one unit = one dispatch of every part,
+    e.g. the two Galerkin products of one level per rebuild)."""
     known = copy_mib * 1024.0 * 1024.0
     f_scale = known / (copy_kib(copy_fetch_dir, "FETCH_SIZE") * 1024.0)
     w_scale = known / (copy_kib(copy_write_dir, "WRITE_SIZE") * 1024.0)
-    f = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel)
-    w = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel)
-    if not f or not w:
-        raise ValueError(f"no dispatches of {kernel}")
-    fb = sum(f) / len(f) * 1024.0 * f_scale
-    wb = sum(w) / len(w) * 1024.0 * w_scale
+    fb = wb = 0.0
+    nd = 0
+    for rx, grid in (parts or [(kernel, None)]):
+        f = counter_per_dispatch(fetch_csv, "FETCH_SIZE", rx, grid)
+        w = counter_per_dispatch(write_csv, "WRITE_SIZE", rx, grid)
+        if not f or not w:
+            raise ValueError(f"no dispatches of {rx} (grid {grid})")
+        fb += sum(f) / len(f) * 1024.0 * f_scale
+        wb += sum(w) / len(w) * 1024.0 * w_scale
+        nd += len(f)
     return {
         "kernel": kernel,
         "source": os.path.relpath(source, os.path.dirname(HERE)),
         "source_sha256_16": source_hash(source),
-        "dispatches": len(f),
+        "dispatches": nd,
         "fetch_bytes_per_launch": fb,
         "write_bytes_per_launch": wb,
         "traffic_bytes_per_launch": fb + wb,
@@ -145,12 +155,15 @@ def main():
     b.add_argument("--copy-mib", type=int, required=True)
     b.add_argument("--command", required=True)
     b.add_argument("--out", required=True)
+    b.add_argument("--part", action="append", default=[], metavar="REGEX:GRID",
+                   help="add the per-dispatch traffic of the dispatches of REGEX with grid size GRID")
     args = ap.parse_args()
     if args.cmd == "stats":
         write_stats(args.csv, args.out, args.command, args.workload)
     else:
+        parts = [(p.rsplit(":", 1)[0], int(p.rsplit(":", 1)[1])) for p in args.part] or None
         rec = traffic(args.kernel, args.source, args.fetch, args.write, args.copy_fetch, args.copy_write,
-                      args.copy_mib, args.command)
+                      args.copy_mib, args.command, parts)
         with open(args.out, "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps(rec, indent=1))
