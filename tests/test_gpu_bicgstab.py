@@ -70,3 +70,24 @@ def test_bicgstab_series_64_and_edge_cases():
     _, info = g.solve_bicgstab(f, x.clone())
     assert info["converged"] and info["iters"] <= 1
     g.close()
+
+
+def test_bicgstab_full_reuse_matches_oracle():
+    """Algorithm 3 (only the Krylov operator changes) under BiCGStab: the products use the
+    CSR form of the new operator, the V-cycle the old hierarchy; iterations and solution
+    follow the oracle's."""
+    p, c, v0 = convdiff_7pt(16, 0)
+    v4 = convdiff_7pt(16, 4)[2]
+    n = len(p) - 1
+    g, o = both(p, c, v0)
+    from paper_2108_02054_amd.amg import OPERATOR_ONLY
+    g.rebuild_ex(T(v4), OPERATOR_ONLY)
+    o.rebuild(v4, 2)
+    f = rhs_uniform(n, 6, 4)
+    u, info = g.solve_bicgstab(T(f))
+    uo, io = o.solve_bicgstab(f)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iters"] - io["iters"]) <= 1, (info, io)
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+    g.close()
+    o.close()
