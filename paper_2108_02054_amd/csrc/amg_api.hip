@@ -114,6 +114,8 @@ void release_csr(amg_ctx* c, Csr& m) {
     release(c, m.col);
     release(c, m.val);
     release(c, m.val32);
+    release(c, m.c16);
+    release(c, m.cblk);
     m = Csr{};
 }
 
@@ -233,13 +235,33 @@ GalForce galerkin_force() {
     return f;
 }
 
-// Launch shapes of a matrix's row kernels (reads its row pointers back once).
-void configure(Csr& A, hipStream_t s) {
+// Launch shapes of a matrix's row kernels (reads its row pointers back once), and its
+// two-byte column indices for the row-block kernels when every block's columns fit
+// (matrices of at least C16_MIN_NNZ entries; AMGMI_NO_C16 keeps int32 everywhere).
+constexpr int64_t C16_MIN_NNZ = 1 << 18;
+void configure(amg_ctx* c, Csr& A, hipStream_t s) {
     A.g = lane_group(A.nrows > 0 ? (double)A.nnz / A.nrows : 1.0);
     std::vector<int32_t> hp((size_t)A.nrows + 1);
     HIP_CHECK(hipMemcpyAsync(hp.data(), A.ptr, hp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
     A.rpb = lanes_only() ? 0 : pick_rows_per_block(hp.data(), A.nrows);
+    release(c, A.c16);
+    release(c, A.cblk);
+    A.c16 = nullptr;
+    A.cblk = nullptr;
+    if (A.rpb == 0 || A.nnz < C16_MIN_NNZ || std::getenv("AMGMI_NO_C16") != nullptr) return;
+    const int nb = (A.nrows + A.rpb - 1) / A.rpb;
+    int32_t* cblk = halloc<int32_t>(c, (size_t)nb);
+    clear_flags(c);
+    launch_c16_bases(A, cblk, c->d_flags + F_ARG, s);
+    read_flags(c);
+    if (c->h_flags[F_ARG]) {  // some block spans more than two bytes of columns
+        release(c, cblk);
+        return;
+    }
+    A.cblk = cblk;
+    A.c16 = halloc<uint16_t>(c, (size_t)A.nnz);
+    launch_c16_fill(A, cblk, A.c16, s);
 }
 
 template <typename T>
@@ -293,10 +315,10 @@ GalShape make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, bool 
 // Launch shapes of a level's row kernels and Galerkin kernels (Ac: the next level's
 // operator, whose pattern is the second Galerkin product's), with the position maps.
 void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
-    configure(L.A, s);
+    configure(c, L.A, s);
     if (L.P.nrows > 0 && Ac != nullptr) {
-        configure(L.P, s);
-        configure(L.R, s);
+        configure(c, L.P, s);
+        configure(c, L.R, s);
         L.gAP = lane_group((double)L.AP.nnz / (L.A.nrows > 0 ? (double)L.A.nrows : 1.0));
         const GalForce f = galerkin_force();
         L.galAP = make_posmap(c, L.A, L.P, L.AP, true, f, s);

@@ -53,6 +53,10 @@ struct Csr {
     // stage, use lane groups) and the lane-group width.
     int rpb = 0;
     int g = 8;
+    // Two-byte column indices for the row-block kernels: col = cblk[row block] + c16[k]
+    // (null when some block's columns span more than 65535)
+    uint16_t* c16 = nullptr;
+    int32_t* cblk = nullptr;
     template <typename T>
     T* v() const;
 };
@@ -216,6 +220,11 @@ struct KernelEvents {
 extern thread_local KernelEvents g_kernel_events;
 
 std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
+// Two-byte column indices of A for its row blocks (A.rpb > 0): writes cblk (one base per
+// block) and sets *wide when a block's columns span more than 65535; then c16.
+void launch_c16_bases(const Csr& A, int32_t* cblk, int* wide, hipStream_t s);
+void launch_c16_fill(const Csr& A, const int32_t* cblk, uint16_t* c16, hipStream_t s);
+
 // Workgroups of the 7-point marching kernels for n rows with plane stride a.
 int march_blocks(int n, int a);
 // Window plan for the sorted offsets (clusters split at gaps wider than a workgroup), or

@@ -94,6 +94,79 @@ __device__ __forceinline__ void rb_load(int row0, int row1, const int* __restric
     __syncthreads();
 }
 
+// Column indices as the row-block kernels of the V-cycle read them: int32, or two bytes
+// relative to a base per row block (rows of a block reach nearby columns: aggregates of
+// neighbouring nodes), which saves 2 of the 12 bytes an FP64 entry costs.
+struct ColSrc {
+    const int* __restrict__ col;
+    const uint16_t* __restrict__ c16;
+    const int* __restrict__ cblk;
+};
+inline ColSrc colsrc(const Csr& A) { return ColSrc{A.col, A.c16, A.cblk}; }
+
+template <typename T, class X>
+__device__ __forceinline__ void rb_load(int row0, int row1, const int* __restrict__ ptr, const ColSrc& cs, int blk,
+                                        const T* __restrict__ val, X xget, int* sptr, T* sp) {
+    const int nr = row1 - row0;
+    for (int i = threadIdx.x; i <= nr; i += RB_THREADS) sptr[i] = ptr[row0 + i];
+    const int cb = cs.c16 != nullptr ? cs.cblk[blk] : 0;
+    __syncthreads();
+    const int k0 = sptr[0], k1 = min(sptr[nr], k0 + RB_CAP);  // blocks are sized within RB_CAP
+    if (cs.c16 != nullptr) {
+#pragma unroll
+        for (int it = 0; it < RB_CAP / RB_THREADS; ++it) {
+            const int k = k0 + it * RB_THREADS + (int)threadIdx.x;
+            if (k < k1) sp[k - k0] = val[k] * xget(cb + (int)cs.c16[k]);
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < RB_CAP / RB_THREADS; ++it) {
+            const int k = k0 + it * RB_THREADS + (int)threadIdx.x;
+            if (k < k1) sp[k - k0] = val[k] * xget(cs.col[k]);
+        }
+    }
+    __syncthreads();
+}
+
+// One base per row block: the smallest column of its rows (rows are sorted, so the
+// first entry of each); *wide = 1 when a block's columns span more than two bytes.
+__global__ __launch_bounds__(TPB) void k_c16_bases(int n, int rpb, const int* __restrict__ ptr,
+                                                   const int* __restrict__ col, int* __restrict__ cblk,
+                                                   int* __restrict__ wide) {
+    const int b = blockIdx.x * TPB + threadIdx.x;
+    const int nb = (n + rpb - 1) / rpb;
+    if (b >= nb) return;
+    const int r0 = b * rpb, r1 = min(r0 + rpb, n);
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int r = r0; r < r1; ++r)
+        if (ptr[r] < ptr[r + 1]) {
+            lo = min(lo, col[ptr[r]]);
+            hi = max(hi, col[ptr[r + 1] - 1]);
+        }
+    if (lo > hi) lo = hi = 0;  // no entries
+    cblk[b] = lo;
+    if ((int64_t)hi - lo > 65535) wide[0] = 1;
+}
+
+__global__ __launch_bounds__(TPB) void k_c16_fill(int n, int rpb, const int* __restrict__ ptr,
+                                                  const int* __restrict__ col, const int* __restrict__ cblk,
+                                                  uint16_t* __restrict__ c16) {
+    const int r = blockIdx.x * TPB + threadIdx.x;
+    if (r >= n) return;
+    const int base = cblk[r / rpb];
+    for (int k = ptr[r]; k < ptr[r + 1]; ++k) c16[k] = (uint16_t)(col[k] - base);
+}
+
+void launch_c16_bases(const Csr& A, int32_t* cblk, int* wide, hipStream_t s) {
+    const int nb = (A.nrows + A.rpb - 1) / A.rpb;
+    k_c16_bases<<<(unsigned)((nb + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, cblk, wide);
+    HIP_LAUNCH_CHECK();
+}
+void launch_c16_fill(const Csr& A, const int32_t* cblk, uint16_t* c16, hipStream_t s) {
+    k_c16_fill<<<(unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, cblk, c16);
+    HIP_LAUNCH_CHECK();
+}
+
 // Threads per staged row: a block of rpb rows gives each row RB_THREADS / rpb threads
 // (at most a wavefront), which add strided subsets of the row and combine them with a
 // fixed butterfly; with one thread per row the sum is in plain column order.
@@ -177,7 +250,7 @@ __device__ __forceinline__ double* rr_dest(const RedScratch& rs, bool bad) {
 // smoothing sweep u = m f from zero at the same time).
 template <typename T>
 __global__ __launch_bounds__(RB_THREADS) void k_rb_spmv(int n, int rpb, const int* __restrict__ ptr,
-                                                        const int* __restrict__ col, const T* __restrict__ val,
+                                                        ColSrc cs, const T* __restrict__ val,
                                                         const T* __restrict__ x, T* __restrict__ y,
                                                         const T* __restrict__ m2, T* __restrict__ y2) {
     __shared__ int sptr[RB_THREADS + 1];
@@ -185,7 +258,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_spmv(int n, int rpb, const in
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, col, val, [&](int j) { return x[j]; }, sptr, sp);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return x[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), r = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
     if (r < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, r, lane, tpr);
@@ -198,7 +271,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_spmv(int n, int rpb, const in
 
 template <typename T>
 __global__ __launch_bounds__(RB_THREADS) void k_rb_residual(int n, int rpb, const int* __restrict__ ptr,
-                                                            const int* __restrict__ col, const T* __restrict__ val,
+                                                            ColSrc cs, const T* __restrict__ val,
                                                             const T* __restrict__ f, const T* __restrict__ u,
                                                             T* __restrict__ r) {
     __shared__ int sptr[RB_THREADS + 1];
@@ -206,7 +279,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_residual(int n, int rpb, cons
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, col, val, [&](int j) { return u[j]; }, sptr, sp);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return u[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
@@ -217,7 +290,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_residual(int n, int rpb, cons
 // One damped-Jacobi / SPAI0 sweep: uout = u + m (f - A u)
 template <typename T>
 __global__ __launch_bounds__(RB_THREADS) void k_rb_jacobi(int n, int rpb, const int* __restrict__ ptr,
-                                                          const int* __restrict__ col, const T* __restrict__ val,
+                                                          ColSrc cs, const T* __restrict__ val,
                                                           const T* __restrict__ m, const T* __restrict__ f,
                                                           const T* __restrict__ u, T* __restrict__ uout) {
     __shared__ int sptr[RB_THREADS + 1];
@@ -225,7 +298,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_jacobi(int n, int rpb, const 
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, col, val, [&](int j) { return u[j]; }, sptr, sp);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return u[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
@@ -238,7 +311,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_jacobi(int n, int rpb, const 
 // neighbours' u_j = m_j f_j are formed from m and f.
 template <typename T>
 __global__ __launch_bounds__(RB_THREADS) void k_rb_smooth0_residual(int n, int rpb, const int* __restrict__ ptr,
-                                                                    const int* __restrict__ col,
+                                                                    ColSrc cs,
                                                                     const T* __restrict__ val, const T* __restrict__ m,
                                                                     const T* __restrict__ f, T* __restrict__ u,
                                                                     T* __restrict__ r) {
@@ -247,7 +320,7 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_smooth0_residual(int n, int r
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, col, val, [&](int j) { return m[j] * f[j]; }, sptr, sp);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return m[j] * f[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
@@ -263,14 +336,14 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_smooth0_residual(int n, int r
 // u += P uc (coarse-grid correction)
 template <typename T>
 __global__ __launch_bounds__(RB_THREADS) void k_rb_prolong_add(int n, int rpb, const int* __restrict__ ptr,
-                                                               const int* __restrict__ col, const T* __restrict__ val,
+                                                               ColSrc cs, const T* __restrict__ val,
                                                                const T* __restrict__ uc, T* __restrict__ u) {
     __shared__ int sptr[RB_THREADS + 1];
     __shared__ T sp[RB_CAP];
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, col, val, [&](int j) { return uc[j]; }, sptr, sp);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return uc[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
@@ -361,28 +434,28 @@ static inline unsigned ew_blocks(int64_t n) {
 
 template <typename T>
 void launch_spmv(const Csr& A, const T* x, T* y, const T* m2, T* y2, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_spmv<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), x, y, m2, y2)),
+    AMG_RB_OR_LG(A, (k_rb_spmv<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), x, y, m2, y2)),
                  0, A.nrows, A.ptr, A.col, A.v<T>(), m2, nullptr, x, y, y2);
 }
 template <typename T>
 void launch_residual(const Csr& A, const T* f, const T* u, T* r, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), f, u, r)),
+    AMG_RB_OR_LG(A, (k_rb_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), f, u, r)),
                  1, A.nrows, A.ptr, A.col, A.v<T>(), nullptr, f, u, r, nullptr);
 }
 template <typename T>
 void launch_jacobi(const Csr& A, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_jacobi<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), m, f, u, uout)),
+    AMG_RB_OR_LG(A, (k_rb_jacobi<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), m, f, u, uout)),
                  2, A.nrows, A.ptr, A.col, A.v<T>(), m, f, u, uout, nullptr);
 }
 template <typename T>
 void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_smooth0_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.v<T>(), m, f, u, r)),
+    AMG_RB_OR_LG(A, (k_rb_smooth0_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), m, f, u, r)),
                  3, A.nrows, A.ptr, A.col, A.v<T>(), m, f, nullptr, u, r);
 }
 template <typename T>
 void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s) {
     const Csr& A = P;
-    AMG_RB_OR_LG(A, (k_rb_prolong_add<T><<<grid_for(P.nrows, P.rpb), RB_THREADS, 0, s>>>(P.nrows, P.rpb, P.ptr, P.col, P.v<T>(), uc, u)),
+    AMG_RB_OR_LG(A, (k_rb_prolong_add<T><<<grid_for(P.nrows, P.rpb), RB_THREADS, 0, s>>>(P.nrows, P.rpb, P.ptr, colsrc(P), P.v<T>(), uc, u)),
                  4, P.nrows, P.ptr, P.col, P.v<T>(), nullptr, nullptr, uc, u, nullptr);
 }
 template <typename T>

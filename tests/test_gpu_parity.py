@@ -541,6 +541,33 @@ def test_windowed_kernels_match_row_kernels(monkeypatch, case, precision):
     assert rel_fro(uw, ur) <= 1e-7
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_byte_columns_change_nothing(monkeypatch, precision):
+    """The row-block kernels reading two-byte block-relative column indices (64^3: level 0's
+    P and R and level 1's operator qualify) give the int32 kernels' results bit for bit."""
+    from paper_2108_02054_amd import AMG
+
+    p, c, v0 = two_fluid_7pt(64, front_moving(64, 0))
+    v1 = two_fluid_7pt(64, front_moving(64, 2))[2]
+    n = len(p) - 1
+    r = np.random.default_rng(15).standard_normal(n)
+    f = rhs_uniform(n, 2, 2)
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), precision=precision)
+        g.rebuild(T(v1))
+        u, info = g.solve(T(f))
+        z = g.vcycle(T(r)).cpu().numpy()
+        out = (z, u.cpu().numpy(), info["iters"])
+        g.close()
+        return out
+
+    a = run()
+    monkeypatch.setenv("AMGMI_NO_C16", "1")
+    b = run()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
 def test_full_size_128_partial_rebuild_and_solve():
     """At the benchmark's full size (two-fluid 128^3, the configuration bench.py times,
     with the diagonal storage and the default launch shapes): after a partial rebuild to a
