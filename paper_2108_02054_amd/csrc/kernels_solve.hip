@@ -479,16 +479,16 @@ void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
 // ------------------------------------------------------------------ diagonal storage
 //
 // Level-0 kernels on the diagonal storage of A_0: one thread per row, the row's
-// diagonals in increasing offset (that is, column) order, each product added into the
-// row sum; an absent entry is stored as 0 and adds nothing, a column outside [0, n) is
-// never read.  Values and vector entries are read with fully coalesced loads and no index
+// diagonals in increasing offset (that is, column) order, each term added to the row sum
+// with a fused multiply-add; an absent entry is stored as 0, and a column outside [0, n)
+// drops its term.  Values and vector entries are read with coalesced loads and no index
 // arrays.  Reductions write one partial per workgroup (logical block order).
-
 //
 // Symmetric values (o.sym): the offsets are -k..k around a main diagonal in the middle,
 // and the entry on diagonal d < nd/2 of row i is read as the entry on the mirrored
 // diagonal nd-1-d of row j = i + off[d]; that is the same number, so the sum (same terms,
 // same order) is the same to the bit, and only the main and upper diagonals are read.
+
 template <typename T>
 __device__ __forceinline__ T fmadd(T a, T b, T c) {
     if constexpr (std::is_same<T, double>::value)
