@@ -14,7 +14,9 @@
  *   - Algorithm 3 (full reuse: the hierarchy is left as built) and Algorithm 4 (partial
  *     reuse: P_l, R_l kept; smoothers, Galerkin operators and the coarse solver rebuilt).
  * The transfer operators are smoothed aggregation (Vanek, Mandel, Brezina 1996); the
- * paper's own runs use plain aggregation, available here as an option.  The Krylov
+ * paper's own runs use plain aggregation, available here as an option; for its systems
+ * with 4x4 blocks (Section 4) the nodes are aggregated (block_size unknowns per node share
+ * an aggregate, chosen on the matrix of block Frobenius norms).  The Krylov
  * methods are preconditioned CG for SPD systems and BiCGStab (the paper's method, for its
  * non-symmetric systems; van der Vorst 1992, the V-cycle applied on the right).  Details
  * the paper leaves open are fixed as follows and documented per function: strength test,
@@ -81,6 +83,7 @@ typedef struct {
     double rtol;           /* stop when ||f - A u|| / ||f|| <= rtol (true residual) */
     int maxiter;
     int flexible_cg;       /* 1: beta = r.(z - z_old) / rho_old */
+    int block_size;        /* unknowns per node (1: scalar); > 1 needs plain aggregation */
 } ora_params;
 
 typedef struct {
@@ -341,6 +344,48 @@ int aggregate(const Csr& A, const std::vector<uint8_t>& strong, const std::vecto
     return ORA_OK;
 }
 
+/* Node matrix of a system with B unknowns per node (unknown b of node I is row I*B + b):
+ * entry (I, J) is the Frobenius norm of the B x B block A(IB.., JB..), its squares added
+ * row by row, column by column.  Every stored block must be full and the B rows of a node
+ * must list the same columns.  map[k] = node entry of stored entry k. */
+int node_matrix(const Csr& A, int B, Csr& Nm, std::vector<int64_t>& map) {
+    if (A.n_rows % B != 0) return fail(ORA_ERR_ARG, "block_size does not divide the row count");
+    const int32_t nn = A.n_rows / B;
+    Nm = Csr();
+    Nm.n_rows = Nm.n_cols = nn;
+    Nm.ptr.assign((size_t)nn + 1, 0);
+    map.assign(A.col.size(), 0);
+    for (int32_t I = 0; I < nn; ++I) {
+        const int32_t r0 = I * B;
+        const int32_t b0 = A.ptr[r0], len = A.ptr[(size_t)r0 + 1] - b0;
+        if (len % B != 0) return fail(ORA_ERR_PATTERN, "block_size needs full blocks");
+        for (int c = 1; c < B; ++c) {
+            const int32_t bc = A.ptr[(size_t)r0 + c];
+            if (A.ptr[(size_t)r0 + c + 1] - bc != len) return fail(ORA_ERR_PATTERN, "block_size needs full blocks");
+            for (int32_t k = 0; k < len; ++k)
+                if (A.col[(size_t)bc + k] != A.col[(size_t)b0 + k])
+                    return fail(ORA_ERR_PATTERN, "block_size needs full blocks");
+        }
+        for (int32_t g = 0; g < len / B; ++g) {
+            const int32_t c0 = A.col[(size_t)b0 + g * B];
+            if (c0 % B != 0) return fail(ORA_ERR_PATTERN, "block_size needs full blocks");
+            for (int q = 1; q < B; ++q)
+                if (A.col[(size_t)b0 + g * B + q] != c0 + q) return fail(ORA_ERR_PATTERN, "block_size needs full blocks");
+            double ss = 0.0;
+            for (int c = 0; c < B; ++c)
+                for (int q = 0; q < B; ++q) {
+                    const int64_t k = (int64_t)A.ptr[(size_t)r0 + c] + g * B + q;
+                    ss += A.val[k] * A.val[k];
+                    map[k] = (int64_t)Nm.col.size();
+                }
+            Nm.col.push_back(c0 / B);
+            Nm.val.push_back(std::sqrt(ss));
+        }
+        Nm.ptr[(size_t)I + 1] = (int32_t)Nm.col.size();
+    }
+    return ORA_OK;
+}
+
 /* Tentative prolongator (O4): P_tent[i, agg(i)] = 1, empty row when agg(i) = -1. */
 Csr tentative(const std::vector<int32_t>& agg, int32_t nc) {
     Csr P;
@@ -581,6 +626,8 @@ int setup(Hierarchy& h, const Csr& A0) {
     h.lv[0].A = A0;
     h.A_outer = A0;
     const ora_params& p = h.prm;
+    if (p.block_size < 1 || (p.block_size > 1 && p.aggregation != 1))
+        return fail(ORA_ERR_ARG, "block_size must be 1, or > 1 with plain aggregation");
     for (int l = 0;; ++l) {
         Level& cur = h.lv[(size_t)l];
         std::vector<int64_t> dpos, tpos;
@@ -588,10 +635,34 @@ int setup(Hierarchy& h, const Csr& A0) {
         if (st) return st;
         if (cur.A.n_rows <= p.coarse_enough || l >= p.max_levels - 1) break;
         double eps = std::ldexp(p.eps_strong, -l);
-        strength(cur.A, eps, dpos, tpos, cur.strong);
         int32_t nc = 0;
-        st = aggregate(cur.A, cur.strong, tpos, cur.agg, nc);
-        if (st) return st;
+        if (p.block_size > 1) {
+            // systems: aggregate nodes (the strength test and MIS-2 on the node matrix of
+            // block norms); unknown b of a node joins unknown b of its node's aggregate
+            const int B = p.block_size;
+            Csr Nm;
+            std::vector<int64_t> map, ndpos, ntpos;
+            st = node_matrix(cur.A, B, Nm, map);
+            if (st) return st;
+            st = check_matrix(Nm, ndpos, ntpos);
+            if (st) return st;
+            std::vector<uint8_t> nstrong;
+            std::vector<int32_t> nagg;
+            strength(Nm, eps, ndpos, ntpos, nstrong);
+            int32_t ncn = 0;
+            st = aggregate(Nm, nstrong, ntpos, nagg, ncn);
+            if (st) return st;
+            cur.agg.assign((size_t)cur.A.n_rows, -1);
+            for (int32_t i = 0; i < cur.A.n_rows; ++i)
+                if (nagg[(size_t)i / B] >= 0) cur.agg[(size_t)i] = nagg[(size_t)i / B] * B + i % B;
+            cur.strong.assign(cur.A.col.size(), 0);
+            for (size_t k = 0; k < cur.A.col.size(); ++k) cur.strong[k] = nstrong[(size_t)map[k]];
+            nc = ncn * B;
+        } else {
+            strength(cur.A, eps, dpos, tpos, cur.strong);
+            st = aggregate(cur.A, cur.strong, tpos, cur.agg, nc);
+            if (st) return st;
+        }
         if (nc == 0 || nc >= cur.A.n_rows) break;
         Csr Pt = tentative(cur.agg, nc);
         if (p.aggregation == 1) {
@@ -882,6 +953,7 @@ void ora_params_default(ora_params* p) {
     p->rtol = 1e-8;
     p->maxiter = 100;
     p->flexible_cg = 0;
+    p->block_size = 1;
 }
 
 int ora_num_threads(void) {

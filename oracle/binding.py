@@ -44,6 +44,7 @@ class OracleParams(C.Structure):
         ("rtol", C.c_double),
         ("maxiter", C.c_int),
         ("flexible_cg", C.c_int),
+        ("block_size", C.c_int),
     ]
 
 

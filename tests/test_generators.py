@@ -93,3 +93,39 @@ def test_seeds_reproducible():
     th, f, ut, cells = logcoef_inputs(8)
     assert len(set(cells.tolist())) == 16
     assert abs(th.std() - 0.5) < 0.1
+
+
+def test_coupled4_matches_loop_assembly():
+    """The 4x4-block coupled system against a loop over nodes and faces."""
+    from workloads.poisson import coupled4_7pt, coupling_blocks
+    N, t, front = 3, 7, 0.5
+    p, c, v = coupled4_7pt(N, t, front=front)
+    A = np.zeros((4 * N ** 3, 4 * N ** 3))
+    for i in range(len(p) - 1):
+        A[i, c[p[i]:p[i + 1]]] = v[p[i]:p[i + 1]]
+    Kh, Kl = coupling_blocks(t)
+    ref = np.zeros_like(A)
+
+    def cell(x, y, z):
+        heavy = (x + 0.5) / N < front and (z + 0.5) / N < 0.6
+        return (1000.0 if heavy else 1.0), (Kh if heavy else Kl)
+
+    for z in range(N):
+        for y in range(N):
+            for x in range(N):
+                I = x + N * (y + N * z)
+                ri, Ki = cell(x, y, z)
+                for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    X, Y, Z = x + d[0], y + d[1], z + d[2]
+                    if 0 <= X < N and 0 <= Y < N and 0 <= Z < N:
+                        rj, Kj = cell(X, Y, Z)
+                        J = X + N * (Y + N * Z)
+                        w, K = 2.0 / (ri + rj), 0.5 * (Ki + Kj)
+                        ref[4 * I:4 * I + 4, 4 * J:4 * J + 4] = -w * K
+                    else:
+                        w, K = 1.0 / ri, Ki
+                    ref[4 * I:4 * I + 4, 4 * I:4 * I + 4] += w * K
+    assert np.allclose(A, ref, rtol=1e-14, atol=0.0)
+    assert np.array_equal(np.diff(p), np.repeat(np.diff(p)[::4], 4))
+    assert np.all(np.linalg.eigvalsh(Kh) > 0) and np.all(np.linalg.eigvalsh(Kl) > 0)
+    assert np.linalg.eigvalsh(A).min() > 0

@@ -194,6 +194,86 @@ def rhs_uniform(n: int, cfg_id: int, t: int) -> np.ndarray:
     return rng(cfg_id, t, STREAM_RHS).uniform(-1.0, 1.0, size=n)
 
 
+# ----------------------------------------------------------------------------- C7 (4x4 blocks)
+
+def coupling_blocks(t: int, period: int = 40):
+    """The two SPD 4x4 coupling matrices of step t (heavy fluid, light fluid):
+    K = L L^T + I/2 with L lower triangular, its off-diagonal part turning with t."""
+    phi = 2.0 * np.pi * t / period
+    out = []
+    for scale, shift in ((1.0, 0.0), (0.5, 0.5 * np.pi)):
+        c, s = np.cos(phi + shift), np.sin(phi + shift)
+        L = np.array([[1.0, 0.0, 0.0, 0.0],
+                      [0.4 * c, 1.0, 0.0, 0.0],
+                      [0.3 * s, 0.2 * c, 1.0, 0.0],
+                      [0.5 * c * s, 0.3 * s, 0.4 * c, 0.6]]) * scale
+        out.append(L @ L.T + 0.5 * np.eye(4))
+    return out
+
+
+def coupled4_7pt(N: int, t: int, front: float | None = None, rho_heavy: float = 1000.0,
+                 zcut: float = 0.6, period: int = 40):
+    """A monolithic system with 4 unknowns per grid node on the 7-point node graph:
+    unknown b of node I is row 4 I + b (node-major), every stored block is a full 4x4
+    block.  Face (I, J) couples the nodes by -w_IJ K_IJ, w_IJ the two-fluid face
+    coefficient of two_fluid_7pt and K_IJ = (K_I + K_J) / 2 with K_c the heavy or light
+    coupling matrix of coupling_blocks(t); the diagonal block is the sum of the node's
+    w_IJ K_IJ plus w_II K_I per missing neighbour (ghost closure).  A sum of Kronecker
+    products (e_I - e_J)(e_I - e_J)^T (x) w K with SPD K, so SPD.  The front moves one
+    cell per step as in the two-fluid series.  Returns (row_ptr, col, val)."""
+    B = 4
+    nx = ny = nz = N
+    front = front_moving(N, t) if front is None else front
+    xc = (np.arange(nx) + 0.5) / nx
+    zc = (np.arange(nz) + 0.5) / nz
+    heavy = np.broadcast_to((xc[None, None, :] < front) & (zc[:, None, None] < zcut), (nz, ny, nx))
+    rho = np.where(heavy, rho_heavy, 1.0)
+    Kh, Kl = coupling_blocks(t, period)
+    Kc = np.where(heavy[..., None, None], Kh, Kl)                 # [nz,ny,nx,4,4]
+    offs = _offsets("7pt")
+    centre = offs.index((0, 0, 0))
+    nptr, ncol, mask = stencil_pattern(nx, ny, nz, "7pt")
+    nn = nx * ny * nz
+    blocks = np.zeros((nn, len(offs), B, B))
+    diag = np.zeros((nz, ny, nx, B, B))
+    for o, (dx, dy, dz) in enumerate(offs):
+        if o == centre:
+            continue
+        rn, m = _shift(rho, dx, dy, dz)
+        w = np.where(m, 2.0 / (rho + np.where(m, rn, rho)), 1.0 / rho)
+        Kn = np.empty_like(Kc)
+        for a in range(B):
+            for b in range(B):
+                Kn[..., a, b], _ = _shift(Kc[..., a, b], dx, dy, dz)
+        Kf = np.where(m[..., None, None], 0.5 * (Kc + Kn), Kc)
+        face = w[..., None, None] * Kf
+        blocks[:, o] = np.where(m[..., None, None], -face, 0.0).reshape(nn, B, B)
+        diag += face                                              # ghost closure when ~m
+    blocks[:, centre] = diag.reshape(nn, B, B)
+    # dof row 4I+b lists, for each stored node column J (increasing), columns 4J..4J+3
+    nblk = np.diff(nptr).astype(np.int64)
+    row_len = np.repeat(nblk * B, B)
+    row_ptr = np.zeros(nn * B + 1, dtype=np.int64)
+    np.cumsum(row_len, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("pattern exceeds int32 indexing")
+    nodes_of = np.repeat(np.arange(nn), nblk)                     # node of each stored block
+    kept = blocks[mask]                                           # [nblocks, 4, 4], row-major per node
+    jcol = ncol.astype(np.int64)
+    # gather per node: row b of the node -> [blocks of the node] x [4 columns]
+    col = np.empty(int(row_ptr[-1]), dtype=np.int64)
+    val = np.empty(int(row_ptr[-1]), dtype=np.float64)
+    start = nptr[:-1].astype(np.int64)
+    for b in range(B):
+        rows = np.arange(nn) * B + b
+        base = row_ptr[rows]                                      # first entry of each dof row
+        pos = base[nodes_of] + (np.arange(len(nodes_of)) - start[nodes_of]) * B
+        for q in range(B):
+            col[pos + q] = jcol * B + q
+            val[pos + q] = kept[:, b, q]
+    return row_ptr.astype(np.int32), col.astype(np.int32), val
+
+
 # ----------------------------------------------------------------------------- presets
 
 CONFIGS = {
@@ -209,6 +289,8 @@ CONFIGS = {
             eps_strong=0.02, precision="mixed"),
     6: dict(name="convdiff_7pt_128", N=128, steps=40, kind="convdiff", eps_strong=0.08,
             precision="fp64"),
+    7: dict(name="coupled4_7pt_56", N=56, steps=40, kind="coupled4", eps_strong=0.08,
+            precision="fp64", block_size=4, aggregation=1),
 }
 
 
@@ -223,6 +305,8 @@ def series_matrix(cfg_id: int, t: int, N: int | None = None):
         return lognormal_27pt(N, t, cfg_id=cfg_id)
     if c["kind"] == "convdiff":
         return convdiff_7pt(N, t)
+    if c["kind"] == "coupled4":
+        return coupled4_7pt(N, t)
     raise ValueError(f"configuration {cfg_id} has no matrix series")
 
 
