@@ -492,6 +492,63 @@ void smoother_diag(const Csr& A, int kind, double omega, std::vector<double>& m)
     }
 }
 
+/* Damped block Jacobi for systems with B unknowns per node: M_I = omega * D_I^{-1}, D_I the
+ * B x B diagonal block of node I, stored row-major at m[I*B*B ..].  The inverse is taken by
+ * Gauss-Jordan elimination with partial pivoting on [D_I | I] (the first row of largest
+ * magnitude in the column is the pivot); a zero pivot means D_I is singular. */
+int block_smoother(const Csr& A, int B, double omega, std::vector<double>& m) {
+    const int32_t nn = A.n_rows / B;
+    m.assign((size_t)A.n_rows * B, 0.0);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int32_t I = 0; I < nn; ++I) {
+        std::vector<double> W((size_t)B * 2 * B, 0.0);  // [D | I], row-major, 2B columns
+        for (int a = 0; a < B; ++a) {
+            const int32_t r = I * B + a;
+            for (int32_t k = A.ptr[r]; k < A.ptr[(size_t)r + 1]; ++k)
+                if (A.col[k] >= I * B && A.col[k] < I * B + B) W[(size_t)a * 2 * B + (A.col[k] - I * B)] = A.val[k];
+            W[(size_t)a * 2 * B + B + a] = 1.0;
+        }
+        for (int k = 0; k < B; ++k) {
+            int piv = k;
+            for (int a = k + 1; a < B; ++a)
+                if (std::fabs(W[(size_t)a * 2 * B + k]) > std::fabs(W[(size_t)piv * 2 * B + k])) piv = a;
+            if (W[(size_t)piv * 2 * B + k] == 0.0) {
+                bad = 1;
+                break;
+            }
+            if (piv != k)
+                for (int q = 0; q < 2 * B; ++q) std::swap(W[(size_t)k * 2 * B + q], W[(size_t)piv * 2 * B + q]);
+            const double d = W[(size_t)k * 2 * B + k];
+            for (int q = 0; q < 2 * B; ++q) W[(size_t)k * 2 * B + q] /= d;
+            for (int a = 0; a < B; ++a) {
+                if (a == k) continue;
+                const double f = W[(size_t)a * 2 * B + k];
+                for (int q = 0; q < 2 * B; ++q) W[(size_t)a * 2 * B + q] -= f * W[(size_t)k * 2 * B + q];
+            }
+        }
+        for (int a = 0; a < B; ++a)
+            for (int q = 0; q < B; ++q) m[((size_t)I * B + a) * B + q] = omega * W[(size_t)a * 2 * B + B + q];
+    }
+    return bad ? fail(ORA_ERR_NOT_SPD, "singular diagonal block") : ORA_OK;
+}
+
+/* u += M t: the scalar diagonal (B = 1) or the block diagonal, each row's block product
+ * summed in column order before it is added. */
+void smoother_apply(const std::vector<double>& m, int B, const std::vector<double>& t, std::vector<double>& u) {
+    const int32_t n = (int32_t)u.size();
+    if (B == 1) {
+        for (int32_t i = 0; i < n; ++i) u[i] += m[i] * t[i];
+        return;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t base = i - i % B;
+        double s = 0.0;
+        for (int q = 0; q < B; ++q) s += m[(size_t)i * B + q] * t[(size_t)base + q];
+        u[i] += s;
+    }
+}
+
 /* ------------------------------------------------------- coarsest solver (O11) */
 
 /* Dense right-looking Cholesky A = L L^T of the coarsest operator (row-major, lower
@@ -604,8 +661,14 @@ const int kMaxDense = 8192;
 
 /* Coarse factorisation and smoothers on every non-coarsest level. */
 int finish_levels(Hierarchy& h) {
-    for (size_t l = 0; l + 1 < h.lv.size(); ++l)
-        smoother_diag(h.lv[l].A, h.prm.smoother, h.prm.jacobi_omega, h.lv[l].m);
+    for (size_t l = 0; l + 1 < h.lv.size(); ++l) {
+        if (h.prm.block_size > 1) {
+            int st = block_smoother(h.lv[l].A, h.prm.block_size, h.prm.jacobi_omega, h.lv[l].m);
+            if (st) return st;
+        } else {
+            smoother_diag(h.lv[l].A, h.prm.smoother, h.prm.jacobi_omega, h.lv[l].m);
+        }
+    }
     Level& c = h.lv.back();
     if (c.A.n_rows > kMaxDense) return fail(ORA_ERR_ARG, "coarsest level too large for a dense solve");
     for (auto& l : h.lv) {
@@ -626,8 +689,8 @@ int setup(Hierarchy& h, const Csr& A0) {
     h.lv[0].A = A0;
     h.A_outer = A0;
     const ora_params& p = h.prm;
-    if (p.block_size < 1 || (p.block_size > 1 && p.aggregation != 1))
-        return fail(ORA_ERR_ARG, "block_size must be 1, or > 1 with plain aggregation");
+    if (p.block_size < 1 || (p.block_size > 1 && (p.aggregation != 1 || p.smoother != 0)))
+        return fail(ORA_ERR_ARG, "block_size must be 1, or > 1 with plain aggregation and damped Jacobi");
     for (int l = 0;; ++l) {
         Level& cur = h.lv[(size_t)l];
         std::vector<int64_t> dpos, tpos;
@@ -710,7 +773,7 @@ void vcycle_level(Hierarchy& h, size_t l) {
     std::fill(L.u.begin(), L.u.end(), 0.0);
     for (int s = 0; s < p.npre; ++s) {
         residual(L.A, L.f.data(), L.u.data(), L.t.data());
-        for (int32_t i = 0; i < n; ++i) L.u[i] += L.m[i] * L.t[i];
+        smoother_apply(L.m, p.block_size, L.t, L.u);
     }
     residual(L.A, L.f.data(), L.u.data(), L.r.data());
     Level& C = h.lv[l + 1];
@@ -720,7 +783,7 @@ void vcycle_level(Hierarchy& h, size_t l) {
     for (int32_t i = 0; i < n; ++i) L.u[i] += L.t[i];
     for (int s = 0; s < p.npost; ++s) {
         residual(L.A, L.f.data(), L.u.data(), L.t.data());
-        for (int32_t i = 0; i < n; ++i) L.u[i] += L.m[i] * L.t[i];
+        smoother_apply(L.m, p.block_size, L.t, L.u);
     }
 }
 

@@ -238,7 +238,7 @@ class OracleHierarchy:
         Ap, Ac, Av = np.zeros(n + 1, np.int32), np.zeros(nnzA, np.int32), np.zeros(nnzA)
         agg = np.full(n, -2, np.int32)
         strong = np.zeros(nnzA, np.uint8)
-        m = np.zeros(n)
+        m = np.zeros(n * max(1, self.params.block_size))   # block_size x block_size per node
         Pp = np.zeros(n + 1, np.int32) if not coarsest else None
         Pc = np.zeros(nnzP, np.int32) if not coarsest else None
         Pv = np.zeros(nnzP) if not coarsest else None

@@ -1,11 +1,14 @@
-"""Pins of the oracle's aggregation for systems with several unknowns per node.
+"""Pins of the oracle for systems with several unknowns per node.
 
-For its monolithic block systems the paper runs plain (non-smoothed) aggregation on
-4x4-block matrices (Section 4).  The oracle aggregates nodes: strength and MIS-2 run
-on the matrix of block Frobenius norms, and unknown b of a node goes to unknown b of the
-node's aggregate.  The checks use the Kronecker identity (L (x) K with plain transfer
-operators P (x) I gives coarse operators (P^T L P) (x) K), node norms computed in NumPy,
-dense triple products and structural invariants.
+For its monolithic block systems the paper runs plain (non-smoothed) aggregation and
+damped Jacobi on 4x4-block matrices (Section 4), where every value is a block.  The
+oracle aggregates nodes (strength and MIS-2 on the matrix of block Frobenius norms;
+unknown b of a node goes to unknown b of the node's aggregate) and smooths with damped
+block Jacobi (omega times the inverse of each node's diagonal block).  The checks use the
+Kronecker identity (L (x) K with plain transfer operators P (x) I gives coarse operators
+(P^T L P) (x) K and smoother blocks omega / l_ii K^{-1}), node norms and block inverses
+computed in NumPy, dense triple products, the textbook two-grid error operator and
+structural invariants.
 """
 import numpy as np
 import pytest
@@ -170,14 +173,16 @@ def test_block_size_argument_errors(ora):
         ora.OracleHierarchy(p, c, v, aggregation=1, block_size=5, coarse_enough=4)
     with pytest.raises(ora.OracleError):
         ora.OracleHierarchy(p, c, v, aggregation=1, block_size=0)
+    with pytest.raises(ora.OracleError):           # block SPAI0 is not defined here
+        ora.OracleHierarchy(p, c, v, aggregation=1, block_size=B, smoother=1, coarse_enough=8)
     sp_, sc, sv = two_fluid_7pt(4, 0.5)             # scalar 7-point: no full 2x2 blocks
     with pytest.raises(ora.OracleError):
         ora.OracleHierarchy(sp_, sc, sv, aggregation=1, block_size=2, coarse_enough=4)
 
 
 def test_node_aggregation_converges_faster_than_scalar(ora):
-    """On the coupled system, aggregating nodes keeps each node's unknowns together; the
-    scalar aggregation of the same matrix needs clearly more PCG iterations."""
+    """On the strongly coupled system, node aggregation with block Jacobi needs clearly fewer
+    PCG iterations than scalar aggregation with point Jacobi on the same matrix."""
     p, c, v = coupled4_7pt(16, 0)
     f = rhs_uniform(len(p) - 1, 7, 0)
     hb = ora.OracleHierarchy(p, c, v, aggregation=1, block_size=B)
@@ -186,3 +191,65 @@ def test_node_aggregation_converges_faster_than_scalar(ora):
     _, is_ = hs.solve(f)
     assert ib["converged"] and is_["converged"]
     assert ib["iters"] * 3 < is_["iters"] * 2
+
+
+@pytest.mark.parametrize("name,make", SCALARS)
+def test_block_smoother_kronecker(ora, name, make):
+    """On L (x) K the diagonal block of node i is l_ii K: M_i = omega / l_ii K^{-1}."""
+    p, c, v = make()
+    K = _spd_block(3)
+    ap, ac, av = _kron(p, c, v, K)
+    omega = 0.72
+    h = ora.OracleHierarchy(ap, ac, av, aggregation=1, block_size=B, coarse_enough=4 * B)
+    m = h.level(0)["m"].reshape(-1, B, B)
+    Ld = dense(p, c, v).diagonal()
+    ref = (omega / Ld)[:, None, None] * np.linalg.inv(K)[None]
+    assert np.abs(m - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_block_smoother_inverts_diagonal_blocks(ora):
+    p, c, v = coupled4_7pt(6, 11, front=0.5)
+    omega = 0.6
+    h = ora.OracleHierarchy(p, c, v, aggregation=1, block_size=B, coarse_enough=8, jacobi_omega=omega)
+    assert h.num_levels >= 3
+    for l in range(h.num_levels - 1):
+        L = h.level(l)
+        A = dense(*L["A"])
+        m = L["m"].reshape(-1, B, B)
+        for I in range(L["n"] // B):
+            D = A[I * B:I * B + B, I * B:I * B + B]
+            assert np.abs(D @ m[I] - omega * np.eye(B)).max() <= 1e-13
+
+
+def _nonsym_kron():
+    """L (x) K with a non-symmetric K (SPD part plus a skew part): diagonal blocks that are
+    not symmetric, so a transposed block product would show."""
+    p, c, v = random_spd_graph(40, 3, 7)
+    K = _spd_block(4)
+    K = K + np.triu(np.full((B, B), 0.7), 1) - np.tril(np.full((B, B), 0.7), -1)
+    return _kron(p, c, v, K)
+
+
+@pytest.mark.parametrize("make", [lambda: coupled4_7pt(4, 5, front=0.5), _nonsym_kron],
+                         ids=["coupled4", "nonsym_kron"])
+def test_block_vcycle_two_grid_identity(ora, make):
+    """Two levels, one pre- and one post-sweep of block Jacobi M = blockdiag(M_I):
+    B = (I - E) A^{-1} with E = (I - M A)(I - P A_c^{-1} P^T A)(I - M A)."""
+    p, c, v = make()
+    n = len(p) - 1
+    h = ora.OracleHierarchy(p, c, v, aggregation=1, block_size=B, max_levels=2)
+    assert h.num_levels == 2
+    A = dense(p, c, v)
+    l0 = h.level(0)
+    Pp, Pc, Pv, nc = l0["P"]
+    P = dense(Pp, Pc, Pv, shape=(n, nc))
+    Ac = dense(*h.level(1)["A"])
+    m = l0["m"].reshape(-1, B, B)
+    M = np.zeros((n, n))
+    for I in range(n // B):
+        M[I * B:I * B + B, I * B:I * B + B] = m[I]
+    Id = np.eye(n)
+    E = (Id - M @ A) @ (Id - P @ np.linalg.solve(Ac, P.T @ A)) @ (Id - M @ A)
+    B_ref = (Id - E) @ np.linalg.inv(A)
+    Bm = np.column_stack([h.vcycle(Id[:, j]) for j in range(n)])
+    assert np.abs(Bm - B_ref).max() <= 1e-10 * np.abs(B_ref).max()

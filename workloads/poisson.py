@@ -198,7 +198,10 @@ def rhs_uniform(n: int, cfg_id: int, t: int) -> np.ndarray:
 
 def coupling_blocks(t: int, period: int = 40):
     """The two SPD 4x4 coupling matrices of step t (heavy fluid, light fluid):
-    K = L L^T + I/2 with L lower triangular, its off-diagonal part turning with t."""
+    K = L L^T + I/2 with L lower triangular, its off-diagonal part turning with
+    phi_t = 2 pi t / period (light fluid: half the scale, a quarter turn ahead).  The
+    blocks are strongly coupled: a point (scalar) Jacobi sweep does not smooth this
+    system, a block Jacobi sweep does."""
     phi = 2.0 * np.pi * t / period
     out = []
     for scale, shift in ((1.0, 0.0), (0.5, 0.5 * np.pi)):
