@@ -66,6 +66,18 @@ typedef struct {
     double rtol;          /* stop when ||f - A u||_2 / ||f||_2 <= rtol, true residual (1e-8) */
     int maxiter;          /* (100) */
     int flexible_cg;      /* 1: beta = r.(z - z_old) / rho_old (robust to an inexact B) */
+    int block_size;       /* unknowns per node (1).  B in 2..8 describes a system whose unknown b
+                           * of node I is row I*B + b and whose stored entries form full B x B
+                           * blocks (every row of a node lists the same columns, in groups of B
+                           * starting at a multiple of B), as in the paper's 4x4-block systems
+                           * (Section 4): the nodes are aggregated on the matrix of block
+                           * Frobenius norms, unknown b of a node joins unknown b of its
+                           * aggregate, and the smoother is damped block Jacobi, omega times
+                           * the inverse of each node's diagonal block (AMG_ERR_NOT_SPD at
+                           * setup for a singular one; after a partial update it shows as a
+                           * breakdown of the next solve).  Needs aggregation = 1, smoother =
+                           * 0, flexible_cg = 0 and n divisible by B (AMG_ERR_ARG otherwise);
+                           * a matrix without full blocks gives AMG_ERR_PATTERN. */
 } amg_params;
 
 typedef struct {          /* host struct filled by amg_solve */
@@ -179,8 +191,9 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims);
 amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread, int* plane);
 
 /* Copy level l to host arrays (any may be NULL).  agg[n_l], strong[nnz(A_l)] exist on
- * aggregated levels; P on non-coarsest levels; m (smoother diagonal) on non-coarsest
- * levels.  In mixed precision A_val/P_val/m are the FP32 values widened to FP64.
+ * aggregated levels; P on non-coarsest levels; m (smoother diagonal, n_l values; with
+ * block_size B > 1 the n_l / B blocks omega * D_I^{-1}, row-major, n_l * B values) on
+ * non-coarsest levels.  In mixed precision A_val/P_val/m are the FP32 values widened to FP64.
  * Synchronises the stream. */
 amg_status amg_export_level(const amg_ctx* c, int l, int32_t* agg, uint8_t* strong, int32_t* A_ptr,
                             int32_t* A_col, double* A_val, int32_t* P_ptr, int32_t* P_col,

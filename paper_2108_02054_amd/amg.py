@@ -53,6 +53,7 @@ class AmgParams(C.Structure):
         ("rtol", C.c_double),
         ("maxiter", C.c_int),
         ("flexible_cg", C.c_int),
+        ("block_size", C.c_int),
     ]
 
 
@@ -293,7 +294,7 @@ class AMG:
         Ap, Ac, Av = np.zeros(n + 1, np.int32), np.zeros(nnzA, np.int32), np.zeros(nnzA)
         agg = np.full(n, -2, np.int32)
         strong = np.full(nnzA, 2, np.uint8)
-        m = np.zeros(n)
+        m = np.zeros(n * max(1, self.params.block_size))   # block_size x block_size per node
         P = None if coarsest else (np.zeros(n + 1, np.int32), np.zeros(nnzP, np.int32), np.zeros(nnzP))
         vp = lambda a: C.c_void_p(a.ctypes.data) if a is not None else None  # noqa: E731
         self._check(lib().amg_export_level(

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libamgmi.so")
 SOURCES = ["amg_api.hip", "kernels_solve.hip", "kernels_galerkin.hip", "kernels_setup.hip",
-           "kernels_logcoef.hip", "kernels_krylov.hip"]
+           "kernels_logcoef.hip", "kernels_krylov.hip", "kernels_block.hip"]
 ARCH = os.environ.get("AMGMI_ARCH", "gfx950")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -42,7 +42,7 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 5) -> str:
+def build(verbose: bool = False, jobs: int = 7) -> str:
     """Compile every HIP source for gfx950 and link the shared library."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -40,6 +40,24 @@ void dfree(void* p, hipStream_t s) {
     if (p) (void)hipFreeAsync(p, s);
 }
 
+// Temporaries of one setup step, released when the step ends or throws.
+struct Temps {
+    hipStream_t s;
+    std::vector<void*> v;
+    template <typename T>
+    T* add(T* p) {
+        v.push_back((void*)p);
+        return p;
+    }
+    template <typename T>
+    T* make(size_t n) {
+        return add(dnew<T>(n, s));
+    }
+    ~Temps() {
+        for (void* p : v) dfree(p, s);
+    }
+};
+
 int lane_group(double avg) {
     int g = 2;
     while (g < 64 && g < avg) g <<= 1;
@@ -333,7 +351,8 @@ void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
 void configure_tail(amg_ctx* c) {
     const int nlev = (int)c->lv.size();
     c->tail = 0;
-    if (nlev < 2 || std::getenv("AMGMI_NO_TAIL") != nullptr) return;
+    // (block smoothers run level by level: the fused tail applies scalar diagonals only)
+    if (nlev < 2 || c->prm.block_size > 1 || std::getenv("AMGMI_NO_TAIL") != nullptr) return;
     int64_t max_nnz = TAIL_MAX_NNZ;
     if (const char* e = std::getenv("AMGMI_TAIL_NNZ")) max_nnz = std::atoll(e);
     int64_t rows = 0, nnz = 0;
@@ -379,7 +398,8 @@ void note_dia_symmetry(amg_ctx* c) {
 
 void configure_dia(amg_ctx* c) {
     release_dia(c);
-    if (std::getenv("AMGMI_NO_DIA") != nullptr) return;
+    // (the diagonal-storage kernels fuse scalar Jacobi sweeps; block smoothers use CSR)
+    if (std::getenv("AMGMI_NO_DIA") != nullptr || c->prm.block_size > 1) return;
     hipStream_t s = c->stream;
     const Csr& A = c->lv[0].A;
     if (A.nrows == 0) return;
@@ -431,6 +451,7 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     c->outer_val = L0.A.val;
     const int nlev = (int)c->lv.size();
     std::vector<char> smoothed((size_t)nlev, 0);
+    const bool blocked = c->prm.block_size > 1;
     // Ingest: the level-0 staged A P kernel takes the new values straight from the caller's
     // array and stores the hierarchy's copies (FP64, and FP32 in mixed precision) as it
     // reads them; otherwise they are copied first.
@@ -445,9 +466,10 @@ void partial_rebuild(amg_ctx* c, const double* val) {
         {
             // the staged A P kernel also forms this level's smoother diagonal
             Trace tr(c, AMG_K_GALERKIN_AP, l);
-            smoothed[(size_t)l] = launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, L.galAP, c->prm.smoother,
-                                                        c->prm.jacobi_omega, L.mv<T>(),
-                                                        (l == 0 && !ingested) ? val : nullptr, s);
+            const bool fused = launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, L.galAP, c->prm.smoother,
+                                                     c->prm.jacobi_omega, blocked ? nullptr : L.mv<T>(),
+                                                     (l == 0 && !ingested) ? val : nullptr, s);
+            smoothed[(size_t)l] = fused && !blocked;
         }
         Trace tr(c, AMG_K_GALERKIN_RAP, l);
         launch_galerkin_rap<T>(L.R, L.AP, c->lv[l + 1].A, c->lv[l + 1].gRAP, L.galRAP, s);
@@ -461,7 +483,10 @@ void partial_rebuild(amg_ctx* c, const double* val) {
         if (smoothed[(size_t)l]) continue;
         const Level& L = c->lv[l];
         Trace tr(c, AMG_K_SMOOTHER, l);
-        launch_smoother_diag<T>(L.A, c->prm.smoother, c->prm.jacobi_omega, L.mv<T>(), s);
+        if (blocked)
+            launch_block_inv<T>(L.A, c->prm.block_size, c->prm.jacobi_omega, L.mv<T>(), nullptr, s);
+        else
+            launch_smoother_diag<T>(L.A, c->prm.smoother, c->prm.jacobi_omega, L.mv<T>(), s);
     }
     HIP_CHECK(hipEventRecord(c->ev[2], s));
     {
@@ -501,7 +526,7 @@ void alloc_shadow(amg_ctx* c) {
             L.P.val32 = halloc<float>(c, (size_t)L.P.nnz);
             L.R.val32 = halloc<float>(c, (size_t)L.R.nnz);
             L.AP.val32 = halloc<float>(c, (size_t)L.AP.nnz);
-            L.m32 = halloc<float>(c, (size_t)L.A.nrows);
+            L.m32 = halloc<float>(c, (size_t)L.A.nrows * c->prm.block_size);
             launch_cast_d2f(L.P.nnz, L.P.val, L.P.val32, s);
             launch_cast_d2f(L.R.nnz, L.R.val, L.R.val32, s);
         }
@@ -614,22 +639,48 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
             validate(c, P, nullptr, "transfer operator");
         } else {
             uint8_t* strong = halloc<uint8_t>(c, (size_t)A.nnz);
-            int32_t* tpos = dnew<int32_t>((size_t)A.nnz, s);
-            uint8_t* iso = dnew<uint8_t>((size_t)nl, s);
-            uint8_t* state = dnew<uint8_t>((size_t)nl, s);
             const double eps = std::ldexp(p.eps_strong, -l);
-            clear_flags(c);
-            launch_strength(A, diag_pos, eps * eps, strong, tpos, iso, c->d_flags, s);
-            read_flags(c);
-            if (c->h_flags[F_PATTERN]) throw Fail{AMG_ERR_PATTERN, "pattern is not structurally symmetric"};
-            run_mis2(A, strong, iso, state, c->d_flags, c->h_flags, s);
             int32_t* agg = halloc<int32_t>(c, (size_t)nl);
-            const int32_t nc = run_aggregate(A, strong, tpos, state, agg, c->d_flags, c->h_flags, s);
+            int32_t nc = 0;
+            if (p.block_size > 1) {
+                // nodes of B unknowns: strength and MIS-2 on the node matrix of block norms
+                const int B = p.block_size;
+                Temps tmp{s, {}};
+                Csr Nm;
+                clear_flags(c);
+                build_node_matrix(A, B, Nm, c->d_flags, c->h_flags, s);
+                tmp.add(Nm.ptr);
+                tmp.add(Nm.col);
+                tmp.add(Nm.val);
+                const int32_t nn = Nm.nrows;
+                int32_t* ndiag = tmp.make<int32_t>((size_t)nn);
+                validate(c, Nm, ndiag, "node matrix");
+                uint8_t* nstrong = tmp.make<uint8_t>((size_t)Nm.nnz);
+                int32_t* ntpos = tmp.make<int32_t>((size_t)Nm.nnz);
+                uint8_t* niso = tmp.make<uint8_t>((size_t)nn);
+                uint8_t* nstate = tmp.make<uint8_t>((size_t)nn);
+                int32_t* nagg = tmp.make<int32_t>((size_t)nn);
+                clear_flags(c);
+                launch_strength(Nm, ndiag, eps * eps, nstrong, ntpos, niso, c->d_flags, s);
+                read_flags(c);
+                if (c->h_flags[F_PATTERN]) throw Fail{AMG_ERR_PATTERN, "pattern is not structurally symmetric"};
+                run_mis2(Nm, nstrong, niso, nstate, c->d_flags, c->h_flags, s);
+                nc = run_aggregate(Nm, nstrong, ntpos, nstate, nagg, c->d_flags, c->h_flags, s) * B;
+                launch_node_expand(A, B, Nm, nstrong, nagg, strong, agg, s);
+            } else {
+                Temps tmp{s, {}};
+                int32_t* tpos = tmp.make<int32_t>((size_t)A.nnz);
+                uint8_t* iso = tmp.make<uint8_t>((size_t)nl);
+                uint8_t* state = tmp.make<uint8_t>((size_t)nl);
+                clear_flags(c);
+                launch_strength(A, diag_pos, eps * eps, strong, tpos, iso, c->d_flags, s);
+                read_flags(c);
+                if (c->h_flags[F_PATTERN]) throw Fail{AMG_ERR_PATTERN, "pattern is not structurally symmetric"};
+                run_mis2(A, strong, iso, state, c->d_flags, c->h_flags, s);
+                nc = run_aggregate(A, strong, tpos, state, agg, c->d_flags, c->h_flags, s);
+            }
             c->lv[(size_t)l].agg = agg;
             c->lv[(size_t)l].strong = strong;
-            dfree(tpos, s);
-            dfree(iso, s);
-            dfree(state, s);
             ph[0] += ms_since(t0);
             if (nc == 0 || nc >= nl) {
                 dfree(diag_pos, s);
@@ -680,12 +731,17 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     alloc_reduction(c);
     auto t0 = Clock::now();
     const int nlev = (int)c->lv.size();
+    clear_flags(c);
     for (int l = 0; l + 1 < nlev; ++l) {
         Level& L = c->lv[(size_t)l];
-        L.m = halloc<double>(c, (size_t)L.A.nrows);
-        launch_smoother_diag<double>(L.A, p.smoother, p.jacobi_omega, L.m, s);
+        L.m = halloc<double>(c, (size_t)L.A.nrows * p.block_size);
+        if (p.block_size > 1)
+            launch_block_inv<double>(L.A, p.block_size, p.jacobi_omega, L.m, c->d_flags, s);
+        else
+            launch_smoother_diag<double>(L.A, p.smoother, p.jacobi_omega, L.m, s);
     }
-    HIP_CHECK(hipStreamSynchronize(s));
+    read_flags(c);
+    if (c->h_flags[F_NOT_SPD]) throw Fail{AMG_ERR_NOT_SPD, "singular diagonal block"};
     ph[4] += ms_since(t0);
     t0 = Clock::now();
     c->nL = c->lv.back().A.nrows;
@@ -795,7 +851,75 @@ struct RzEpilogue {
 // level's u (the restriction forms it on coarser levels); 2: so is the residual f - A u
 // in the level's r (the fused CG update forms both on level 0; one pre-sweep only).
 template <typename T>
-T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, int ready = 0) {
+T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, int ready = 0);
+
+// A non-coarsest level with damped block Jacobi (systems with B unknowns per node): each
+// sweep is a residual followed by the block-diagonal product u += M (f - A u); the first
+// sweep from zero is u = M f.  Algorithm 2 with no fused kernels.
+template <typename T>
+T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep) {
+    hipStream_t s = c->stream;
+    const Level& L = c->lv[(size_t)l];
+    const amg_params& p = c->prm;
+    const int B = p.block_size;
+    const int n = L.A.nrows;
+    T* cur = (T*)L.u;
+    T* other = (T*)L.t;
+    T* r = (T*)L.r;
+    const T* m = L.mv<T>();
+    const T* rres = f;
+    auto sweep = [&](const T* uu, T* uout) {
+        launch_residual<T>(L.A, f, uu, r, s);
+        launch_block_apply<T>(n, B, m, r, uu, uout, s);
+    };
+    if (p.npre == 0) {
+        HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)n * sizeof(T), s));
+    } else {
+        {
+            Trace tr(c, AMG_K_SMOOTH0_RES, l);
+            launch_block_apply<T>(n, B, m, f, (const T*)nullptr, cur, s);
+        }
+        for (int it = 1; it < p.npre; ++it) {
+            Trace tr(c, AMG_K_JACOBI, l);
+            sweep(cur, other);
+            std::swap(cur, other);
+        }
+        Trace tr(c, AMG_K_SMOOTH0_RES, l);
+        launch_residual<T>(L.A, f, cur, r, s);
+        rres = r;
+    }
+    const Level& C = c->lv[(size_t)l + 1];
+    {
+        Trace tr(c, AMG_K_RESTRICT, l);
+        launch_spmv<T>(L.R, rres, (T*)C.f, (const T*)nullptr, (T*)nullptr, s);
+    }
+    const T* uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, 0);
+    {
+        Trace tr(c, AMG_K_PROLONG, l);
+        launch_prolong_add<T>(L.P, uc, cur, s);
+    }
+    for (int it = 0; it < p.npost; ++it) {
+        T* dst = (out && it == p.npost - 1) ? out : other;
+        Trace tr(c, AMG_K_JACOBI, l);
+        sweep(cur, dst);
+        if (dst == other)
+            std::swap(cur, other);
+        else
+            cur = dst;
+    }
+    if (out && cur != out) {
+        d2d(out, cur, (size_t)n * sizeof(T), s);
+        cur = out;
+    }
+    if (ep) {
+        Trace tr(c, AMG_K_CG_RZ, 0);
+        ep->nb = launch_cg_rz(n, (const double*)f, (const double*)cur, c->rs, s);
+    }
+    return cur;
+}
+
+template <typename T>
+T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep, int ready) {
     hipStream_t s = c->stream;
     const Level& L = c->lv[(size_t)l];
     const int nlev = (int)c->lv.size();
@@ -817,6 +941,7 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
     const T* m = L.mv<T>();
     const T* rres = r;
     const int n = L.A.nrows;
+    if (p.block_size > 1) return vcycle_level_block<T>(c, l, f, out, ep);
     const bool dia = l == 0 && c->dia.ndiag > 0;  // level 0 in diagonal storage
     auto residual = [&](const T* uu) {
         if (dia)
@@ -1264,7 +1389,8 @@ amg_status check_params(const amg_params& p) {
     if (p.smoother < 0 || p.smoother > 1 || p.aggregation < 0 || p.aggregation > 1 || p.precision < 0 ||
         p.precision > 1 || p.npre < 0 || p.npre > 16 || p.npost < 0 || p.npost > 16 || p.coarse_enough < 1 ||
         p.max_levels < 1 || p.max_levels > 64 || !(p.rtol > 0.0) || p.maxiter < 0 || !(p.eps_strong >= 0.0) ||
-        !(p.jacobi_omega > 0.0))
+        !(p.jacobi_omega > 0.0) || p.block_size < 1 || p.block_size > 8 ||
+        (p.block_size > 1 && (p.aggregation != 1 || p.smoother != 0 || p.flexible_cg != 0)))
         return AMG_ERR_ARG;
     return AMG_OK;
 }
@@ -1349,6 +1475,7 @@ amg_status amg_params_default(amg_params* p) {
     p->rtol = 1e-8;
     p->maxiter = 100;
     p->flexible_cg = 0;
+    p->block_size = 1;
     return AMG_OK;
 }
 
@@ -1603,7 +1730,7 @@ amg_status amg_export_level(const amg_ctx* cc, int l, int32_t* agg, uint8_t* str
             d2h(P_ptr, L.P.ptr, ((size_t)n + 1) * sizeof(int32_t));
             d2h(P_col, L.P.col, (size_t)L.P.nnz * sizeof(int32_t));
             vals(P_val, L.P.val, L.P.val32, L.P.nnz);
-            vals(m, L.m, L.m32, n);
+            vals(m, L.m, L.m32, (int64_t)n * c->prm.block_size);
         }
         HIP_CHECK(hipStreamSynchronize(s));
         return AMG_OK;

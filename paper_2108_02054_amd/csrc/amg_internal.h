@@ -343,7 +343,7 @@ void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalSh
 
 // ------------------------------------------------------------------ setup
 // flags: device int[8], see SetupFlag.
-enum SetupFlag { F_ARG = 0, F_PATTERN = 1, F_NOT_SPD = 2, F_UNDECIDED = 3, F_NOAGG = 4, F_COUNT = 8 };
+enum SetupFlag { F_ARG = 0, F_PATTERN = 1, F_NOT_SPD = 2, F_UNDECIDED = 3, F_NOAGG = 4, F_BLOCK = 5, F_COUNT = 8 };
 
 void launch_validate(const Csr& A, int32_t* diag_pos, int* flags, hipStream_t s);
 void launch_strength(const Csr& A, const int32_t* diag_pos, double eps2, uint8_t* strong, int32_t* tpos,
@@ -358,6 +358,16 @@ void build_prolongator(const Csr& A, const uint8_t* strong, const int32_t* diag_
 void build_transpose(const Csr& P, Csr& R, hipStream_t s);
 void symbolic_spgemm(const Csr& A, const Csr& B, Csr& C, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+// Systems with B unknowns per node (unknown b of node I is row I*B + b): the node matrix
+// of block Frobenius norms (its arrays are dnew allocations of the caller), and the
+// expansion of node aggregates and strength flags to the unknowns.
+void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, hipStream_t s);
+template <typename T>
+void launch_block_inv(const Csr& A, int B, double omega, T* m, int* flags, hipStream_t s);
+template <typename T>
+void launch_block_apply(int n, int B, const T* m, const T* r, const T* uin, T* uout, hipStream_t s);
+void launch_node_expand(const Csr& A, int B, const Csr& Nm, const uint8_t* nstrong, const int32_t* nagg,
+                        uint8_t* strong, int32_t* agg, hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 int64_t max_i64(const int64_t* in, int64_t n, hipStream_t s);  // synchronises
 

@@ -323,6 +323,101 @@ int32_t run_aggregate(const Csr& A, const uint8_t* strong, const int32_t* tpos, 
     return nc;
 }
 
+// ------------------------------------------------------------------ block systems
+
+// Node I owns rows I*B .. I*B+B-1.  Its rows must list the same columns, in groups of B
+// consecutive columns starting at a multiple of B (full blocks); the node row then has
+// one entry per group.  The input has passed k_validate, so every index is in range.
+__global__ void k_node_count(int nn, int B, const int* __restrict__ ptr, const int* __restrict__ col,
+                             int* __restrict__ cnt, int* __restrict__ flags) {
+    const int I = xcd_block() * TPB + threadIdx.x;
+    if (I >= nn) return;
+    const int r0 = I * B;
+    const int b0 = ptr[r0], len = ptr[r0 + 1] - b0;
+    bool ok = len % B == 0;
+    for (int c = 1; c < B && ok; ++c) {
+        const int bc = ptr[r0 + c];
+        if (ptr[r0 + c + 1] - bc != len) ok = false;
+        for (int k = 0; k < len && ok; ++k)
+            if (col[bc + k] != col[b0 + k]) ok = false;
+    }
+    for (int g = 0; g < len / B && ok; ++g) {
+        const int c0 = col[b0 + g * B];
+        if (c0 % B != 0) ok = false;
+        for (int q = 1; q < B && ok; ++q)
+            if (col[b0 + g * B + q] != c0 + q) ok = false;
+    }
+    if (!ok) atomicOr(&flags[F_BLOCK], 1);
+    cnt[I] = ok ? len / B : 0;
+}
+
+// Entry (I, J) of the node matrix: the Frobenius norm of block (I, J), its squares summed
+// over the block's rows in order and along each row in column order, then one square root.
+__global__ void k_node_fill(int nn, int B, const int* __restrict__ ptr, const int* __restrict__ col,
+                            const double* __restrict__ val, const int* __restrict__ Nptr, int* __restrict__ Ncol,
+                            double* __restrict__ Nval) {
+    const int I = xcd_block() * TPB + threadIdx.x;
+    if (I >= nn) return;
+    const int r0 = I * B;
+    const int nb = Nptr[I], ng = Nptr[I + 1] - nb;
+    for (int g = 0; g < ng; ++g) {
+        double ss = 0.0;
+        for (int c = 0; c < B; ++c) {
+            const double* v = val + ptr[r0 + c] + g * B;
+            for (int q = 0; q < B; ++q) ss += v[q] * v[q];
+        }
+        Ncol[nb + g] = col[ptr[r0] + g * B] / B;
+        Nval[nb + g] = sqrt(ss);
+    }
+}
+
+// Unknown b of node I joins unknown b of the node's aggregate (none when the node is
+// isolated); an entry of block (I, J) takes the strength flag of node entry (I, J).
+__global__ void k_node_expand(int n, int B, const int* __restrict__ ptr, const int* __restrict__ Nptr,
+                              const uint8_t* __restrict__ nstrong, const int* __restrict__ nagg,
+                              uint8_t* __restrict__ strong, int* __restrict__ agg) {
+    const int r = xcd_block() * TPB + threadIdx.x;
+    if (r >= n) return;
+    const int I = r / B;
+    const int a = nagg[I];
+    agg[r] = a >= 0 ? a * B + (r - I * B) : -1;
+    const int b = ptr[r], nb = Nptr[I];
+    for (int k = b; k < ptr[r + 1]; ++k) strong[k] = nstrong[nb + (k - b) / B];
+}
+
+void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, hipStream_t s) {
+    if (B < 2 || A.nrows % B != 0) throw Fail{AMG_ERR_ARG, "block_size does not divide the row count"};
+    const int nn = A.nrows / B;
+    int* cnt = dnew<int>((size_t)nn + 1, s);
+    k_node_count<<<blocks_for(nn), TPB, 0, s>>>(nn, B, A.ptr, A.col, cnt, flags);
+    HIP_LAUNCH_CHECK();
+    HIP_CHECK(hipMemsetAsync(cnt + nn, 0, sizeof(int), s));
+    Nm.nrows = Nm.ncols = nn;
+    Nm.ptr = dnew<int32_t>((size_t)nn + 1, s);
+    scan_exclusive<int, int>(cnt, Nm.ptr, nn + 1, s);
+    int32_t nnz = 0;
+    HIP_CHECK(hipMemcpyAsync(&nnz, Nm.ptr + nn, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(h_flags, flags, F_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    dfree(cnt, s);
+    if (h_flags[F_BLOCK]) {
+        dfree(Nm.ptr, s);
+        Nm.ptr = nullptr;
+        throw Fail{AMG_ERR_PATTERN, "block_size needs full blocks with the same columns in every row of a node"};
+    }
+    Nm.nnz = nnz;
+    Nm.col = dnew<int32_t>((size_t)nnz, s);
+    Nm.val = dnew<double>((size_t)nnz, s);
+    k_node_fill<<<blocks_for(nn), TPB, 0, s>>>(nn, B, A.ptr, A.col, A.val, Nm.ptr, Nm.col, Nm.val);
+    HIP_LAUNCH_CHECK();
+}
+
+void launch_node_expand(const Csr& A, int B, const Csr& Nm, const uint8_t* nstrong, const int32_t* nagg,
+                        uint8_t* strong, int32_t* agg, hipStream_t s) {
+    k_node_expand<<<blocks_for(A.nrows), TPB, 0, s>>>(A.nrows, B, A.ptr, Nm.ptr, nstrong, nagg, strong, agg);
+    HIP_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------ prolongator
 
 // Filtered operator A_F (lumped): for a non-isolated row the diagonal is

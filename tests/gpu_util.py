@@ -3,7 +3,7 @@ import numpy as np
 import torch
 
 ORACLE_KEYS = {"smoother", "aggregation", "jacobi_omega", "eps_strong", "coarse_enough", "max_levels", "npre",
-               "npost", "rtol", "maxiter", "flexible_cg"}
+               "npost", "rtol", "maxiter", "flexible_cg", "block_size"}
 
 
 def dev():

@@ -1,0 +1,160 @@
+"""Systems with 4 unknowns per node (the paper's 4x4-block systems, Section 4) on the
+device against the oracle: node aggregation bit-exact (node matrix of block norms,
+strength, MIS-2, expansion to the unknowns), coarse operators and block Jacobi smoothers
+within 1e-10, partial rebuilds over a series, CG and BiCGStab solves, sweep counts, both
+row-kernel families, mixed precision, argument errors, and the full-size coupled
+56^3-node system that bench.py times."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from tests.dense import random_spd_graph
+from tests.gpu_util import T, both, compare_levels, rel_fro
+from workloads import rhs_uniform, two_fluid_7pt
+from workloads.poisson import coupled4_7pt
+
+pytestmark = pytest.mark.gpu
+
+B = 4
+BLOCK = dict(block_size=B, aggregation=1)
+
+
+@pytest.mark.parametrize("N", [9, 13])
+def test_block_setup_parity(N):
+    """13^3 nodes = 8788 rows: several 256-row tiles and a ragged tail."""
+    p, c, v = coupled4_7pt(N, 2)
+    print(f"case coupled4 N={N}", flush=True)
+    g, o = both(p, c, v, **BLOCK)
+    compare_levels(g, o, tol=1e-10)
+    assert g.num_levels >= 3
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_block_kronecker_random_graph(seed):
+    pp, cc, vv = random_spd_graph(400, 4, seed)
+    rg = np.random.default_rng(seed)
+    M = rg.uniform(-1.0, 1.0, size=(B, B))
+    K = M @ M.T + B * np.eye(B)
+    A = sp.kron(sp.csr_matrix((vv, cc, pp), shape=(400, 400)), sp.csr_matrix(K), format="csr")
+    A.sort_indices()
+    p, c, v = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+    print(f"case kron seed={seed}", flush=True)
+    g, o = both(p, c, v, coarse_enough=32, **BLOCK)
+    compare_levels(g, o, tol=1e-10)
+    g.close()
+    o.close()
+
+
+def test_block_partial_series_and_solves():
+    N = 14
+    p, c, v0 = coupled4_7pt(N, 0)
+    n = len(p) - 1
+    print("case coupled4 N=14 series", flush=True)
+    g, o = both(p, c, v0, **BLOCK)
+    for t in (1, 2, 3):
+        v = coupled4_7pt(N, t)[2]
+        g.rebuild(T(v))
+        o.rebuild(v, 0)
+        compare_levels(g, o, tol=1e-10)
+        f = rhs_uniform(n, 7, t)
+        u, info = g.solve(T(f))
+        uo, io = o.solve(f)
+        assert info["converged"] and info["rel_res_true"] <= 1e-8, info
+        assert abs(info["iters"] - io["iters"]) <= 1, (info, io)
+        assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+    u, info = g.solve_bicgstab(T(f))
+    uo, io = o.solve_bicgstab(f)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iters"] - io["iters"]) <= 1, (info, io)
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+    g.close()
+    o.close()
+
+
+def test_block_mixed_precision():
+    N = 12
+    p, c, v0 = coupled4_7pt(N, 0)
+    v1 = coupled4_7pt(N, 2)[2]
+    print("case coupled4 N=12 mixed", flush=True)
+    g, o = both(p, c, v0, precision=1, **BLOCK)
+    g.rebuild(T(v1))
+    o.rebuild(v1, 0)
+    f = rhs_uniform(len(p) - 1, 7, 2)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and info["rel_res_true"] <= 1e-8
+    assert abs(info["iters"] - io["iters"]) <= 3, (info, io)
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+    g.close()
+    o.close()
+
+
+@pytest.mark.parametrize("kernels,npre,npost", [("default", 2, 2), ("default", 0, 2), ("lanes", 1, 1)])
+def test_block_sweeps_and_kernel_families(monkeypatch, kernels, npre, npost):
+    if kernels == "lanes":
+        monkeypatch.setenv("AMGMI_ROW_KERNELS", "lanes")
+    N = 11
+    p, c, v0 = coupled4_7pt(N, 0)
+    v1 = coupled4_7pt(N, 3)[2]
+    print(f"case coupled4 N=11 {kernels} npre={npre} npost={npost}", flush=True)
+    g, o = both(p, c, v0, npre=npre, npost=npost, **BLOCK)
+    g.rebuild(T(v1))
+    o.rebuild(v1, 0)
+    compare_levels(g, o, tol=1e-10)
+    f = rhs_uniform(len(p) - 1, 7, 3)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iters"] - io["iters"]) <= 1, (info, io)
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+    r = np.random.default_rng(5).standard_normal(len(p) - 1)
+    z = g.vcycle(T(r)).cpu().numpy()
+    assert rel_fro(z, o.vcycle(r)) <= 1e-10
+    g.close()
+    o.close()
+
+
+def test_block_argument_errors():
+    from paper_2108_02054_amd import AMG, AmgError
+    p, c, v = coupled4_7pt(3, 0)
+    for bad, code in ((dict(block_size=B, aggregation=0), -1),    # needs plain aggregation
+                      (dict(block_size=5, aggregation=1), -1),    # 108 rows
+                      (dict(block_size=9, aggregation=1), -1),
+                      (dict(block_size=0, aggregation=1), -1),
+                      (dict(block_size=B, aggregation=1, smoother=1), -1),
+                      (dict(block_size=B, aggregation=1, flexible_cg=1), -1)):
+        with pytest.raises(AmgError) as e:
+            AMG(T(p), T(c), T(v), coarse_enough=8, **bad)
+        assert e.value.code == code, bad
+    sp_, sc, sv = two_fluid_7pt(4, 0.5)                           # no full 2x2 blocks
+    with pytest.raises(AmgError) as e:
+        AMG(T(sp_), T(sc), T(sv), coarse_enough=4, block_size=2, aggregation=1)
+    assert e.value.code == -4
+    g = AMG(T(p), T(c), T(v), coarse_enough=8, **BLOCK)            # still usable afterwards
+    _, info = g.solve(T(rhs_uniform(len(p) - 1, 7, 0)))
+    assert info["converged"]
+
+
+def test_full_size_coupled4_56_partial_rebuild_and_solve():
+    """The configuration bench.py times for block systems (56^3 nodes, 702,464 rows,
+    19.4M entries): after a partial rebuild to a later step every level matches the
+    oracle (aggregates and patterns bit for bit, values within 1e-10) and the solve agrees."""
+    N = 56
+    p, c, v0 = coupled4_7pt(N, 0)
+    v5 = coupled4_7pt(N, 5)[2]
+    print("case coupled4 56^3 step 0 -> 5", flush=True)
+    g, o = both(p, c, v0, **BLOCK)
+    print(f"level-0 format {g.level_format(0)}", flush=True)
+    g.rebuild(T(v5))
+    o.rebuild(v5, 0)
+    compare_levels(g, o, tol=1e-10)
+    f = rhs_uniform(len(p) - 1, 7, 5)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and info["rel_res_true"] <= 1e-8
+    assert abs(info["iters"] - io["iters"]) <= 1, (info, io)
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
+    g.close()
+    o.close()
