@@ -40,11 +40,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed time steps")
     ap.add_argument("--warmup", type=int, default=3, help="untimed time steps before the timed ones")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5, 6],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5, 6, 7],
                     help="matrix series: 2 = two-fluid 7-point 128^3 FP64 (the headline), 3 = two-fluid "
                          "7-point 192^3, 5 = lognormal 27-point 160^3 with the FP32 hierarchy, 6 = non-symmetric "
-                         "convection-diffusion 7-point 128^3 solved by BiCGStab")
-    ap.add_argument("--n", type=int, default=0, help="grid size N (N^3 unknowns); 0: the series' own")
+                         "convection-diffusion 7-point 128^3 solved by BiCGStab, 7 = coupled system with 4x4 "
+                         "blocks on 56^3 nodes (node aggregation, block Jacobi)")
+    ap.add_argument("--n", type=int, default=0, help="grid size N (N^3 nodes); 0: the series' own")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle partial steps in the CPU sample")
@@ -58,11 +59,14 @@ def workload_name(cfg_id, N, n, nnz):
     series = {2: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               3: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               5: "27-point lognormal-coefficient Poisson (sigma 1.5) with smooth drift per step",
-              6: "non-symmetric upwind convection-diffusion 7-point, flow turning 9 degrees per step"}[cfg_id]
+              6: "non-symmetric upwind convection-diffusion 7-point, flow turning 9 degrees per step",
+              7: "coupled system, 4 unknowns per node in full 4x4 blocks on the 7-point node graph (two-fluid "
+                 "face weights, SPD couplings turning 9 degrees per step, interface +1 cell/step)"}[cfg_id]
     form = ("FP32 hierarchy and V-cycle under FP64 CG" if cfg_id == 5 else "FP64")
     krylov = "BiCGStab" if cfg_id == 6 else "PCG"
-    return (f"{series}, {N}^3 (n={n}, nnz={nnz}); partial reuse (numeric-only cached RAP + smoother), "
-            f"{form}, {krylov} to 1e-8 true rel res")
+    amg = ("plain aggregation of nodes on block norms, damped block Jacobi; " if cfg_id == 7 else "")
+    return (f"{series}, {N}^3 {'nodes' if cfg_id == 7 else 'cells'} (n={n}, nnz={nnz}); {amg}partial reuse "
+            f"(numeric-only cached RAP + smoother), {form}, {krylov} to 1e-8 true rel res")
 
 
 def copy_probe(mib):
@@ -135,7 +139,6 @@ def main():
     cfg = CONFIGS[cfg_id]
     N = args.n or cfg["N"]
     K, W = args.steps, args.warmup
-    n = N**3
     nsteps = W + K + 1
     # the series' own precision for the headline line: FP64, or the FP32 hierarchy under
     # FP64 CG for the 27-point series
@@ -145,6 +148,9 @@ def main():
     def solve(amg, f, x):
         return amg.solve_bicgstab(f, x) if bicg else amg.solve(f, x)
     amg_params = dict(eps_strong=cfg["eps_strong"])
+    for key in ("block_size", "aggregation"):
+        if key in cfg:
+            amg_params[key] = cfg[key]
 
     # ---------------------------------------------------------------- inputs in HBM
     t0 = time.time()
@@ -152,6 +158,7 @@ def main():
     for t in range(nsteps):
         p, c, v = series_matrix(cfg_id, t, N)
         if t == 0:
+            n = len(p) - 1
             ptr = torch.from_numpy(p).to(dev)
             col = torch.from_numpy(c).to(dev)
         vals.append(torch.from_numpy(v).to(dev))
@@ -328,7 +335,7 @@ def main():
             plan = [("full", "full", 1), ("fp64_partial", "partial", 0)]
         elif cfg_id == 3:
             plan = [("mixed", "partial", 1), ("full", "full", 0)]
-        elif cfg_id == 6:
+        elif cfg_id in (6, 7):
             plan = [("full", "full", 0), ("mixed", "partial", 1)]
         else:
             plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1), ("policy", "policy", 0)]
