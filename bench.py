@@ -84,16 +84,23 @@ def copy_probe(mib):
 
 # ------------------------------------------------------------------ algorithmic bytes
 
-def kernel_bytes(dims, sv_h, ndiag=0, sym=False):
+def kernel_bytes(dims, sv_h, ndiag=0, sym=False, block=1):
     """Algorithmic bytes per launch of the level-0 kernels: each operand read once, each
     output written once, vector gathers counted once.  CSR: 4-byte indices; an operator
     in diagonal storage (ndiag > 0) needs no index arrays, so its bytes are its values,
-    and with symmetric values (sym) only the main diagonal and the entries above it.
-    sv_h is the value size of the hierarchy (8 FP64, 4 FP32); the CG kernels are FP64."""
+    and with symmetric values (sym) only the main diagonal and the entries above it; an
+    operator of full block x block blocks needs one index per block and one pointer per
+    node.  sv_h is the value size of the hierarchy (8 FP64, 4 FP32); the CG kernels are
+    FP64."""
     n, nnzA, nc, nnzP, nnzAP = dims[0]
     nnzAc = dims[1][1]
     ind = lambda rows, nnz: 4 * (rows + 1) + 4 * nnz  # noqa: E731
-    ind0 = (lambda rows, nnz: 0) if ndiag > 0 else ind  # noqa: E731
+    if ndiag > 0:
+        ind0 = lambda rows, nnz: 0  # noqa: E731
+    elif block > 1:
+        ind0 = lambda rows, nnz: 4 * (rows // block + 1) + 4 * (nnz // (block * block))  # noqa: E731
+    else:
+        ind0 = ind
     a0 = (nnzA + n) // 2 if (ndiag > 0 and sym) else nnzA  # level-0 matrix entries read
     b = {}
     # Krylov operator SpMV fused with p = z + beta p and p.q: A, z, p_old read; p_new, q written
@@ -229,6 +236,8 @@ def main():
         pq_kernel = "k_m7_cg_pq"
     elif ndiag:
         pq_kernel = "k_w_cg_pq" if ndiag != 7 else "k_dia_cg_pq"
+    elif cfg.get("block_size", 1) > 1:
+        pq_kernel = "k_rb_spmv" if bicg else "k_node_cg_pq"
     else:
         pq_kernel = "k_rb_spmv" if bicg else "k_cg_pq"
     log(f"levels: {[(d[0], d[1]) for d in dims]}")
@@ -251,7 +260,7 @@ def main():
     amg.trace([], level=0)
     amg.close()
 
-    kb = kernel_bytes(dims, 8, ndiag, sym=0 < nread < ndiag)
+    kb = kernel_bytes(dims, 8, ndiag, sym=0 < nread < ndiag, block=cfg.get("block_size", 1))
     # live measurement over the timed region
     pq_ms, pq_cnt = kt.get(spmv_cls, (0.0, 0))
     n_solves = K
@@ -286,6 +295,10 @@ def main():
     pq_traffic = load_traffic(os.path.join(ROOT, "profiles", "cg_pq_two_fluid_128_traffic.json"))
     if pq_traffic is not None:
         pq_traffic["_path"] = "cg_pq_two_fluid_128_traffic.json"
+    if cfg_id == 7:
+        pq_traffic = load_traffic(os.path.join(ROOT, "profiles", "cg_pq_coupled4_56_traffic.json"))
+        if pq_traffic is not None:
+            pq_traffic["_path"] = "cg_pq_coupled4_56_traffic.json"
     rap_traffic = load_traffic(os.path.join(ROOT, "profiles", "galerkin_two_fluid_128_traffic.json"))
     if rap_traffic is not None:
         rap_traffic["_path"] = "galerkin_two_fluid_128_traffic.json"
@@ -319,7 +332,7 @@ def main():
                                       if bicg else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
                          pq_ms, pq_cnt,
                          spmv_bytes / pq_cnt if pq_cnt else 0,
-                         pq_traffic if (cfg_id == 2 and N == 128 and pq_traffic is not None
+                         pq_traffic if (N == cfg["N"] and cfg_id in (2, 7) and pq_traffic is not None
                                         and pq_traffic["kernel"] == pq_kernel) else None),
         "roofline_rap": roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
                              kb["galerkin"],

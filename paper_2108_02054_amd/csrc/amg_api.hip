@@ -854,8 +854,10 @@ template <typename T>
 T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, int ready = 0);
 
 // A non-coarsest level with damped block Jacobi (systems with B unknowns per node): each
-// sweep is a residual followed by the block-diagonal product u += M (f - A u); the first
-// sweep from zero is u = M f.  Algorithm 2 with no fused kernels.
+// sweep u += M (f - A u) is one node-group pass (residual and block-diagonal product); the
+// first sweep from zero is u = M f, the pre-smoothing residual a node-group pass on
+// level 0 and a row-block pass below.
+// Algorithm 2 with the scalar-diagonal fused forms left out.
 template <typename T>
 T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep) {
     hipStream_t s = c->stream;
@@ -868,10 +870,7 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
     T* r = (T*)L.r;
     const T* m = L.mv<T>();
     const T* rres = f;
-    auto sweep = [&](const T* uu, T* uout) {
-        launch_residual<T>(L.A, f, uu, r, s);
-        launch_block_apply<T>(n, B, m, r, uu, uout, s);
-    };
+    auto sweep = [&](const T* uu, T* uout) { launch_node_sweep<T>(L.A, B, m, f, uu, uout, s); };
     if (p.npre == 0) {
         HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)n * sizeof(T), s));
     } else {
@@ -885,7 +884,11 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
             std::swap(cur, other);
         }
         Trace tr(c, AMG_K_SMOOTH0_RES, l);
-        launch_residual<T>(L.A, f, cur, r, s);
+        // (on the coarser levels the LDS-staged row-block residual is faster)
+        if (l == 0)
+            launch_node_residual<T>(L.A, B, f, cur, r, s);
+        else
+            launch_residual<T>(L.A, f, cur, r, s);
         rres = r;
     }
     const Level& C = c->lv[(size_t)l + 1];
@@ -1151,9 +1154,12 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
             Trace tr(c, AMG_K_CG_PQ, 0);
             // the diagonal storage holds the hierarchy's A_0, which is the Krylov operator
             // except after an operator-only update (full reuse)
-            nb_pq = (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
-                        ? launch_dia_cg_pq(n, c->dia, c->z, pold, pnew, c->q, it == 1, c->rs, s)
-                        : launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+            if (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
+                nb_pq = launch_dia_cg_pq(n, c->dia, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+            else if (p.block_size > 1)  // the Krylov operator has the pattern of A_0
+                nb_pq = launch_node_cg_pq(L0.A, p.block_size, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+            else
+                nb_pq = launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
         }
         launch_fin_pq(nb_pq, c->rs, s);
         int ready = 0;

@@ -366,6 +366,12 @@ template <typename T>
 void launch_block_inv(const Csr& A, int B, double omega, T* m, int* flags, hipStream_t s);
 template <typename T>
 void launch_block_apply(int n, int B, const T* m, const T* r, const T* uin, T* uout, hipStream_t s);
+template <typename T>
+void launch_node_residual(const Csr& A, int B, const T* f, const T* u, T* r, hipStream_t s);
+template <typename T>
+void launch_node_sweep(const Csr& A, int B, const T* m, const T* f, const T* uin, T* uout, hipStream_t s);
+int launch_node_cg_pq(const Csr& A, int B, const double* val, const double* z, const double* pold, double* pnew,
+                      double* q, int first, const RedScratch& rs, hipStream_t s);
 void launch_node_expand(const Csr& A, int B, const Csr& Nm, const uint8_t* nstrong, const int32_t* nagg,
                         uint8_t* strong, int32_t* agg, hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);

@@ -7,6 +7,10 @@
 // order of its definition (the first row of largest magnitude in the column is the pivot),
 // with separately rounded products, so that in FP64 it reproduces the definition's
 // rounding.  B is a compile-time constant (2..8): the working block stays in registers.
+#include <algorithm>
+
+#include <hip/hip_ext.h>
+
 #include "amg_internal.h"
 
 #pragma clang fp contract(off)
@@ -105,6 +109,124 @@ __global__ __launch_bounds__(TPB_B) void k_block_apply(int n, const T* __restric
     uout[i] = uin != nullptr ? uin[i] + s : s;
 }
 
+// ------------------------------------------------------------------ node-group products
+//
+// The rows of a node list the same columns (full blocks) and are consecutive in CSR, so
+// row a of node I starts at ptr[I*B] + a*len with len the common row length.  A group of
+// NG lanes walks the node's column list once (row 0's columns: one index read per column
+// for all B rows) and reads the B rows' values at the same offsets, coalesced across the
+// group; every lane keeps B partial sums, a butterfly over the group leaves the B row sums
+// in every lane, and lanes 0..B-1 finish one row each.  16 nodes per workgroup.
+constexpr int NG = 16;
+constexpr int NODES_PER_WG = TPB_B / NG;
+
+__device__ __forceinline__ double bfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float bfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <int B, typename T, typename X>
+__device__ __forceinline__ void node_rowsums(int base, int len, int lane, const int* __restrict__ col,
+                                             const T* __restrict__ val, X x, T (&s)[B]) {
+#pragma unroll
+    for (int a = 0; a < B; ++a) s[a] = 0;
+    for (int k = lane; k < len; k += NG) {
+        const T xj = x(col[base + k]);
+#pragma unroll
+        for (int a = 0; a < B; ++a) s[a] = bfma(val[base + a * len + k], xj, s[a]);
+    }
+#pragma unroll
+    for (int o = NG / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < B; ++a) s[a] += __shfl_xor(s[a], o, NG);
+    }
+}
+
+// s[lane] for lane < B, by selects (the array stays in registers)
+template <int B, typename T>
+__device__ __forceinline__ T pick(const T (&s)[B], int lane) {
+    T v = s[0];
+#pragma unroll
+    for (int a = 1; a < B; ++a) v = lane == a ? s[a] : v;
+    return v;
+}
+
+// r = f - A u
+template <int B, typename T>
+__global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __restrict__ ptr,
+                                                         const int* __restrict__ col, const T* __restrict__ val,
+                                                         const T* __restrict__ f, const T* __restrict__ u,
+                                                         T* __restrict__ r) {
+    const int I = xcd_block() * NODES_PER_WG + (int)threadIdx.x / NG;
+    const int lane = threadIdx.x & (NG - 1);
+    if (I >= nn) return;
+    const int base = ptr[I * B], len = ptr[I * B + 1] - base;
+    T s[B];
+    node_rowsums<B>(base, len, lane, col, val, [&](int j) { return u[j]; }, s);
+    if (lane < B) {
+        const int i = I * B + lane;
+        r[i] = f[i] - pick<B>(s, lane);
+    }
+}
+
+// uout = uin + M (f - A uin): a residual and the block-diagonal product in one pass
+template <int B, typename T>
+__global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const T* __restrict__ val, const T* __restrict__ m,
+                                                      const T* __restrict__ f, const T* __restrict__ uin,
+                                                      T* __restrict__ uout) {
+    const int I = xcd_block() * NODES_PER_WG + (int)threadIdx.x / NG;
+    const int lane = threadIdx.x & (NG - 1);
+    if (I >= nn) return;
+    const int base = ptr[I * B], len = ptr[I * B + 1] - base;
+    T s[B];
+    node_rowsums<B>(base, len, lane, col, val, [&](int j) { return uin[j]; }, s);
+    if (lane < B) {
+        const int i = I * B + lane;
+        const T* mi = m + (size_t)i * B;
+        T d = 0;
+#pragma unroll
+        for (int q = 0; q < B; ++q) d = d + mi[q] * (f[I * B + q] - s[q]);
+        uout[i] = uin[i] + d;
+    }
+}
+
+// p_new = z + beta p_old (z on the first iteration), q = A p_new, p_new.q partials (FP64).
+// Neighbours' p_new entries are formed with the same fma as the owner row, so q is A
+// applied to exactly the stored p_new.  Bounded grid, nodes by grid stride: one partial
+// per workgroup, in a fixed order.
+template <int B>
+__global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restrict__ ptr,
+                                                      const int* __restrict__ col, const double* __restrict__ val,
+                                                      const double* __restrict__ z, const double* __restrict__ pold,
+                                                      double* __restrict__ pnew, double* __restrict__ q, int first,
+                                                      RedScratch rs) {
+    const double beta = first ? 0.0 : rs.scal()[S_BETA];
+    auto pv = [&](int j) { return first ? z[j] : __builtin_fma(beta, pold[j], z[j]); };
+    const int lane = threadIdx.x & (NG - 1);
+    double loc = 0.0;
+    for (int I = blockIdx.x * NODES_PER_WG + (int)threadIdx.x / NG; I < nn; I += gridDim.x * NODES_PER_WG) {
+        const int base = ptr[I * B], len = ptr[I * B + 1] - base;
+        double s[B];
+        node_rowsums<B>(base, len, lane, col, val, pv, s);
+        if (lane < B) {
+            const int i = I * B + lane;
+            const double pi = pv(i), qi = pick<B>(s, lane);
+            pnew[i] = pi;
+            q[i] = qi;
+            loc += pi * qi;
+        }
+    }
+    __shared__ double sm[TPB_B / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) loc += __shfl_xor(loc, o, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = loc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < TPB_B / 64; ++w) t += sm[w];
+        rs.region(P_PQ)[blockIdx.x] = t;
+    }
+}
+
 static unsigned bgrid(int64_t n) {
     const int64_t b = (n + TPB_B - 1) / TPB_B;
     return (unsigned)(b > 0 ? b : 1);
@@ -135,6 +257,50 @@ void launch_block_apply(int n, int B_, const T* m, const T* r, const T* uin, T* 
     HIP_LAUNCH_CHECK();
 }
 
+template <typename T>
+void launch_node_residual(const Csr& A, int B_, const T* f, const T* u, T* r, hipStream_t s) {
+    const int nn = A.nrows / B_;
+    const unsigned nb = (unsigned)((nn + NODES_PER_WG - 1) / NODES_PER_WG);
+    AMG_WITH_B(B_, k_node_residual<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, A.ptr, A.col, A.v<T>(), f, u, r));
+    HIP_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_node_sweep(const Csr& A, int B_, const T* m, const T* f, const T* uin, T* uout, hipStream_t s) {
+    const int nn = A.nrows / B_;
+    const unsigned nb = (unsigned)((nn + NODES_PER_WG - 1) / NODES_PER_WG);
+    AMG_WITH_B(B_, k_node_sweep<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, A.ptr, A.col, A.v<T>(), m, f, uin, uout));
+    HIP_LAUNCH_CHECK();
+}
+
+// The Krylov operator product of a block system (values `val` on the pattern of A).  Like
+// the other Krylov SpMV launchers it takes the events that a kernel trace left for it, so
+// the trace times the kernel itself.
+int launch_node_cg_pq(const Csr& A, int B_, const double* val, const double* z, const double* pold, double* pnew,
+                      double* q, int first, const RedScratch& rs, hipStream_t s) {
+    const int nn = A.nrows / B_;
+    int64_t want = ((int64_t)nn + NODES_PER_WG - 1) / NODES_PER_WG;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(want, rs.cap));
+    const KernelEvents e = g_kernel_events;
+    g_kernel_events = KernelEvents{};
+    AMG_WITH_B(B_, {
+        if (e.start != nullptr)
+            hipExtLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, e.start, e.stop, 0, nn,
+                                  (const int*)A.ptr, (const int*)A.col, val, z, pold, pnew, q, first, rs);
+        else
+            hipLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)A.ptr,
+                               (const int*)A.col, val, z, pold, pnew, q, first, rs);
+    });
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+
+template void launch_node_residual<double>(const Csr&, int, const double*, const double*, double*, hipStream_t);
+template void launch_node_residual<float>(const Csr&, int, const float*, const float*, float*, hipStream_t);
+template void launch_node_sweep<double>(const Csr&, int, const double*, const double*, const double*, double*,
+                                        hipStream_t);
+template void launch_node_sweep<float>(const Csr&, int, const float*, const float*, const float*, float*,
+                                       hipStream_t);
 template void launch_block_inv<double>(const Csr&, int, double, double*, int*, hipStream_t);
 template void launch_block_inv<float>(const Csr&, int, double, float*, int*, hipStream_t);
 template void launch_block_apply<double>(int, int, const double*, const double*, const double*, double*, hipStream_t);
