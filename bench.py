@@ -69,6 +69,28 @@ def workload_name(cfg_id, N, n, nnz):
             f"(numeric-only cached RAP + smoother), {form}, {krylov} to 1e-8 true rel res")
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """Measured device-copy bandwidth (read + write bytes over the copy's time, best of reps),
+    the practical ceiling the HBM-bound kernels are compared with besides the 8 TB/s peak."""
+    import torch
+
+    x = torch.rand(mib * 131072, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * mib * 2**20 / (best * 1e-3) / 1e9
+
+
 def copy_probe(mib):
     """A plain device copy of known size (read mib MiB, write mib MiB), three launches."""
     import torch
@@ -180,8 +202,12 @@ def main():
 
     def series(mode, precision=0, trace=None):
         """Setup at t=0 (untimed), W warm-up steps, K timed steps."""
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter()
         amg = AMG(ptr, col, vals[0], precision=precision, **amg_params)
-        info_log = {"iters": [], "rebuilds": 0, "converged": True, "rel_res_max": 0.0}
+        torch.cuda.synchronize()
+        info_log = {"iters": [], "rebuilds": 0, "converged": True, "rel_res_max": 0.0,
+                    "setup_ms": (time.perf_counter() - t_setup) * 1e3}
 
         def step(t, record):
             if mode == "partial":
@@ -273,6 +299,9 @@ def main():
     g_cnt = kt.get("galerkin_rap", (0.0, 0))[1]
     rap_gbs = g_cnt * kb["galerkin"] / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None
 
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write, 1 GiB, best of 5)")
+
     # dominant kernel class of a partial step (all levels), by total time
     dom = max(breakdown_all.items(), key=lambda kv: kv[1][0])[0] if breakdown_all else "cg_pq"
     log("kernel time per partial step (ms, launches), all levels: "
@@ -325,6 +354,8 @@ def main():
         "converged_all": info_p["converged"],
         "rel_res_max": info_p["rel_res_max"],
         "rebuild_phase_ms": ph,
+        "setup_ms_step0": info_p["setup_ms"],
+        "copy_gbs_measured": copy_gbs,
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
