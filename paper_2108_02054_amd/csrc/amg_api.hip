@@ -228,6 +228,16 @@ void validate(amg_ctx* c, const Csr& A, int32_t* diag_pos, const char* what) {
         throw Fail{AMG_ERR_NOT_SPD, std::string(what) + ": missing or non-positive diagonal entry"};
 }
 
+// Systems with block_size unknowns per node: the pattern of A must consist of full blocks
+// (AMG_ERR_PATTERN) and its row count be a multiple of the block size (AMG_ERR_ARG).
+void check_blocks(amg_ctx* c, const Csr& A) {
+    Csr pat = A, Nm;
+    pat.val = nullptr;
+    clear_flags(c);
+    build_node_matrix(pat, c->prm.block_size, Nm, c->d_flags, c->h_flags, c->stream);
+    dfree(Nm.ptr, c->stream);
+}
+
 // AMGMI_ROW_KERNELS=lanes selects the lane-group kernels everywhere (used by the tests
 // to cover both kernel families); the default picks LDS-staged row blocks where they fit.
 bool lanes_only() {
@@ -619,6 +629,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
         const int32_t nl = A.nrows;
         int32_t* diag_pos = dnew<int32_t>((size_t)nl, s);
         validate(c, A, diag_pos, l == 0 ? "input matrix" : "coarse operator");
+        if (p.block_size > 1) check_blocks(c, A);  // the block smoother and products need full blocks
         const bool stop = tr ? (l >= tr->nlev) : (nl <= p.coarse_enough || l >= p.max_levels - 1);
         if (stop) {
             dfree(diag_pos, s);
@@ -800,6 +811,7 @@ void repattern(amg_ctx* c) {
     int32_t* diag_pos = dnew<int32_t>((size_t)A.nrows, s);
     validate(c, pat, diag_pos, "new pattern");
     dfree(diag_pos, s);
+    if (c->prm.block_size > 1) check_blocks(c, pat);  // the block kernels need full blocks
     const int nlev = (int)c->lv.size();
     for (int l = 0; l + 1 < nlev; ++l) {
         Level& L = c->lv[(size_t)l];

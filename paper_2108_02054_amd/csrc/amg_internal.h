@@ -359,7 +359,8 @@ void build_transpose(const Csr& P, Csr& R, hipStream_t s);
 void symbolic_spgemm(const Csr& A, const Csr& B, Csr& C, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 // Systems with B unknowns per node (unknown b of node I is row I*B + b): the node matrix
-// of block Frobenius norms (its arrays are dnew allocations of the caller), and the
+// of block Frobenius norms (its arrays are dnew allocations of the caller; for a pattern
+// without values only the block structure is checked and Nm.ptr built), and the
 // expansion of node aggregates and strength flags to the unknowns.
 void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, hipStream_t s);
 template <typename T>

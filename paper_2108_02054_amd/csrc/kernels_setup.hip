@@ -406,6 +406,7 @@ void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, h
         throw Fail{AMG_ERR_PATTERN, "block_size needs full blocks with the same columns in every row of a node"};
     }
     Nm.nnz = nnz;
+    if (A.val == nullptr) return;  // a pattern: the block structure is checked, Nm.ptr only
     Nm.col = dnew<int32_t>((size_t)nnz, s);
     Nm.val = dnew<double>((size_t)nnz, s);
     k_node_fill<<<blocks_for(nn), TPB, 0, s>>>(nn, B, A.ptr, A.col, A.val, Nm.ptr, Nm.col, Nm.val);

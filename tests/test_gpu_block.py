@@ -132,9 +132,16 @@ def test_block_argument_errors():
     with pytest.raises(AmgError) as e:
         AMG(T(sp_), T(sc), T(sv), coarse_enough=4, block_size=2, aggregation=1)
     assert e.value.code == -4
+    with pytest.raises(AmgError) as e:                              # also on a single level
+        AMG(T(sp_), T(sc), T(sv), coarse_enough=128, block_size=2, aggregation=1)
+    assert e.value.code == -4
     g = AMG(T(p), T(c), T(v), coarse_enough=8, **BLOCK)            # still usable afterwards
     _, info = g.solve(T(rhs_uniform(len(p) - 1, 7, 0)))
     assert info["converged"]
+    g1 = AMG(T(p), T(c), T(v), coarse_enough=128, **BLOCK)         # one level: a direct solve
+    assert g1.num_levels == 1
+    _, info = g1.solve(T(rhs_uniform(len(p) - 1, 7, 0)))
+    assert info["converged"] and info["iters"] == 1
 
 
 def test_full_size_coupled4_56_partial_rebuild_and_solve():
@@ -158,3 +165,69 @@ def test_full_size_coupled4_56_partial_rebuild_and_solve():
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
     g.close()
     o.close()
+
+
+def test_block_rebuild_modes():
+    """Full reuse keeps the hierarchy (the Krylov operator alone takes the new values) and
+    a full rebuild equals a fresh setup, with block smoothers."""
+    from paper_2108_02054_amd import AMG, FULL, OPERATOR_ONLY
+    N = 10
+    p, c, v0 = coupled4_7pt(N, 0)
+    v1 = coupled4_7pt(N, 4)[2]
+    f = rhs_uniform(len(p) - 1, 7, 4)
+    print("case coupled4 N=10 modes", flush=True)
+    g, o = both(p, c, v0, **BLOCK)
+    g.rebuild_ex(T(v1), OPERATOR_ONLY)
+    o.rebuild(v1, 2)
+    _, ig = g.solve(T(f))
+    _, io = o.solve(f)
+    assert ig["converged"] == io["converged"]
+    assert abs(ig["iters"] - io["iters"]) <= 2, (ig, io)
+    assert np.array_equal(g.level(0)["A"][2], v0)
+    g.rebuild_ex(T(v1), FULL)
+    fresh = AMG(T(p), T(c), T(v1), **BLOCK)
+    for l in range(fresh.num_levels):
+        a, b = g.level(l), fresh.level(l)
+        assert np.array_equal(a["A"][2], b["A"][2]) and np.array_equal(a["A"][1], b["A"][1])
+        if a["P"] is not None:
+            assert np.array_equal(a["m"], b["m"])
+    g.close()
+    o.close()
+
+
+def test_block_pattern_change_same_size():
+    """A new full-block pattern with the same row count keeps P_l (node aggregates) and
+    recomputes the Galerkin patterns (reference: the oracle with those transfer operators);
+    a pattern without full blocks is refused."""
+    import oracle
+    from paper_2108_02054_amd import AMG, AmgError
+    from workloads import lognormal_27pt
+    N = 8
+    p, c, v = coupled4_7pt(N, 0)
+    g = AMG(T(p), T(c), T(v), coarse_enough=16, **BLOCK)
+    Ps = [g.level(l)["P"] for l in range(g.num_levels - 1)]
+    lp, lc, lv = lognormal_27pt(N, 0)
+    K = np.array([[3.0, 0.5, 0.2, 0.1], [0.5, 2.0, 0.3, 0.2], [0.2, 0.3, 2.5, 0.4], [0.1, 0.2, 0.4, 1.5]])
+    A2 = sp.kron(sp.csr_matrix((lv, lc, lp), shape=(N**3, N**3)), sp.csr_matrix(K), format="csr")
+    A2.sort_indices()
+    p2, c2, v2 = A2.indptr.astype(np.int32), A2.indices.astype(np.int32), A2.data.copy()
+    print("case coupled4 N=8 pattern change", flush=True)
+    g.set_pattern(T(p2), T(c2))
+    g.rebuild(T(v2), pattern_changed=True)
+    o = oracle.OracleHierarchy(p2, c2, v2, transfer=Ps, coarse_enough=16, **BLOCK)
+    assert g.num_levels == o.num_levels
+    for l in range(o.num_levels):
+        gl, ol = g.level(l), o.level(l)
+        assert np.array_equal(gl["A"][0], ol["A"][0]) and np.array_equal(gl["A"][1], ol["A"][1])
+        assert rel_fro(gl["A"][2], ol["A"][2]) <= 1e-10
+        if ol["P"] is not None:
+            assert rel_fro(gl["m"], ol["m"]) <= 1e-10
+    f = rhs_uniform(len(p2) - 1, 7, 1)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1, (info, io)
+    sp3, sc3, _ = two_fluid_7pt(N, 0.5, nz=4 * N)                   # same n, scalar pattern
+    g.set_pattern(T(sp3), T(sc3))
+    with pytest.raises(AmgError) as e:
+        g.rebuild(T(np.ones(len(sc3))), pattern_changed=True)
+    assert e.value.code == -4
