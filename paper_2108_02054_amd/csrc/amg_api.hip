@@ -228,14 +228,21 @@ void validate(amg_ctx* c, const Csr& A, int32_t* diag_pos, const char* what) {
         throw Fail{AMG_ERR_NOT_SPD, std::string(what) + ": missing or non-positive diagonal entry"};
 }
 
-// Systems with block_size unknowns per node: the pattern of A must consist of full blocks
-// (AMG_ERR_PATTERN) and its row count be a multiple of the block size (AMG_ERR_ARG).
-void check_blocks(amg_ctx* c, const Csr& A) {
-    Csr pat = A, Nm;
+// Systems with block_size unknowns per node: the pattern of L.A must consist of full blocks
+// (AMG_ERR_PATTERN) and its row count be a multiple of the block size (AMG_ERR_ARG); its
+// node pattern is kept for the node-group kernels.
+void node_pattern(amg_ctx* c, Level& L) {
+    release(c, L.nptr);
+    release(c, L.ncol);
+    L.nptr = L.ncol = nullptr;
+    Csr pat = L.A, Nm;
     pat.val = nullptr;
     clear_flags(c);
     build_node_matrix(pat, c->prm.block_size, Nm, c->d_flags, c->h_flags, c->stream);
-    dfree(Nm.ptr, c->stream);
+    L.nptr = Nm.ptr;
+    L.ncol = Nm.col;
+    c->hier_allocs.push_back(L.nptr);
+    c->hier_allocs.push_back(L.ncol);
 }
 
 // AMGMI_ROW_KERNELS=lanes selects the lane-group kernels everywhere (used by the tests
@@ -559,6 +566,7 @@ void alloc_cg(amg_ctx* c) {
 void alloc_reduction(amg_ctx* c) {
     const Csr& A = c->lv[0].A;
     int cap = full_grid_rows(A.nrows, A.rpb, A.g);
+    if (c->prm.block_size > 1) cap = std::max(cap, node_grid(A.nrows / c->prm.block_size));
     if (cap < RED_BLOCKS) cap = RED_BLOCKS;
     c->rs.cap = cap;
     c->rs.part = halloc<double>(c, RedScratch::doubles(cap));
@@ -629,7 +637,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
         const int32_t nl = A.nrows;
         int32_t* diag_pos = dnew<int32_t>((size_t)nl, s);
         validate(c, A, diag_pos, l == 0 ? "input matrix" : "coarse operator");
-        if (p.block_size > 1) check_blocks(c, A);  // the block smoother and products need full blocks
+        if (p.block_size > 1) node_pattern(c, c->lv[(size_t)l]);  // full blocks, node pattern
         const bool stop = tr ? (l >= tr->nlev) : (nl <= p.coarse_enough || l >= p.max_levels - 1);
         if (stop) {
             dfree(diag_pos, s);
@@ -811,7 +819,7 @@ void repattern(amg_ctx* c) {
     int32_t* diag_pos = dnew<int32_t>((size_t)A.nrows, s);
     validate(c, pat, diag_pos, "new pattern");
     dfree(diag_pos, s);
-    if (c->prm.block_size > 1) check_blocks(c, pat);  // the block kernels need full blocks
+    if (c->prm.block_size > 1) node_pattern(c, L0);  // the block kernels need full blocks
     const int nlev = (int)c->lv.size();
     for (int l = 0; l + 1 < nlev; ++l) {
         Level& L = c->lv[(size_t)l];
@@ -835,6 +843,8 @@ void repattern(amg_ctx* c) {
         N.gRAP = lane_group((double)Ac.nnz / (Ac.nrows > 0 ? (double)Ac.nrows : 1.0));
     }
     if (mixed(c)) L0.A.val32 = halloc<float>(c, (size_t)L0.A.nnz);
+    if (c->prm.block_size > 1)
+        for (int l = 1; l < nlev; ++l) node_pattern(c, c->lv[(size_t)l]);
     set_groups(c, c->lv.back(), nullptr, s);
     release(c, c->rs.part);
     alloc_reduction(c);
@@ -882,7 +892,7 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
     T* r = (T*)L.r;
     const T* m = L.mv<T>();
     const T* rres = f;
-    auto sweep = [&](const T* uu, T* uout) { launch_node_sweep<T>(L.A, B, m, f, uu, uout, s); };
+    auto sweep = [&](const T* uu, T* uout) { launch_node_sweep<T>(L, B, m, f, uu, uout, s); };
     if (p.npre == 0) {
         HIP_CHECK(hipMemsetAsync(cur, 0, (size_t)n * sizeof(T), s));
     } else {
@@ -898,7 +908,7 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
         Trace tr(c, AMG_K_SMOOTH0_RES, l);
         // (on the coarser levels the LDS-staged row-block residual is faster)
         if (l == 0)
-            launch_node_residual<T>(L.A, B, f, cur, r, s);
+            launch_node_residual<T>(L, B, f, cur, r, s);
         else
             launch_residual<T>(L.A, f, cur, r, s);
         rres = r;
@@ -1169,7 +1179,7 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
             if (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
                 nb_pq = launch_dia_cg_pq(n, c->dia, c->z, pold, pnew, c->q, it == 1, c->rs, s);
             else if (p.block_size > 1)  // the Krylov operator has the pattern of A_0
-                nb_pq = launch_node_cg_pq(L0.A, p.block_size, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
+                nb_pq = launch_node_cg_pq(L0, p.block_size, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
             else
                 nb_pq = launch_cg_pq(L0.A, c->outer_val, c->z, pold, pnew, c->q, it == 1, c->rs, s);
         }

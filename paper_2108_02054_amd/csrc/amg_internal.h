@@ -89,6 +89,10 @@ struct Level {
     Csr P, R;    // P_l and R_l = P_l^T (empty on the coarsest level)
     Csr AP;      // cached pattern (and values) of A_l P_l, the first Galerkin factor
     int32_t* agg = nullptr;      // aggregate of each row (setup product, kept for export)
+    // block systems: node pattern of A_l (node row pointers, node columns), read by the
+    // node-group kernels in place of A_l's own index arrays
+    int32_t* nptr = nullptr;
+    int32_t* ncol = nullptr;
     uint8_t* strong = nullptr;   // strength flag per stored entry of A_l
     double* m = nullptr;         // smoother diagonal
     float* m32 = nullptr;
@@ -360,18 +364,22 @@ void symbolic_spgemm(const Csr& A, const Csr& B, Csr& C, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
 // Systems with B unknowns per node (unknown b of node I is row I*B + b): the node matrix
 // of block Frobenius norms (its arrays are dnew allocations of the caller; for a pattern
-// without values only the block structure is checked and Nm.ptr built), and the
-// expansion of node aggregates and strength flags to the unknowns.
+// without values, its pattern only), and the expansion of node aggregates and strength
+// flags to the unknowns.
 void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, hipStream_t s);
 template <typename T>
 void launch_block_inv(const Csr& A, int B, double omega, T* m, int* flags, hipStream_t s);
 template <typename T>
 void launch_block_apply(int n, int B, const T* m, const T* r, const T* uin, T* uout, hipStream_t s);
+// Node-group products on level L of a block system (L.nptr, L.ncol: its node pattern).
+// node_grid(nn): workgroups that give every node group its own (the reduction scratch is
+// sized for it, so the Krylov product runs without a grid-stride second pass).
+int node_grid(int nn);
 template <typename T>
-void launch_node_residual(const Csr& A, int B, const T* f, const T* u, T* r, hipStream_t s);
+void launch_node_residual(const Level& L, int B, const T* f, const T* u, T* r, hipStream_t s);
 template <typename T>
-void launch_node_sweep(const Csr& A, int B, const T* m, const T* f, const T* uin, T* uout, hipStream_t s);
-int launch_node_cg_pq(const Csr& A, int B, const double* val, const double* z, const double* pold, double* pnew,
+void launch_node_sweep(const Level& L, int B, const T* m, const T* f, const T* uin, T* uout, hipStream_t s);
+int launch_node_cg_pq(const Level& L, int B, const double* val, const double* z, const double* pold, double* pnew,
                       double* q, int first, const RedScratch& rs, hipStream_t s);
 void launch_node_expand(const Csr& A, int B, const Csr& Nm, const uint8_t* nstrong, const int32_t* nagg,
                         uint8_t* strong, int32_t* agg, hipStream_t s);

@@ -112,11 +112,13 @@ __global__ __launch_bounds__(TPB_B) void k_block_apply(int n, const T* __restric
 // ------------------------------------------------------------------ node-group products
 //
 // The rows of a node list the same columns (full blocks) and are consecutive in CSR, so
-// row a of node I starts at ptr[I*B] + a*len with len the common row length.  A group of
-// NG lanes walks the node's column list once (row 0's columns: one index read per column
-// for all B rows) and reads the B rows' values at the same offsets, coalesced across the
-// group; every lane keeps B partial sums, a butterfly over the group leaves the B row sums
-// in every lane, and lanes 0..B-1 finish one row each.  16 nodes per workgroup.
+// with the node pattern (nptr, ncol) node I's rows hold B * B * nptr[I] entries before
+// them, each row has len = B * (nptr[I+1] - nptr[I]) entries, and entry k of a row lies in
+// column B * ncol[nptr[I] + k / B] + k % B: one 4-byte index per block instead of one
+// per entry.  A group of NG lanes walks the row positions once and reads the B rows'
+// values at the same offsets, coalesced across the group; every lane keeps B partial
+// sums, a butterfly over the group leaves the B row sums in every lane, and lanes
+// 0..B-1 finish one row each.  16 nodes per workgroup.
 constexpr int NG = 16;
 constexpr int NODES_PER_WG = TPB_B / NG;
 
@@ -124,14 +126,32 @@ __device__ __forceinline__ double bfma(double a, double b, double c) { return __
 __device__ __forceinline__ float bfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <int B, typename T, typename X>
-__device__ __forceinline__ void node_rowsums(int base, int len, int lane, const int* __restrict__ col,
-                                             const T* __restrict__ val, X x, T (&s)[B]) {
+__device__ __forceinline__ void node_rowsums(int I, int lane, const int* __restrict__ nptr,
+                                             const int* __restrict__ ncol, const T* __restrict__ val, X x,
+                                             T (&s)[B]) {
+    const int nb = nptr[I];
+    const int len = B * (nptr[I + 1] - nb);
+    const T* v = val + (size_t)B * B * nb;
 #pragma unroll
     for (int a = 0; a < B; ++a) s[a] = 0;
-    for (int k = lane; k < len; k += NG) {
-        const T xj = x(col[base + k]);
+    int k = lane;
+    for (; k + NG < len; k += 2 * NG) {  // two positions per pass: their loads in flight together
+        const int k2 = k + NG;
+        const int j1 = B * ncol[nb + k / B] + k % B, j2 = B * ncol[nb + k2 / B] + k2 % B;
+        T v1[B], v2[B];
 #pragma unroll
-        for (int a = 0; a < B; ++a) s[a] = bfma(val[base + a * len + k], xj, s[a]);
+        for (int a = 0; a < B; ++a) {
+            v1[a] = v[a * len + k];
+            v2[a] = v[a * len + k2];
+        }
+        const T x1 = x(j1), x2 = x(j2);
+#pragma unroll
+        for (int a = 0; a < B; ++a) s[a] = bfma(v2[a], x2, bfma(v1[a], x1, s[a]));
+    }
+    if (k < len) {
+        const T xj = x(B * ncol[nb + k / B] + k % B);
+#pragma unroll
+        for (int a = 0; a < B; ++a) s[a] = bfma(v[a * len + k], xj, s[a]);
     }
 #pragma unroll
     for (int o = NG / 2; o > 0; o >>= 1) {
@@ -151,16 +171,15 @@ __device__ __forceinline__ T pick(const T (&s)[B], int lane) {
 
 // r = f - A u
 template <int B, typename T>
-__global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __restrict__ ptr,
-                                                         const int* __restrict__ col, const T* __restrict__ val,
+__global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __restrict__ nptr,
+                                                         const int* __restrict__ ncol, const T* __restrict__ val,
                                                          const T* __restrict__ f, const T* __restrict__ u,
                                                          T* __restrict__ r) {
     const int I = xcd_block() * NODES_PER_WG + (int)threadIdx.x / NG;
     const int lane = threadIdx.x & (NG - 1);
     if (I >= nn) return;
-    const int base = ptr[I * B], len = ptr[I * B + 1] - base;
     T s[B];
-    node_rowsums<B>(base, len, lane, col, val, [&](int j) { return u[j]; }, s);
+    node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return u[j]; }, s);
     if (lane < B) {
         const int i = I * B + lane;
         r[i] = f[i] - pick<B>(s, lane);
@@ -169,16 +188,15 @@ __global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __re
 
 // uout = uin + M (f - A uin): a residual and the block-diagonal product in one pass
 template <int B, typename T>
-__global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restrict__ ptr, const int* __restrict__ col,
+__global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restrict__ nptr, const int* __restrict__ ncol,
                                                       const T* __restrict__ val, const T* __restrict__ m,
                                                       const T* __restrict__ f, const T* __restrict__ uin,
                                                       T* __restrict__ uout) {
     const int I = xcd_block() * NODES_PER_WG + (int)threadIdx.x / NG;
     const int lane = threadIdx.x & (NG - 1);
     if (I >= nn) return;
-    const int base = ptr[I * B], len = ptr[I * B + 1] - base;
     T s[B];
-    node_rowsums<B>(base, len, lane, col, val, [&](int j) { return uin[j]; }, s);
+    node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return uin[j]; }, s);
     if (lane < B) {
         const int i = I * B + lane;
         const T* mi = m + (size_t)i * B;
@@ -194,8 +212,8 @@ __global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restr
 // applied to exactly the stored p_new.  Bounded grid, nodes by grid stride: one partial
 // per workgroup, in a fixed order.
 template <int B>
-__global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restrict__ ptr,
-                                                      const int* __restrict__ col, const double* __restrict__ val,
+__global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restrict__ nptr,
+                                                      const int* __restrict__ ncol, const double* __restrict__ val,
                                                       const double* __restrict__ z, const double* __restrict__ pold,
                                                       double* __restrict__ pnew, double* __restrict__ q, int first,
                                                       RedScratch rs) {
@@ -204,9 +222,8 @@ __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restr
     const int lane = threadIdx.x & (NG - 1);
     double loc = 0.0;
     for (int I = blockIdx.x * NODES_PER_WG + (int)threadIdx.x / NG; I < nn; I += gridDim.x * NODES_PER_WG) {
-        const int base = ptr[I * B], len = ptr[I * B + 1] - base;
         double s[B];
-        node_rowsums<B>(base, len, lane, col, val, pv, s);
+        node_rowsums<B>(I, lane, nptr, ncol, val, pv, s);
         if (lane < B) {
             const int i = I * B + lane;
             const double pi = pv(i), qi = pick<B>(s, lane);
@@ -257,28 +274,38 @@ void launch_block_apply(int n, int B_, const T* m, const T* r, const T* uin, T* 
     HIP_LAUNCH_CHECK();
 }
 
+int node_grid(int nn) { return (int)(((int64_t)nn + NODES_PER_WG - 1) / NODES_PER_WG); }
+
+static void need_nodes(const Level& L) {
+    if (L.nptr == nullptr || L.ncol == nullptr) throw Fail{AMG_ERR_STATE, "node pattern missing"};
+}
+
 template <typename T>
-void launch_node_residual(const Csr& A, int B_, const T* f, const T* u, T* r, hipStream_t s) {
-    const int nn = A.nrows / B_;
+void launch_node_residual(const Level& L, int B_, const T* f, const T* u, T* r, hipStream_t s) {
+    need_nodes(L);
+    const int nn = L.A.nrows / B_;
     const unsigned nb = (unsigned)((nn + NODES_PER_WG - 1) / NODES_PER_WG);
-    AMG_WITH_B(B_, k_node_residual<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, A.ptr, A.col, A.v<T>(), f, u, r));
+    AMG_WITH_B(B_, k_node_residual<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r));
     HIP_LAUNCH_CHECK();
 }
 
 template <typename T>
-void launch_node_sweep(const Csr& A, int B_, const T* m, const T* f, const T* uin, T* uout, hipStream_t s) {
-    const int nn = A.nrows / B_;
+void launch_node_sweep(const Level& L, int B_, const T* m, const T* f, const T* uin, T* uout, hipStream_t s) {
+    need_nodes(L);
+    const int nn = L.A.nrows / B_;
     const unsigned nb = (unsigned)((nn + NODES_PER_WG - 1) / NODES_PER_WG);
-    AMG_WITH_B(B_, k_node_sweep<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, A.ptr, A.col, A.v<T>(), m, f, uin, uout));
+    AMG_WITH_B(B_, k_node_sweep<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin,
+                                                                          uout));
     HIP_LAUNCH_CHECK();
 }
 
 // The Krylov operator product of a block system (values `val` on the pattern of A).  Like
 // the other Krylov SpMV launchers it takes the events that a kernel trace left for it, so
 // the trace times the kernel itself.
-int launch_node_cg_pq(const Csr& A, int B_, const double* val, const double* z, const double* pold, double* pnew,
+int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z, const double* pold, double* pnew,
                       double* q, int first, const RedScratch& rs, hipStream_t s) {
-    const int nn = A.nrows / B_;
+    need_nodes(L);
+    const int nn = L.A.nrows / B_;
     int64_t want = ((int64_t)nn + NODES_PER_WG - 1) / NODES_PER_WG;
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(want, rs.cap));
     const KernelEvents e = g_kernel_events;
@@ -286,20 +313,20 @@ int launch_node_cg_pq(const Csr& A, int B_, const double* val, const double* z, 
     AMG_WITH_B(B_, {
         if (e.start != nullptr)
             hipExtLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, e.start, e.stop, 0, nn,
-                                  (const int*)A.ptr, (const int*)A.col, val, z, pold, pnew, q, first, rs);
+                                  (const int*)L.nptr, (const int*)L.ncol, val, z, pold, pnew, q, first, rs);
         else
-            hipLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)A.ptr,
-                               (const int*)A.col, val, z, pold, pnew, q, first, rs);
+            hipLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)L.nptr,
+                               (const int*)L.ncol, val, z, pold, pnew, q, first, rs);
     });
     HIP_LAUNCH_CHECK();
     return nb;
 }
 
-template void launch_node_residual<double>(const Csr&, int, const double*, const double*, double*, hipStream_t);
-template void launch_node_residual<float>(const Csr&, int, const float*, const float*, float*, hipStream_t);
-template void launch_node_sweep<double>(const Csr&, int, const double*, const double*, const double*, double*,
+template void launch_node_residual<double>(const Level&, int, const double*, const double*, double*, hipStream_t);
+template void launch_node_residual<float>(const Level&, int, const float*, const float*, float*, hipStream_t);
+template void launch_node_sweep<double>(const Level&, int, const double*, const double*, const double*, double*,
                                         hipStream_t);
-template void launch_node_sweep<float>(const Csr&, int, const float*, const float*, const float*, float*,
+template void launch_node_sweep<float>(const Level&, int, const float*, const float*, const float*, float*,
                                        hipStream_t);
 template void launch_block_inv<double>(const Csr&, int, double, double*, int*, hipStream_t);
 template void launch_block_inv<float>(const Csr&, int, double, float*, int*, hipStream_t);

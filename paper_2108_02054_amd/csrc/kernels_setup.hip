@@ -361,12 +361,13 @@ __global__ void k_node_fill(int nn, int B, const int* __restrict__ ptr, const in
     const int r0 = I * B;
     const int nb = Nptr[I], ng = Nptr[I + 1] - nb;
     for (int g = 0; g < ng; ++g) {
+        Ncol[nb + g] = col[ptr[r0] + g * B] / B;
+        if (val == nullptr) continue;  // the pattern only
         double ss = 0.0;
         for (int c = 0; c < B; ++c) {
             const double* v = val + ptr[r0 + c] + g * B;
             for (int q = 0; q < B; ++q) ss += v[q] * v[q];
         }
-        Ncol[nb + g] = col[ptr[r0] + g * B] / B;
         Nval[nb + g] = sqrt(ss);
     }
 }
@@ -406,9 +407,8 @@ void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, h
         throw Fail{AMG_ERR_PATTERN, "block_size needs full blocks with the same columns in every row of a node"};
     }
     Nm.nnz = nnz;
-    if (A.val == nullptr) return;  // a pattern: the block structure is checked, Nm.ptr only
     Nm.col = dnew<int32_t>((size_t)nnz, s);
-    Nm.val = dnew<double>((size_t)nnz, s);
+    Nm.val = A.val != nullptr ? dnew<double>((size_t)nnz, s) : nullptr;
     k_node_fill<<<blocks_for(nn), TPB, 0, s>>>(nn, B, A.ptr, A.col, A.val, Nm.ptr, Nm.col, Nm.val);
     HIP_LAUNCH_CHECK();
 }
