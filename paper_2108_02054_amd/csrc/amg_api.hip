@@ -368,8 +368,7 @@ void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
 void configure_tail(amg_ctx* c) {
     const int nlev = (int)c->lv.size();
     c->tail = 0;
-    // (block smoothers run level by level: the fused tail applies scalar diagonals only)
-    if (nlev < 2 || c->prm.block_size > 1 || std::getenv("AMGMI_NO_TAIL") != nullptr) return;
+    if (nlev < 2 || std::getenv("AMGMI_NO_TAIL") != nullptr) return;
     int64_t max_nnz = TAIL_MAX_NNZ;
     if (const char* e = std::getenv("AMGMI_TAIL_NNZ")) max_nnz = std::atoll(e);
     int64_t rows = 0, nnz = 0;
@@ -872,6 +871,49 @@ struct RzEpilogue {
 // residual) and z.  `ready` = 1: the first smoothing sweep u = m f is already in the
 // level's u (the restriction forms it on coarser levels); 2: so is the residual f - A u
 // in the level's r (the fused CG update forms both on level 0; one pre-sweep only).
+// Restriction of level l's residual into the coarse tail and the tail levels down to the
+// coarsest and back, in one workgroup; the tail's finest level gets its correction in u.
+template <typename T>
+void run_tail(amg_ctx* c, int l, const T* rres) {
+    const Level& L = c->lv[(size_t)l];
+    const Level& C = c->lv[(size_t)l + 1];
+    const amg_params& p = c->prm;
+    const int nlev = (int)c->lv.size();
+    TailArgs<T> ta;
+    ta.nlev = nlev - c->tail;
+    ta.npre = p.npre;
+    ta.npost = p.npost;
+    ta.bs = p.block_size;
+    ta.rin_ptr = L.R.ptr;
+    ta.rin_col = L.R.col;
+    ta.rin_val = L.R.v<T>();
+    ta.rin = rres;
+    ta.uout = (T*)C.u;
+    ta.cinv = c->cinv;
+    int soff = 0;
+    for (int k = 0; k < ta.nlev; ++k) {
+        const Level& Lk = c->lv[(size_t)(c->tail + k)];
+        TailLevel<T>& tk = ta.lv[k];
+        tk.n = Lk.A.nrows;
+        tk.soff = soff;
+        soff += 3 * tk.n;
+        tk.Aptr = Lk.A.ptr;
+        tk.Acol = Lk.A.col;
+        tk.Aval = Lk.A.v<T>();
+        tk.m = Lk.mv<T>();
+        if (k + 1 < ta.nlev) {
+            tk.Rptr = Lk.R.ptr;
+            tk.Rcol = Lk.R.col;
+            tk.Rval = Lk.R.v<T>();
+            tk.Pptr = Lk.P.ptr;
+            tk.Pcol = Lk.P.col;
+            tk.Pval = Lk.P.v<T>();
+        }
+    }
+    Trace tr(c, AMG_K_TAIL, l + 1);
+    launch_vcycle_tail<T>(ta, c->stream);
+}
+
 template <typename T>
 T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nullptr, int ready = 0);
 
@@ -879,7 +921,8 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep = nu
 // sweep u += M (f - A u) is one node-group pass (residual and block-diagonal product); the
 // first sweep from zero is u = M f, the pre-smoothing residual a node-group pass on
 // level 0 and a row-block pass below.
-// Algorithm 2 with the scalar-diagonal fused forms left out.
+// Algorithm 2 with the scalar-diagonal fused forms left out; the coarse tail as for
+// scalar systems.
 template <typename T>
 T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep) {
     hipStream_t s = c->stream;
@@ -914,11 +957,17 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
         rres = r;
     }
     const Level& C = c->lv[(size_t)l + 1];
-    {
-        Trace tr(c, AMG_K_RESTRICT, l);
-        launch_spmv<T>(L.R, rres, (T*)C.f, (const T*)nullptr, (T*)nullptr, s);
+    const T* uc;
+    if (c->tail > 0 && l + 1 == c->tail) {
+        run_tail<T>(c, l, rres);
+        uc = (const T*)C.u;
+    } else {
+        {
+            Trace tr(c, AMG_K_RESTRICT, l);
+            launch_spmv<T>(L.R, rres, (T*)C.f, (const T*)nullptr, (T*)nullptr, s);
+        }
+        uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, 0);
     }
-    const T* uc = vcycle_level<T>(c, l + 1, (const T*)C.f, nullptr, nullptr, 0);
     {
         Trace tr(c, AMG_K_PROLONG, l);
         launch_prolong_add<T>(L.P, uc, cur, s);
@@ -1006,39 +1055,7 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep, int
     const Level& C = c->lv[(size_t)l + 1];
     const T* uc;
     if (c->tail > 0 && l + 1 == c->tail) {
-        // restriction and levels tail .. L in one workgroup
-        TailArgs<T> ta;
-        ta.nlev = nlev - c->tail;
-        ta.npre = p.npre;
-        ta.npost = p.npost;
-        ta.rin_ptr = L.R.ptr;
-        ta.rin_col = L.R.col;
-        ta.rin_val = L.R.v<T>();
-        ta.rin = rres;
-        ta.uout = (T*)C.u;
-        ta.cinv = c->cinv;
-        int soff = 0;
-        for (int k = 0; k < ta.nlev; ++k) {
-            const Level& Lk = c->lv[(size_t)(c->tail + k)];
-            TailLevel<T>& tk = ta.lv[k];
-            tk.n = Lk.A.nrows;
-            tk.soff = soff;
-            soff += 3 * tk.n;
-            tk.Aptr = Lk.A.ptr;
-            tk.Acol = Lk.A.col;
-            tk.Aval = Lk.A.v<T>();
-            tk.m = Lk.mv<T>();
-            if (k + 1 < ta.nlev) {
-                tk.Rptr = Lk.R.ptr;
-                tk.Rcol = Lk.R.col;
-                tk.Rval = Lk.R.v<T>();
-                tk.Pptr = Lk.P.ptr;
-                tk.Pcol = Lk.P.col;
-                tk.Pval = Lk.P.v<T>();
-            }
-        }
-        Trace tr(c, AMG_K_TAIL, l + 1);
-        launch_vcycle_tail<T>(ta, s);
+        run_tail<T>(c, l, rres);
         uc = (const T*)C.u;
     } else {
         // the next level's first sweep from zero is formed by the restriction

@@ -297,6 +297,7 @@ template <typename T>
 struct TailArgs {
     int nlev = 0;
     int npre = 1, npost = 1;
+    int bs = 1;                    // unknowns per node: > 1 smooths with B x B blocks (m: B per row)
     const int* rin_ptr = nullptr;  // R_{t-1} and r_{t-1}
     const int* rin_col = nullptr;
     const T* rin_val = nullptr;

@@ -1417,10 +1417,32 @@ __device__ __forceinline__ T tail_row(const int* __restrict__ ptr, const int* __
     return group_sum<TAIL_G, T>(s);
 }
 
-// One smoothing sweep u <- u + m (f - A u) on a tail level (through w).
+// Block smoother product (M x)_i on a tail level with bs unknowns per node: row i of its
+// node's block times the node's entries of x, in column order.
 template <typename T>
-__device__ __forceinline__ void tail_sweep(const TailLevel<T>& L, const T* f, T* u, T* w, int r0, int g) {
+__device__ __forceinline__ T tail_mblock(const T* __restrict__ m, const T* x, int i, int bs) {
+    const int base = i - i % bs;
+    const T* mi = m + (size_t)i * bs;
+    T d = 0;
+    for (int q = 0; q < bs; ++q) d = d + mi[q] * x[base + q];
+    return d;
+}
+
+// One smoothing sweep u <- u + m (f - A u) on a tail level (through w); with blocks
+// (bs > 1) the residual goes to w first and u <- u + M w follows.
+template <typename T>
+__device__ __forceinline__ void tail_sweep(const TailLevel<T>& L, int bs, const T* f, T* u, T* w, int r0, int g) {
     constexpr int RS = TAIL_THREADS / TAIL_G;
+    if (bs > 1) {
+        for (int i = r0; i < L.n; i += RS) {
+            const T au = tail_row<T>(L.Aptr, L.Acol, L.Aval, u, i, g);
+            if (g == 0) w[i] = f[i] - au;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < L.n; i += TAIL_THREADS) u[i] = u[i] + tail_mblock<T>(L.m, w, i, bs);
+        __syncthreads();
+        return;
+    }
     for (int i = r0; i < L.n; i += RS) {
         const T au = tail_row<T>(L.Aptr, L.Acol, L.Aval, u, i, g);
         if (g == 0) w[i] = u[i] + L.m[i] * (f[i] - au);
@@ -1452,10 +1474,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vcycle_tail(TailArgs<T> a) {
         T* f = sm + L.soff;
         T* u = f + n;
         T* w = u + n;
-        // pre-smoothing from u = 0: the first sweep is u = m f
-        for (int i = threadIdx.x; i < n; i += TAIL_THREADS) u[i] = a.npre > 0 ? L.m[i] * f[i] : (T)0;
+        // pre-smoothing from u = 0: the first sweep is u = m f (u = M f with blocks)
+        for (int i = threadIdx.x; i < n; i += TAIL_THREADS)
+            u[i] = a.npre > 0 ? (a.bs > 1 ? tail_mblock<T>(L.m, f, i, a.bs) : L.m[i] * f[i]) : (T)0;
         __syncthreads();
-        for (int it = 1; it < a.npre; ++it) tail_sweep<T>(L, f, u, w, r0, g);
+        for (int it = 1; it < a.npre; ++it) tail_sweep<T>(L, a.bs, f, u, w, r0, g);
         // residual into w, restricted to the next level
         for (int i = r0; i < n; i += RS) {
             const T au = tail_row<T>(L.Aptr, L.Acol, L.Aval, u, i, g);
@@ -1496,7 +1519,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vcycle_tail(TailArgs<T> a) {
             if (g == 0) u[i] = u[i] + v;
         }
         __syncthreads();
-        for (int it = 0; it < a.npost; ++it) tail_sweep<T>(L, f, u, w, r0, g);
+        for (int it = 0; it < a.npost; ++it) tail_sweep<T>(L, a.bs, f, u, w, r0, g);
     }
     {
         const T* u0 = sm + a.lv[0].soff + a.lv[0].n;
