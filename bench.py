@@ -69,6 +69,16 @@ def workload_name(cfg_id, N, n, nnz):
             f"(numeric-only cached RAP + smoother), {form}, {krylov} to 1e-8 true rel res")
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def copy_bandwidth(mib=1024, reps=5):
     """Measured device-copy bandwidth (read + write bytes over the copy's time, best of reps),
     the practical ceiling the HBM-bound kernels are compared with besides the 8 TB/s peak."""
@@ -435,13 +445,25 @@ def main():
             elapsed += time.perf_counter() - ts
             its.append(io["iters"])
         cpu_ms = elapsed * 1e3 / ks
+        # one more step on one thread (the oracle's results do not depend on the count)
+        oracle.set_num_threads(1)
+        _, _, vt = series_matrix(cfg_id, ks + 1, N)
+        ft = rhs_uniform(n, cfg_id, ks + 1)
+        ts = time.perf_counter()
+        h.rebuild(vt, 0)
+        _, io1 = h.solve_bicgstab(ft) if bicg else h.solve(ft)
+        cpu1_ms = (time.perf_counter() - ts) * 1e3
+        oracle.set_num_threads(nthr)
         h.close()
-        log(f"oracle: setup {t_setup:.1f}s, partial step {cpu_ms:.0f} ms ({nthr} threads), iters {its}")
+        log(f"oracle: setup {t_setup:.1f}s, partial step {cpu_ms:.0f} ms ({nthr} threads), iters {its}; "
+            f"one thread {cpu1_ms:.0f} ms")
         result["cpu_baseline"] = {"value": cpu_ms, "unit": "ms/step", "cores": nthr, "kind": "oracle",
                                   "sample": f"oracle (FP64) partial rebuild + {'BiCGStab' if bicg else 'PCG'} solve "
                                             f"to 1e-8 of {cfg['name']} at "
                                             f"{N}^3, steps t=1..{ks} after an untimed setup at t=0 (full setup "
-                                            f"took {t_setup:.1f}s); iterations {its}"}
+                                            f"took {t_setup:.1f}s); iterations {its}",
+                                  "cpu_model": cpu_model(),
+                                  "single_thread_ms_per_step": cpu1_ms}
     print(json.dumps(result), flush=True)
 
 
