@@ -500,7 +500,7 @@ void partial_rebuild(amg_ctx* c, const double* val) {
         const Level& L = c->lv[l];
         Trace tr(c, AMG_K_SMOOTHER, l);
         if (blocked)
-            launch_block_inv<T>(L.A, c->prm.block_size, c->prm.jacobi_omega, L.mv<T>(), nullptr, s);
+            launch_block_inv<T>(L, c->prm.block_size, c->prm.jacobi_omega, L.mv<T>(), nullptr, s);
         else
             launch_smoother_diag<T>(L.A, c->prm.smoother, c->prm.jacobi_omega, L.mv<T>(), s);
     }
@@ -754,7 +754,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
         Level& L = c->lv[(size_t)l];
         L.m = halloc<double>(c, (size_t)L.A.nrows * p.block_size);
         if (p.block_size > 1)
-            launch_block_inv<double>(L.A, p.block_size, p.jacobi_omega, L.m, c->d_flags, s);
+            launch_block_inv<double>(L, p.block_size, p.jacobi_omega, L.m, c->d_flags, s);
         else
             launch_smoother_diag<double>(L.A, p.smoother, p.jacobi_omega, L.m, s);
     }

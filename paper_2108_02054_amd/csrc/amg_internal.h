@@ -369,7 +369,7 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t 
 // flags to the unknowns.
 void build_node_matrix(const Csr& A, int B, Csr& Nm, int* flags, int* h_flags, hipStream_t s);
 template <typename T>
-void launch_block_inv(const Csr& A, int B, double omega, T* m, int* flags, hipStream_t s);
+void launch_block_inv(const Level& L, int B, double omega, T* m, int* flags, hipStream_t s);
 template <typename T>
 void launch_block_apply(int n, int B, const T* m, const T* r, const T* uin, T* uout, hipStream_t s);
 // Node-group products on level L of a block system (L.nptr, L.ncol: its node pattern).

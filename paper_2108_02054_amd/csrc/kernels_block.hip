@@ -1,7 +1,8 @@
-// kernels_block.hip -- damped block Jacobi for systems with B unknowns per node (the
-// paper's 4x4-block systems, Section 4, where every matrix value is a block and the
-// Jacobi smoother inverts the diagonal block).  Unknown b of node I is row I*B + b; the
-// smoother of a level holds omega * D_I^{-1} for every node, row-major, B*B values per node.
+// kernels_block.hip -- systems with B unknowns per node (the paper's 4x4-block systems,
+// Section 4, where every matrix value is a block): damped block Jacobi, whose smoother
+// holds omega * D_I^{-1} for every node I (row-major, B*B values per node), and the
+// node-group products (residual, sweep, Krylov SpMV) that read the level's node pattern.
+// Unknown b of node I is row I*B + b; every stored entry belongs to a full B x B block.
 //
 // The inverse is Gauss-Jordan elimination with partial pivoting on [D_I | I], in the
 // order of its definition (the first row of largest magnitude in the column is the pivot),
@@ -19,14 +20,15 @@ namespace amgmi {
 
 constexpr int TPB_B = 256;
 
-// One thread per node.  Values are read in T (FP64, or the FP32 copies of a mixed
-// hierarchy), the elimination runs in FP64 and the result is stored in T.  A zero pivot
-// (singular block) sets flags[F_NOT_SPD] when flags is given; the block then holds
-// non-finite values.
+// One thread per node; its diagonal block is found in the node pattern (nptr, ncol: node
+// I's rows hold B * B * nptr[I] entries before them, each row B * (nptr[I+1] - nptr[I])).
+// Values are read in T (FP64, or the FP32 copies of a mixed hierarchy), the elimination
+// runs in FP64 and the result is stored in T.  A zero pivot (singular block) sets
+// flags[F_NOT_SPD] when flags is given; the block then holds non-finite values.
 template <int B, typename T>
-__global__ __launch_bounds__(TPB_B) void k_block_inv(int nn, const int* __restrict__ ptr, const int* __restrict__ col,
-                                                     const T* __restrict__ val, double omega, T* __restrict__ m,
-                                                     int* __restrict__ flags) {
+__global__ __launch_bounds__(TPB_B) void k_block_inv(int nn, const int* __restrict__ nptr,
+                                                     const int* __restrict__ ncol, const T* __restrict__ val,
+                                                     double omega, T* __restrict__ m, int* __restrict__ flags) {
     const int I = xcd_block() * TPB_B + threadIdx.x;
     if (I >= nn) return;
     double W[B][2 * B];
@@ -35,17 +37,15 @@ __global__ __launch_bounds__(TPB_B) void k_block_inv(int nn, const int* __restri
 #pragma unroll
         for (int q = 0; q < 2 * B; ++q) W[a][q] = (q == B + a) ? 1.0 : 0.0;
     }
-    const int c0 = I * B;
+    const int nb = nptr[I], ne = nptr[I + 1], len = B * (ne - nb);
+    int g = nb;
+    while (g < ne && ncol[g] < I) ++g;  // the diagonal block's position (absent: zero block)
+    if (g < ne && ncol[g] == I) {
+        const T* v = val + (size_t)B * B * nb + (size_t)B * (g - nb);
 #pragma unroll
-    for (int a = 0; a < B; ++a) {
-        const int r = c0 + a;
-        int k = ptr[r];
-        const int e = ptr[r + 1];
-        while (k < e && col[k] < c0) ++k;  // first entry of the diagonal block
+        for (int a = 0; a < B; ++a) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) {
-            // every stored block is full, so these are columns c0 .. c0 + B - 1
-            if (k + q < e && col[k + q] == c0 + q) W[a][q] = (double)val[k + q];
+            for (int q = 0; q < B; ++q) W[a][q] = (double)v[a * len + q];
         }
     }
     bool singular = false;
@@ -261,10 +261,15 @@ static unsigned bgrid(int64_t n) {
         default: throw Fail{AMG_ERR_ARG, "block_size must be 1 .. 8"}; \
     }
 
+static void need_nodes(const Level& L) {
+    if (L.nptr == nullptr || L.ncol == nullptr) throw Fail{AMG_ERR_STATE, "node pattern missing"};
+}
+
 template <typename T>
-void launch_block_inv(const Csr& A, int B_, double omega, T* m, int* flags, hipStream_t s) {
-    const int nn = A.nrows / B_;
-    AMG_WITH_B(B_, k_block_inv<B, T><<<bgrid(nn), TPB_B, 0, s>>>(nn, A.ptr, A.col, A.v<T>(), omega, m, flags));
+void launch_block_inv(const Level& L, int B_, double omega, T* m, int* flags, hipStream_t s) {
+    need_nodes(L);
+    const int nn = L.A.nrows / B_;
+    AMG_WITH_B(B_, k_block_inv<B, T><<<bgrid(nn), TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), omega, m, flags));
     HIP_LAUNCH_CHECK();
 }
 
@@ -276,16 +281,12 @@ void launch_block_apply(int n, int B_, const T* m, const T* r, const T* uin, T* 
 
 int node_grid(int nn) { return (int)(((int64_t)nn + NODES_PER_WG - 1) / NODES_PER_WG); }
 
-static void need_nodes(const Level& L) {
-    if (L.nptr == nullptr || L.ncol == nullptr) throw Fail{AMG_ERR_STATE, "node pattern missing"};
-}
-
 template <typename T>
 void launch_node_residual(const Level& L, int B_, const T* f, const T* u, T* r, hipStream_t s) {
     need_nodes(L);
     const int nn = L.A.nrows / B_;
-    const unsigned nb = (unsigned)((nn + NODES_PER_WG - 1) / NODES_PER_WG);
-    AMG_WITH_B(B_, k_node_residual<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r));
+    const unsigned nb = (unsigned)std::max(1, node_grid(nn));
+    AMG_WITH_B(B_, k_node_residual<B, T><<<nb, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r));
     HIP_LAUNCH_CHECK();
 }
 
@@ -293,8 +294,8 @@ template <typename T>
 void launch_node_sweep(const Level& L, int B_, const T* m, const T* f, const T* uin, T* uout, hipStream_t s) {
     need_nodes(L);
     const int nn = L.A.nrows / B_;
-    const unsigned nb = (unsigned)((nn + NODES_PER_WG - 1) / NODES_PER_WG);
-    AMG_WITH_B(B_, k_node_sweep<B, T><<<nb > 0 ? nb : 1, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin,
+    const unsigned nb = (unsigned)std::max(1, node_grid(nn));
+    AMG_WITH_B(B_, k_node_sweep<B, T><<<nb, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin,
                                                                           uout));
     HIP_LAUNCH_CHECK();
 }
@@ -306,8 +307,7 @@ int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z
                       double* q, int first, const RedScratch& rs, hipStream_t s) {
     need_nodes(L);
     const int nn = L.A.nrows / B_;
-    int64_t want = ((int64_t)nn + NODES_PER_WG - 1) / NODES_PER_WG;
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(want, rs.cap));
+    const int nb = std::max(1, std::min(node_grid(nn), rs.cap));
     const KernelEvents e = g_kernel_events;
     g_kernel_events = KernelEvents{};
     AMG_WITH_B(B_, {
@@ -328,8 +328,8 @@ template void launch_node_sweep<double>(const Level&, int, const double*, const 
                                         hipStream_t);
 template void launch_node_sweep<float>(const Level&, int, const float*, const float*, const float*, float*,
                                        hipStream_t);
-template void launch_block_inv<double>(const Csr&, int, double, double*, int*, hipStream_t);
-template void launch_block_inv<float>(const Csr&, int, double, float*, int*, hipStream_t);
+template void launch_block_inv<double>(const Level&, int, double, double*, int*, hipStream_t);
+template void launch_block_inv<float>(const Level&, int, double, float*, int*, hipStream_t);
 template void launch_block_apply<double>(int, int, const double*, const double*, const double*, double*, hipStream_t);
 template void launch_block_apply<float>(int, int, const float*, const float*, const float*, float*, hipStream_t);
 
