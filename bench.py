@@ -101,6 +101,35 @@ def copy_bandwidth(mib=1024, reps=5):
     return 2 * mib * 2**20 / (best * 1e-3) / 1e9
 
 
+def operator_timing(amg, n, reps=7, scrub_mib=512):
+    """Median time (us) of the level-0 Krylov SpMV (its first-iteration form, through the
+    library's operator entry point) back to back, and after a read of scrub_mib MiB that
+    evicts the operator from the caches (L2 and the 256 MB MALL) without leaving dirty
+    lines to write back."""
+    import torch
+
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    scrub = torch.ones(scrub_mib * 131072, dtype=torch.float64, device="cuda")
+    amg.apply_operator(x, y)
+
+    def once(cold, k):
+        if cold:
+            scrub.sum()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        amg.apply_operator(x, y)
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) * 1e3
+
+    hot = sorted(once(False, k) for k in range(reps))
+    cold = sorted(once(True, k) for k in range(reps))
+    del scrub
+    torch.cuda.empty_cache()
+    return hot[reps // 2], cold[reps // 2]
+
+
 def copy_probe(mib):
     """A plain device copy of known size (read mib MiB, write mib MiB), three launches."""
     import torch
@@ -294,6 +323,7 @@ def main():
     solve(amg, rhs[W + 1], u)
     breakdown_l0 = amg.trace_read()
     amg.trace([], level=0)
+    spmv_hot_us, spmv_cold_us = operator_timing(amg, n)
     amg.close()
 
     kb = kernel_bytes(dims, 8, ndiag, sym=0 < nread < ndiag, block=cfg.get("block_size", 1))
@@ -305,6 +335,8 @@ def main():
     else:
         spmv_bytes = pq_cnt * kb["cg_pq"] - n_solves * 8 * n  # first iteration reads no p_old
     spmv_gbs = spmv_bytes / (pq_ms * 1e-3) / 1e9 if pq_ms > 0 else None
+    spmv_first_bytes = kb["cg_pq"] - 8 * n  # the CG's kernel on its first iteration reads no p_old
+    first_kernel = pq_kernel if not pq_kernel.startswith("k_rb") else "k_cg_pq"
     g_ms = kt.get("galerkin_ap", (0.0, 0))[0] + kt.get("galerkin_rap", (0.0, 0))[0]
     g_cnt = kt.get("galerkin_rap", (0.0, 0))[1]
     rap_gbs = g_cnt * kb["galerkin"] / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None
@@ -366,6 +398,13 @@ def main():
         "rebuild_phase_ms": ph,
         "setup_ms_step0": info_p["setup_ms"],
         "copy_gbs_measured": copy_gbs,
+        "krylov_spmv_first_iteration": {
+            "kernel": first_kernel, "algorithmic_bytes": spmv_first_bytes,
+            "hot_us": spmv_hot_us, "cold_us": spmv_cold_us,
+            "hot_frac": spmv_first_bytes / (spmv_hot_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "cold_frac": spmv_first_bytes / (spmv_cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "note": "y = A x through amg_apply_operator (p = z, no p_old read), median of 7; cold: after a "
+                    "512 MiB read that evicts L2 and the MALL"},
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,

@@ -165,6 +165,13 @@ amg_status amg_solve_bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_
 /* One V-cycle z = B r from a zero initial guess (r, z: device, n entries). */
 amg_status amg_vcycle(amg_ctx* c, const double* r, double* z);
 
+/* y = A x with the Krylov operator (the values of the last update, pattern of level 0),
+ * by the kernel the CG applies on its first iteration (the level-0 SpMV of Section 2's
+ * Krylov loop): x, y device arrays of n entries, distinct; asynchronous on the stream.
+ * For measurements and checks; it overwrites the CG's work vectors.  AMG_ERR_ARG for
+ * NULL or aliased arguments. */
+amg_status amg_apply_operator(amg_ctx* c, const double* x, double* y);
+
 amg_status amg_destroy(amg_ctx* c);
 
 /* Description of the last failure of c (or of the last failed amg_setup when c is NULL). */

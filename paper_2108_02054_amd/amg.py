@@ -25,7 +25,7 @@ EXPORTED = [
     "amg_rebuild_ex", "amg_solve", "amg_vcycle", "amg_destroy", "amg_last_error", "amg_num_levels",
     "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
     "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read", "amg_policy_pick",
-    "amg_rebuild_auto", "amg_solve_bicgstab",
+    "amg_rebuild_auto", "amg_solve_bicgstab", "amg_apply_operator",
 ]
 MODE_NAMES = {PARTIAL: "partial", FULL: "full", OPERATOR_ONLY: "operator_only"}
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
@@ -101,6 +101,7 @@ def lib():
         L.amg_solve.argtypes = [V, V, V, C.POINTER(AmgSolveInfo)]
         L.amg_solve_bicgstab.argtypes = [V, V, V, C.POINTER(AmgSolveInfo)]
         L.amg_vcycle.argtypes = [V, V, V]
+        L.amg_apply_operator.argtypes = [V, V, V]
         L.amg_destroy.argtypes = [V]
         L.amg_last_error.argtypes = [V]
         L.amg_last_error.restype = C.c_char_p
@@ -248,6 +249,14 @@ class AMG:
         info = AmgSolveInfo()
         self._check(lib().amg_solve_bicgstab(self.ctx, _ptr(f), _ptr(u), C.byref(info)))
         return u, dict(iters=info.iters, converged=bool(info.converged), rel_res_true=info.rel_res_true)
+
+    def apply_operator(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        """y = A x by the level-0 Krylov SpMV kernel (asynchronous on the stream)."""
+        _dev(x, torch.float64, "x")
+        y = torch.empty_like(x) if y is None else y
+        _dev(y, torch.float64, "y")
+        self._check(lib().amg_apply_operator(self.ctx, _ptr(x), _ptr(y)))
+        return y
 
     def vcycle(self, r: torch.Tensor) -> torch.Tensor:
         _dev(r, torch.float64, "r")

@@ -1701,6 +1701,24 @@ amg_status amg_solve_bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_
     return st;
 }
 
+amg_status amg_apply_operator(amg_ctx* c, const double* x, double* y) {
+    if (!c || !x || !y || x == y) return AMG_ERR_ARG;
+    return guard(c, [&] {
+        // the CG's Krylov SpMV in its first-iteration form (p = z = x, q = y); its p copy
+        // goes to the CG's second direction vector, its p.q partials are not read
+        const Level& L0 = c->lv[0];
+        const int n = L0.A.nrows;
+        double* w = c->pb;
+        if (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
+            launch_dia_cg_pq(n, c->dia, x, x, w, y, 1, c->rs, c->stream);
+        else if (c->prm.block_size > 1)
+            launch_node_cg_pq(L0, c->prm.block_size, c->outer_val, x, x, w, y, 1, c->rs, c->stream);
+        else
+            launch_cg_pq(L0.A, c->outer_val, x, x, w, y, 1, c->rs, c->stream);
+        return AMG_OK;
+    });
+}
+
 amg_status amg_vcycle(amg_ctx* c, const double* r, double* z) {
     if (!c || !r || !z) return AMG_ERR_ARG;
     return guard(c, [&] {
