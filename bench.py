@@ -330,12 +330,17 @@ def main():
     # live measurement over the timed region
     pq_ms, pq_cnt = kt.get(spmv_cls, (0.0, 0))
     n_solves = K
+    block = cfg.get("block_size", 1) > 1
     if bicg:
         spmv_bytes = pq_cnt * kb["krylov_spmv"]
+    elif block:  # the product after its own direction update: p read, q written
+        spmv_bytes = pq_cnt * (kb["cg_pq"] - 16 * n)
     else:
         spmv_bytes = pq_cnt * kb["cg_pq"] - n_solves * 8 * n  # first iteration reads no p_old
     spmv_gbs = spmv_bytes / (pq_ms * 1e-3) / 1e9 if pq_ms > 0 else None
-    spmv_first_bytes = kb["cg_pq"] - 8 * n  # the CG's kernel on its first iteration reads no p_old
+    # y = A x as the CG's first iteration forms it: no p_old read (block systems: the
+    # direction update and the product together)
+    spmv_first_bytes = kb["cg_pq"] - 8 * n
     first_kernel = pq_kernel if not pq_kernel.startswith("k_rb") else "k_cg_pq"
     g_ms = kt.get("galerkin_ap", (0.0, 0))[0] + kt.get("galerkin_rap", (0.0, 0))[0]
     g_cnt = kt.get("galerkin_rap", (0.0, 0))[1]
@@ -408,8 +413,9 @@ def main():
         "spmv_gbs": spmv_gbs,
         "rap_gbs": rap_gbs,
         "dominant_kernel": dom,
-        "roofline": roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, level 0)"
-                                      if bicg else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
+        "roofline": roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, level 0)" if bicg
+                                      else " (Krylov operator SpMV q = A p and p.q after the direction update, level 0)"
+                                      if block else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
                          pq_ms, pq_cnt,
                          spmv_bytes / pq_cnt if pq_cnt else 0,
                          pq_traffic if (N == cfg["N"] and cfg_id in (2, 7) and pq_traffic is not None

@@ -207,29 +207,34 @@ __global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restr
     }
 }
 
-// p_new = z + beta p_old (z on the first iteration), q = A p_new, p_new.q partials (FP64).
-// Neighbours' p_new entries are formed with the same fma as the owner row, so q is A
-// applied to exactly the stored p_new.  Bounded grid, nodes by grid stride: one partial
-// per workgroup, in a fixed order.
+// p_new = z + beta p_old (z on the first iteration), elementwise.  The fma is the one the
+// CG kernels of scalar systems use for the same update.
+__global__ __launch_bounds__(TPB_B) void k_node_pupdate(int n, const double* __restrict__ z,
+                                                        const double* __restrict__ pold, double* __restrict__ pnew,
+                                                        int first, RedScratch rs) {
+    const double beta = first ? 0.0 : rs.scal()[S_BETA];
+    const int i = xcd_block() * TPB_B + threadIdx.x;
+    if (i < n) pnew[i] = first ? z[i] : __builtin_fma(beta, pold[i], z[i]);
+}
+
+// q = A p and p.q partials (FP64), p formed by k_node_pupdate: one gathered vector per
+// block column.  Bounded grid, nodes by grid stride: one partial per workgroup, in a
+// fixed order.
 template <int B>
 __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restrict__ nptr,
                                                       const int* __restrict__ ncol, const double* __restrict__ val,
-                                                      const double* __restrict__ z, const double* __restrict__ pold,
-                                                      double* __restrict__ pnew, double* __restrict__ q, int first,
+                                                      const double* __restrict__ p, double* __restrict__ q,
                                                       RedScratch rs) {
-    const double beta = first ? 0.0 : rs.scal()[S_BETA];
-    auto pv = [&](int j) { return first ? z[j] : __builtin_fma(beta, pold[j], z[j]); };
     const int lane = threadIdx.x & (NG - 1);
     double loc = 0.0;
     for (int I = blockIdx.x * NODES_PER_WG + (int)threadIdx.x / NG; I < nn; I += gridDim.x * NODES_PER_WG) {
         double s[B];
-        node_rowsums<B>(I, lane, nptr, ncol, val, pv, s);
+        node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return p[j]; }, s);
         if (lane < B) {
             const int i = I * B + lane;
-            const double pi = pv(i), qi = pick<B>(s, lane);
-            pnew[i] = pi;
+            const double qi = pick<B>(s, lane);
             q[i] = qi;
-            loc += pi * qi;
+            loc += p[i] * qi;
         }
     }
     __shared__ double sm[TPB_B / 64];
@@ -300,23 +305,27 @@ void launch_node_sweep(const Level& L, int B_, const T* m, const T* f, const T* 
     HIP_LAUNCH_CHECK();
 }
 
-// The Krylov operator product of a block system (values `val` on the pattern of A).  Like
-// the other Krylov SpMV launchers it takes the events that a kernel trace left for it, so
-// the trace times the kernel itself.
+// The Krylov operator product of a block system (values `val` on the pattern of A): the
+// direction update, then q = A p_new with the p.q partials.  Like the other Krylov SpMV
+// launchers it takes the events that a kernel trace left for it, for the product (the
+// elementwise update before it is not in them).
 int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z, const double* pold, double* pnew,
                       double* q, int first, const RedScratch& rs, hipStream_t s) {
     need_nodes(L);
-    const int nn = L.A.nrows / B_;
+    const int n = L.A.nrows, nn = n / B_;
     const int nb = std::max(1, std::min(node_grid(nn), rs.cap));
     const KernelEvents e = g_kernel_events;
     g_kernel_events = KernelEvents{};
+    k_node_pupdate<<<bgrid(n), TPB_B, 0, s>>>(n, z, pold, pnew, first, rs);
+    HIP_LAUNCH_CHECK();
+    const double* p = pnew;
     AMG_WITH_B(B_, {
         if (e.start != nullptr)
             hipExtLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, e.start, e.stop, 0, nn,
-                                  (const int*)L.nptr, (const int*)L.ncol, val, z, pold, pnew, q, first, rs);
+                                  (const int*)L.nptr, (const int*)L.ncol, val, p, q, rs);
         else
             hipLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)L.nptr,
-                               (const int*)L.ncol, val, z, pold, pnew, q, first, rs);
+                               (const int*)L.ncol, val, p, q, rs);
     });
     HIP_LAUNCH_CHECK();
     return nb;
