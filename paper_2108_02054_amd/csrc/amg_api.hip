@@ -44,6 +44,9 @@ void dfree(void* p, hipStream_t s) {
 struct Temps {
     hipStream_t s;
     std::vector<void*> v;
+    explicit Temps(hipStream_t st) : s(st) {}
+    Temps(const Temps&) = delete;
+    Temps& operator=(const Temps&) = delete;
     template <typename T>
     T* add(T* p) {
         v.push_back((void*)p);
@@ -663,7 +666,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
             if (p.block_size > 1) {
                 // nodes of B unknowns: strength and MIS-2 on the node matrix of block norms
                 const int B = p.block_size;
-                Temps tmp{s, {}};
+                Temps tmp(s);
                 Csr Nm;
                 clear_flags(c);
                 build_node_matrix(A, B, Nm, c->d_flags, c->h_flags, s);
@@ -686,7 +689,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
                 nc = run_aggregate(Nm, nstrong, ntpos, nstate, nagg, c->d_flags, c->h_flags, s) * B;
                 launch_node_expand(A, B, Nm, nstrong, nagg, strong, agg, s);
             } else {
-                Temps tmp{s, {}};
+                Temps tmp(s);
                 int32_t* tpos = tmp.make<int32_t>((size_t)A.nnz);
                 uint8_t* iso = tmp.make<uint8_t>((size_t)nl);
                 uint8_t* state = tmp.make<uint8_t>((size_t)nl);
