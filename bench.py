@@ -280,10 +280,14 @@ def main():
             amg.trace_read()
         torch.cuda.synchronize()
         ts = time.perf_counter()
+        marks = [ts]
         for t in range(W + 1, W + K + 1):
             step(t, True)
+            marks.append(time.perf_counter())  # a solve returns once it has read its last residual
         torch.cuda.synchronize()
         te = time.perf_counter()
+        per = sorted((b - a) * 1e3 for a, b in zip(marks, marks[1:]))
+        info_log["step_ms"] = {"median": per[len(per) // 2], "min": per[0], "max": per[-1]}
         kt = amg.trace_read() if trace else {}
         amg.trace([], level=0)
         return amg, (te - ts) * 1e3 / K, info_log, kt
@@ -402,6 +406,7 @@ def main():
         "rel_res_max": info_p["rel_res_max"],
         "rebuild_phase_ms": ph,
         "setup_ms_step0": info_p["setup_ms"],
+        "step_ms_spread": info_p["step_ms"],
         "copy_gbs_measured": copy_gbs,
         "krylov_spmv_first_iteration": {
             "kernel": first_kernel, "algorithmic_bytes": spmv_first_bytes,
