@@ -975,10 +975,20 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
         Trace tr(c, AMG_K_PROLONG, l);
         launch_prolong_add<T>(L.P, uc, cur, s);
     }
+    bool fused = false;
     for (int it = 0; it < p.npost; ++it) {
         T* dst = (out && it == p.npost - 1) ? out : other;
         Trace tr(c, AMG_K_JACOBI, l);
-        sweep(cur, dst);
+        if constexpr (std::is_same<T, double>::value) {
+            if (ep && dst == out) {  // the CG's r.z partials in the same pass
+                ep->nb = launch_node_sweep_rz(L, B, m, f, cur, dst, c->rs, s);
+                fused = true;
+            } else {
+                sweep(cur, dst);
+            }
+        } else {
+            sweep(cur, dst);
+        }
         if (dst == other)
             std::swap(cur, other);
         else
@@ -988,7 +998,7 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
         d2d(out, cur, (size_t)n * sizeof(T), s);
         cur = out;
     }
-    if (ep) {
+    if (ep && !fused) {
         Trace tr(c, AMG_K_CG_RZ, 0);
         ep->nb = launch_cg_rz(n, (const double*)f, (const double*)cur, c->rs, s);
     }

@@ -382,6 +382,9 @@ template <typename T>
 void launch_node_sweep(const Level& L, int B, const T* m, const T* f, const T* uin, T* uout, hipStream_t s);
 int launch_node_cg_pq(const Level& L, int B, const double* val, const double* z, const double* pold, double* pnew,
                       double* q, int first, const RedScratch& rs, hipStream_t s);
+// z = uin + M (r - A uin) on level 0 with the r.z partials; returns their count.
+int launch_node_sweep_rz(const Level& L, int B, const double* m, const double* r, const double* uin, double* z,
+                         const RedScratch& rs, hipStream_t s);
 void launch_node_expand(const Csr& A, int B, const Csr& Nm, const uint8_t* nstrong, const int32_t* nagg,
                         uint8_t* strong, int32_t* agg, hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);

@@ -207,6 +207,43 @@ __global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restr
     }
 }
 
+// The last post-sweep of a block system's level 0 with the CG's r.z partials (FP64): z =
+// uin + M (r - A uin), one partial of r.z per workgroup (the full node grid).
+template <int B>
+__global__ __launch_bounds__(TPB_B) void k_node_sweep_rz(int nn, const int* __restrict__ nptr,
+                                                         const int* __restrict__ ncol, const double* __restrict__ val,
+                                                         const double* __restrict__ m, const double* __restrict__ r,
+                                                         const double* __restrict__ uin, double* __restrict__ z,
+                                                         RedScratch rs) {
+    const int I = xcd_block() * NODES_PER_WG + (int)threadIdx.x / NG;
+    const int lane = threadIdx.x & (NG - 1);
+    double loc = 0.0;
+    if (I < nn) {
+        double s[B];
+        node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return uin[j]; }, s);
+        if (lane < B) {
+            const int i = I * B + lane;
+            const double* mi = m + (size_t)i * B;
+            double d = 0;
+#pragma unroll
+            for (int q = 0; q < B; ++q) d = d + mi[q] * (r[I * B + q] - s[q]);
+            const double zi = uin[i] + d;
+            z[i] = zi;
+            loc += r[i] * zi;
+        }
+    }
+    __shared__ double sm[TPB_B / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) loc += __shfl_xor(loc, o, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = loc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < TPB_B / 64; ++w) t += sm[w];
+        rs.region(P_RZ)[blockIdx.x] = t;
+    }
+}
+
 // p_new = z + beta p_old (z on the first iteration), elementwise.  The fma is the one the
 // CG kernels of scalar systems use for the same update.
 __global__ __launch_bounds__(TPB_B) void k_node_pupdate(int n, const double* __restrict__ z,
@@ -327,6 +364,17 @@ int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z
             hipLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)L.nptr,
                                (const int*)L.ncol, val, p, q, rs);
     });
+    HIP_LAUNCH_CHECK();
+    return nb;
+}
+
+int launch_node_sweep_rz(const Level& L, int B_, const double* m, const double* r, const double* uin, double* z,
+                         const RedScratch& rs, hipStream_t s) {
+    need_nodes(L);
+    const int nn = L.A.nrows / B_;
+    const int nb = std::max(1, node_grid(nn));
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+    AMG_WITH_B(B_, k_node_sweep_rz<B><<<nb, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.val, m, r, uin, z, rs));
     HIP_LAUNCH_CHECK();
     return nb;
 }
