@@ -1476,7 +1476,20 @@ void destroy_ctx(amg_ctx* c) {
     delete c;
 }
 
+// The hierarchy lives in the device's default stream-ordered pool.  A full setup frees and
+// allocates hundreds of MB; with the pool's default release threshold (0) that memory goes
+// back to the driver at every synchronisation and is mapped again, which made full setups
+// after other work 50-70 % slower.  The pool keeps what it has once it is set to retain.
+void retain_pool_memory() {
+    int dev = 0;
+    hipMemPool_t pool = nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
+    uint64_t keep = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+}
+
 amg_ctx* create_ctx(const amg_params& p, void* stream) {
+    retain_pool_memory();
     amg_ctx* c = new amg_ctx();
     c->prm = p;
     c->stream = (hipStream_t)stream;
