@@ -91,7 +91,10 @@ amg_status amg_params_default(amg_params* p);
 
 /* Algorithm 1 on the device.  n rows, nnz entries; row_ptr[n+1], col[nnz], val[nnz] are
  * device arrays; p is a host struct (NULL: defaults).  Synchronises the stream (coarse
- * sizes are needed on the host).  *out receives a new context on AMG_OK, NULL otherwise. */
+ * sizes are needed on the host).  *out receives a new context on AMG_OK, NULL otherwise.
+ * Device memory comes from the current device's default stream-ordered pool
+ * (hipMallocAsync on the given stream); the call sets that pool to keep freed memory
+ * (release threshold UINT64_MAX), so repeated setups reuse it instead of mapping it anew. */
 amg_status amg_setup(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr,
                      const int32_t* col, const double* val, const amg_params* p, void* hip_stream);
 
