@@ -11,9 +11,13 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
 #include <utility>
+#include <vector>
 
 #include "amg_internal.h"
 
@@ -27,17 +31,87 @@ namespace amgmi {
     throw Fail{st, std::string(hipGetErrorString(e)) + " in " + expr + " (" + file + ":" + std::to_string(line) + ")"};
 }
 
+// Freed device blocks are kept, per stream and exact size, for the next allocation of that
+// size on that stream.  A full setup allocates the same sizes in the same order every time,
+// so its temporaries and its new hierarchy come from this list rather than from the
+// driver's stream-ordered pool, whose host cost per call grew from microseconds to several
+// milliseconds once buffers that outlive a setup (the Krylov operator of a full-reuse
+// update) were interleaved with setups.  Reuse keeps the pool's stream ordering: a block
+// freed on stream s after its last use is handed out again only on s, to work enqueued
+// after that free.  At most BLOCK_CACHE_MAX bytes are kept; the rest goes back to the pool.
+namespace {
+constexpr size_t BLOCK_CACHE_MAX = (size_t)4 << 30;
+using BlockKey = std::pair<hipStream_t, size_t>;
+std::mutex g_blk_mu;
+std::unordered_map<void*, BlockKey> g_blk_live;
+std::map<BlockKey, std::vector<void*>> g_blk_free;
+size_t g_blk_cached = 0;
+}  // namespace
+
+void release_cached_blocks(hipStream_t s) {
+    std::vector<void*> out;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        for (auto it = g_blk_free.begin(); it != g_blk_free.end();) {
+            if (it->first.first == s) {
+                g_blk_cached -= it->first.second * it->second.size();
+                out.insert(out.end(), it->second.begin(), it->second.end());
+                it = g_blk_free.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    for (void* p : out) (void)hipFreeAsync(p, s);
+}
+
 void* dalloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 8;
+    const BlockKey key{s, bytes};
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        auto it = g_blk_free.find(key);
+        if (it != g_blk_free.end() && !it->second.empty()) {
+            void* p = it->second.back();
+            it->second.pop_back();
+            g_blk_cached -= bytes;
+            g_blk_live.emplace(p, key);
+            return p;
+        }
+    }
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes ? bytes : 8, s);
-    if (e == hipErrorOutOfMemory)
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e == hipErrorOutOfMemory) {  // give the kept blocks back and try once more
+        (void)hipGetLastError();
+        release_cached_blocks(s);
+        e = hipMallocAsync(&p, bytes, s);
+    }
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
         throw Fail{AMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
     if (e != hipSuccess) throw_hip(e, "hipMallocAsync", __FILE__, __LINE__);
+    std::lock_guard<std::mutex> lk(g_blk_mu);
+    g_blk_live.emplace(p, key);
     return p;
 }
 
 void dfree(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_blk_mu);
+        auto it = g_blk_live.find(p);
+        if (it != g_blk_live.end()) {
+            const BlockKey key = it->second;
+            g_blk_live.erase(it);
+            if (key.first == s && g_blk_cached + key.second <= BLOCK_CACHE_MAX) {
+                g_blk_free[key].push_back(p);
+                g_blk_cached += key.second;
+                return;
+            }
+        }
+    }
+    (void)hipFreeAsync(p, s);
 }
 
 // Temporaries of one setup step, released when the step ends or throws.
@@ -1461,6 +1535,7 @@ void destroy_ctx(amg_ctx* c) {
     for (void* p : c->own_allocs) dfree(p, s);
     dfree(c->pend_ptr, s);
     dfree(c->pend_col, s);
+    release_cached_blocks(s);
     (void)hipStreamSynchronize(s);
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->h_bi) (void)hipHostFree(c->h_bi);

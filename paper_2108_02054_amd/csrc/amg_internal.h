@@ -33,6 +33,7 @@ struct Fail {
 // ------------------------------------------------------------------ memory
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
+void release_cached_blocks(hipStream_t s);  // kept free blocks of stream s back to the pool
 
 template <typename T>
 T* dnew(size_t n, hipStream_t s) {
