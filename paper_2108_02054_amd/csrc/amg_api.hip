@@ -31,16 +31,39 @@ namespace amgmi {
     throw Fail{st, std::string(hipGetErrorString(e)) + " in " + expr + " (" + file + ":" + std::to_string(line) + ")"};
 }
 
-// Freed device blocks are kept, per stream and exact size, for the next allocation of that
-// size on that stream.  A full setup allocates the same sizes in the same order every time,
-// so its temporaries and its new hierarchy come from this list rather than from the
-// driver's stream-ordered pool, whose host cost per call grew from microseconds to several
-// milliseconds once buffers that outlive a setup (the Krylov operator of a full-reuse
-// update) were interleaved with setups.  Reuse keeps the pool's stream ordering: a block
-// freed on stream s after its last use is handed out again only on s, to work enqueued
-// after that free.  At most BLOCK_CACHE_MAX bytes are kept; the rest goes back to the pool.
+// Freed device blocks are kept, per stream and size class, for the next allocation of that
+// class on that stream.  A full setup allocates nearly the same sizes in the same order
+// every time (the coarse sizes drift a little with the aggregates), so its temporaries and
+// its new hierarchy come from this list rather than from the driver's stream-ordered pool,
+// whose host cost per call grew from microseconds to several milliseconds once buffers that
+// outlive a setup (the Krylov operator of a full-reuse update) were interleaved with
+// setups.  Reuse keeps the pool's stream ordering: a block freed on stream s after its last
+// use is handed out again only on s, to work enqueued after that free.  Size classes split
+// each power-of-two range into 8 steps (at most 12.5 % padding).  The kept blocks are
+// bounded by a sixteenth of the device's memory (at least 4 GiB): a full setup of a 128^3
+// operator frees its old hierarchy and several GB of sort keys, and a smaller bound made
+// every setup spill its blocks back to the pool and allocate them again.  When the bound
+// would be passed, the stream's kept blocks go back to the pool at once.
 namespace {
-constexpr size_t BLOCK_CACHE_MAX = (size_t)4 << 30;
+size_t cache_limit() {
+    static const size_t lim = [] {
+        size_t fr = 0, tot = 0;
+        const size_t floor = (size_t)4 << 30;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            return floor;
+        }
+        return std::max(floor, tot / 16);
+    }();
+    return lim;
+}
+
+size_t block_class(size_t b) {
+    if (b <= 4096) return (b + 255) & ~(size_t)255;
+    const int e = 63 - __builtin_clzll((unsigned long long)b);  // 2^e <= b < 2^(e+1)
+    const size_t step = (size_t)1 << (e - 3);
+    return (b + step - 1) & ~(step - 1);
+}
 using BlockKey = std::pair<hipStream_t, size_t>;
 std::mutex g_blk_mu;
 std::unordered_map<void*, BlockKey> g_blk_live;
@@ -66,7 +89,7 @@ void release_cached_blocks(hipStream_t s) {
 }
 
 void* dalloc(size_t bytes, hipStream_t s) {
-    if (bytes == 0) bytes = 8;
+    bytes = block_class(bytes ? bytes : 8);
     const BlockKey key{s, bytes};
     {
         std::lock_guard<std::mutex> lk(g_blk_mu);
@@ -98,19 +121,25 @@ void* dalloc(size_t bytes, hipStream_t s) {
 
 void dfree(void* p, hipStream_t s) {
     if (!p) return;
+    bool flush = false;
     {
         std::lock_guard<std::mutex> lk(g_blk_mu);
         auto it = g_blk_live.find(p);
         if (it != g_blk_live.end()) {
             const BlockKey key = it->second;
             g_blk_live.erase(it);
-            if (key.first == s && g_blk_cached + key.second <= BLOCK_CACHE_MAX) {
-                g_blk_free[key].push_back(p);
-                g_blk_cached += key.second;
-                return;
+            const size_t lim = cache_limit();
+            if (key.first == s && key.second <= lim) {
+                flush = g_blk_cached + key.second > lim;
+                if (!flush) {
+                    g_blk_free[key].push_back(p);
+                    g_blk_cached += key.second;
+                    return;
+                }
             }
         }
     }
+    if (flush) release_cached_blocks(s);
     (void)hipFreeAsync(p, s);
 }
 
