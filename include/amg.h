@@ -95,10 +95,11 @@ amg_status amg_params_default(amg_params* p);
  * Device memory comes from the current device's default stream-ordered pool
  * (hipMallocAsync on the given stream); the call sets that pool to keep freed memory
  * (release threshold UINT64_MAX), so repeated setups reuse it instead of mapping it anew.
- * Blocks of up to 256 MiB that the library frees are also kept, per stream and size class
- * (at most 12.5 % padding), for its next allocations on that stream, up to a sixteenth of
- * the device's memory (at least 4 GiB) over all contexts; amg_destroy returns the kept
- * blocks of its stream to the pool, and a failed allocation returns them and retries once. */
+ * Blocks that the library frees are also kept, per stream and size class (at most 12.5 %
+ * padding), for its next allocations on that stream, up to a quarter of the device's
+ * memory (at least 4 GiB) over all contexts, single blocks up to a quarter of that;
+ * amg_destroy returns the kept blocks of its stream to the pool, and a failed allocation
+ * returns them and retries once. */
 amg_status amg_setup(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr,
                      const int32_t* col, const double* val, const amg_params* p, void* hip_stream);
 

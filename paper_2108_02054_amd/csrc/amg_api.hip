@@ -34,23 +34,19 @@ namespace amgmi {
 // Freed device blocks are kept, per stream and size class, for the next allocation of that
 // class on that stream.  A full setup allocates nearly the same sizes in the same order
 // every time (the coarse sizes drift a little with the aggregates), so its temporaries and
-// its new hierarchy come from this list rather than from the driver's stream-ordered pool,
-// whose host cost per call grew from microseconds to several milliseconds once buffers that
-// outlive a setup (the Krylov operator of a full-reuse update) were interleaved with
-// setups.  Reuse keeps the pool's stream ordering: a block freed on stream s after its last
-// use is handed out again only on s, to work enqueued after that free.  Size classes split
-// each power-of-two range into 8 steps (at most 12.5 % padding).  The kept blocks are
-// bounded by a sixteenth of the device's memory (at least 4 GiB): a full setup of a 128^3
-// operator frees its old hierarchy and several GB of sort keys, and a smaller bound made
-// every setup spill its blocks back to the pool and allocate them again.  When the bound
-// would be passed, the stream's kept blocks go back to the pool at once.  Blocks above
-// BLOCK_CACHE_LARGEST (the multi-GB sort keys of large setups) are not kept: they are few,
-// so the pool's cost per call matters little for them, and keeping them tied memory the
-// pool then had to map anew for other sizes (a 160^3 27-point full-rebuild series took
-// 676 instead of 604 ms per step).
+// its new hierarchy come from this list rather than from the driver's stream-ordered pool.
+// The pool's host cost per call grew from microseconds to several milliseconds once buffers
+// that outlive a setup (the Krylov operator of a full-reuse update) were interleaved with
+// setups, and at 160^3 (27-point) its calls for the multi-GB sort keys stalled for up to
+// seconds after about ten setups.  Reuse keeps the pool's stream ordering: a block freed
+// on stream s after its last use is handed out again only on s, to work enqueued after
+// that free.  Size classes split each power-of-two range into 8 steps (at most 12.5 %
+// padding).  The kept blocks are bounded by a quarter of the device's memory (at least
+// 4 GiB), blocks above a quarter of that bound are never kept, and when the bound would be
+// passed the stream's kept blocks go back to the pool at once.  Smaller bounds (4 GiB, then
+// a sixteenth of the memory) were passed by the working set of a full setup (the old
+// hierarchy plus the sort keys), which then spilled and refilled at every setup.
 namespace {
-constexpr size_t BLOCK_CACHE_LARGEST = (size_t)256 << 20;
-
 size_t cache_limit() {
     static const size_t lim = [] {
         size_t fr = 0, tot = 0;
@@ -59,7 +55,7 @@ size_t cache_limit() {
             (void)hipGetLastError();
             return floor;
         }
-        return std::max(floor, tot / 16);
+        return std::max(floor, tot / 4);
     }();
     return lim;
 }
@@ -95,7 +91,7 @@ void release_cached_blocks(hipStream_t s) {
 }
 
 void* dalloc(size_t bytes, hipStream_t s) {
-    const bool keep = bytes <= BLOCK_CACHE_LARGEST;  // larger: straight from the pool
+    const bool keep = bytes <= cache_limit() / 4;  // larger: straight from the pool
     if (keep) bytes = block_class(bytes ? bytes : 8);
     const BlockKey key{s, bytes};
     if (keep) {
