@@ -21,8 +21,15 @@
  *  - All device work is enqueued on the HIP stream given to amg_setup (NULL: the null
  *    stream).  The caller's buffers must be ready on that stream.
  *  - Every call returns an amg_status and never throws across the interface.  After a
- *    HIP runtime error the context is unusable: later calls return AMG_ERR_STATE until
- *    amg_destroy.  amg_last_error() describes the last failure of a context.
+ *    HIP runtime error, and after any failure of a call that replaces the hierarchy (a full
+ *    rebuild, AMG_FULL or a size change; a pattern change), the context is unusable: every
+ *    later call on it returns AMG_ERR_STATE, and only amg_last_error and amg_destroy
+ *    remain.  Other failures (invalid arguments, a CG breakdown, a failed allocation before
+ *    anything changed) leave the context as it was.  amg_last_error() describes the last
+ *    failure of a context.
+ *  - Device memory: from the caller's allocator when amg_params.alloc/dealloc are set
+ *    (e.g. PyTorch's caching allocator), else from a stream-ordered pool private to the
+ *    context (see amg_setup).
  */
 #ifndef AMGMI_AMG_H
 #define AMGMI_AMG_H
@@ -44,7 +51,7 @@ typedef enum {
     AMG_ERR_PATTERN = -4,   /* pattern not structurally symmetric, or changed unexpectedly */
     AMG_ERR_NOT_SPD = -5,   /* non-positive diagonal or coarse pivot */
     AMG_ERR_BREAKDOWN = -6, /* CG breakdown: p.Ap <= 0 or a non-finite scalar */
-    AMG_ERR_STATE = -7      /* context unusable after an earlier HIP error */
+    AMG_ERR_STATE = -7      /* context unusable after an earlier HIP error or failed replacement */
 } amg_status;
 
 /* How amg_rebuild_ex updates the hierarchy for new matrix values (same pattern). */
@@ -78,6 +85,17 @@ typedef struct {
                            * breakdown of the next solve).  Needs aggregation = 1, smoother =
                            * 0, flexible_cg = 0 and n divisible by B (AMG_ERR_ARG otherwise);
                            * a matrix without full blocks gives AMG_ERR_PATTERN. */
+    /* Device allocator of the context (both NULL, the default: the library's own).  alloc
+     * returns a block of at least `bytes` bytes usable by work enqueued on `stream` (the
+     * context's stream) after the call, or NULL when it has none (the call then fails with
+     * AMG_ERR_OOM); dealloc receives each block back with the size asked for, once the
+     * library has enqueued its last use of it on `stream` (stream-ordered: the block may be
+     * reused by later work on that stream, not by other streams before it completes).
+     * user is passed through.  Called only from the thread that called the library; both
+     * must be set or both NULL (AMG_ERR_ARG). */
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*dealloc)(void* ptr, size_t bytes, void* stream, void* user);
+    void* alloc_user;
 } amg_params;
 
 typedef struct {          /* host struct filled by amg_solve */
@@ -92,14 +110,15 @@ amg_status amg_params_default(amg_params* p);
 /* Algorithm 1 on the device.  n rows, nnz entries; row_ptr[n+1], col[nnz], val[nnz] are
  * device arrays; p is a host struct (NULL: defaults).  Synchronises the stream (coarse
  * sizes are needed on the host).  *out receives a new context on AMG_OK, NULL otherwise.
- * Device memory comes from the current device's default stream-ordered pool
- * (hipMallocAsync on the given stream); the call sets that pool to keep freed memory
- * (release threshold UINT64_MAX), so repeated setups reuse it instead of mapping it anew.
- * Blocks that the library frees are also kept, per stream and size class (at most 12.5 %
- * padding), for its next allocations on that stream, up to a quarter of the device's
- * memory (at least 4 GiB) over all contexts, single blocks up to a quarter of that;
- * amg_destroy returns the kept blocks of its stream to the pool, and a failed allocation
- * returns them and retries once. */
+ * Device memory: with p->alloc set, every block comes from the caller's allocator.
+ * Otherwise the context creates a stream-ordered pool of its own on the current device
+ * (hipMemPoolCreate; it keeps freed memory, release threshold UINT64_MAX, so repeated
+ * setups reuse it instead of mapping it anew; no other pool is changed) and keeps the
+ * blocks it frees, per size class (at most 12.5 % padding), for its next allocations; the
+ * kept blocks never exceed the context's own peak of live device memory.  A failed
+ * allocation hands back the kept blocks of this context, then of every context of the
+ * library, trims their pools and retries.  amg_destroy frees everything and destroys the
+ * pool. */
 amg_status amg_setup(amg_ctx** out, int32_t n, int64_t nnz, const int32_t* row_ptr,
                      const int32_t* col, const double* val, const amg_params* p, void* hip_stream);
 
@@ -121,7 +140,13 @@ amg_status amg_setup_transfer(amg_ctx** out, int32_t n, int64_t nnz, const int32
  * (a size change, Section 3).  Non-zero without a pending pattern returns AMG_ERR_ARG. */
 amg_status amg_rebuild(amg_ctx* c, const double* val, int pattern_changed);
 
-/* Register a new pattern (device arrays) for the next amg_rebuild(..., 1). */
+/* Register a new pattern (device arrays, n rows, nnz entries, borrowed for the call and
+ * copied) for the next amg_rebuild(..., 1).  Section 3 notes that the pattern of
+ * discretised PDE matrices seldom changes between steps and that a change of size (e.g. by
+ * adaptive remeshing) needs a full rebuild; with the same n this library keeps the transfer
+ * operators and recomputes only the Galerkin patterns.  Nothing is checked or changed until
+ * that rebuild (which validates the pattern).  Errors: AMG_ERR_ARG for a NULL context or
+ * array, n <= 0, nnz <= 0 or nnz >= 2^31; AMG_ERR_OOM. */
 amg_status amg_set_pattern(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* row_ptr,
                            const int32_t* col);
 
@@ -154,8 +179,9 @@ amg_status amg_policy_pick(const amg_policy* p, int updates, int iters_ref, int 
  * NULL) receives m.  Errors: those of amg_policy_pick and amg_rebuild_ex. */
 amg_status amg_rebuild_auto(amg_ctx* c, const double* val, const amg_policy* p, amg_rebuild_mode* taken);
 
-/* CG preconditioned by one V-cycle per iteration.  f[n] (device, read), u[n] (device,
- * in: initial guess, out: solution).  info (host) may be NULL.  Returns after convergence
+/* CG preconditioned by one V-cycle per iteration (the V-cycle of Algorithm 2 used as the
+ * preconditioner of a Krylov method, last paragraph of Section 2).  f[n] (device, read),
+ * u[n] (device, in: initial guess, out: solution).  info (host) may be NULL.  Returns after convergence
  * or maxiter: one 16-byte device-to-host read per iteration decides the stop.  Not
  * converging is not an error (info->converged = 0). */
 amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* info);
@@ -170,7 +196,9 @@ amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* inf
  * positive elimination pivots (diagonally dominant M-matrices have them). */
 amg_status amg_solve_bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info);
 
-/* One V-cycle z = B r from a zero initial guess (r, z: device, n entries). */
+/* One V-cycle z = B r from a zero initial guess (Algorithm 2: pre-smoothing, restriction,
+ * recursion, the coarsest direct solve, prolongation, post-smoothing; r, z: device, n
+ * entries, z overwritten; asynchronous on the stream).  AMG_ERR_ARG for NULL arguments. */
 amg_status amg_vcycle(amg_ctx* c, const double* r, double* z);
 
 /* y = A x with the Krylov operator (the values of the last update, pattern of level 0),
@@ -180,6 +208,10 @@ amg_status amg_vcycle(amg_ctx* c, const double* r, double* z);
  * NULL or aliased arguments. */
 amg_status amg_apply_operator(amg_ctx* c, const double* x, double* y);
 
+/* Release the context: waits for its stream, frees all its device memory (to the caller's
+ * allocator, or by destroying its private pool), its pinned host buffers and events.
+ * Valid on a broken context.  AMG_ERR_ARG for NULL.  (Not a step of the paper; the end of
+ * the time loop of Algorithms 3 and 4.) */
 amg_status amg_destroy(amg_ctx* c);
 
 /* Description of the last failure of c (or of the last failed amg_setup when c is NULL). */

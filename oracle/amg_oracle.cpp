@@ -12,7 +12,8 @@
  *   - Algorithm 2 (V-cycle), used once per Krylov iteration as the preconditioner
  *     (Section 2, last paragraph).
  *   - Algorithm 3 (full reuse: the hierarchy is left as built) and Algorithm 4 (partial
- *     reuse: P_l, R_l kept; smoothers, Galerkin operators and the coarse solver rebuilt).
+ *     reuse: P_l, R_l kept; smoothers, Galerkin operators and the coarse solver rebuilt),
+ *     and the choice between them and a full rebuild from the solves so far (Section 3).
  * The transfer operators are smoothed aggregation (Vanek, Mandel, Brezina 1996); the
  * paper's own runs use plain aggregation, available here as an option; for its systems
  * with 4x4 blocks (Section 4) the nodes are aggregated (block_size unknowns per node share
@@ -648,6 +649,16 @@ struct Level {
     std::vector<double> u, f, r, t;  // V-cycle work vectors
 };
 
+/* What the rebuild policy looks at (Section 3): updates since the last full build, the
+ * iterations of the first solve after it (0: none yet), the last solve's iterations (0:
+ * none yet; a solve that needed none counts as one) and whether it converged. */
+struct History {
+    int updates = 0;
+    int iters_ref = 0;
+    int last_iters = 0;
+    int last_converged = 0;
+};
+
 struct Hierarchy {
     ora_params prm{};
     std::vector<Level> lv;
@@ -655,6 +666,7 @@ struct Hierarchy {
     std::vector<double> L;  // Cholesky factor of the coarsest operator, or its packed LU
     bool coarse_lu = false; // A_0 is not symmetric: L holds the coarsest operator's L U
     bool transfer_given = false;
+    History hist;
 };
 
 const int kMaxDense = 8192;
@@ -684,6 +696,7 @@ int finish_levels(Hierarchy& h) {
 
 /* Algorithm 1: build the hierarchy from A. */
 int setup(Hierarchy& h, const Csr& A0) {
+    h.hist = History{};
     h.lv.clear();
     h.lv.emplace_back();
     h.lv[0].A = A0;
@@ -997,6 +1010,32 @@ void neighbours7(int nx, int ny, int nz, int64_t c, int64_t nb[6], int& cnt) {
 
 }  // namespace
 
+/* ------------------------------------------------------------------ rebuild policy */
+
+enum { MODE_PARTIAL = 0, MODE_FULL = 1, MODE_OPERATOR_ONLY = 2 };
+
+/* Which update the next time step gets.  Algorithm 3 (full reuse) keeps the hierarchy
+ * while the last solve converged within the iteration limit and rebuilds it otherwise.
+ * Section 3 lets partial reuse rebuild from time to time as well: regularly, as the every-th
+ * update after the last full build, or on a convergence criterion, here the last solve
+ * needing more than growth times the iterations of the first solve after that build.
+ * base is the update used when nothing asks for a rebuild (partial or operator only). */
+int policy_mode(int base, int every, double growth, const History& hs) {
+    if (base == MODE_OPERATOR_ONLY && hs.last_iters > 0 && !hs.last_converged) return MODE_FULL;
+    if (every > 0 && hs.updates + 1 >= every) return MODE_FULL;
+    if (growth > 0.0 && hs.iters_ref > 0 && hs.last_iters > 0 && (double)hs.last_iters > growth * (double)hs.iters_ref)
+        return MODE_FULL;
+    return base;
+}
+
+/* The solve's outcome enters the history (a failed solve counts as maxiter, unconverged). */
+void record_solve(Hierarchy& h, int status, const ora_info& info) {
+    History& hs = h.hist;
+    hs.last_iters = status == ORA_OK ? std::max(info.iters, 1) : std::max(h.prm.maxiter, 1);
+    hs.last_converged = status == ORA_OK ? info.converged : 0;
+    if (hs.iters_ref == 0 && status == ORA_OK) hs.iters_ref = hs.last_iters;
+}
+
 /* =============================================================== exported interface */
 extern "C" {
 
@@ -1114,15 +1153,20 @@ int ora_rebuild(void* hp, const double* val, int mode) {
     Hierarchy* h = (Hierarchy*)hp;
     if (!h || !val) return fail(ORA_ERR_ARG, "bad argument");
     try {
-        if (mode == 0) return partial_rebuild(*h, val);
-        if (mode == 1) {
+        if (mode == MODE_PARTIAL) {
+            int st = partial_rebuild(*h, val);
+            if (st == ORA_OK) ++h->hist.updates;
+            return st;
+        }
+        if (mode == MODE_FULL) {
             if (h->transfer_given) return fail(ORA_ERR_ARG, "full rebuild of a prescribed-transfer hierarchy");
             Csr A = h->A_outer;
             std::copy(val, val + A.nnz(), A.val.begin());
             return setup(*h, A);
         }
-        if (mode == 2) {
+        if (mode == MODE_OPERATOR_ONLY) {
             std::copy(val, val + h->A_outer.nnz(), h->A_outer.val.begin());
+            ++h->hist.updates;
             return ORA_OK;
         }
     } catch (const std::bad_alloc&) {
@@ -1131,16 +1175,31 @@ int ora_rebuild(void* hp, const double* val, int mode) {
     return fail(ORA_ERR_ARG, "unknown rebuild mode");
 }
 
+/* The update the rebuild policy (base, every, growth; see policy_mode) picks from h's
+ * history, applied with new values; *taken receives the mode. */
+int ora_rebuild_auto(void* hp, const double* val, int base, int every, double growth, int* taken) {
+    Hierarchy* h = (Hierarchy*)hp;
+    if (!h || !val || (base != MODE_PARTIAL && base != MODE_OPERATOR_ONLY) || every < 0 || !(growth >= 0.0))
+        return fail(ORA_ERR_ARG, "bad argument");
+    const int m = policy_mode(base, every, growth, h->hist);
+    if (taken) *taken = m;
+    return ora_rebuild(hp, val, m);
+}
+
 int ora_solve(void* hp, const double* f, double* u, ora_info* info) {
     Hierarchy* h = (Hierarchy*)hp;
     if (!h || !f || !u || !info) return fail(ORA_ERR_ARG, "bad argument");
-    return pcg(*h, f, u, info);
+    int st = pcg(*h, f, u, info);
+    record_solve(*h, st, *info);
+    return st;
 }
 
 int ora_solve_bicgstab(void* hp, const double* f, double* u, ora_info* info) {
     Hierarchy* h = (Hierarchy*)hp;
     if (!h || !f || !u || !info) return fail(ORA_ERR_ARG, "bad argument");
-    return bicgstab(*h, f, u, info);
+    int st = bicgstab(*h, f, u, info);
+    record_solve(*h, st, *info);
+    return st;
 }
 
 int ora_vcycle(void* hp, const double* r, double* z) {

@@ -75,6 +75,7 @@ def lib():
                                          C.POINTER(pi32), C.POINTER(pi32), C.POINTER(pd), pi32,
                                          C.POINTER(OracleParams)]
         L.ora_rebuild.argtypes = [P, pd, C.c_int]
+        L.ora_rebuild_auto.argtypes = [P, pd, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int)]
         L.ora_solve.argtypes = [P, pd, pd, C.POINTER(OracleInfo)]
         L.ora_solve_bicgstab.argtypes = [P, pd, pd, C.POINTER(OracleInfo)]
         L.ora_vcycle.argtypes = [P, pd, pd]
@@ -200,6 +201,15 @@ class OracleHierarchy:
     def rebuild(self, val, mode: int = 0):
         val = np.ascontiguousarray(val, dtype=np.float64)
         _check(lib().ora_rebuild(self.h, _p(val, C.c_double), int(mode)))
+
+    def rebuild_auto(self, val, base: int = 0, every: int = 0, growth: float = 0.0) -> int:
+        """The update the rebuild policy picks from this hierarchy's history, applied; returns
+        the mode taken (0 partial, 1 full, 2 operator only)."""
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        m = C.c_int(-1)
+        _check(lib().ora_rebuild_auto(self.h, _p(val, C.c_double), int(base), int(every), float(growth),
+                                      C.byref(m)))
+        return m.value
 
     def solve(self, f, u=None):
         f = np.ascontiguousarray(f, dtype=np.float64)

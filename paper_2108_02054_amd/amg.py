@@ -39,6 +39,31 @@ class AmgError(RuntimeError):
         self.code = code
 
 
+# amg_params.alloc / dealloc: the device allocator a context takes its memory from
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, user):
+    """A block from PyTorch's caching allocator on the context's stream (user: the device
+    index); NULL when it has none, which the library reports as AMG_ERR_OOM."""
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(user or 0), stream=int(stream or 0))
+    except Exception:  # out of memory: the library raises its own error
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, user):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:  # interpreter shutdown: torch already torn down
+        pass
+
+
+_TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+_TORCH_FREE = FREE_FN(_torch_free)
+
+
 class AmgParams(C.Structure):
     _fields_ = [
         ("smoother", C.c_int),
@@ -54,6 +79,9 @@ class AmgParams(C.Structure):
         ("maxiter", C.c_int),
         ("flexible_cg", C.c_int),
         ("block_size", C.c_int),
+        ("alloc", ALLOC_FN),
+        ("dealloc", FREE_FN),
+        ("alloc_user", C.c_void_p),
     ]
 
 
@@ -152,9 +180,15 @@ def _ptr(t):
 
 
 class AMG:
-    """A device-resident AMG hierarchy for a series of matrices with one pattern."""
+    """A device-resident AMG hierarchy for a series of matrices with one pattern.
 
-    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, transfer=None, **params):
+    allocator="torch" (the default) gives the library PyTorch's caching allocator for all
+    its device memory (torch.cuda.memory_allocated() then counts the hierarchy);
+    allocator="library" lets it use a stream-ordered pool of its own; a tuple (ALLOC_FN,
+    FREE_FN[, user]) passes the caller's own callbacks."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, transfer=None,
+                 allocator: str = "torch", **params):
         _dev(row_ptr, torch.int32, "row_ptr")
         _dev(col, torch.int32, "col")
         _dev(val, torch.float64, "val")
@@ -163,6 +197,16 @@ class AMG:
         if val.numel() != self.nnz:
             raise ValueError("val and col lengths differ")
         self.params = default_params(**params)
+        if allocator == "torch":
+            self.params.alloc = _TORCH_ALLOC
+            self.params.dealloc = _TORCH_FREE
+            self.params.alloc_user = C.c_void_p(val.device.index or 0)
+        elif isinstance(allocator, tuple):  # (ALLOC_FN, FREE_FN[, user]) of the caller's
+            self.params.alloc, self.params.dealloc = allocator[0], allocator[1]
+            self.params.alloc_user = C.c_void_p(allocator[2] if len(allocator) > 2 else None)
+        elif allocator != "library":
+            raise ValueError(f"allocator must be 'torch', 'library' or (alloc, dealloc), not {allocator!r}")
+        self.allocator = allocator
         self.device = val.device
         self._stream = _stream()
         ctx = C.c_void_p()

@@ -31,34 +31,13 @@ namespace amgmi {
     throw Fail{st, std::string(hipGetErrorString(e)) + " in " + expr + " (" + file + ":" + std::to_string(line) + ")"};
 }
 
-// Freed device blocks are kept, per stream and size class, for the next allocation of that
-// class on that stream.  A full setup allocates nearly the same sizes in the same order
-// every time (the coarse sizes drift a little with the aggregates), so its temporaries and
-// its new hierarchy come from this list rather than from the driver's stream-ordered pool.
-// The pool's host cost per call grew from microseconds to several milliseconds once buffers
-// that outlive a setup (the Krylov operator of a full-reuse update) were interleaved with
-// setups, and at 160^3 (27-point) its calls for the multi-GB sort keys stalled for up to
-// seconds after about ten setups.  Reuse keeps the pool's stream ordering: a block freed
-// on stream s after its last use is handed out again only on s, to work enqueued after
-// that free.  Size classes split each power-of-two range into 8 steps (at most 12.5 %
-// padding).  The kept blocks are bounded by a quarter of the device's memory (at least
-// 4 GiB), blocks above a quarter of that bound are never kept, and when the bound would be
-// passed the stream's kept blocks go back to the pool at once.  Smaller bounds (4 GiB, then
-// a sixteenth of the memory) were passed by the working set of a full setup (the old
-// hierarchy plus the sort keys), which then spilled and refilled at every setup.
 namespace {
-size_t cache_limit() {
-    static const size_t lim = [] {
-        size_t fr = 0, tot = 0;
-        const size_t floor = (size_t)4 << 30;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-            (void)hipGetLastError();
-            return floor;
-        }
-        return std::max(floor, tot / 4);
-    }();
-    return lim;
-}
+thread_local DevMem* g_mem = nullptr;
+
+// Contexts that own a private pool, so that an allocation that fails can have the kept
+// blocks of every context handed back before it gives up.
+std::mutex g_mems_mu;
+std::vector<DevMem*> g_mems;
 
 size_t block_class(size_t b) {
     if (b <= 4096) return (b + 255) & ~(size_t)255;
@@ -66,86 +45,176 @@ size_t block_class(size_t b) {
     const size_t step = (size_t)1 << (e - 3);
     return (b + step - 1) & ~(step - 1);
 }
-using BlockKey = std::pair<hipStream_t, size_t>;
-std::mutex g_blk_mu;
-std::unordered_map<void*, BlockKey> g_blk_live;
-std::map<BlockKey, std::vector<void*>> g_blk_free;
-size_t g_blk_cached = 0;
+
+// Kept blocks of m back to its pool (caller holds m.mu).
+void flush_kept(DevMem& m) {
+    for (auto& kv : m.kept)
+        for (void* p : kv.second) (void)hipFreeAsync(p, m.s);
+    m.kept.clear();
+    m.kept_bytes = 0;
+}
+
+hipError_t pool_alloc(DevMem& m, void** p, size_t bytes) {
+    return m.pool ? hipMallocFromPoolAsync(p, bytes, m.pool, m.s) : hipMallocAsync(p, bytes, m.s);
+}
+
+// After a failed allocation: the kept blocks of this context, then of every context, go
+// back to their pools and the pools release what no allocation uses.
+bool reclaim(DevMem& m, int round) {
+    if (round == 0) {
+        {
+            std::lock_guard<std::mutex> lk(m.mu);
+            flush_kept(m);
+        }
+        (void)hipStreamSynchronize(m.s);
+        if (m.pool) (void)hipMemPoolTrimTo(m.pool, 0);
+        return true;
+    }
+    if (round == 1) {
+        std::lock_guard<std::mutex> g(g_mems_mu);
+        for (DevMem* o : g_mems) {
+            if (o == &m) continue;
+            std::lock_guard<std::mutex> lk(o->mu);
+            flush_kept(*o);
+        }
+        (void)hipDeviceSynchronize();
+        for (DevMem* o : g_mems)
+            if (o->pool) (void)hipMemPoolTrimTo(o->pool, 0);
+        return true;
+    }
+    return false;
+}
 }  // namespace
 
-void release_cached_blocks(hipStream_t s) {
-    std::vector<void*> out;
-    {
-        std::lock_guard<std::mutex> lk(g_blk_mu);
-        for (auto it = g_blk_free.begin(); it != g_blk_free.end();) {
-            if (it->first.first == s) {
-                g_blk_cached -= it->first.second * it->second.size();
-                out.insert(out.end(), it->second.begin(), it->second.end());
-                it = g_blk_free.erase(it);
-            } else {
-                ++it;
-            }
-        }
+MemScope::MemScope(DevMem* m) : prev(g_mem) { g_mem = m; }
+MemScope::~MemScope() { g_mem = prev; }
+
+void mem_init(DevMem& m, hipStream_t s, void* (*a)(size_t, void*, void*), void (*f)(void*, size_t, void*, void*),
+              void* user) {
+    m.s = s;
+    m.hook_alloc = a;
+    m.hook_free = f;
+    m.hook_user = user;
+    if (a) return;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    if (hipMemPoolCreate(&m.pool, &props) != hipSuccess) {  // the default pool then, as it is
+        (void)hipGetLastError();
+        m.pool = nullptr;
+    } else {
+        uint64_t keep = UINT64_MAX;
+        HIP_CHECK(hipMemPoolSetAttribute(m.pool, hipMemPoolAttrReleaseThreshold, &keep));
     }
-    for (void* p : out) (void)hipFreeAsync(p, s);
+    std::lock_guard<std::mutex> g(g_mems_mu);
+    g_mems.push_back(&m);
+}
+
+void mem_release(DevMem& m) {
+    {
+        std::lock_guard<std::mutex> g(g_mems_mu);
+        g_mems.erase(std::remove(g_mems.begin(), g_mems.end(), &m), g_mems.end());
+    }
+    {
+        std::lock_guard<std::mutex> lk(m.mu);
+        flush_kept(m);
+        if (!m.hook_free)
+            for (auto& kv : m.live) (void)hipFreeAsync(kv.first, m.s);
+        else
+            for (auto& kv : m.live) m.hook_free(kv.first, kv.second, (void*)m.s, m.hook_user);
+        m.live.clear();
+        m.live_bytes = 0;
+    }
+    (void)hipStreamSynchronize(m.s);
+    if (m.pool) {
+        (void)hipMemPoolDestroy(m.pool);
+        m.pool = nullptr;
+    }
 }
 
 void* dalloc(size_t bytes, hipStream_t s) {
-    const bool keep = bytes <= cache_limit() / 4;  // larger: straight from the pool
-    if (keep) bytes = block_class(bytes ? bytes : 8);
-    const BlockKey key{s, bytes};
-    if (keep) {
-        std::lock_guard<std::mutex> lk(g_blk_mu);
-        auto it = g_blk_free.find(key);
-        if (it != g_blk_free.end() && !it->second.empty()) {
+    DevMem* m = g_mem;
+    if (bytes == 0) bytes = 8;
+    if (!m) {
+        void* p = nullptr;
+        hipError_t e = hipMallocAsync(&p, bytes, s);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            throw Fail{AMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+        }
+        if (e != hipSuccess) throw_hip(e, "hipMallocAsync", __FILE__, __LINE__);
+        return p;
+    }
+    if (m->hook_alloc) {
+        void* p = m->hook_alloc(bytes, (void*)m->s, m->hook_user);
+        if (!p) throw Fail{AMG_ERR_OOM, "the caller's allocator returned no block of " + std::to_string(bytes) + " bytes"};
+        std::lock_guard<std::mutex> lk(m->mu);
+        m->live.emplace(p, bytes);
+        m->live_bytes += bytes;
+        m->peak_bytes = std::max(m->peak_bytes, m->live_bytes);
+        return p;
+    }
+    bytes = block_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(m->mu);
+        auto it = m->kept.find(bytes);
+        if (it != m->kept.end() && !it->second.empty()) {
             void* p = it->second.back();
             it->second.pop_back();
-            g_blk_cached -= bytes;
-            g_blk_live.emplace(p, key);
+            m->kept_bytes -= bytes;
+            m->live.emplace(p, bytes);
+            m->live_bytes += bytes;
+            m->peak_bytes = std::max(m->peak_bytes, m->live_bytes);
             return p;
         }
     }
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e == hipErrorOutOfMemory) {  // give the kept blocks back and try once more
+    hipError_t e = pool_alloc(*m, &p, bytes);
+    for (int round = 0; e == hipErrorOutOfMemory && reclaim(*m, round); ++round) {
         (void)hipGetLastError();
-        release_cached_blocks(s);
-        e = hipMallocAsync(&p, bytes, s);
+        e = pool_alloc(*m, &p, bytes);
     }
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
         throw Fail{AMG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
     }
-    if (e != hipSuccess) throw_hip(e, "hipMallocAsync", __FILE__, __LINE__);
-    if (keep) {
-        std::lock_guard<std::mutex> lk(g_blk_mu);
-        g_blk_live.emplace(p, key);
-    }
+    if (e != hipSuccess) throw_hip(e, "hipMallocFromPoolAsync", __FILE__, __LINE__);
+    std::lock_guard<std::mutex> lk(m->mu);
+    m->live.emplace(p, bytes);
+    m->live_bytes += bytes;
+    m->peak_bytes = std::max(m->peak_bytes, m->live_bytes);
     return p;
 }
 
 void dfree(void* p, hipStream_t s) {
     if (!p) return;
-    bool flush = false;
-    {
-        std::lock_guard<std::mutex> lk(g_blk_mu);
-        auto it = g_blk_live.find(p);
-        if (it != g_blk_live.end()) {
-            const BlockKey key = it->second;
-            g_blk_live.erase(it);
-            const size_t lim = cache_limit();
-            if (key.first == s && key.second <= lim) {
-                flush = g_blk_cached + key.second > lim;
-                if (!flush) {
-                    g_blk_free[key].push_back(p);
-                    g_blk_cached += key.second;
-                    return;
-                }
-            }
-        }
+    DevMem* m = g_mem;
+    if (!m) {
+        (void)hipFreeAsync(p, s);
+        return;
     }
-    if (flush) release_cached_blocks(s);
-    (void)hipFreeAsync(p, s);
+    std::lock_guard<std::mutex> lk(m->mu);
+    auto it = m->live.find(p);
+    if (it == m->live.end()) {  // not this context's block (not expected)
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    const size_t bytes = it->second;
+    m->live.erase(it);
+    m->live_bytes -= bytes;
+    if (m->hook_free) {
+        m->hook_free(p, bytes, (void*)m->s, m->hook_user);
+        return;
+    }
+    // keep it for the next allocation of its class on this context's stream, within the
+    // context's own peak working set
+    if (m->live_bytes + m->kept_bytes + bytes > m->peak_bytes) flush_kept(*m);
+    m->kept[bytes].push_back(p);
+    m->kept_bytes += bytes;
 }
 
 // Temporaries of one setup step, released when the step ends or throws.
@@ -1556,7 +1625,8 @@ amg_status check_params(const amg_params& p) {
         p.precision > 1 || p.npre < 0 || p.npre > 16 || p.npost < 0 || p.npost > 16 || p.coarse_enough < 1 ||
         p.max_levels < 1 || p.max_levels > 64 || !(p.rtol > 0.0) || p.maxiter < 0 || !(p.eps_strong >= 0.0) ||
         !(p.jacobi_omega > 0.0) || p.block_size < 1 || p.block_size > 8 ||
-        (p.block_size > 1 && (p.aggregation != 1 || p.smoother != 0 || p.flexible_cg != 0)))
+        (p.block_size > 1 && (p.aggregation != 1 || p.smoother != 0 || p.flexible_cg != 0)) ||
+        ((p.alloc == nullptr) != (p.dealloc == nullptr)))
         return AMG_ERR_ARG;
     return AMG_OK;
 }
@@ -1565,12 +1635,14 @@ void destroy_ctx(amg_ctx* c) {
     if (!c) return;
     hipStream_t s = c->stream;
     (void)hipStreamSynchronize(s);
-    for (void* p : c->hier_allocs) dfree(p, s);
-    for (void* p : c->own_allocs) dfree(p, s);
-    dfree(c->pend_ptr, s);
-    dfree(c->pend_col, s);
-    release_cached_blocks(s);
-    (void)hipStreamSynchronize(s);
+    {
+        MemScope scope(&c->mem);
+        for (void* p : c->hier_allocs) dfree(p, s);
+        for (void* p : c->own_allocs) dfree(p, s);
+        dfree(c->pend_ptr, s);
+        dfree(c->pend_col, s);
+    }
+    mem_release(c->mem);
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->h_bi) (void)hipHostFree(c->h_bi);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
@@ -1585,24 +1657,13 @@ void destroy_ctx(amg_ctx* c) {
     delete c;
 }
 
-// The hierarchy lives in the device's default stream-ordered pool.  A full setup frees and
-// allocates hundreds of MB; with the pool's default release threshold (0) that memory goes
-// back to the driver at every synchronisation and is mapped again, which made full setups
-// after other work 50-70 % slower.  The pool keeps what it has once it is set to retain.
-void retain_pool_memory() {
-    int dev = 0;
-    hipMemPool_t pool = nullptr;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess) return;
-    uint64_t keep = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-}
-
 amg_ctx* create_ctx(const amg_params& p, void* stream) {
-    retain_pool_memory();
     amg_ctx* c = new amg_ctx();
     c->prm = p;
     c->stream = (hipStream_t)stream;
     try {
+        mem_init(c->mem, c->stream, p.alloc, p.dealloc, p.alloc_user);
+        MemScope scope(&c->mem);
         c->d_flags = oalloc<int>(c, F_COUNT);
         HIP_CHECK(hipHostMalloc((void**)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault));
         for (hipEvent_t& e : c->ev) HIP_CHECK(hipEventCreate(&e));
@@ -1614,27 +1675,42 @@ amg_ctx* create_ctx(const amg_params& p, void* stream) {
     return c;
 }
 
+// Runs f with c's device memory.  A HIP runtime error, or any failure while a full setup or
+// a pattern change was replacing the hierarchy (its old arrays may already be freed, its
+// new levels incomplete), leaves the context broken: later calls return AMG_ERR_STATE.
 template <typename F>
 amg_status guard(amg_ctx* c, F&& f) {
     if (c && c->broken) return AMG_ERR_STATE;
+    MemScope scope(c ? &c->mem : nullptr);
+    amg_status st = AMG_OK;
     try {
         return f();
     } catch (const Fail& e) {
-        if (c) {
-            c->err = e.msg;
-            if (e.st == AMG_ERR_HIP) c->broken = true;
-        } else {
-            g_setup_err = e.msg;
-        }
-        return e.st;
+        if (c) c->err = e.msg;
+        else g_setup_err = e.msg;
+        st = e.st;
     } catch (const std::bad_alloc&) {
         if (c) c->err = "host allocation failed";
-        return AMG_ERR_OOM;
+        st = AMG_ERR_OOM;
     } catch (...) {
         if (c) c->err = "unexpected exception";
-        return AMG_ERR_HIP;
+        st = AMG_ERR_HIP;
     }
+    if (c && (st == AMG_ERR_HIP || c->replacing)) {
+        c->broken = true;
+        if (c->replacing) c->err += " (while replacing the hierarchy: the context must be destroyed)";
+    }
+    return st;
 }
+
+// Marks the scope of a full setup or pattern change on an existing context.
+struct Replacing {
+    amg_ctx* c;
+    explicit Replacing(amg_ctx* cc) : c(cc) { c->replacing = true; }
+    void done() { c->replacing = false; }
+    Replacing(const Replacing&) = delete;
+    Replacing& operator=(const Replacing&) = delete;
+};
 
 }  // namespace
 
@@ -1656,6 +1732,9 @@ amg_status amg_params_default(amg_params* p) {
     p->maxiter = 100;
     p->flexible_cg = 0;
     p->block_size = 1;
+    p->alloc = nullptr;
+    p->dealloc = nullptr;
+    p->alloc_user = nullptr;
     return AMG_OK;
 }
 
@@ -1729,7 +1808,9 @@ amg_status amg_rebuild_ex(amg_ctx* c, const double* val, amg_rebuild_mode m) {
             case AMG_FULL: {
                 if (c->transfer_given) throw Fail{AMG_ERR_ARG, "full rebuild of a hierarchy with prescribed transfer operators"};
                 const Csr A = c->lv[0].A;
+                Replacing rp(c);
                 build_hierarchy(c, A.nrows, A.nnz, A.ptr, A.col, val, nullptr);
+                rp.done();
                 return AMG_OK;
             }
             case AMG_OPERATOR_ONLY: {
@@ -1780,6 +1861,7 @@ amg_status amg_rebuild(amg_ctx* c, const double* val, int pattern_changed) {
             int32_t* pc = c->pend_col;
             c->pend_ptr = c->pend_col = nullptr;
             c->pend_n = 0;
+            Replacing rp(c);
             try {
                 build_hierarchy(c, n, nnz, pp, pc, val, nullptr);
             } catch (...) {
@@ -1789,10 +1871,13 @@ amg_status amg_rebuild(amg_ctx* c, const double* val, int pattern_changed) {
             }
             dfree(pp, c->stream);
             dfree(pc, c->stream);
+            rp.done();
             return AMG_OK;
         }
+        Replacing rp(c);
         repattern(c);
         partial_any(c, val);
+        rp.done();
         return AMG_OK;
     });
 }
@@ -1872,12 +1957,14 @@ const char* amg_last_error(const amg_ctx* c) { return c ? c->err.c_str() : g_set
 
 amg_status amg_num_levels(const amg_ctx* c, int* L) {
     if (!c || !L) return AMG_ERR_ARG;
+    if (c->broken) return AMG_ERR_STATE;
     *L = (int)c->lv.size();
     return AMG_OK;
 }
 
 amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims) {
     if (!c || !dims || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
+    if (c->broken) return AMG_ERR_STATE;
     const Level& L = c->lv[(size_t)l];
     dims[0] = L.A.nrows;
     dims[1] = L.A.nnz;
@@ -1889,6 +1976,7 @@ amg_status amg_level_dims(const amg_ctx* c, int l, int64_t* dims) {
 
 amg_status amg_level_format(const amg_ctx* c, int l, int* ndiag, int* nread, int* plane) {
     if (!c || !ndiag || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
+    if (c->broken) return AMG_ERR_STATE;
     *ndiag = l == 0 ? c->dia.ndiag : 0;
     if (nread) *nread = (l == 0 && c->dia.off.sym) ? (c->dia.ndiag + 1) / 2 : *ndiag;
     if (plane) *plane = l == 0 ? c->dia.march_a : 0;

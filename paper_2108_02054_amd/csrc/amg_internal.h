@@ -7,7 +7,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "amg.h"
@@ -31,9 +34,42 @@ struct Fail {
 #define HIP_LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
 
 // ------------------------------------------------------------------ memory
+// Device memory of one context.  With the caller's allocator (amg_params.alloc/dealloc)
+// every block comes from it and goes back to it when the library frees it.  Otherwise the
+// context owns a private stream-ordered pool (hipMemPoolCreate, set to keep what it has,
+// destroyed with the context) and keeps the blocks it frees, per size class, for its next
+// allocations: a full setup allocates nearly the same sizes in the same order every time,
+// so its temporaries and its new hierarchy come from these blocks rather than from the
+// pool, whose host cost per call was measured to grow from microseconds to ~0.1 ms once
+// long-lived buffers were interleaved with setups.  The kept blocks are bounded by the
+// context's own peak of live device memory; past it they all go back to the pool.
+struct DevMem {
+    void* (*hook_alloc)(size_t, void*, void*) = nullptr;
+    void (*hook_free)(void*, size_t, void*, void*) = nullptr;
+    void* hook_user = nullptr;
+    hipStream_t s = nullptr;
+    hipMemPool_t pool = nullptr;                // private pool (no caller allocator)
+    std::unordered_map<void*, size_t> live;     // block -> bytes (the class size when kept)
+    std::map<size_t, std::vector<void*>> kept;  // freed blocks by size class
+    size_t live_bytes = 0, kept_bytes = 0, peak_bytes = 0;
+    std::mutex mu;
+};
+
+// Allocations made between the construction and destruction of a MemScope use its DevMem
+// (every entry point that takes a context opens one); outside any scope dalloc/dfree go
+// straight to hipMallocAsync/hipFreeAsync.
+struct MemScope {
+    DevMem* prev;
+    explicit MemScope(DevMem* m);
+    ~MemScope();
+    MemScope(const MemScope&) = delete;
+    MemScope& operator=(const MemScope&) = delete;
+};
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
-void release_cached_blocks(hipStream_t s);  // kept free blocks of stream s back to the pool
+void mem_init(DevMem& m, hipStream_t s, void* (*a)(size_t, void*, void*), void (*f)(void*, size_t, void*, void*),
+              void* user);
+void mem_release(DevMem& m);  // kept blocks back, stream synchronised, private pool destroyed
 
 template <typename T>
 T* dnew(size_t n, hipStream_t s) {
@@ -451,6 +487,7 @@ struct amg_ctx {
     // allocations: the hierarchy (released by a full rebuild) and the context's own
     std::vector<void*> hier_allocs;
     std::vector<void*> own_allocs;
+    amgmi::DevMem mem;            // where the device memory of this context comes from
     // phase times of the last setup / rebuild (Table 1 breakdown)
     double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool phase_pending = false;   // partial rebuild: times still to be read from ev[]
@@ -465,6 +502,9 @@ struct amg_ctx {
         hipEvent_t a, b;
     };
     std::vector<Traced> traced;
+    // set while a full setup or a pattern change replaces the hierarchy: a failure then
+    // leaves the context unusable (broken)
+    bool replacing = false;
     bool broken = false;
     std::string err;
 };

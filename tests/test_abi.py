@@ -86,3 +86,35 @@ def test_rebuild_policy_decisions():
     assert lib().amg_policy_pick(None, 0, 0, 0, 0, C.byref(m)) == -1
     assert lib().amg_policy_pick(C.byref(plain), 0, 0, 0, 0, None) == -1
     assert lib().amg_rebuild_auto(None, None, C.byref(plain), None) == -1
+
+
+def test_params_struct_layout(tmp_path):
+    """The binding's amg_params has the C struct's size and field offsets."""
+    from paper_2108_02054_amd.amg import AmgParams
+    fields = [f[0] for f in AmgParams._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "amg.h"', 'int main(void){',
+           'printf("%zu\\n", sizeof(amg_params));']
+    src += [f'printf("%zu\\n", offsetof(amg_params, {f}));' for f in fields]
+    src += ['return 0;}']
+    f = tmp_path / "layout.c"
+    f.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(f), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == C.sizeof(AmgParams)
+    assert out[1:] == [getattr(AmgParams, name).offset for name in fields]
+
+
+def test_allocator_hooks_must_come_in_pairs():
+    """alloc without dealloc is refused before any device work (the arrays are not read)."""
+    from paper_2108_02054_amd import lib
+    from paper_2108_02054_amd.amg import ALLOC_FN, AmgParams
+    L = lib()
+    p = AmgParams()
+    L.amg_params_default(C.byref(p))
+    assert not p.alloc and not p.dealloc
+    p.alloc = ALLOC_FN(lambda n, s, u: None)
+    ctx = C.c_void_p()
+    dummy = C.c_void_p(8)
+    assert L.amg_setup(C.byref(ctx), 4, 4, dummy, dummy, dummy, C.byref(p), None) == -1
+    assert not ctx.value

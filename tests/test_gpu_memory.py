@@ -1,0 +1,217 @@
+"""Device memory at the boundary and the state after failures (GPU).
+
+* PyTorch's caching allocator as the library's allocator: the hierarchy shows in
+  torch.cuda.memory_allocated() and is given back at close; results are bit for bit those
+  of the library's own pool, and match the oracle.
+* The partial update and the solve allocate nothing; a full rebuild returns every block.
+* A failure while a full setup or a pattern change replaces the hierarchy leaves the
+  context broken: every later call returns AMG_ERR_STATE (checked on the host before any
+  launch), and close still works.  Other failures leave it usable.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_util import T, both, compare_levels, rel_max
+from workloads import front_moving, rhs_uniform, two_fluid_7pt
+
+pytestmark = pytest.mark.gpu
+
+ERR_STATE = -7
+
+
+def test_torch_allocator_holds_the_hierarchy():
+    from paper_2108_02054_amd import AMG
+    N = 32
+    p, c, v = two_fluid_7pt(N, front_moving(N, 0))
+    _, _, v1 = two_fluid_7pt(N, front_moving(N, 1))
+    f = rhs_uniform(N**3, 1, 1)
+    Tp, Tc, Tv, Tv1, Tf = T(p), T(c), T(v), T(v1), T(f)
+    torch.cuda.synchronize()
+    print("case torch allocator 32^3", flush=True)
+    base = torch.cuda.memory_allocated()
+    g = AMG(Tp, Tc, Tv, allocator="torch")
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - base
+    # at least level 0's CSR copy (values + columns) and the CG vectors
+    assert held >= len(c) * 12 + 8 * N**3 * 8, held
+    g.rebuild(Tv1)
+    u, info = g.solve(Tf)
+    torch.cuda.synchronize()
+    ref = AMG(Tp, Tc, Tv, allocator="library")
+    ref.rebuild(Tv1)
+    ur, ir = ref.solve(Tf)
+    assert info["iters"] == ir["iters"]
+    assert torch.equal(u, ur)
+    for l in range(g.num_levels):
+        a, b = g.level(l), ref.level(l)
+        assert np.array_equal(a["A"][2], b["A"][2])
+    ref.close()
+    import oracle
+    o = oracle.OracleHierarchy(p, c, v)
+    o.rebuild(v1, 0)
+    compare_levels(g, o)
+    uo, io = o.solve(f)
+    assert abs(info["iters"] - io["iters"]) <= 1
+    assert rel_max(u.cpu().numpy(), uo) <= 1e-6
+    g.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+
+
+def _counting_allocator():
+    from paper_2108_02054_amd.amg import ALLOC_FN, FREE_FN
+    stats = {"alloc": 0, "free": 0, "live": {}}
+
+    def a(nbytes, stream, user):
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), device=0, stream=int(stream or 0))
+        stats["alloc"] += 1
+        stats["live"][ptr] = int(nbytes)
+        return ptr
+
+    def f(ptr, nbytes, stream, user):
+        assert stats["live"].pop(int(ptr)) == int(nbytes)
+        stats["free"] += 1
+        torch.cuda.caching_allocator_delete(int(ptr))
+    cb = (ALLOC_FN(a), FREE_FN(f))
+    return stats, cb
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_partial_update_and_solve_allocate_nothing(precision):
+    from paper_2108_02054_amd import AMG, FULL
+    N = 24
+    stats, cb = _counting_allocator()
+    p, c, v = two_fluid_7pt(N, front_moving(N, 0))
+    print(f"case counting allocator 24^3 precision {precision}", flush=True)
+    g = AMG(T(p), T(c), T(v), allocator=cb, precision=precision)
+    n_setup = stats["alloc"]
+    assert n_setup > 0 and len(stats["live"]) > 0
+    live_after_setup = dict(stats["live"])
+    for t in range(1, 4):
+        _, _, vt = two_fluid_7pt(N, front_moving(N, t))
+        g.rebuild(T(vt))
+        _, info = g.solve(T(rhs_uniform(N**3, 1, t)))
+        assert info["converged"]
+    torch.cuda.synchronize()
+    assert stats["alloc"] == n_setup and stats["free"] == 0
+    # a full rebuild gives back the old hierarchy and its temporaries
+    g.rebuild_ex(T(vt), FULL)
+    torch.cuda.synchronize()
+    assert stats["free"] > 0
+    assert sum(stats["live"].values()) == sum(live_after_setup.values())
+    g.close()
+    assert stats["live"] == {} and stats["alloc"] == stats["free"]
+
+
+def test_two_contexts_on_two_streams():
+    """Each context keeps its own blocks: two hierarchies built and updated on two streams
+    give the results each gives alone."""
+    from paper_2108_02054_amd import AMG, FULL
+    N = 20
+    p, c, v = two_fluid_7pt(N, front_moving(N, 0))
+    _, _, v1 = two_fluid_7pt(N, front_moving(N, 2))
+    f = T(rhs_uniform(N**3, 1, 2))
+    Tp, Tc, Tv, Tv1 = T(p), T(c), T(v), T(v1)
+    print("case two contexts on two streams", flush=True)
+    alone = AMG(Tp, Tc, Tv, allocator="library")
+    alone.rebuild_ex(Tv1, FULL)
+    u0, i0 = alone.solve(f)
+    alone.close()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    out = []
+    ctxs = []
+    for s in (s1, s2):
+        with torch.cuda.stream(s):
+            g = AMG(Tp, Tc, Tv, allocator="library")
+            ctxs.append(g)
+    for _ in range(2):
+        for s, g in zip((s1, s2), ctxs):
+            with torch.cuda.stream(s):
+                g.rebuild_ex(Tv1, FULL)
+    for s, g in zip((s1, s2), ctxs):
+        with torch.cuda.stream(s):
+            out.append(g.solve(f))
+    torch.cuda.synchronize()
+    for u, info in out:
+        assert info["iters"] == i0["iters"]
+        assert torch.equal(u, u0)
+    for g in ctxs:
+        g.close()
+
+
+def test_library_pool_returns_memory_at_close():
+    from paper_2108_02054_amd import AMG, FULL
+    N = 48
+    p, c, v = two_fluid_7pt(N, front_moving(N, 0))
+    Tp, Tc, Tv = T(p), T(c), T(v)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    print("case library pool 48^3", flush=True)
+    g = AMG(Tp, Tc, Tv, allocator="library")
+    for _ in range(3):
+        g.rebuild_ex(Tv, FULL)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free0 - free1 > len(c) * 12  # the hierarchy is held outside torch
+    g.close()
+    torch.cuda.synchronize()
+    free2, _ = torch.cuda.mem_get_info()
+    assert abs(free0 - free2) <= 64 << 20, (free0, free2)
+
+
+def _expect_state(fn):
+    from paper_2108_02054_amd import AmgError
+    with pytest.raises(AmgError) as e:
+        fn()
+    assert e.value.code == ERR_STATE, e.value
+
+
+@pytest.mark.parametrize("allocator", ["torch", "library"])
+def test_failed_full_rebuild_breaks_the_context(allocator):
+    from paper_2108_02054_amd import AMG, AmgError, FULL, PARTIAL
+    N = 10
+    p, c, v = two_fluid_7pt(N, 0.5)
+    f = T(rhs_uniform(N**3, 1, 0))
+    print(f"case failed full rebuild ({allocator})", flush=True)
+    g = AMG(T(p), T(c), T(v), coarse_enough=20, allocator=allocator)
+    # a failure before anything changes leaves the context usable
+    with pytest.raises(AmgError) as e:
+        g.rebuild(T(v), pattern_changed=True)
+    assert e.value.code == -1
+    _, info = g.solve(f)
+    assert info["converged"]
+    vn = v.copy()
+    vn[7] = np.nan
+    with pytest.raises(AmgError) as e:
+        g.rebuild_ex(T(vn), FULL)
+    assert e.value.code == -1
+    _expect_state(lambda: g.solve(f))
+    _expect_state(lambda: g.rebuild(T(v)))
+    _expect_state(lambda: g.rebuild_ex(T(v), PARTIAL))
+    _expect_state(lambda: g.vcycle(f))
+    _expect_state(lambda: g.num_levels)
+    _expect_state(lambda: g.level(0))
+    g.close()
+
+
+def test_failed_pattern_change_breaks_the_context():
+    from paper_2108_02054_amd import AMG, AmgError
+    N = 8
+    p, c, v = two_fluid_7pt(N, 0.5)
+    f = T(rhs_uniform(N**3, 1, 0))
+    print("case failed pattern change", flush=True)
+    g = AMG(T(p), T(c), T(v), coarse_enough=20)
+    # same n, columns of row 0 out of order: refused after the new pattern was installed
+    c2 = c.copy()
+    c2[p[0]], c2[p[0] + 1] = c2[p[0] + 1], c2[p[0]]
+    g.set_pattern(T(p), T(c2))
+    with pytest.raises(AmgError) as e:
+        g.rebuild(T(v), pattern_changed=True)
+    assert e.value.code == -1
+    _expect_state(lambda: g.solve(f))
+    _expect_state(lambda: g.rebuild(T(v)))
+    g.close()

@@ -71,3 +71,57 @@ def test_growth_and_missed_convergence_trigger_full_setups():
     _, info = g.solve(f)
     assert info["converged"]
     g.close()
+
+
+def _borderline(hist_iters, converged, ref, growth, maxiter):
+    """Whether the next decision could flip if the last solve took one iteration more or
+    less (the device and the oracle may differ by one)."""
+    if hist_iters is None:
+        return False
+    if growth > 0 and ref and abs(hist_iters - growth * ref) <= 1.0:
+        return True
+    return abs(hist_iters - maxiter) <= 1 and converged
+
+
+@pytest.mark.parametrize("base,every,growth,maxiter", [(0, 4, 0.0, 100), (0, 3, 0.0, 100), (2, 0, 0.0, 100),
+                                                       (2, 3, 0.0, 100)])
+def test_policy_series_matches_oracle(base, every, growth, maxiter):
+    """The same rebuild policy on the device and in the oracle over a 32^3 two-fluid series
+    (interface three cells per step): the same mode at every step and iterations within
+    one.  The series are chosen so that no decision is within one iteration of a threshold
+    (the growth rule, whose thresholds these series approach within one iteration, is
+    checked by the oracle's pins and the host logic)."""
+    import oracle
+    from paper_2108_02054_amd import AMG
+    from paper_2108_02054_amd.amg import policy
+    from workloads import front_moving
+
+    N = 32
+    p, c, v0 = two_fluid_7pt(N, front_moving(N, 0))
+    vals = [two_fluid_7pt(N, front_moving(N, 3 * t))[2] for t in range(12)]
+    print(f"case policy base={base} every={every} growth={growth}", flush=True)
+    g = AMG(T(p), T(c), T(v0), maxiter=maxiter)
+    o = oracle.OracleHierarchy(p, c, v0, maxiter=maxiter)
+    pol = policy(base, every=every, growth=growth)
+    last, conv, ref = None, True, None
+    compared = 0
+    modes = []
+    for t in range(1, 12):
+        if _borderline(last, conv, ref, growth, maxiter):
+            break
+        mg = g.rebuild_auto(T(vals[t]), pol)
+        mo = o.rebuild_auto(vals[t], base, every, growth)
+        assert mg == mo, (t, mg, mo)
+        f = rhs_uniform(N**3, 1, t)
+        _, ig = g.solve(T(f))
+        _, io = o.solve(f)
+        assert ig["converged"] == io["converged"], t
+        assert abs(ig["iters"] - io["iters"]) <= 1, (t, ig, io)
+        if mo == 1 or ref is None:  # the first solve after the last full build
+            ref = io["iters"]
+        last, conv = io["iters"], io["converged"]
+        modes.append(mo)
+        compared += 1
+    assert compared == 11, compared
+    assert 1 in modes
+    g.close()
