@@ -10,9 +10,13 @@ residual of 1e-8.  All inputs (values and right-hand sides of every step) are re
 in HBM before the timed region.
 
 Also measured on the same steps: full rebuild every step (Algorithm 1), full reuse
-(Algorithm 3, with a rebuild-and-retry when a solve does not converge in maxiter), the
-mixed-precision form (FP32 hierarchy under FP64 CG), per-kernel HIP-event timings, and
-the CPU oracle on a bounded sample of the same series.
+(Algorithm 3, with a rebuild-and-retry when a solve does not converge in maxiter, and as
+the paper runs it), an occasional-full-rebuild policy, the mixed-precision form (FP32
+hierarchy under FP64 CG), the setup and solve time of each strategy (the paper's Table 2
+form) and the phases of the full setup (its Table 1 form), per-kernel HIP-event timings on
+every level, the roofline of the step's dominant kernel, of the Krylov SpMV and of the
+level-0 Galerkin product, short legs of the 192^3 two-fluid and 160^3 27-point series
+(working sets beyond the 256 MB MALL), and the CPU oracle on a bounded sample.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -48,21 +52,25 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="grid size N (N^3 nodes); 0: the series' own")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-legs", action="store_true", help="skip the short 192^3 and 160^3 legs")
+    ap.add_argument("--leg-steps", type=int, default=2, help="timed steps of each short leg")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle partial steps in the CPU sample")
+    ap.add_argument("--allocator", default="torch", choices=["torch", "library"],
+                    help="device memory of the hierarchy: PyTorch's caching allocator or the library's pool")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized FP64 buffer 3 times and exit: the known-size reference "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters of the other kernels")
     return ap.parse_args()
 
 
-def workload_name(cfg_id, N, n, nnz):
+def workload_name(cfg_id, N, n, nnz, prec):
     series = {2: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               3: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               5: "27-point lognormal-coefficient Poisson (sigma 1.5) with smooth drift per step",
               6: "non-symmetric upwind convection-diffusion 7-point, flow turning 9 degrees per step",
               7: "coupled system, 4 unknowns per node in full 4x4 blocks on the 7-point node graph (two-fluid "
                  "face weights, SPD couplings turning 9 degrees per step, interface +1 cell/step)"}[cfg_id]
-    form = ("FP32 hierarchy and V-cycle under FP64 CG" if cfg_id == 5 else "FP64")
+    form = "FP32 hierarchy and V-cycle under FP64 CG" if prec == 1 else "FP64"
     krylov = "BiCGStab" if cfg_id == 6 else "PCG"
     amg = ("plain aggregation of nodes on block norms, damped block Jacobi; " if cfg_id == 7 else "")
     return (f"{series}, {N}^3 {'nodes' if cfg_id == 7 else 'cells'} (n={n}, nnz={nnz}); {amg}partial reuse "
@@ -113,7 +121,7 @@ def operator_timing(amg, n, reps=7, scrub_mib=512):
     scrub = torch.ones(scrub_mib * 131072, dtype=torch.float64, device="cuda")
     amg.apply_operator(x, y)
 
-    def once(cold, k):
+    def once(cold):
         if cold:
             scrub.sum()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -123,8 +131,8 @@ def operator_timing(amg, n, reps=7, scrub_mib=512):
         b.synchronize()
         return a.elapsed_time(b) * 1e3
 
-    hot = sorted(once(False, k) for k in range(reps))
-    cold = sorted(once(True, k) for k in range(reps))
+    hot = sorted(once(False) for _ in range(reps))
+    cold = sorted(once(True) for _ in range(reps))
     del scrub
     torch.cuda.empty_cache()
     return hot[reps // 2], cold[reps // 2]
@@ -145,85 +153,169 @@ def copy_probe(mib):
 
 # ------------------------------------------------------------------ algorithmic bytes
 
-def kernel_bytes(dims, sv_h, ndiag=0, sym=False, block=1):
-    """Algorithmic bytes per launch of the level-0 kernels: each operand read once, each
-    output written once, vector gathers counted once.  CSR: 4-byte indices; an operator
-    in diagonal storage (ndiag > 0) needs no index arrays, so its bytes are its values,
-    and with symmetric values (sym) only the main diagonal and the entries above it; an
-    operator of full block x block blocks needs one index per block and one pointer per
-    node.  sv_h is the value size of the hierarchy (8 FP64, 4 FP32); the CG kernels are
-    FP64."""
-    n, nnzA, nc, nnzP, nnzAP = dims[0]
-    nnzAc = dims[1][1]
-    ind = lambda rows, nnz: 4 * (rows + 1) + 4 * nnz  # noqa: E731
-    if ndiag > 0:
-        ind0 = lambda rows, nnz: 0  # noqa: E731
-    elif block > 1:
-        ind0 = lambda rows, nnz: 4 * (rows // block + 1) + 4 * (nnz // (block * block))  # noqa: E731
-    else:
-        ind0 = ind
-    a0 = (nnzA + n) // 2 if (ndiag > 0 and sym) else nnzA  # level-0 matrix entries read
-    b = {}
-    # Krylov operator SpMV fused with p = z + beta p and p.q: A, z, p_old read; p_new, q written
-    b["cg_pq"] = ind0(n, nnzA) + 8 * a0 + 8 * 4 * n
-    b["krylov_spmv"] = ind0(n, nnzA) + 8 * a0 + 8 * 2 * n   # y = A x: A, x read, y written
-    b["cg_update"] = 8 * 6 * n          # p, q, x, r read; x, r written
-    b["cg_rz"] = 8 * 2 * n
-    b["cg_init"] = ind(n, nnzA) + 8 * nnzA + 8 * 3 * n
-    b["smooth0_res"] = ind0(n, nnzA) + sv_h * a0 + sv_h * 4 * n   # m, f read; u, r written
-    b["jacobi"] = ind0(n, nnzA) + sv_h * a0 + sv_h * 4 * n        # m, f, u read; u' written
-    b["restrict"] = ind(nc, nnzP) + sv_h * nnzP + sv_h * (n + nc)
-    b["prolong"] = ind(n, nnzP) + sv_h * nnzP + sv_h * (nc + 2 * n)
-    b["smoother"] = ind(n, nnzA) + sv_h * nnzA + sv_h * n
-    # Galerkin product of level 0, per rebuild: A, P, R read once, A_1 written once with its
-    # cached columns read once; the A P intermediate is an implementation cost, not counted
-    rap = ind(n, nnzA) + sv_h * nnzA + 2 * (ind(n, nnzP) + sv_h * nnzP) + ind(nc, nnzAc) + sv_h * nnzAc
-    b["galerkin"] = rap
-    b["cast"] = 12 * n
-    return b
+class ByteModel:
+    """Algorithmic bytes per launch of each kernel class on each level: every operand read
+    once, every output written once, vector gathers counted once.  CSR operators count
+    their row pointers (4 B), their columns as the kernels read them (4 B, or 2 B per
+    entry plus one 4 B base per row block when the level keeps two-byte column offsets)
+    and their values (8 B FP64, 4 B FP32); an operator in diagonal storage counts its
+    values only, with symmetric values only the main and upper diagonals; an operator of
+    full B x B blocks one index per block and one pointer per node (its Krylov SpMV)."""
+
+    def __init__(self, dims, storage, ndiag=0, nread=0, block=1):
+        self.L = len(dims)
+        self.dims = dims
+        self.st = storage
+        self.ndiag = ndiag
+        self.nread = nread
+        self.block = block
+        self.s = self.st[0]["value_bytes"]
+
+    @classmethod
+    def of(cls, amg, block=1):
+        L = amg.num_levels
+        return cls([amg.dims(l) for l in range(L)], [amg.level_storage(l) for l in range(L)],
+                   amg.level_format(0), amg.diagonals_read(0), block)
+
+    def _csr(self, rows, nnz, c16, rpb, s):
+        cols = 2 * nnz + (4 * ((rows + rpb - 1) // rpb) if rpb > 0 else 0) if c16 else 4 * nnz
+        return 4 * (rows + 1) + cols + s * nnz
+
+    def a0_entries(self):
+        n, nnz = self.dims[0][0], self.dims[0][1]
+        return (nnz + n) // 2 if (self.ndiag > 0 and 0 < self.nread < self.ndiag) else nnz
+
+    def A(self, l, s=None):
+        s = self.s if s is None else s
+        n, nnz = self.dims[l][0], self.dims[l][1]
+        if l == 0 and self.ndiag > 0:
+            return s * self.a0_entries()
+        return self._csr(n, nnz, self.st[l]["A_c16"], self.st[l]["A_rpb"], s)
+
+    def P(self, l):
+        n, _, nc, nnzP, _ = self.dims[l]
+        return self._csr(n, nnzP, self.st[l]["P_c16"], self.st[l]["P_rpb"], self.s)
+
+    def R(self, l):
+        n, _, nc, nnzP, _ = self.dims[l]
+        return self._csr(nc, nnzP, self.st[l]["R_c16"], self.st[l]["R_rpb"], self.s)
+
+    def krylov_A(self):
+        """Level-0 operator as the FP64 Krylov SpMV reads it."""
+        n, nnz = self.dims[0][0], self.dims[0][1]
+        if self.ndiag > 0:
+            return 8 * self.a0_entries()
+        if self.block > 1:
+            B = self.block
+            return 4 * (n // B + 1) + 4 * (nnz // (B * B)) + 8 * nnz
+        return 4 * (n + 1) + 4 * nnz + 8 * nnz
+
+    def galerkin(self, l):
+        """A_l, P_l, R_l read once, A_{l+1} written once with its cached columns read once
+        (the A_l P_l intermediate and the cached plan are implementation costs)."""
+        n, nnzA, nc, nnzP, _ = self.dims[l]
+        nnzAc = self.dims[l + 1][1]
+        s = self.s
+        ind = lambda rows, nnz: 4 * (rows + 1) + 4 * nnz  # noqa: E731
+        return (ind(n, nnzA) + s * nnzA + 2 * (ind(n, nnzP) + s * nnzP) - 4 * (n + 1) + 4 * (nc + 1)
+                + ind(nc, nnzAc) + s * nnzAc)
+
+    def bytes(self, cls, l):
+        """Bytes per launch of class cls on level l, or None when the class has no model
+        there."""
+        s = self.s
+        n = self.dims[l][0]
+        nc = self.dims[l][2]
+        last = self.L - 1
+        if cls == "cg_pq" and l == 0:
+            if self.block > 1:   # product after its own direction update: p read, q written
+                return self.krylov_A() + 16 * n
+            return self.krylov_A() + 32 * n      # z, p_old read; p_new, q written
+        if cls == "cg_update" and l == 0:
+            if self.ndiag > 0 and s == 8:        # fused with the first sweep and its residual
+                return 8 * self.a0_entries() + 72 * n
+            return 48 * n if s == 8 else None
+        if cls == "cg_rz" and l == 0:
+            return 16 * n
+        if cls == "jacobi" and l < last:          # u' = u + m (f - A u); level 0: + r.z
+            return self.A(l) + 4 * s * n
+        if cls == "smooth0_res" and l < last:
+            # level 0: u = m f and r = f - A u; below, the restriction formed u and the
+            # kernel forms the residual (f, u read, r written)
+            return self.A(l) + (4 if l == 0 else 3) * s * n
+        if cls == "restrict" and l < last:
+            smooths = (l + 2 < self.L) and not self.st[l + 1]["tail"]
+            return self.R(l) + s * n + s * nc + (2 * s * nc if smooths else 0)
+        if cls == "prolong" and l < last:
+            return self.P(l) + s * nc + 2 * s * n
+        if cls == "coarse_gemv" and l == last:
+            return 8 * n * n + 2 * s * n
+        return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: runs on several GPUs "
-              f"(row-block sharding of every level) are not implemented.", file=sys.stderr)
-        sys.exit(2)
+def roof(name, ms, launches, alg_bytes_total, traffic_rec=None):
+    """Roofline record of one kernel from its live HIP-event timing: algorithmic bytes per
+    launch over the average launch duration; traffic = measured HBM bytes per launch
+    (FETCH_SIZE + WRITE_SIZE, scaled by a known-size copy) when the stored counters were
+    taken on the current kernel source, else null."""
+    avg_us = ms * 1e3 / launches if launches else None
+    per = alg_bytes_total / launches if launches else 0.0
+    achieved = per / (avg_us * 1e-6) / 1e9 if avg_us else None
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic_rec["traffic_bytes_per_launch"] if traffic_rec else None,
+            "algorithmic_bytes": per, "avg_launch_us": avg_us, "launches": launches,
+            "traffic_source": (f"profiles/{os.path.basename(traffic_rec['_path'])}" if traffic_rec else None)}
 
-    if args.copy_probe > 0:
-        copy_probe(args.copy_probe)
-        return
 
-    import numpy as np
+def kernel_names(cls, bm, plane, block):
+    """The kernels a class launches in the configurations measured here (level 0, then below)."""
+    lv0 = {"cg_pq": "k_m7_cg_pq" if plane else ("k_w_cg_pq/k_dia_cg_pq" if bm.ndiag else
+                                                   ("k_node_cg_pq" if block > 1 else "k_cg_pq")),
+           "cg_update": "k_m7_update_smooth0" if plane else "k_cg_update",
+           "jacobi": "k_m7_jacobi_rz" if plane else "k_jacobi_rz"}
+    rest = {"restrict": "k_rb_spmv (R_l)", "prolong": "k_rb_prolong_add (P_l)", "jacobi": "k_rb_jacobi",
+            "smooth0_res": "k_rb_residual / k_rb_smooth0_residual", "coarse_gemv": "k_coarse_gemv",
+            "tail": "k_vcycle_tail"}
+    return lv0.get(cls, rest.get(cls, cls))
+
+
+def load_traffic_rec(name):
+    from paper_2108_02054_amd.profiling import load_traffic
+    rec = load_traffic(os.path.join(ROOT, "profiles", name))
+    if rec is not None:
+        rec["_path"] = name
+    return rec
+
+
+# ------------------------------------------------------------------ one configuration
+
+def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mode=False):
+    import numpy as np  # noqa: F401
     import torch
 
     from paper_2108_02054_amd import AMG, FULL, OPERATOR_ONLY
-    from paper_2108_02054_amd.amg import PARTIAL, policy
+    from paper_2108_02054_amd.amg import KERNEL_CLASSES, PARTIAL, policy
+    from workloads import CONFIGS, rhs_uniform, series_matrix
+
     POLICY = policy(PARTIAL, every=10)  # an occasional full setup between partial updates (Section 3)
     # full reuse as the paper runs it: a solve that misses the iteration limit is not
     # repeated; the next update is a full setup (Algorithm 3, Section 3)
     POLICY_REUSE = policy(OPERATOR_ONLY)
-    from workloads import CONFIGS, rhs_uniform, series_matrix
-
     dev = torch.device("cuda:0")
-    cfg_id = args.config
     cfg = CONFIGS[cfg_id]
-    N = args.n or cfg["N"]
-    K, W = args.steps, args.warmup
+    head_prec = (1 if cfg_id == 5 else 0) if headline_prec is None else headline_prec
+    bicg = cfg_id == 6
+    block = cfg.get("block_size", 1)
     nsteps = W + K + 1
-    # the series' own precision for the headline line: FP64, or the FP32 hierarchy under
-    # FP64 CG for the 27-point series
-    head_prec = 1 if cfg_id == 5 else 0
-    bicg = cfg_id == 6  # the non-symmetric series: BiCGStab, the paper's Krylov method
-
-    def solve(amg, f, x):
-        return amg.solve_bicgstab(f, x) if bicg else amg.solve(f, x)
-    amg_params = dict(eps_strong=cfg["eps_strong"])
+    amg_params = dict(eps_strong=cfg["eps_strong"], allocator=args.allocator)
     for key in ("block_size", "aggregation"):
         if key in cfg:
             amg_params[key] = cfg[key]
 
-    # ---------------------------------------------------------------- inputs in HBM
+    def solve(amg, f, x):
+        return amg.solve_bicgstab(f, x) if bicg else amg.solve(f, x)
+
     t0 = time.time()
     vals, rhs = [], []
     for t in range(nsteps):
@@ -239,182 +331,211 @@ def main():
     nnz = int(col.numel())
     log(f"inputs: {nsteps} steps of {cfg['name']} at {N}^3 (n={n}, nnz={nnz}) generated and uploaded in "
         f"{time.time() - t0:.1f}s")
-
     u = torch.zeros(n, dtype=torch.float64, device=dev)
+    spmv_cls = "bicg_spmv" if bicg else "cg_pq"
 
-    def series(mode, precision=0, trace=None):
-        """Setup at t=0 (untimed), W warm-up steps, K timed steps."""
+    def series(mode, precision=0, diag=False):
+        """Setup at t=0 (untimed), W warm-up steps, optionally a per-level kernel table
+        (untimed), K timed steps with the setup and solve of each step timed apart."""
         torch.cuda.synchronize()
         t_setup = time.perf_counter()
         amg = AMG(ptr, col, vals[0], precision=precision, **amg_params)
         torch.cuda.synchronize()
-        info_log = {"iters": [], "rebuilds": 0, "converged": True, "rel_res_max": 0.0,
-                    "setup_ms": (time.perf_counter() - t_setup) * 1e3}
+        log_ = {"iters": [], "rebuilds": 0, "converged": True, "rel_res_max": 0.0, "missed": 0,
+                "setup_ms": (time.perf_counter() - t_setup) * 1e3, "phases": []}
 
-        def step(t, record):
+        def step(t, record, ev=None):
+            if ev is not None:
+                ev[0].record()
+            full = False
             if mode == "partial":
                 amg.rebuild(vals[t])
             elif mode in ("policy", "reuse_paper"):
-                pol = POLICY if mode == "policy" else POLICY_REUSE
-                if amg.rebuild_auto(vals[t], pol) == FULL and record:
-                    info_log["rebuilds"] += 1
+                full = amg.rebuild_auto(vals[t], POLICY if mode == "policy" else POLICY_REUSE) == FULL
             elif mode == "full":
                 amg.rebuild_ex(vals[t], FULL)
+                full = True
             else:
                 amg.rebuild_ex(vals[t], OPERATOR_ONLY)
+            if full and record:
+                log_["rebuilds"] += 1
+                log_["phases"].append(amg.phase_times())
+            if ev is not None:
+                ev[1].record()
             u.zero_()
             _, info = solve(amg, rhs[t], u)
             its = info["iters"]
             if mode == "reuse" and not info["converged"]:
+                if ev is not None:
+                    ev[2].record()
+                    ev[3].record()
                 amg.rebuild_ex(vals[t], FULL)
+                if ev is not None:
+                    ev[4].record()
                 u.zero_()
                 _, info = solve(amg, rhs[t], u)
                 its += info["iters"]
                 if record:
-                    info_log["rebuilds"] += 1
+                    log_["rebuilds"] += 1
+            elif ev is not None:
+                for e in ev[2:5]:
+                    e.record()
+            if ev is not None:
+                ev[5].record()
             if record:
-                info_log["iters"].append(its)
-                info_log.setdefault("missed", 0)
-                info_log["missed"] += 0 if info["converged"] else 1
+                log_["iters"].append(its)
+                log_["missed"] += 0 if info["converged"] else 1
                 if mode != "reuse_paper":  # that series misses the limit by design
-                    info_log["converged"] &= bool(info["converged"])
-                info_log["rel_res_max"] = max(info_log["rel_res_max"], info["rel_res_true"])
+                    log_["converged"] &= bool(info["converged"])
+                log_["rel_res_max"] = max(log_["rel_res_max"], info["rel_res_true"])
 
         for t in range(1, W + 1):
             step(t, False)
-        if trace:
-            amg.trace(trace, level=0)
+        kt_levels = None
+        if diag:
+            # per-level kernel table of one step (repeats step W; untimed)
+            L = amg.num_levels
+            kt_levels = [dict() for _ in range(L)]
+            for l in range(L):
+                amg.trace(KERNEL_CLASSES, level=l)
+                amg.trace_read()
+                step(max(W, 1), False)
+                got = amg.trace_read_levels()
+                kt_levels[l] = got[l]
+            amg.trace([], level=0)
+        traced = None
+        if diag:
+            tot = {}
+            for lv in kt_levels:
+                for k, (ms, _) in lv.items():
+                    tot[k] = tot.get(k, 0.0) + ms
+            dom = max((k for k in tot if k not in ("galerkin_ap", "galerkin_rap")), key=lambda k: tot[k])
+            traced = sorted({spmv_cls, "galerkin_ap", "galerkin_rap", dom})
+            amg.trace(traced, level=-1)
             amg.trace_read()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
         torch.cuda.synchronize()
         ts = time.perf_counter()
         marks = [ts]
-        for t in range(W + 1, W + K + 1):
-            step(t, True)
+        for i, t in enumerate(range(W + 1, W + K + 1)):
+            step(t, True, evs[i])
             marks.append(time.perf_counter())  # a solve returns once it has read its last residual
         torch.cuda.synchronize()
         te = time.perf_counter()
         per = sorted((b - a) * 1e3 for a, b in zip(marks, marks[1:]))
-        info_log["step_ms"] = {"median": per[len(per) // 2], "min": per[0], "max": per[-1]}
-        kt = amg.trace_read() if trace else {}
+        log_["step_ms"] = {"median": per[len(per) // 2], "min": per[0], "max": per[-1]}
+        setup_ms = sum(e[0].elapsed_time(e[1]) + e[3].elapsed_time(e[4]) for e in evs) / K
+        solve_ms = sum(e[1].elapsed_time(e[2]) + e[4].elapsed_time(e[5]) for e in evs) / K
+        log_["setup_ms_per_step"], log_["solve_ms_per_step"] = setup_ms, solve_ms
+        kt = amg.trace_read_levels() if traced else None
         amg.trace([], level=0)
-        return amg, (te - ts) * 1e3 / K, info_log, kt
+        log_["kt_levels"], log_["kt"] = kt_levels, kt
+        return amg, (te - ts) * 1e3 / K, log_
 
     # ---------------------------------------------------------------- partial reuse (headline)
-    spmv_cls = "bicg_spmv" if bicg else "cg_pq"
-    traced = [spmv_cls, "galerkin_ap", "galerkin_rap"]
-    amg, ms_partial, info_p, kt = series("partial", precision=head_prec, trace=traced)
-    L = amg.num_levels
-    dims = [amg.dims(l) for l in range(L)]
-    ndiag = amg.level_format(0)
-    nread = amg.diagonals_read(0)
+    amg, ms_partial, info_p = series("partial", precision=head_prec, diag=True)
+    bm = ByteModel.of(amg, block)
+    L = bm.L
+    dims = bm.dims
     plane = amg.march_plane(0)
+    log(f"levels: {[(d[0], d[1]) for d in dims]}")
+    log(f"partial reuse: {ms_partial:.3f} ms/step (setup {info_p['setup_ms_per_step']:.3f} + solve "
+        f"{info_p['solve_ms_per_step']:.3f}), iters {info_p['iters']}")
+    spmv_hot_us, spmv_cold_us = operator_timing(amg, n)
+    amg.close()
+    del amg
+    torch.cuda.empty_cache()
+
+    # kernel table of one partial step, per level and class
+    ktl = info_p["kt_levels"]
+    totals = {}
+    for l, lv in enumerate(ktl):
+        for k, (ms, cnt) in lv.items():
+            a = totals.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+    log("kernel time per partial step (ms, launches), all levels: "
+        + ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])))
+
+    # live records over the timed region
+    kt = info_p["kt"]
+
+    def class_live(cls, levels=None):
+        ms = cnt = 0
+        byt = 0.0
+        ok = True
+        for l in (range(L) if levels is None else levels):
+            m_, c_ = kt[l].get(cls, (0.0, 0))
+            if not c_:
+                continue
+            b = bm.bytes(cls, l)
+            if b is None:
+                ok = False
+            else:
+                byt += b * c_
+            ms += m_
+            cnt += c_
+        return ms, cnt, (byt if ok else None)
+
+    dom = max((k for k in totals if k not in ("galerkin_ap", "galerkin_rap")), key=lambda k: totals[k][0])
+    d_ms, d_cnt, d_bytes = class_live(dom)
+    pq_ms, pq_cnt, _ = class_live(spmv_cls, [0])
+    if bicg:
+        spmv_bytes = pq_cnt * (bm.krylov_A() + 16 * n)
+    elif block > 1:
+        spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0)
+    else:
+        spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0) - K * 8 * n  # first iteration reads no p_old
+    g_ms = kt[0].get("galerkin_ap", (0.0, 0))[0] + kt[0].get("galerkin_rap", (0.0, 0))[0]
+    g_cnt = kt[0].get("galerkin_rap", (0.0, 0))[1]
+    rap_all_ms = sum(kt[l].get("galerkin_ap", (0.0, 0))[0] + kt[l].get("galerkin_rap", (0.0, 0))[0]
+                     for l in range(L))
+    rap_all_bytes = sum(bm.galerkin(l) * kt[l].get("galerkin_rap", (0.0, 0))[1] for l in range(L - 1))
+
     if plane:
         pq_kernel = "k_m7_cg_pq"
-    elif ndiag:
-        pq_kernel = "k_w_cg_pq" if ndiag != 7 else "k_dia_cg_pq"
-    elif cfg.get("block_size", 1) > 1:
+    elif bm.ndiag:
+        pq_kernel = "k_w_cg_pq" if bm.ndiag != 7 else "k_dia_cg_pq"
+    elif block > 1:
         pq_kernel = "k_rb_spmv" if bicg else "k_node_cg_pq"
     else:
         pq_kernel = "k_rb_spmv" if bicg else "k_cg_pq"
-    log(f"levels: {[(d[0], d[1]) for d in dims]}")
-    log(f"partial reuse: {ms_partial:.3f} ms/step, iters {info_p['iters']}")
-    ph = amg.phase_times()
-
-    # per-kernel breakdown of one partial step on every level (diagnostic pass, not timed)
-    from paper_2108_02054_amd.amg import KERNEL_CLASSES
-    amg.trace(KERNEL_CLASSES, level=-1)
-    amg.trace_read()
-    amg.rebuild(vals[W + 1])
-    u.zero_()
-    solve(amg, rhs[W + 1], u)
-    breakdown_all = amg.trace_read()
-    amg.trace(KERNEL_CLASSES, level=0)
-    amg.rebuild(vals[W + 1])
-    u.zero_()
-    solve(amg, rhs[W + 1], u)
-    breakdown_l0 = amg.trace_read()
-    amg.trace([], level=0)
-    spmv_hot_us, spmv_cold_us = operator_timing(amg, n)
-    amg.close()
-
-    kb = kernel_bytes(dims, 8, ndiag, sym=0 < nread < ndiag, block=cfg.get("block_size", 1))
-    # live measurement over the timed region
-    pq_ms, pq_cnt = kt.get(spmv_cls, (0.0, 0))
-    n_solves = K
-    block = cfg.get("block_size", 1) > 1
-    if bicg:
-        spmv_bytes = pq_cnt * kb["krylov_spmv"]
-    elif block:  # the product after its own direction update: p read, q written
-        spmv_bytes = pq_cnt * (kb["cg_pq"] - 16 * n)
-    else:
-        spmv_bytes = pq_cnt * kb["cg_pq"] - n_solves * 8 * n  # first iteration reads no p_old
-    spmv_gbs = spmv_bytes / (pq_ms * 1e-3) / 1e9 if pq_ms > 0 else None
-    # y = A x as the CG's first iteration forms it: no p_old read (block systems: the
-    # direction update and the product together)
-    spmv_first_bytes = kb["cg_pq"] - 8 * n
     first_kernel = pq_kernel if not pq_kernel.startswith("k_rb") else "k_cg_pq"
-    g_ms = kt.get("galerkin_ap", (0.0, 0))[0] + kt.get("galerkin_rap", (0.0, 0))[0]
-    g_cnt = kt.get("galerkin_rap", (0.0, 0))[1]
-    rap_gbs = g_cnt * kb["galerkin"] / (g_ms * 1e-3) / 1e9 if g_ms > 0 else None
+    spmv_first_bytes = (bm.bytes("cg_pq", 0) - 8 * n) if not block > 1 else bm.bytes("cg_pq", 0)
 
-    copy_gbs = copy_bandwidth()
-    log(f"device copy: {copy_gbs:.0f} GB/s (read + write, 1 GiB, best of 5)")
+    work = workload_name(cfg_id, N, n, nnz, head_prec)
+    is_headline = cfg_id == 2 and N == 128 and head_prec == 0
+    dom_traffic = None
+    pq_traffic = None
+    rap_traffic = None
+    if is_headline:
+        dom_traffic = load_traffic_rec(f"{dom}_two_fluid_128_traffic.json")
+        pq_traffic = load_traffic_rec("cg_pq_two_fluid_128_traffic.json")
+        rap_traffic = load_traffic_rec("galerkin_two_fluid_128_traffic.json")
+    elif cfg_id == 7:
+        pq_traffic = load_traffic_rec("cg_pq_coupled4_56_traffic.json")
+    dom_rec = roof(f"{kernel_names(dom, bm, plane, block)}: class '{dom}', every level (the step's largest "
+                   f"kernel time)", d_ms, d_cnt, d_bytes or 0.0,
+                   dom_traffic)
+    dom_rec["per_level"] = [{"level": l, "launches": kt[l].get(dom, (0, 0))[1],
+                             "avg_us": (kt[l][dom][0] * 1e3 / kt[l][dom][1]) if kt[l].get(dom, (0, 0))[1] else None,
+                             "algorithmic_bytes": bm.bytes(dom, l)} for l in range(L) if kt[l].get(dom, (0, 0))[1]]
+    spmv_rec = roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, level 0)" if bicg
+                                 else " (Krylov operator SpMV q = A p and p.q after the direction update, level 0)"
+                                 if block > 1 else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
+                    pq_ms, pq_cnt, spmv_bytes,
+                    pq_traffic if (pq_traffic and pq_traffic["kernel"] == pq_kernel) else None)
+    rap_rec = roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
+                   g_cnt * bm.galerkin(0), rap_traffic)
 
-    # dominant kernel class of a partial step (all levels), by total time
-    dom = max(breakdown_all.items(), key=lambda kv: kv[1][0])[0] if breakdown_all else "cg_pq"
-    log("kernel time per partial step (ms, launches), all levels: "
-        + ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(breakdown_all.items(), key=lambda kv: -kv[1][0])))
-
-    def roof(name, ms, launches, alg_bytes, traffic_rec=None):
-        """Roofline record of one kernel from its live HIP-event timing: algorithmic bytes per
-        launch over the average launch duration; traffic = measured HBM bytes per launch
-        (FETCH_SIZE + WRITE_SIZE, scaled by a known-size copy) when the stored counters were
-        taken on the current kernel source, else null."""
-        avg_us = ms * 1e3 / launches if launches else None
-        achieved = alg_bytes / (avg_us * 1e-6) / 1e9 if avg_us else None
-        return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": traffic_rec["traffic_bytes_per_launch"] if traffic_rec else None,
-                "algorithmic_bytes": alg_bytes, "avg_launch_us": avg_us, "launches": launches,
-                "traffic_source": (f"profiles/{os.path.basename(traffic_rec['_path'])}" if traffic_rec else None)}
-
-    from paper_2108_02054_amd.profiling import load_traffic
-    pq_traffic = load_traffic(os.path.join(ROOT, "profiles", "cg_pq_two_fluid_128_traffic.json"))
-    if pq_traffic is not None:
-        pq_traffic["_path"] = "cg_pq_two_fluid_128_traffic.json"
-    if cfg_id == 7:
-        pq_traffic = load_traffic(os.path.join(ROOT, "profiles", "cg_pq_coupled4_56_traffic.json"))
-        if pq_traffic is not None:
-            pq_traffic["_path"] = "cg_pq_coupled4_56_traffic.json"
-    rap_traffic = load_traffic(os.path.join(ROOT, "profiles", "galerkin_two_fluid_128_traffic.json"))
-    if rap_traffic is not None:
-        rap_traffic["_path"] = "galerkin_two_fluid_128_traffic.json"
-
-    result = {
-        "metric": METRIC,
-        "value": ms_partial,
-        "unit": "ms/step",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": ms_partial,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if head_prec == 0 else "f32 hierarchy and V-cycle, f64 CG",
-        "data": "synthetic",
-        "config": {"workload": workload_name(cfg_id, N, n, nnz),
-                   "grid": N, "n": n, "nnz": nnz, "levels": L, "level_rows": [d[0] for d in dims],
-                   "level_nnz": [d[1] for d in dims], "level0_storage": ((f"{ndiag} diagonals, {nread} read per row"
-                                      + (f", marching planes of {plane} rows" if plane else "")) if ndiag else "CSR"),
-                   "parallelism": "single GPU"},
-        "iters_partial": info_p["iters"],
-        "converged_all": info_p["converged"],
-        "rel_res_max": info_p["rel_res_max"],
-        "rebuild_phase_ms": ph,
-        "setup_ms_step0": info_p["setup_ms"],
-        "step_ms_spread": info_p["step_ms"],
-        "copy_gbs_measured": copy_gbs,
+    res = {
+        "ms_partial": ms_partial, "n": n, "nnz": nnz, "work": work, "head_prec": head_prec,
+        "levels": L, "dims": dims, "ndiag": bm.ndiag, "nread": bm.nread, "plane": plane,
+        "info_p": info_p, "dom": dom, "roofline_dominant": dom_rec, "roofline_spmv": spmv_rec,
+        "roofline_rap": rap_rec,
+        "rap_all_levels": {"ms_per_rebuild": rap_all_ms / max(g_cnt, 1),
+                           "algorithmic_bytes": rap_all_bytes / max(g_cnt, 1),
+                           "frac": (rap_all_bytes / (rap_all_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if rap_all_ms else None},
         "krylov_spmv_first_iteration": {
             "kernel": first_kernel, "algorithmic_bytes": spmv_first_bytes,
             "hot_us": spmv_hot_us, "cold_us": spmv_cold_us,
@@ -422,50 +543,172 @@ def main():
             "cold_frac": spmv_first_bytes / (spmv_cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
             "note": "y = A x through amg_apply_operator (p = z, no p_old read), median of 7; cold: after a "
                     "512 MiB read that evicts L2 and the MALL"},
-        "spmv_gbs": spmv_gbs,
-        "rap_gbs": rap_gbs,
-        "dominant_kernel": dom,
-        "roofline": roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, level 0)" if bicg
-                                      else " (Krylov operator SpMV q = A p and p.q after the direction update, level 0)"
-                                      if block else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
-                         pq_ms, pq_cnt,
-                         spmv_bytes / pq_cnt if pq_cnt else 0,
-                         pq_traffic if (N == cfg["N"] and cfg_id in (2, 7) and pq_traffic is not None
-                                        and pq_traffic["kernel"] == pq_kernel) else None),
-        "roofline_rap": roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
-                             kb["galerkin"],
-                             rap_traffic if (cfg_id == 2 and N == 128 and head_prec == 0) else None),
-        "kernels_level0_ms": {k: v for k, v in breakdown_l0.items()},
-        "kernels_all_levels_ms": {k: v for k, v in breakdown_all.items()},
+        "kernels_by_level": [{k: [round(v[0], 4), v[1]] for k, v in lv.items()} for lv in ktl],
+        "kernels_all_levels_ms": {k: [round(v[0], 4), v[1]] for k, v in totals.items()},
     }
+    if not compare:
+        return res
 
     # ---------------------------------------------------------------- comparators
-    if not args.no_compare:
-        runs = {}
-        if cfg_id == 5:
-            plan = [("full", "full", 1), ("fp64_partial", "partial", 0)]
-        elif cfg_id == 3:
-            plan = [("mixed", "partial", 1), ("full", "full", 0)]
-        elif cfg_id in (6, 7):
-            plan = [("full", "full", 0), ("mixed", "partial", 1)]
-        else:
-            plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1), ("policy", "policy", 0),
-                    ("reuse_paper", "reuse_paper", 0)]
-        for name, mode, prec in plan:
-            _, ms_x, info_x, _ = series(mode, precision=prec)
-            runs[name] = (ms_x, info_x)
-            extra = f", full setups {info_x['rebuilds']}" if mode in ("reuse", "policy", "reuse_paper") else ""
-            if mode == "reuse_paper":
-                extra += f", solves past the iteration limit {info_x.get('missed', 0)}"
-            log(f"{name}: {ms_x:.3f} ms/step, iters {info_x['iters']}{extra}")
-        conv = info_p["converged"]
-        for name, (ms_x, info_x) in runs.items():
-            conv = conv and bool(info_x["converged"])
+    runs = {}
+    if legs_mode:
+        plan = [("full", "full", head_prec)] + ([("mixed", "partial", 1)] if head_prec == 0 else
+                                                [("fp64_partial", "partial", 0)])
+    elif cfg_id == 5:
+        plan = [("full", "full", 1), ("fp64_partial", "partial", 0)]
+    elif cfg_id == 3:
+        plan = [("mixed", "partial", 1), ("full", "full", 0)]
+    elif cfg_id in (6, 7):
+        plan = [("full", "full", 0), ("mixed", "partial", 1)]
+    else:
+        plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1), ("policy", "policy", 0),
+                ("reuse_paper", "reuse_paper", 0)]
+    for name, mode, prec in plan:
+        a, ms_x, info_x = series(mode, precision=prec)
+        a.close()
+        del a
+        runs[name] = (ms_x, info_x)
+        extra = f", full setups {info_x['rebuilds']}" if mode in ("reuse", "policy", "reuse_paper") else ""
+        if mode == "reuse_paper":
+            extra += f", solves past the iteration limit {info_x['missed']}"
+        log(f"{name}: {ms_x:.3f} ms/step (setup {info_x['setup_ms_per_step']:.3f} + solve "
+            f"{info_x['solve_ms_per_step']:.3f}), iters {info_x['iters']}{extra}")
+    res["runs"] = runs
+    return res
+
+
+def table1(phases):
+    """The paper's Table 1 form: share of each phase of the full setup (mean over the full
+    setups of the series; host clock between the device synchronisations of the setup)."""
+    if not phases:
+        return None
+    keys = ["aggregation", "prolongator", "symbolic", "galerkin", "smoother", "coarse", "total"]
+    mean = {k: sum(p[k] for p in phases) / len(phases) for k in keys}
+    tot = mean["total"]
+    rows = {"transfer operators (strength, aggregation, P, R = P^T)": mean["aggregation"] + mean["prolongator"],
+            "Galerkin operators (symbolic + numeric)": mean["symbolic"] + mean["galerkin"],
+            "smoothers": mean["smoother"], "coarsest solver (dense inverse)": mean["coarse"],
+            "hierarchy copied to the backend": 0.0}
+    other = tot - sum(rows.values())
+    out = {k: {"ms": v, "pct": 100.0 * v / tot} for k, v in rows.items()}
+    out["other (allocation, vectors, diagonal storage, synchronisation)"] = {"ms": other, "pct": 100.0 * other / tot}
+    out["total_ms"] = tot
+    out["setups"] = len(phases)
+    return out
+
+
+def table2(ms_partial, info_p, runs):
+    """The paper's Table 2 form per strategy: setup and solve ms per step (device events
+    around the update and around the solve), iterations, full setups, and speedups over
+    no reuse (a full setup every step) in the paper's form (t_base / t - 1) * 100."""
+    rows = {"partial reuse": (ms_partial, info_p)}
+    names = {"full": "no reuse (full setup every step)", "reuse": "full reuse (miss -> setup and re-solve)",
+             "reuse_paper": "full reuse (miss -> setup at the next step)",
+             "policy": "partial reuse + full setup every 10th step"}
+    for k, v in runs.items():
+        if k in names:
+            rows[names[k]] = v
+    base = rows.get("no reuse (full setup every step)")
+    out = {}
+    for k, (ms, info) in rows.items():
+        r = {"ms_per_step": ms, "setup_ms_per_step": info["setup_ms_per_step"],
+             "solve_ms_per_step": info["solve_ms_per_step"],
+             "avg_iters": sum(info["iters"]) / len(info["iters"]), "full_setups": info["rebuilds"]}
+        if base is not None:
+            r["total_speedup_pct"] = (base[0] / ms - 1.0) * 100.0
+            bs = base[1]["setup_ms_per_step"]
+            r["setup_speedup_pct"] = (bs / info["setup_ms_per_step"] - 1.0) * 100.0 if info["setup_ms_per_step"] else None
+        out[k] = r
+    return out
+
+
+def leg_record(res):
+    info = res["info_p"]
+    rec = {"workload": res["work"], "ms_per_step": res["ms_partial"],
+           "setup_ms_per_step": info["setup_ms_per_step"], "solve_ms_per_step": info["solve_ms_per_step"],
+           "iters": info["iters"], "converged_all": info["converged"], "rel_res_max": info["rel_res_max"],
+           "levels": res["levels"], "level_rows": [d[0] for d in res["dims"]],
+           "roofline_dominant": res["roofline_dominant"], "roofline_spmv": res["roofline_spmv"],
+           "roofline_rap": res["roofline_rap"], "krylov_spmv_first_iteration": res["krylov_spmv_first_iteration"]}
+    for name, (ms, inf) in res.get("runs", {}).items():
+        rec[f"{name}_ms_per_step"] = ms
+        rec[f"{name}_iters"] = inf["iters"]
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: runs on several GPUs "
+              f"(row-block sharding of every level) are not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
+
+    from workloads import CONFIGS, rhs_uniform, series_matrix
+
+    cfg_id = args.config
+    cfg = CONFIGS[cfg_id]
+    N = args.n or cfg["N"]
+    K, W = args.steps, args.warmup
+    res = run_config(cfg_id, N, K, W, args, compare=not args.no_compare)
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write, 1 GiB, best of 5)")
+    info_p = res["info_p"]
+    dims = res["dims"]
+    n, nnz = res["n"], res["nnz"]
+    result = {
+        "metric": METRIC,
+        "value": res["ms_partial"],
+        "unit": "ms/step",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": res["ms_partial"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if res["head_prec"] == 0 else "f32 hierarchy and V-cycle, f64 CG",
+        "data": "synthetic",
+        "config": {"workload": res["work"],
+                   "grid": N, "n": n, "nnz": nnz, "levels": res["levels"], "level_rows": [d[0] for d in dims],
+                   "level_nnz": [d[1] for d in dims],
+                   "level0_storage": ((f"{res['ndiag']} diagonals, {res['nread']} read per row"
+                                       + (f", marching planes of {res['plane']} rows" if res["plane"] else ""))
+                                      if res["ndiag"] else "CSR"),
+                   "parallelism": "single GPU"},
+        "iters_partial": info_p["iters"],
+        "converged_all": info_p["converged"],
+        "rel_res_max": info_p["rel_res_max"],
+        "partial_setup_ms_per_step": info_p["setup_ms_per_step"],
+        "partial_solve_ms_per_step": info_p["solve_ms_per_step"],
+        "setup_ms_step0": info_p["setup_ms"],
+        "step_ms_spread": info_p["step_ms"],
+        "copy_gbs_measured": copy_gbs,
+        "roofline": res["roofline_dominant"],
+        "roofline_spmv": res["roofline_spmv"],
+        "roofline_rap": res["roofline_rap"],
+        "rap_all_levels": res["rap_all_levels"],
+        "krylov_spmv_first_iteration": res["krylov_spmv_first_iteration"],
+        "dominant_kernel_class": res["dom"],
+        "mall_note": "MI355X has a 256 MB memory-side cache (MALL); at 128^3 part of a kernel's working set can "
+                     "stay in it between kernels, so the 128^3 fractions can exceed what HBM alone gives; the "
+                     "legs at 192^3 and 160^3 have working sets beyond it",
+        "kernels_by_level_ms": res["kernels_by_level"],
+        "kernels_all_levels_ms": res["kernels_all_levels_ms"],
+        "allocator": args.allocator,
+    }
+    runs = res.get("runs", {})
+    if runs:
+        conv = info_p["converged"] and all(bool(v[1]["converged"]) for v in runs.values())
+        result["converged_all"] = conv
         if "full" in runs:
             result["full_rebuild_ms_per_step"] = runs["full"][0]
             result["iters_full_rebuild"] = runs["full"][1]["iters"]
-            # the paper's speedup form: (t_base / t - 1) * 100
-            result["total_speedup_vs_full_rebuild_pct"] = (runs["full"][0] / ms_partial - 1.0) * 100.0
+            result["total_speedup_vs_full_rebuild_pct"] = (runs["full"][0] / res["ms_partial"] - 1.0) * 100.0
+            result["table1_full_setup_phases"] = table1(runs["full"][1]["phases"])
         if "reuse" in runs:
             result["full_reuse_ms_per_step"] = runs["reuse"][0]
             result["iters_full_reuse"] = runs["reuse"][1]["iters"]
@@ -473,27 +716,41 @@ def main():
         if "mixed" in runs:
             result["mixed_partial_ms_per_step"] = runs["mixed"][0]
             result["iters_mixed"] = runs["mixed"][1]["iters"]
-            result["mixed_speedup_vs_fp64_pct"] = (ms_partial / runs["mixed"][0] - 1.0) * 100.0
+            result["mixed_speedup_vs_fp64_pct"] = (res["ms_partial"] / runs["mixed"][0] - 1.0) * 100.0
         if "policy" in runs:
             result["policy_every_ms_per_step"] = runs["policy"][0]
-            result["policy"] = f"partial reuse with a full setup every {POLICY.every}th step"
+            result["policy"] = "partial reuse with a full setup every 10th step"
             result["iters_policy"] = runs["policy"][1]["iters"]
             result["policy_full_setups"] = runs["policy"][1]["rebuilds"]
         if "reuse_paper" in runs:
             result["full_reuse_paper_ms_per_step"] = runs["reuse_paper"][0]
             result["iters_full_reuse_paper"] = runs["reuse_paper"][1]["iters"]
             result["full_reuse_paper_full_setups"] = runs["reuse_paper"][1]["rebuilds"]
-            result["full_reuse_paper_missed_solves"] = runs["reuse_paper"][1].get("missed", 0)
+            result["full_reuse_paper_missed_solves"] = runs["reuse_paper"][1]["missed"]
         if "fp64_partial" in runs:
             result["fp64_partial_ms_per_step"] = runs["fp64_partial"][0]
             result["iters_fp64"] = runs["fp64_partial"][1]["iters"]
-            result["mixed_speedup_vs_fp64_pct"] = (runs["fp64_partial"][0] / ms_partial - 1.0) * 100.0
-        result["converged_all"] = conv
+            result["mixed_speedup_vs_fp64_pct"] = (runs["fp64_partial"][0] / res["ms_partial"] - 1.0) * 100.0
+        result["table2_strategies"] = table2(res["ms_partial"], info_p, runs)
+
+    # ---------------------------------------------------------------- short legs beyond the MALL
+    if cfg_id == 2 and not args.no_legs:
+        import torch
+        legs = {}
+        for lid, prec in ((3, 0), (5, 1)):
+            c = CONFIGS[lid]
+            log(f"leg: {c['name']}")
+            r = run_config(lid, c["N"], args.leg_steps, 1, args, headline_prec=prec, compare=True, legs_mode=True)
+            legs[c["name"]] = leg_record(r)
+            torch.cuda.empty_cache()
+        result["legs"] = legs
 
     # ---------------------------------------------------------------- CPU oracle sample
     if not args.no_cpu:
         import oracle
         nthr = oracle.num_threads()
+        bicg = cfg_id == 6
+        amg_params = {k: cfg[k] for k in ("eps_strong", "block_size", "aggregation") if k in cfg}
         p, c, v0 = series_matrix(cfg_id, 0, N)
         t0 = time.time()
         h = oracle.OracleHierarchy(p, c, v0, **amg_params)

@@ -25,7 +25,7 @@ EXPORTED = [
     "amg_rebuild_ex", "amg_solve", "amg_vcycle", "amg_destroy", "amg_last_error", "amg_num_levels",
     "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
     "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read", "amg_policy_pick",
-    "amg_rebuild_auto", "amg_solve_bicgstab", "amg_apply_operator",
+    "amg_rebuild_auto", "amg_solve_bicgstab", "amg_apply_operator", "amg_trace_read_levels", "amg_level_storage",
 ]
 MODE_NAMES = {PARTIAL: "partial", FULL: "full", OPERATOR_ONLY: "operator_only"}
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
@@ -143,6 +143,8 @@ def lib():
         L.amg_logcoef7_adjoint.argtypes = [I32, I32, I32, V, V, V, V, V]
         L.amg_trace.argtypes = [V, C.c_uint, I]
         L.amg_trace_read.argtypes = [V, C.POINTER(D), C.POINTER(I64)]
+        L.amg_trace_read_levels.argtypes = [V, I, C.POINTER(D), C.POINTER(I64)]
+        L.amg_level_storage.argtypes = [V, I, C.POINTER(I)]
         L.amg_policy_pick.argtypes = [C.POINTER(AmgPolicy), I, I, I, I, C.POINTER(I)]
         L.amg_rebuild_auto.argtypes = [V, V, C.POINTER(AmgPolicy), C.POINTER(I)]
         for name in EXPORTED:
@@ -383,6 +385,23 @@ class AMG:
         cnt = (C.c_int64 * 16)()
         self._check(lib().amg_trace_read(self.ctx, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES) if cnt[i]}
+
+    def trace_read_levels(self) -> list:
+        """Per level: {class: (total ms, launches)} since the previous read."""
+        L = self.num_levels
+        K = len(KERNEL_CLASSES)
+        ms = (C.c_double * (L * K))()
+        cnt = (C.c_int64 * (L * K))()
+        self._check(lib().amg_trace_read_levels(self.ctx, L, ms, cnt))
+        return [{k: (ms[l * K + i], cnt[l * K + i]) for i, k in enumerate(KERNEL_CLASSES) if cnt[l * K + i]}
+                for l in range(L)]
+
+    def level_storage(self, l: int) -> dict:
+        """Column format and launch shape of level l's operators in the solve kernels."""
+        out = (C.c_int * 8)()
+        self._check(lib().amg_level_storage(self.ctx, l, out))
+        return dict(A_c16=out[0], P_c16=out[1], R_c16=out[2], A_rpb=out[3], P_rpb=out[4], R_rpb=out[5],
+                    tail=out[6], value_bytes=out[7])
 
     def phase_times(self) -> dict:
         out = (C.c_double * 8)()

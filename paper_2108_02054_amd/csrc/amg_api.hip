@@ -326,7 +326,7 @@ bool mixed(const amg_ctx* c) { return c->prm.precision == 1; }
 // Brackets the launches inside its scope with events when the class is traced.
 struct Trace {
     amg_ctx* c;
-    int cls;
+    int cls, level;
     hipEvent_t a = nullptr, b = nullptr;
     static hipEvent_t take(amg_ctx* c) {
         if (c->ev_pool.empty()) {
@@ -338,14 +338,16 @@ struct Trace {
         c->ev_pool.pop_back();
         return e;
     }
-    // The Krylov SpMV (one launch) records its own events at launch, which time the kernel
-    // alone; every other class is bracketed by events recorded on the stream around it.
+    // Classes that are one kernel launch (the Krylov SpMV, restriction, prolongation) have
+    // the launch record its own events, which time the kernel alone; every other class is
+    // bracketed by events recorded on the stream around it.
+    static bool single_launch(int k) { return k == AMG_K_CG_PQ || k == AMG_K_RESTRICT || k == AMG_K_PROLONG; }
     bool own = false;
-    Trace(amg_ctx* cc, int k, int level) : c(cc), cls(k) {
-        if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == level)) {
+    Trace(amg_ctx* cc, int k, int lvl) : c(cc), cls(k), level(lvl) {
+        if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == lvl)) {
             a = take(c);
             b = take(c);
-            if (k == AMG_K_CG_PQ) {
+            if (single_launch(k)) {
                 own = true;
                 g_kernel_events = KernelEvents{a, b};
             } else {
@@ -362,7 +364,7 @@ struct Trace {
             (void)hipEventRecord(a, c->stream);
             (void)hipEventRecord(b, c->stream);
         }
-        c->traced.push_back({cls, a, b});
+        c->traced.push_back({cls, level, a, b});
     }
 };
 
@@ -2061,10 +2063,11 @@ amg_status amg_trace(amg_ctx* c, unsigned mask, int level) {
     return AMG_OK;
 }
 
-amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches) {
-    if (!c || !ms || !launches) return AMG_ERR_ARG;
+// Sums the traced intervals per class (nlev == 0) or per level and class into ms/launches.
+static amg_status trace_collect(amg_ctx* c, int nlev, double* ms, int64_t* launches) {
     return guard(c, [&] {
-        for (int k = 0; k < AMG_K_COUNT; ++k) {
+        const int rows = nlev > 0 ? nlev : 1;
+        for (int k = 0; k < rows * AMG_K_COUNT; ++k) {
             ms[k] = 0.0;
             launches[k] = 0;
         }
@@ -2072,9 +2075,10 @@ amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches) {
         for (auto& t : c->traced) {
             float x = 0.f;
             HIP_CHECK(hipEventElapsedTime(&x, t.a, t.b));
+            const int row = nlev > 0 ? std::min(std::max(t.level, 0), nlev - 1) : 0;
             if (t.cls >= 0 && t.cls < AMG_K_COUNT) {
-                ms[t.cls] += x;
-                launches[t.cls] += 1;
+                ms[row * AMG_K_COUNT + t.cls] += x;
+                launches[row * AMG_K_COUNT + t.cls] += 1;
             }
             c->ev_pool.push_back(t.a);
             c->ev_pool.push_back(t.b);
@@ -2082,6 +2086,31 @@ amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches) {
         c->traced.clear();
         return AMG_OK;
     });
+}
+
+amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return AMG_ERR_ARG;
+    return trace_collect(c, 0, ms, launches);
+}
+
+amg_status amg_trace_read_levels(amg_ctx* c, int nlev, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches || nlev <= 0) return AMG_ERR_ARG;
+    return trace_collect(c, nlev, ms, launches);
+}
+
+amg_status amg_level_storage(const amg_ctx* c, int l, int* out) {
+    if (!c || !out || l < 0 || l >= (int)c->lv.size()) return AMG_ERR_ARG;
+    if (c->broken) return AMG_ERR_STATE;
+    const Level& L = c->lv[(size_t)l];
+    out[0] = L.A.c16 != nullptr;
+    out[1] = L.P.c16 != nullptr;
+    out[2] = L.R.c16 != nullptr;
+    out[3] = L.A.rpb;
+    out[4] = L.P.rpb;
+    out[5] = L.R.rpb;
+    out[6] = (c->tail > 0 && l >= c->tail) ? 1 : 0;
+    out[7] = mixed(c) ? 4 : 8;
+    return AMG_OK;
 }
 
 amg_status amg_logcoef7_assemble(int32_t nx, int32_t ny, int32_t nz, const double* theta, double* val,

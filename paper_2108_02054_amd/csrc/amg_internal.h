@@ -499,6 +499,7 @@ struct amg_ctx {
     std::vector<hipEvent_t> ev_pool;
     struct Traced {
         int cls;
+        int level;
         hipEvent_t a, b;
     };
     std::vector<Traced> traced;

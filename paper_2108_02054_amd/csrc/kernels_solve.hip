@@ -77,21 +77,55 @@ static inline unsigned grid_for(int64_t items, int per_block) {
 
 // ------------------------------------------------------------------ row-block staging
 
-// Loads ptr[row0 .. row1] into sptr, then val[k] * xget(col[k]) for the block's nonzeros
-// into sp.  Every thread of the block must call it.
+// One staging pass group: U strided entries per thread.  Every column and value load is
+// issued before the first gather and every gather before the first product, so a thread
+// keeps U loads of each kind in flight instead of walking its entries one round trip at a
+// time.  Indices past the block's range are clamped to its last entry (in bounds, their
+// products dropped).
+template <int U, typename T, class C, class X>
+__device__ __forceinline__ void rb_stage(int k0, int k1, C colat, const T* __restrict__ val, X xget, T* sp) {
+    int jj[U];
+    T vv[U], xx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = min(k0 + u * RB_THREADS + (int)threadIdx.x, k1 - 1);
+        jj[u] = colat(k);
+        vv[u] = val[k];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xx[u] = xget(jj[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * RB_THREADS + (int)threadIdx.x;
+        if (k < k1) sp[k - k0] = vv[u] * xx[u];
+    }
+}
+
+// Loads ptr[row0 .. row1] into sptr and val[k] * xget(col(k)) for the block's nonzeros into
+// sp.  The block's entry range comes from two uniform loads of ptr, so the entry loads do
+// not wait for the pointer stage; one barrier at the end publishes both.  Every thread of
+// the block must call it.
+template <typename T, class C, class X>
+__device__ __forceinline__ void rb_load_core(int row0, int row1, const int* __restrict__ ptr, C colat,
+                                             const T* __restrict__ val, X xget, int* sptr, T* sp) {
+    const int nr = row1 - row0;
+    for (int i = threadIdx.x; i <= nr; i += RB_THREADS) sptr[i] = ptr[row0 + i];
+    const int k0 = ptr[row0];
+    const int k1 = min(ptr[row1], k0 + RB_CAP);  // blocks are sized within RB_CAP
+    const int passes = (k1 - k0 + RB_THREADS - 1) / RB_THREADS;
+    if (passes > 4)
+        rb_stage<RB_CAP / RB_THREADS>(k0, k1, colat, val, xget, sp);
+    else if (passes > 2)
+        rb_stage<4>(k0, k1, colat, val, xget, sp);
+    else if (passes > 0)
+        rb_stage<2>(k0, k1, colat, val, xget, sp);
+    __syncthreads();
+}
+
 template <typename T, class X>
 __device__ __forceinline__ void rb_load(int row0, int row1, const int* __restrict__ ptr, const int* __restrict__ col,
                                         const T* __restrict__ val, X xget, int* sptr, T* sp) {
-    const int nr = row1 - row0;
-    for (int i = threadIdx.x; i <= nr; i += RB_THREADS) sptr[i] = ptr[row0 + i];
-    __syncthreads();
-    const int k0 = sptr[0], k1 = min(sptr[nr], k0 + RB_CAP);  // blocks are sized within RB_CAP
-#pragma unroll
-    for (int it = 0; it < RB_CAP / RB_THREADS; ++it) {
-        const int k = k0 + it * RB_THREADS + (int)threadIdx.x;
-        if (k < k1) sp[k - k0] = val[k] * xget(col[k]);
-    }
-    __syncthreads();
+    rb_load_core(row0, row1, ptr, [&](int k) { return col[k]; }, val, xget, sptr, sp);
 }
 
 // Column indices as the row-block kernels of the V-cycle read them: int32, or two bytes
@@ -107,25 +141,12 @@ inline ColSrc colsrc(const Csr& A) { return ColSrc{A.col, A.c16, A.cblk}; }
 template <typename T, class X>
 __device__ __forceinline__ void rb_load(int row0, int row1, const int* __restrict__ ptr, const ColSrc& cs, int blk,
                                         const T* __restrict__ val, X xget, int* sptr, T* sp) {
-    const int nr = row1 - row0;
-    for (int i = threadIdx.x; i <= nr; i += RB_THREADS) sptr[i] = ptr[row0 + i];
-    const int cb = cs.c16 != nullptr ? cs.cblk[blk] : 0;
-    __syncthreads();
-    const int k0 = sptr[0], k1 = min(sptr[nr], k0 + RB_CAP);  // blocks are sized within RB_CAP
     if (cs.c16 != nullptr) {
-#pragma unroll
-        for (int it = 0; it < RB_CAP / RB_THREADS; ++it) {
-            const int k = k0 + it * RB_THREADS + (int)threadIdx.x;
-            if (k < k1) sp[k - k0] = val[k] * xget(cb + (int)cs.c16[k]);
-        }
+        const int cb = cs.cblk[blk];
+        rb_load_core(row0, row1, ptr, [&](int k) { return cb + (int)cs.c16[k]; }, val, xget, sptr, sp);
     } else {
-#pragma unroll
-        for (int it = 0; it < RB_CAP / RB_THREADS; ++it) {
-            const int k = k0 + it * RB_THREADS + (int)threadIdx.x;
-            if (k < k1) sp[k - k0] = val[k] * xget(cs.col[k]);
-        }
+        rb_load_core(row0, row1, ptr, [&](int k) { return cs.col[k]; }, val, xget, sptr, sp);
     }
-    __syncthreads();
 }
 
 // One base per row block: the smallest column of its rows (rows are sorted, so the
@@ -246,6 +267,10 @@ __device__ __forceinline__ double* rr_dest(const RedScratch& rs, bool bad) {
 
 // ------------------------------------------------------------------ V-cycle kernels
 
+// The row-block V-cycle kernels below read their own row's epilogue operands (m, f, u)
+// before the staging barrier, so those loads overlap the entry loads instead of following
+// them.
+
 // y = A x; with m2 given also y2 = m2 * y (the restriction forms the coarse level's first
 // smoothing sweep u = m f from zero at the same time).
 template <typename T>
@@ -258,13 +283,15 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_spmv(int n, int rpb, const in
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return x[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), r = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    const bool own = r < row1 - row0 && lane == 0;
+    const T mi = (own && m2 != nullptr) ? m2[row0 + r] : T(0);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return x[j]; }, sptr, sp);
     if (r < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, r, lane, tpr);
         if (lane == 0) {
             y[row0 + r] = v;
-            if (m2 != nullptr) y2[row0 + r] = m2[row0 + r] * v;
+            if (m2 != nullptr) y2[row0 + r] = mi * v;
         }
     }
 }
@@ -279,11 +306,13 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_residual(int n, int rpb, cons
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return u[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    const bool own = t < row1 - row0 && lane == 0;
+    const T fi = own ? f[row0 + t] : T(0);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return u[j]; }, sptr, sp);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
-        if (lane == 0) r[row0 + t] = f[row0 + t] - v;
+        if (lane == 0) r[row0 + t] = fi - v;
     }
 }
 
@@ -298,12 +327,14 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_jacobi(int n, int rpb, const 
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return u[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    const bool own = t < row1 - row0 && lane == 0;
+    const int i = row0 + t;
+    const T ui = own ? u[i] : T(0), mi = own ? m[i] : T(0), fi = own ? f[i] : T(0);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return u[j]; }, sptr, sp);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
-        const int i = row0 + t;
-        if (lane == 0) uout[i] = u[i] + m[i] * (f[i] - v);
+        if (lane == 0) uout[i] = ui + mi * (fi - v);
     }
 }
 
@@ -320,14 +351,15 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_smooth0_residual(int n, int r
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return m[j] * f[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    const bool own = t < row1 - row0 && lane == 0;
+    const int i = row0 + t;
+    const T mi = own ? m[i] : T(0), fi = own ? f[i] : T(0);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return m[j] * f[j]; }, sptr, sp);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
-        const int i = row0 + t;
         if (lane == 0) {
-            const T fi = f[i];
-            u[i] = m[i] * fi;
+            u[i] = mi * fi;
             r[i] = fi - v;
         }
     }
@@ -343,11 +375,13 @@ __global__ __launch_bounds__(RB_THREADS) void k_rb_prolong_add(int n, int rpb, c
     const int row0 = xcd_block() * rpb;
     if (row0 >= n) return;
     const int row1 = min(row0 + rpb, n);
-    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return uc[j]; }, sptr, sp);
     const int tpr = rb_tpr(rpb), t = threadIdx.x / tpr, lane = threadIdx.x & (tpr - 1);
+    const bool own = t < row1 - row0 && lane == 0;
+    const T ui = own ? u[row0 + t] : T(0);
+    rb_load(row0, row1, ptr, cs, xcd_block(), val, [&](int j) { return uc[j]; }, sptr, sp);
     if (t < row1 - row0) {
         const T v = rb_rowsum(sptr, sp, t, lane, tpr);
-        if (lane == 0) u[row0 + t] += v;
+        if (lane == 0) u[row0 + t] = ui + v;
     }
 }
 
@@ -432,10 +466,19 @@ static inline unsigned ew_blocks(int64_t n) {
         HIP_LAUNCH_CHECK();                                                                             \
     } while (0)
 
+// The restriction and the prolongation go through timed_launch: when their class is
+// traced the launch records its own events.
 template <typename T>
 void launch_spmv(const Csr& A, const T* x, T* y, const T* m2, T* y2, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_spmv<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), x, y, m2, y2)),
-                 0, A.nrows, A.ptr, A.col, A.v<T>(), m2, nullptr, x, y, y2);
+    if (A.rpb > 0) {
+        timed_launch(k_rb_spmv<T>, grid_for(A.nrows, A.rpb), RB_THREADS, 0, s, A.nrows, A.rpb, (const int*)A.ptr,
+                     colsrc(A), (const T*)A.v<T>(), x, y, m2, y2);
+    } else {
+        AMG_WITH_G(A.g, timed_launch(k_lg<G, T, 0>, grid_for((int64_t)A.nrows * G, TPB), TPB, 0, s, A.nrows,
+                                     (const int*)A.ptr, (const int*)A.col, (const T*)A.v<T>(), m2, (const T*)nullptr,
+                                     x, y, y2));
+    }
+    HIP_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_residual(const Csr& A, const T* f, const T* u, T* r, hipStream_t s) {
@@ -454,9 +497,15 @@ void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, h
 }
 template <typename T>
 void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s) {
-    const Csr& A = P;
-    AMG_RB_OR_LG(A, (k_rb_prolong_add<T><<<grid_for(P.nrows, P.rpb), RB_THREADS, 0, s>>>(P.nrows, P.rpb, P.ptr, colsrc(P), P.v<T>(), uc, u)),
-                 4, P.nrows, P.ptr, P.col, P.v<T>(), nullptr, nullptr, uc, u, nullptr);
+    if (P.rpb > 0) {
+        timed_launch(k_rb_prolong_add<T>, grid_for(P.nrows, P.rpb), RB_THREADS, 0, s, P.nrows, P.rpb,
+                     (const int*)P.ptr, colsrc(P), (const T*)P.v<T>(), uc, u);
+    } else {
+        AMG_WITH_G(P.g, timed_launch(k_lg<G, T, 4>, grid_for((int64_t)P.nrows * G, TPB), TPB, 0, s, P.nrows,
+                                     (const int*)P.ptr, (const int*)P.col, (const T*)P.v<T>(), (const T*)nullptr,
+                                     (const T*)nullptr, uc, u, (T*)nullptr));
+    }
+    HIP_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s) {

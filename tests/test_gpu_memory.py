@@ -57,6 +57,7 @@ def test_torch_allocator_holds_the_hierarchy():
     assert abs(info["iters"] - io["iters"]) <= 1
     assert rel_max(u.cpu().numpy(), uo) <= 1e-6
     g.close()
+    del u, ur
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == base
 
@@ -87,7 +88,7 @@ def test_partial_update_and_solve_allocate_nothing(precision):
     p, c, v = two_fluid_7pt(N, front_moving(N, 0))
     print(f"case counting allocator 24^3 precision {precision}", flush=True)
     g = AMG(T(p), T(c), T(v), allocator=cb, precision=precision)
-    n_setup = stats["alloc"]
+    n_setup, n_free_setup = stats["alloc"], stats["free"]
     assert n_setup > 0 and len(stats["live"]) > 0
     live_after_setup = dict(stats["live"])
     for t in range(1, 4):
@@ -96,14 +97,21 @@ def test_partial_update_and_solve_allocate_nothing(precision):
         _, info = g.solve(T(rhs_uniform(N**3, 1, t)))
         assert info["converged"]
     torch.cuda.synchronize()
-    assert stats["alloc"] == n_setup and stats["free"] == 0
+    assert stats["alloc"] == n_setup and stats["free"] == n_free_setup
     # a full rebuild gives back the old hierarchy and its temporaries
     g.rebuild_ex(T(vt), FULL)
     torch.cuda.synchronize()
-    assert stats["free"] > 0
-    assert sum(stats["live"].values()) == sum(live_after_setup.values())
+    assert stats["free"] > n_free_setup
+    # what stays allocated is what a fresh setup from the same values holds
+    stats2, cb2 = _counting_allocator()
+    fresh = AMG(T(p), T(c), T(vt), allocator=cb2, precision=precision)
+    torch.cuda.synchronize()
+    assert sorted(stats["live"].values()) == sorted(stats2["live"].values())
+    fresh.close()
     g.close()
     assert stats["live"] == {} and stats["alloc"] == stats["free"]
+    assert stats2["live"] == {}
+    del live_after_setup
 
 
 def test_two_contexts_on_two_streams():
