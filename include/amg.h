@@ -208,6 +208,21 @@ amg_status amg_vcycle(amg_ctx* c, const double* r, double* z);
  * NULL or aliased arguments. */
 amg_status amg_apply_operator(amg_ctx* c, const double* x, double* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): amg_apply_operator with the same kernels
+ * and results, whose scratch (the copy of p the Krylov SpMV writes and its block partials)
+ * lives in a static device array of the library instead of the context's CG vectors.  The
+ * call allocates nothing and never touches the CG's work vectors.  The array holds
+ * 2^23 + 2^20 doubles (72 MiB) on every device the library is used on, from the library's
+ * load to the end of the process; its address on a device is looked up on the first call
+ * there.  Limits: n <= 2^23 rows, and the SpMV's grid within the partial region; beyond
+ * them AMG_ERR_ARG with a message.  The context's device must be current (AMG_ERR_ARG
+ * otherwise).  All calls on one device share the array: calls that overlap on a device
+ * (other streams, other threads) race and must be serialised by the caller.  Asynchronous
+ * on the context's stream; AMG_ERR_ARG for NULL or aliased x, y; AMG_ERR_STATE on a broken
+ * context. */
+amg_status amg_apply_operator_noalloc(amg_ctx* c, const double* x, double* y);
+
 /* Release the context: waits for its stream, frees all its device memory (to the caller's
  * allocator, or by destroying its private pool), its pinned host buffers and events.
  * Valid on a broken context.  AMG_ERR_ARG for NULL.  (Not a step of the paper; the end of

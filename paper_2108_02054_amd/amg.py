@@ -26,6 +26,7 @@ EXPORTED = [
     "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
     "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read", "amg_policy_pick",
     "amg_rebuild_auto", "amg_solve_bicgstab", "amg_apply_operator", "amg_trace_read_levels", "amg_level_storage",
+    "amg_apply_operator_noalloc",
 ]
 MODE_NAMES = {PARTIAL: "partial", FULL: "full", OPERATOR_ONLY: "operator_only"}
 KERNEL_CLASSES = ["galerkin_ap", "galerkin_rap", "smoother", "coarse_inv", "cg_pq", "cg_update", "cg_rz",
@@ -130,6 +131,7 @@ def lib():
         L.amg_solve_bicgstab.argtypes = [V, V, V, C.POINTER(AmgSolveInfo)]
         L.amg_vcycle.argtypes = [V, V, V]
         L.amg_apply_operator.argtypes = [V, V, V]
+        L.amg_apply_operator_noalloc.argtypes = [V, V, V]
         L.amg_destroy.argtypes = [V]
         L.amg_last_error.argtypes = [V]
         L.amg_last_error.restype = C.c_char_p

@@ -1664,6 +1664,7 @@ amg_ctx* create_ctx(const amg_params& p, void* stream) {
     c->prm = p;
     c->stream = (hipStream_t)stream;
     try {
+        HIP_CHECK(hipGetDevice(&c->device));
         mem_init(c->mem, c->stream, p.alloc, p.dealloc, p.alloc_user);
         MemScope scope(&c->mem);
         c->d_flags = oalloc<int>(c, F_COUNT);
@@ -1941,12 +1942,76 @@ amg_status amg_apply_operator(amg_ctx* c, const double* x, double* y) {
     });
 }
 
+// ------------------------------------------------------------------ allocation-free operator
+//
+// amg_apply_operator_noalloc runs the kernels of amg_apply_operator with their scratch (the
+// copy of p the Krylov SpMV writes, and its p.q block partials) in this file-scope device
+// array instead of the context's CG vectors.  Each device holds its own copy from the load
+// of the library to the end of the process; its address on a device is taken once, with
+// that device current, and only that address is handed to kernels.
+namespace {
+constexpr size_t NOALLOC_ROWS = (size_t)1 << 23;        // most rows (the p copy)
+constexpr size_t NOALLOC_PART = (size_t)1 << 20;        // doubles for the reduction partials
+static __device__ __align__(256) double scratch[NOALLOC_ROWS + NOALLOC_PART];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+double* scratch_on(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) throw Fail{AMG_ERR_ARG, "device index out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 amg_status amg_vcycle(amg_ctx* c, const double* r, double* z) {
     if (!c || !r || !z) return AMG_ERR_ARG;
     return guard(c, [&] {
         vcycle_apply(c, r, z);
         return AMG_OK;
     });
+}
+
+amg_status amg_apply_operator_noalloc(amg_ctx* c, const double* x, double* y) {
+    if (!c || !x || !y || x == y) return AMG_ERR_ARG;
+    if (c->broken) return AMG_ERR_STATE;
+    // no MemScope: nothing here allocates
+    try {
+        int dev = -1;
+        HIP_CHECK(hipGetDevice(&dev));
+        if (dev != c->device) throw Fail{AMG_ERR_ARG, "amg_apply_operator_noalloc: the context's device is not current"};
+        const Level& L0 = c->lv[0];
+        const int n = L0.A.nrows;
+        if ((size_t)n > NOALLOC_ROWS)
+            throw Fail{AMG_ERR_ARG, "amg_apply_operator_noalloc: " + std::to_string(n) + " rows exceed its " +
+                                        std::to_string(NOALLOC_ROWS) + "-row scratch"};
+        double* sp = scratch_on(dev);
+        RedScratch rs;
+        rs.cap = (int)((NOALLOC_PART - S_COUNT - RED_BLOCKS) / 4);
+        rs.part = sp + NOALLOC_ROWS;
+        rs.host = nullptr;
+        double* w = sp;  // the p copy
+        if (c->dia.ndiag > 0 && c->outer_val == L0.A.val)
+            launch_dia_cg_pq(n, c->dia, x, x, w, y, 1, rs, c->stream);
+        else if (c->prm.block_size > 1)
+            launch_node_cg_pq(L0, c->prm.block_size, c->outer_val, x, x, w, y, 1, rs, c->stream);
+        else
+            launch_cg_pq(L0.A, c->outer_val, x, x, w, y, 1, rs, c->stream);
+        return AMG_OK;
+    } catch (const Fail& e) {
+        c->err = e.msg;
+        if (e.st == AMG_ERR_HIP) c->broken = true;
+        return e.st;
+    } catch (...) {
+        c->err = "unexpected exception";
+        return AMG_ERR_HIP;
+    }
 }
 
 amg_status amg_destroy(amg_ctx* c) {

@@ -488,6 +488,7 @@ struct amg_ctx {
     std::vector<void*> hier_allocs;
     std::vector<void*> own_allocs;
     amgmi::DevMem mem;            // where the device memory of this context comes from
+    int device = 0;               // the device current at amg_setup
     // phase times of the last setup / rebuild (Table 1 breakdown)
     double phase_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool phase_pending = false;   // partial rebuild: times still to be read from ev[]

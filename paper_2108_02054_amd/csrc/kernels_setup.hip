@@ -6,7 +6,10 @@
 // they are made with separately rounded products (contraction off) in the same
 // association as the definitions below, so that on the same input they are bit-exact
 // and independent of scheduling.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_reduce.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
 
 #include "amg_internal.h"
 
@@ -270,9 +273,9 @@ __global__ void k_is_root(int n, const uint8_t* __restrict__ state, int* __restr
 template <typename Tin, typename Tout>
 static void scan_exclusive(const Tin* in, Tout* out, int64_t n, hipStream_t s) {
     size_t bytes = 0;
-    HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, s));
+    HIP_CHECK(rocprim::exclusive_scan(nullptr, bytes, in, out, Tout(0), (size_t)n, rocprim::plus<Tout>(), s));
     void* tmp = dalloc(bytes, s);
-    HIP_CHECK(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, s));
+    HIP_CHECK(rocprim::exclusive_scan(tmp, bytes, in, out, Tout(0), (size_t)n, rocprim::plus<Tout>(), s));
     dfree(tmp, s);
 }
 
@@ -287,9 +290,9 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t 
 int64_t max_i64(const int64_t* in, int64_t n, hipStream_t s) {
     int64_t* out = dnew<int64_t>(1, s);
     size_t bytes = 0;
-    HIP_CHECK(hipcub::DeviceReduce::Max(nullptr, bytes, in, out, (int)n, s));
+    HIP_CHECK(rocprim::reduce(nullptr, bytes, in, out, (size_t)n, rocprim::maximum<int64_t>(), s));
     void* tmp = dalloc(bytes, s);
-    HIP_CHECK(hipcub::DeviceReduce::Max(tmp, bytes, in, out, (int)n, s));
+    HIP_CHECK(rocprim::reduce(tmp, bytes, in, out, (size_t)n, rocprim::maximum<int64_t>(), s));
     int64_t h = 0;
     HIP_CHECK(hipMemcpyAsync(&h, out, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
@@ -565,18 +568,18 @@ void build_prolongator(const Csr& A, const uint8_t* strong, const int32_t* diag_
 template <typename K, typename V>
 static void radix_sort_pairs(K* kin, K* kout, V* vin, V* vout, int64_t n, int end_bit, hipStream_t s) {
     size_t bytes = 0;
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, s));
+    HIP_CHECK(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)end_bit, s));
     void* tmp = dalloc(bytes, s);
-    HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, (int)n, 0, end_bit, s));
+    HIP_CHECK(rocprim::radix_sort_pairs(tmp, bytes, kin, kout, vin, vout, (size_t)n, 0u, (unsigned)end_bit, s));
     dfree(tmp, s);
 }
 
 template <typename K>
 static void radix_sort_keys(K* kin, K* kout, int64_t n, int end_bit, hipStream_t s) {
     size_t bytes = 0;
-    HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, kin, kout, (int)n, 0, end_bit, s));
+    HIP_CHECK(rocprim::radix_sort_keys(nullptr, bytes, kin, kout, (size_t)n, 0u, (unsigned)end_bit, s));
     void* tmp = dalloc(bytes, s);
-    HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(tmp, bytes, kin, kout, (int)n, 0, end_bit, s));
+    HIP_CHECK(rocprim::radix_sort_keys(tmp, bytes, kin, kout, (size_t)n, 0u, (unsigned)end_bit, s));
     dfree(tmp, s);
 }
 
@@ -717,9 +720,9 @@ void symbolic_spgemm(const Csr& A, const Csr& B, Csr& C, hipStream_t s) {
     // unique keys into k0
     int* nsel = dnew<int>(1, s);
     size_t bytes = 0;
-    HIP_CHECK(hipcub::DeviceSelect::Unique(nullptr, bytes, k1, k0, nsel, (int)total, s));
+    HIP_CHECK(rocprim::unique(nullptr, bytes, k1, k0, nsel, (size_t)total, rocprim::equal_to<uint64_t>(), s));
     void* tmp = dalloc(bytes, s);
-    HIP_CHECK(hipcub::DeviceSelect::Unique(tmp, bytes, k1, k0, nsel, (int)total, s));
+    HIP_CHECK(rocprim::unique(tmp, bytes, k1, k0, nsel, (size_t)total, rocprim::equal_to<uint64_t>(), s));
     dfree(tmp, s);
     int nnz = 0;
     if (total > 0) {
