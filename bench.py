@@ -268,16 +268,34 @@ def roof(name, ms, launches, alg_bytes_total, traffic_rec=None):
             "traffic_source": (f"profiles/{os.path.basename(traffic_rec['_path'])}" if traffic_rec else None)}
 
 
-def kernel_names(cls, bm, plane, block):
-    """The kernels a class launches in the configurations measured here (level 0, then below)."""
-    lv0 = {"cg_pq": "k_m7_cg_pq" if plane else ("k_w_cg_pq/k_dia_cg_pq" if bm.ndiag else
-                                                   ("k_node_cg_pq" if block > 1 else "k_cg_pq")),
-           "cg_update": "k_m7_update_smooth0" if plane else "k_cg_update",
-           "jacobi": "k_m7_jacobi_rz" if plane else "k_jacobi_rz"}
-    rest = {"restrict": "k_rb_spmv (R_l)", "prolong": "k_rb_prolong_add (P_l)", "jacobi": "k_rb_jacobi",
-            "smooth0_res": "k_rb_residual / k_rb_smooth0_residual", "coarse_gemv": "k_coarse_gemv",
-            "tail": "k_vcycle_tail"}
-    return lv0.get(cls, rest.get(cls, cls))
+def kernel_groups(L, bm, plane, block, bicg):
+    """The kernels of a step as (name, class, levels): a traced class restricted to the
+    levels on which one kernel function runs it, so that times compare with a kernel
+    trace's per-kernel statistics."""
+    up = set(range(1, L))
+    if bicg:
+        pq = "k_m7_cg_pq (BiCGStab products)" if plane else "k_rb_spmv (BiCGStab products)"
+    elif plane:
+        pq = "k_m7_cg_pq"
+    elif bm.ndiag:
+        pq = "k_w_cg_pq" if bm.ndiag != 7 else "k_dia_cg_pq"
+    else:
+        pq = "k_node_cg_pq" if block > 1 else "k_cg_pq"
+    if plane:
+        upd, post = "k_m7_update_smooth0", "k_m7_jacobi_rz"
+    elif bm.ndiag:
+        upd, post = "k_w_update_smooth0 / k_dia_update_smooth0", "k_w_jacobi_rz / k_dia_jacobi_rz"
+    elif block > 1:
+        upd, post = "k_cg_update", "k_node_sweep_rz"
+    else:
+        upd, post = "k_cg_update", "k_jacobi_rz"
+    g = [(pq, "bicg_spmv" if bicg else "cg_pq", {0}), (upd, "cg_update", {0}),
+         (post + " (level-0 post-sweep)", "jacobi", {0}),
+         ("k_rb_jacobi" if block == 1 else "k_node_sweep / k_rb_jacobi", "jacobi", up),
+         ("k_rb_residual", "smooth0_res", up), ("k_rb_spmv (restriction R_l)", "restrict", set(range(L))),
+         ("k_rb_prolong_add (prolongation P_l)", "prolong", set(range(L))),
+         ("k_vcycle_tail", "tail", set(range(L))), ("k_coarse_gemv", "coarse_gemv", set(range(L)))]
+    return g
 
 
 def load_traffic_rec(name):
@@ -333,6 +351,16 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         f"{time.time() - t0:.1f}s")
     u = torch.zeros(n, dtype=torch.float64, device=dev)
     spmv_cls = "bicg_spmv" if bicg else "cg_pq"
+
+    def groups_of(amg):
+        bm_ = ByteModel.of(amg, block)
+        return kernel_groups(bm_.L, bm_, amg.march_plane(0), block, bicg)
+
+    def dominant(ktl, groups):
+        """The kernel with the largest total time in one step (per-level table)."""
+        def tot(gr):
+            return sum(ktl[l].get(gr[1], (0.0, 0))[0] for l in gr[2] if l < len(ktl))
+        return max(groups, key=tot)
 
     def series(mode, precision=0, diag=False):
         """Setup at t=0 (untimed), W warm-up steps, optionally a per-level kernel table
@@ -405,12 +433,8 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
             amg.trace([], level=0)
         traced = None
         if diag:
-            tot = {}
-            for lv in kt_levels:
-                for k, (ms, _) in lv.items():
-                    tot[k] = tot.get(k, 0.0) + ms
-            dom = max((k for k in tot if k not in ("galerkin_ap", "galerkin_rap")), key=lambda k: tot[k])
-            traced = sorted({spmv_cls, "galerkin_ap", "galerkin_rap", dom})
+            dom = dominant(kt_levels, groups_of(amg))
+            traced = sorted({spmv_cls, "galerkin_ap", "galerkin_rap", dom[1]})
             amg.trace(traced, level=-1)
             amg.trace_read()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
@@ -477,8 +501,15 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
             cnt += c_
         return ms, cnt, (byt if ok else None)
 
-    dom = max((k for k in totals if k not in ("galerkin_ap", "galerkin_rap")), key=lambda k: totals[k][0])
-    d_ms, d_cnt, d_bytes = class_live(dom)
+    groups = kernel_groups(L, bm, plane, block, bicg)
+    dom_name, dom, dom_levels = dominant(ktl, groups)
+    d_ms, d_cnt, d_bytes = class_live(dom, sorted(dom_levels))
+    by_kernel = {}
+    for name, cls, lvls in groups:
+        ms_ = sum(ktl[l].get(cls, (0.0, 0))[0] for l in lvls if l < L)
+        cnt_ = sum(ktl[l].get(cls, (0.0, 0))[1] for l in lvls if l < L)
+        if cnt_:
+            by_kernel[name] = [round(ms_, 4), cnt_]
     pq_ms, pq_cnt, _ = class_live(spmv_cls, [0])
     if bicg:
         spmv_bytes = pq_cnt * (bm.krylov_A() + 16 * n)
@@ -508,18 +539,19 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
     dom_traffic = None
     pq_traffic = None
     rap_traffic = None
+    dom_file = dom_name.split(" ")[0]
     if is_headline:
-        dom_traffic = load_traffic_rec(f"{dom}_two_fluid_128_traffic.json")
+        dom_traffic = load_traffic_rec(f"{dom_file}_two_fluid_128_traffic.json")
         pq_traffic = load_traffic_rec("cg_pq_two_fluid_128_traffic.json")
         rap_traffic = load_traffic_rec("galerkin_two_fluid_128_traffic.json")
     elif cfg_id == 7:
         pq_traffic = load_traffic_rec("cg_pq_coupled4_56_traffic.json")
-    dom_rec = roof(f"{kernel_names(dom, bm, plane, block)}: class '{dom}', every level (the step's largest "
-                   f"kernel time)", d_ms, d_cnt, d_bytes or 0.0,
-                   dom_traffic)
+    dom_rec = roof(f"{dom_name}: levels {sorted(dom_levels)} (the kernel with the step's largest time)",
+                   d_ms, d_cnt, d_bytes or 0.0, dom_traffic)
     dom_rec["per_level"] = [{"level": l, "launches": kt[l].get(dom, (0, 0))[1],
                              "avg_us": (kt[l][dom][0] * 1e3 / kt[l][dom][1]) if kt[l].get(dom, (0, 0))[1] else None,
-                             "algorithmic_bytes": bm.bytes(dom, l)} for l in range(L) if kt[l].get(dom, (0, 0))[1]]
+                             "algorithmic_bytes": bm.bytes(dom, l)}
+                            for l in sorted(dom_levels) if l < L and kt[l].get(dom, (0, 0))[1]]
     spmv_rec = roof(pq_kernel + (" (BiCGStab Krylov operator products v = A p^, t = A s^, level 0)" if bicg
                                  else " (Krylov operator SpMV q = A p and p.q after the direction update, level 0)"
                                  if block > 1 else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
@@ -531,7 +563,7 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
     res = {
         "ms_partial": ms_partial, "n": n, "nnz": nnz, "work": work, "head_prec": head_prec,
         "levels": L, "dims": dims, "ndiag": bm.ndiag, "nread": bm.nread, "plane": plane,
-        "info_p": info_p, "dom": dom, "roofline_dominant": dom_rec, "roofline_spmv": spmv_rec,
+        "info_p": info_p, "dom": dom_name, "roofline_dominant": dom_rec, "by_kernel": by_kernel, "roofline_spmv": spmv_rec,
         "roofline_rap": rap_rec,
         "rap_all_levels": {"ms_per_rebuild": rap_all_ms / max(g_cnt, 1),
                            "algorithmic_bytes": rap_all_bytes / max(g_cnt, 1),
@@ -692,7 +724,8 @@ def main():
         "roofline_rap": res["roofline_rap"],
         "rap_all_levels": res["rap_all_levels"],
         "krylov_spmv_first_iteration": res["krylov_spmv_first_iteration"],
-        "dominant_kernel_class": res["dom"],
+        "dominant_kernel": res["dom"],
+        "kernels_per_step_ms": res["by_kernel"],
         "mall_note": "MI355X has a 256 MB memory-side cache (MALL); at 128^3 part of a kernel's working set can "
                      "stay in it between kernels, so the 128^3 fractions can exceed what HBM alone gives; the "
                      "legs at 192^3 and 160^3 have working sets beyond it",

@@ -338,10 +338,15 @@ struct Trace {
         c->ev_pool.pop_back();
         return e;
     }
-    // Classes that are one kernel launch (the Krylov SpMV, restriction, prolongation) have
-    // the launch record its own events, which time the kernel alone; every other class is
-    // bracketed by events recorded on the stream around it.
-    static bool single_launch(int k) { return k == AMG_K_CG_PQ || k == AMG_K_RESTRICT || k == AMG_K_PROLONG; }
+    // Classes whose scope is one kernel launch have the launch record its own events, which
+    // time the kernel alone (not the dispatch gap before it, and with no extra commands in
+    // the stream); the others (Galerkin products with their smoother, casts, the coarse
+    // inverse, BiCGStab's products) are bracketed by events recorded on the stream.
+    static bool single_launch(int k) {
+        return k == AMG_K_CG_PQ || k == AMG_K_RESTRICT || k == AMG_K_PROLONG || k == AMG_K_JACOBI ||
+               k == AMG_K_SMOOTH0_RES || k == AMG_K_CG_UPDATE || k == AMG_K_CG_RZ || k == AMG_K_CG_INIT ||
+               k == AMG_K_COARSE_GEMV || k == AMG_K_TAIL;
+    }
     bool own = false;
     Trace(amg_ctx* cc, int k, int lvl) : c(cc), cls(k), level(lvl) {
         if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == lvl)) {
@@ -359,10 +364,11 @@ struct Trace {
         if (!a) return;
         if (!own) {
             (void)hipEventRecord(b, c->stream);
-        } else if (g_kernel_events.start == a) {  // no timed launch took them (not expected)
+        } else if (g_kernel_events.start == a) {  // the scope launched nothing: not a launch
             g_kernel_events = KernelEvents{};
-            (void)hipEventRecord(a, c->stream);
-            (void)hipEventRecord(b, c->stream);
+            c->ev_pool.push_back(a);
+            c->ev_pool.push_back(b);
+            return;
         }
         c->traced.push_back({cls, level, a, b});
     }

@@ -4,6 +4,7 @@
 // between host and device after setup except a few scalars per CG iteration.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -259,6 +260,20 @@ struct KernelEvents {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 extern thread_local KernelEvents g_kernel_events;
+
+// Launches kernel k; when the host's trace asked for this kernel's own timing, the launch
+// records its start and stop events itself (hipExtLaunchKernel), so that they bracket the
+// kernel's execution and not the dispatch gap before it.
+template <typename F, typename... Args>
+void timed_launch(F k, unsigned grid, unsigned block, unsigned shmem, hipStream_t s, Args... args) {
+    if (g_kernel_events.start != nullptr) {
+        const KernelEvents e = g_kernel_events;
+        g_kernel_events = KernelEvents{};
+        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, e.start, e.stop, 0, args...);
+    } else {
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, args...);
+    }
+}
 
 std::vector<int> dia_offsets(const Csr& A, hipStream_t s);
 // Two-byte column indices of A for its row blocks (A.rpb > 0): writes cblk (one base per

@@ -311,13 +311,13 @@ template <typename T>
 void launch_block_inv(const Level& L, int B_, double omega, T* m, int* flags, hipStream_t s) {
     need_nodes(L);
     const int nn = L.A.nrows / B_;
-    AMG_WITH_B(B_, k_block_inv<B, T><<<bgrid(nn), TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), omega, m, flags));
+    AMG_WITH_B(B_, timed_launch(k_block_inv<B, T>, bgrid(nn), TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), omega, m, flags));
     HIP_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_block_apply(int n, int B_, const T* m, const T* r, const T* uin, T* uout, hipStream_t s) {
-    AMG_WITH_B(B_, k_block_apply<B, T><<<bgrid(n), TPB_B, 0, s>>>(n, m, r, uin, uout));
+    AMG_WITH_B(B_, timed_launch(k_block_apply<B, T>, bgrid(n), TPB_B, 0, s, n, m, r, uin, uout));
     HIP_LAUNCH_CHECK();
 }
 
@@ -328,7 +328,7 @@ void launch_node_residual(const Level& L, int B_, const T* f, const T* u, T* r, 
     need_nodes(L);
     const int nn = L.A.nrows / B_;
     const unsigned nb = (unsigned)std::max(1, node_grid(nn));
-    AMG_WITH_B(B_, k_node_residual<B, T><<<nb, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r));
+    AMG_WITH_B(B_, timed_launch(k_node_residual<B, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r));
     HIP_LAUNCH_CHECK();
 }
 
@@ -337,7 +337,7 @@ void launch_node_sweep(const Level& L, int B_, const T* m, const T* f, const T* 
     need_nodes(L);
     const int nn = L.A.nrows / B_;
     const unsigned nb = (unsigned)std::max(1, node_grid(nn));
-    AMG_WITH_B(B_, k_node_sweep<B, T><<<nb, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin,
+    AMG_WITH_B(B_, timed_launch(k_node_sweep<B, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin,
                                                                           uout));
     HIP_LAUNCH_CHECK();
 }
@@ -353,7 +353,7 @@ int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z
     const int nb = std::max(1, std::min(node_grid(nn), rs.cap));
     const KernelEvents e = g_kernel_events;
     g_kernel_events = KernelEvents{};
-    k_node_pupdate<<<bgrid(n), TPB_B, 0, s>>>(n, z, pold, pnew, first, rs);
+    timed_launch(k_node_pupdate, bgrid(n), TPB_B, 0, s, n, z, pold, pnew, first, rs);
     HIP_LAUNCH_CHECK();
     const double* p = pnew;
     AMG_WITH_B(B_, {
@@ -374,7 +374,7 @@ int launch_node_sweep_rz(const Level& L, int B_, const double* m, const double* 
     const int nn = L.A.nrows / B_;
     const int nb = std::max(1, node_grid(nn));
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    AMG_WITH_B(B_, k_node_sweep_rz<B><<<nb, TPB_B, 0, s>>>(nn, L.nptr, L.ncol, L.A.val, m, r, uin, z, rs));
+    AMG_WITH_B(B_, timed_launch(k_node_sweep_rz<B>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.val, m, r, uin, z, rs));
     HIP_LAUNCH_CHECK();
     return nb;
 }

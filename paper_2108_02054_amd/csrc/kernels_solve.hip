@@ -56,20 +56,6 @@ __device__ __forceinline__ T wave_sum(T s) {
 
 thread_local KernelEvents g_kernel_events;
 
-// Launches kernel k; when the host's trace asked for this kernel's own timing, the launch
-// records its start and stop events itself (hipExtLaunchKernel), so that they bracket the
-// kernel's execution and not the dispatch gap before it.
-template <typename F, typename... Args>
-void timed_launch(F k, unsigned grid, unsigned block, unsigned shmem, hipStream_t s, Args... args) {
-    if (g_kernel_events.start != nullptr) {
-        const KernelEvents e = g_kernel_events;
-        g_kernel_events = KernelEvents{};
-        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, e.start, e.stop, 0, args...);
-    } else {
-        hipLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, args...);
-    }
-}
-
 static inline unsigned grid_for(int64_t items, int per_block) {
     int64_t b = (items + per_block - 1) / per_block;
     return (unsigned)(b > 0 ? b : 1);
@@ -180,11 +166,11 @@ __global__ __launch_bounds__(TPB) void k_c16_fill(int n, int rpb, const int* __r
 
 void launch_c16_bases(const Csr& A, int32_t* cblk, int* wide, hipStream_t s) {
     const int nb = (A.nrows + A.rpb - 1) / A.rpb;
-    k_c16_bases<<<(unsigned)((nb + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, cblk, wide);
+    timed_launch(k_c16_bases, (unsigned)((nb + TPB - 1) / TPB), TPB, 0, s, A.nrows, A.rpb, A.ptr, A.col, cblk, wide);
     HIP_LAUNCH_CHECK();
 }
 void launch_c16_fill(const Csr& A, const int32_t* cblk, uint16_t* c16, hipStream_t s) {
-    k_c16_fill<<<(unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, cblk, c16);
+    timed_launch(k_c16_fill, (unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s, A.nrows, A.rpb, A.ptr, A.col, cblk, c16);
     HIP_LAUNCH_CHECK();
 }
 
@@ -461,7 +447,7 @@ static inline unsigned ew_blocks(int64_t n) {
         if ((A).rpb > 0) {                                                                              \
             RBCALL;                                                                                     \
         } else {                                                                                        \
-            AMG_WITH_G((A).g, (k_lg<G, T, KIND><<<grid_for((int64_t)(A).nrows * G, TPB), TPB, 0, s>>>(__VA_ARGS__))); \
+            AMG_WITH_G((A).g, (timed_launch(k_lg<G, T, KIND>, grid_for((int64_t)(A).nrows * G, TPB), TPB, 0, s, __VA_ARGS__))); \
         }                                                                                               \
         HIP_LAUNCH_CHECK();                                                                             \
     } while (0)
@@ -482,17 +468,17 @@ void launch_spmv(const Csr& A, const T* x, T* y, const T* m2, T* y2, hipStream_t
 }
 template <typename T>
 void launch_residual(const Csr& A, const T* f, const T* u, T* r, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), f, u, r)),
+    AMG_RB_OR_LG(A, (timed_launch(k_rb_residual<T>, grid_for(A.nrows, A.rpb), RB_THREADS, 0, s, A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), f, u, r)),
                  1, A.nrows, A.ptr, A.col, A.v<T>(), nullptr, f, u, r, nullptr);
 }
 template <typename T>
 void launch_jacobi(const Csr& A, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_jacobi<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), m, f, u, uout)),
+    AMG_RB_OR_LG(A, (timed_launch(k_rb_jacobi<T>, grid_for(A.nrows, A.rpb), RB_THREADS, 0, s, A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), m, f, u, uout)),
                  2, A.nrows, A.ptr, A.col, A.v<T>(), m, f, u, uout, nullptr);
 }
 template <typename T>
 void launch_smooth0_residual(const Csr& A, const T* m, const T* f, T* u, T* r, hipStream_t s) {
-    AMG_RB_OR_LG(A, (k_rb_smooth0_residual<T><<<grid_for(A.nrows, A.rpb), RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), m, f, u, r)),
+    AMG_RB_OR_LG(A, (timed_launch(k_rb_smooth0_residual<T>, grid_for(A.nrows, A.rpb), RB_THREADS, 0, s, A.nrows, A.rpb, A.ptr, colsrc(A), A.v<T>(), m, f, u, r)),
                  3, A.nrows, A.ptr, A.col, A.v<T>(), m, f, nullptr, u, r);
 }
 template <typename T>
@@ -509,19 +495,19 @@ void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s) {
 }
 template <typename T>
 void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s) {
-    k_coarse_gemv<T><<<grid_for((int64_t)n * 64, TPB), TPB, 0, s>>>(n, inv, f, u);
+    timed_launch(k_coarse_gemv<T>, grid_for((int64_t)n * 64, TPB), TPB, 0, s, n, inv, f, u);
     HIP_LAUNCH_CHECK();
 }
 void launch_cast_d2f(int64_t n, const double* a, float* b, hipStream_t s) {
-    k_cast_d2f<<<ew_blocks(n), TPB, 0, s>>>(n, a, b);
+    timed_launch(k_cast_d2f, ew_blocks(n), TPB, 0, s, n, a, b);
     HIP_LAUNCH_CHECK();
 }
 void launch_cast_f2d(int64_t n, const float* a, double* b, hipStream_t s) {
-    k_cast_f2d<<<ew_blocks(n), TPB, 0, s>>>(n, a, b);
+    timed_launch(k_cast_f2d, ew_blocks(n), TPB, 0, s, n, a, b);
     HIP_LAUNCH_CHECK();
 }
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t s) {
-    k_copy<<<ew_blocks(n), TPB, 0, s>>>(n, a, b);
+    timed_launch(k_copy, ew_blocks(n), TPB, 0, s, n, a, b);
     HIP_LAUNCH_CHECK();
 }
 
@@ -803,7 +789,7 @@ std::vector<int> dia_offsets(const Csr& A, hipStream_t s) {
     std::vector<int> init(DIA_TAB + 1, DIA_EMPTY);
     init[DIA_TAB] = 0;
     HIP_CHECK(hipMemcpyAsync(buf, init.data(), init.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    k_dia_offsets<<<(unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.ptr, A.col, buf, buf + DIA_TAB);
+    timed_launch(k_dia_offsets, (unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s, A.nrows, A.ptr, A.col, buf, buf + DIA_TAB);
     HIP_LAUNCH_CHECK();
     std::vector<int> h(DIA_TAB + 1);
     HIP_CHECK(hipMemcpyAsync(h.data(), buf, h.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -819,7 +805,7 @@ std::vector<int> dia_offsets(const Csr& A, hipStream_t s) {
 }
 
 void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s) {
-    k_dia_slots<<<(unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s>>>(A.nrows, A.ptr, A.col, D.ndiag, D.off, D.slot);
+    timed_launch(k_dia_slots, (unsigned)((A.nrows + TPB - 1) / TPB), TPB, 0, s, A.nrows, A.ptr, A.col, D.ndiag, D.off, D.slot);
     HIP_LAUNCH_CHECK();
 }
 
@@ -1289,80 +1275,74 @@ inline bool march_call(const Dia& D, F&& f) {
 template <typename T>
 void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s) {
     if (D.ndiag >= SC_TILE_MIN_DIAG)
-        k_dia_scatter<T><<<grid_for(A.nrows, SC_ROWS), TPB, 0, s>>>(A.nrows, D.ndiag, A.ptr, D.slot, val, dval);
+        timed_launch(k_dia_scatter<T>, grid_for(A.nrows, SC_ROWS), TPB, 0, s, A.nrows, D.ndiag, A.ptr, D.slot, val, dval);
     else
-        k_dia_scatter_rows<T><<<dia_blocks(A.nrows), TPB, 0, s>>>(A.nrows, A.ptr, D.slot, val, dval);
+        timed_launch(k_dia_scatter_rows<T>, dia_blocks(A.nrows), TPB, 0, s, A.nrows, A.ptr, D.slot, val, dval);
     HIP_LAUNCH_CHECK();
 }
 
 void launch_dia_symcheck(int n, const Dia& D, double* scal, hipStream_t s) {
-    k_dia_clear<<<1, 64, 0, s>>>(scal + S_ASYM);
+    timed_launch(k_dia_clear, 1, 64, 0, s, scal + S_ASYM);
     HIP_LAUNCH_CHECK();
     if (n == 0) return;
-    k_dia_symcheck<<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.val, scal + S_ASYM);
+    timed_launch(k_dia_symcheck, dia_blocks(n), TPB, 0, s, n, D.ndiag, D.off, D.val, scal + S_ASYM);
     HIP_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T* u, T* r, hipStream_t s) {
     if (march_call(D, [&](auto S) {
-            k_m7_smooth0_residual<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
-                n, D.march_a, D.march_b, D.v<T>(), m, f, u, r);
+            timed_launch(k_m7_smooth0_residual<decltype(S)::value, T>, march_blocks(n, D.march_a), TPB, 0, s, n, D.march_a, D.march_b, D.v<T>(), m, f, u, r);
         })) {
         HIP_LAUNCH_CHECK();
         return;
     }
     if (win_call(D, [&](auto K, auto S) {
-            k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, T>
-                <<<dia_blocks(n), TPB, win_bytes<T>(D), s>>>(n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
+            timed_launch(k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, T>, dia_blocks(n), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
         }, std::is_same<T, double>::value)) {
         HIP_LAUNCH_CHECK();
         return;
     }
     dia_nd(D.ndiag, [&](auto K) {
-        k_dia_smooth0_residual<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, r);
+        timed_launch(k_dia_smooth0_residual<T, decltype(K)::value>, dia_blocks(n), TPB, 0, s, n, D.ndiag, D.off, D.v<T>(), m, f, u, r);
     });
     HIP_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipStream_t s) {
     if (march_call(D, [&](auto S) {
-            k_m7_residual<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
-                n, D.march_a, D.march_b, D.v<T>(), f, u, r);
+            timed_launch(k_m7_residual<decltype(S)::value, T>, march_blocks(n, D.march_a), TPB, 0, s, n, D.march_a, D.march_b, D.v<T>(), f, u, r);
         })) {
         HIP_LAUNCH_CHECK();
         return;
     }
     if (win_call(D, [&](auto K, auto S) {
-            k_w_residual<decltype(K)::value, decltype(S)::value, T>
-                <<<dia_blocks(n), TPB, win_bytes<T>(D), s>>>(n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
+            timed_launch(k_w_residual<decltype(K)::value, decltype(S)::value, T>, dia_blocks(n), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
         })) {
         HIP_LAUNCH_CHECK();
         return;
     }
     dia_nd(D.ndiag, [&](auto K) {
-        k_dia_residual<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), f, u, r);
+        timed_launch(k_dia_residual<T, decltype(K)::value>, dia_blocks(n), TPB, 0, s, n, D.ndiag, D.off, D.v<T>(), f, u, r);
     });
     HIP_LAUNCH_CHECK();
 }
 template <typename T>
 void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, T* uout, hipStream_t s) {
     if (march_call(D, [&](auto S) {
-            k_m7_jacobi<decltype(S)::value, T><<<march_blocks(n, D.march_a), TPB, 0, s>>>(
-                n, D.march_a, D.march_b, D.v<T>(), m, f, u, uout);
+            timed_launch(k_m7_jacobi<decltype(S)::value, T>, march_blocks(n, D.march_a), TPB, 0, s, n, D.march_a, D.march_b, D.v<T>(), m, f, u, uout);
         })) {
         HIP_LAUNCH_CHECK();
         return;
     }
     if (win_call(D, [&](auto K, auto S) {
-            k_w_jacobi<decltype(K)::value, decltype(S)::value, T>
-                <<<dia_blocks(n), TPB, win_bytes<T>(D), s>>>(n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
+            timed_launch(k_w_jacobi<decltype(K)::value, decltype(S)::value, T>, dia_blocks(n), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
         })) {
         HIP_LAUNCH_CHECK();
         return;
     }
     dia_nd(D.ndiag, [&](auto K) {
-        k_dia_jacobi<T, decltype(K)::value><<<dia_blocks(n), TPB, 0, s>>>(n, D.ndiag, D.off, D.v<T>(), m, f, u, uout);
+        timed_launch(k_dia_jacobi<T, decltype(K)::value>, dia_blocks(n), TPB, 0, s, n, D.ndiag, D.off, D.v<T>(), m, f, u, uout);
     });
     HIP_LAUNCH_CHECK();
 }
@@ -1370,7 +1350,7 @@ int launch_dia_cg_init(int n, const Dia& D, const double* f, const double* x, do
                        hipStream_t s) {
     const int nb = red_grid_elems(n);
     dia_nd(D.ndiag, [&](auto K) {
-        k_dia_cg_init<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, f, x, r, rs);
+        timed_launch(k_dia_cg_init<decltype(K)::value>, nb, TPB, 0, s, n, D.ndiag, D.off, D.val, f, x, r, rs);
     });
     HIP_LAUNCH_CHECK();
     return nb;
@@ -1381,7 +1361,7 @@ int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, 
         const int nb = march_blocks(n, D.march_a);
         if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
         march_call(D, [&](auto S) {
-            k_m7_jacobi_rz<decltype(S)::value><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, m, r, u, z,
+            timed_launch(k_m7_jacobi_rz<decltype(S)::value>, nb, TPB, 0, s, n, D.march_a, D.march_b, D.val, m, r, u, z,
                                                                    flexible, rs);
         });
         HIP_LAUNCH_CHECK();
@@ -1390,14 +1370,13 @@ int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, 
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     if (win_call(D, [&](auto K, auto S) {
-            k_w_jacobi_rz<decltype(K)::value, decltype(S)::value>
-                <<<nb, TPB, win_bytes<double>(D), s>>>(n, D.ndiag, D.off, D.win, D.val, m, r, u, z, flexible, rs);
+            timed_launch(k_w_jacobi_rz<decltype(K)::value, decltype(S)::value>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, m, r, u, z, flexible, rs);
         })) {
         HIP_LAUNCH_CHECK();
         return nb;
     }
     dia_nd(D.ndiag, [&](auto K) {
-        k_dia_jacobi_rz<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
+        timed_launch(k_dia_jacobi_rz<decltype(K)::value>, nb, TPB, 0, s, n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
     });
     HIP_LAUNCH_CHECK();
     return nb;
@@ -1453,7 +1432,7 @@ int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double
         const int nb = march_blocks(n, D.march_a);
         if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
         march_call(D, [&](auto S) {
-            k_m7_update_smooth0<decltype(S)::value><<<nb, TPB, 0, s>>>(n, D.march_a, D.march_b, D.val, p, q, x, r,
+            timed_launch(k_m7_update_smooth0<decltype(S)::value>, nb, TPB, 0, s, n, D.march_a, D.march_b, D.val, p, q, x, r,
                                                                         rn, m, u, rv, rs);
         });
         HIP_LAUNCH_CHECK();
@@ -1462,14 +1441,13 @@ int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double
     const int nb = (int)dia_blocks(n);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     if (win_call(D, [&](auto K, auto S) {
-            k_w_update_smooth0<decltype(K)::value, decltype(S)::value>
-                <<<nb, TPB, win_bytes<double>(D), s>>>(n, D.ndiag, D.off, D.win, D.val, p, q, x, r, rn, m, u, rv, rs);
+            timed_launch(k_w_update_smooth0<decltype(K)::value, decltype(S)::value>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, p, q, x, r, rn, m, u, rv, rs);
         }, true)) {
         HIP_LAUNCH_CHECK();
         return nb;
     }
     dia_nd(D.ndiag, [&](auto K) {
-        k_dia_update_smooth0<decltype(K)::value><<<nb, TPB, 0, s>>>(n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
+        timed_launch(k_dia_update_smooth0<decltype(K)::value>, nb, TPB, 0, s, n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
     });
     HIP_LAUNCH_CHECK();
     return nb;
@@ -1631,7 +1609,7 @@ void launch_vcycle_tail(const TailArgs<T>& a, hipStream_t s) {
     }
     const size_t sm = need * sizeof(T);
     if (sm > TAIL_SMEM_MAX) throw Fail{AMG_ERR_ARG, "coarse tail too large"};
-    k_vcycle_tail<T><<<1, TAIL_THREADS, sm, s>>>(a);
+    timed_launch(k_vcycle_tail<T>, 1, TAIL_THREADS, sm, s, a);
     HIP_LAUNCH_CHECK();
 }
 
@@ -1910,7 +1888,7 @@ __global__ __launch_bounds__(TPB) void k_cg_update_cast(int n, const double* __r
 int launch_cg_init(const Csr& A, const double* val, const double* f, const double* x, double* r, const RedScratch& rs,
                    hipStream_t s) {
     const int nb = red_grid_rows(A.nrows, A.rpb, A.g);
-    AMG_WITH_G(A.g, k_cg_init<G><<<nb, RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, val, f, x, r, rs));
+    AMG_WITH_G(A.g, timed_launch(k_cg_init<G>, nb, RB_THREADS, 0, s, A.nrows, A.rpb, A.ptr, A.col, val, f, x, r, rs));
     HIP_LAUNCH_CHECK();
     return nb;
 }
@@ -1918,29 +1896,29 @@ int launch_jacobi_rz(const Csr& A, const double* m, const double* r, const doubl
                      const RedScratch& rs, hipStream_t s) {
     const int nb = full_grid_rows(A.nrows, A.rpb, A.g);
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    AMG_WITH_G(A.g, k_jacobi_rz<G><<<nb, RB_THREADS, 0, s>>>(A.nrows, A.rpb, A.ptr, A.col, A.val, m, r, u, z, flexible, rs));
+    AMG_WITH_G(A.g, timed_launch(k_jacobi_rz<G>, nb, RB_THREADS, 0, s, A.nrows, A.rpb, A.ptr, A.col, A.val, m, r, u, z, flexible, rs));
     HIP_LAUNCH_CHECK();
     return nb;
 }
 int launch_cast_rz(int n, const float* z32, const double* r, double* z, int flexible, const RedScratch& rs,
                    hipStream_t s) {
     const int nb = red_grid_elems(n);
-    k_cast_rz<<<nb, TPB, 0, s>>>(n, z32, r, z, flexible, rs);
+    timed_launch(k_cast_rz, nb, TPB, 0, s, n, z32, r, z, flexible, rs);
     HIP_LAUNCH_CHECK();
     return nb;
 }
 int launch_cg_rz(int n, const double* r, const double* z, const RedScratch& rs, hipStream_t s) {
     const int nb = red_grid_elems(n);
-    k_cg_rz<<<nb, TPB, 0, s>>>(n, r, z, rs);
+    timed_launch(k_cg_rz, nb, TPB, 0, s, n, r, z, rs);
     HIP_LAUNCH_CHECK();
     return nb;
 }
 void launch_fin_rz(int nb, int flexible, int first, const RedScratch& rs, hipStream_t s) {
-    k_fin_rz<<<1, FIN_THREADS, 0, s>>>(nb, flexible, first, rs);
+    timed_launch(k_fin_rz, 1, FIN_THREADS, 0, s, nb, flexible, first, rs);
     HIP_LAUNCH_CHECK();
 }
 void launch_fin_pq(int nb, const RedScratch& rs, hipStream_t s) {
-    k_fin_pq<<<1, FIN_THREADS, 0, s>>>(nb, rs);
+    timed_launch(k_fin_pq, 1, FIN_THREADS, 0, s, nb, rs);
     HIP_LAUNCH_CHECK();
 }
 int launch_cg_pq(const Csr& A, const double* val, const double* z, const double* pold, double* pnew, double* q,
@@ -1955,14 +1933,14 @@ int launch_cg_pq(const Csr& A, const double* val, const double* z, const double*
 int launch_cg_update(int n, const double* p, const double* q, double* x, double* r, const RedScratch& rs,
                      hipStream_t s) {
     const int nb = red_grid_elems(n);
-    k_cg_update<<<nb, TPB, 0, s>>>(n, p, q, x, r, rs);
+    timed_launch(k_cg_update, nb, TPB, 0, s, n, p, q, x, r, rs);
     HIP_LAUNCH_CHECK();
     return nb;
 }
 int launch_cg_update_cast(int n, const double* p, const double* q, double* x, double* r, float* r32,
                           const RedScratch& rs, hipStream_t s) {
     const int nb = red_grid_elems(n);
-    k_cg_update_cast<<<nb, TPB, 0, s>>>(n, p, q, x, r, r32, rs);
+    timed_launch(k_cg_update_cast, nb, TPB, 0, s, n, p, q, x, r, r32, rs);
     HIP_LAUNCH_CHECK();
     return nb;
 }
