@@ -66,7 +66,8 @@ typedef struct {
     int aggregation;      /* 0: smoothed aggregation; 1: plain aggregation (P = tentative) */
     double jacobi_omega;  /* Jacobi damping (0.72) */
     double eps_strong;    /* strength threshold on level 0, halved per level (0.08) */
-    int coarse_enough;    /* stop coarsening at <= this many rows (128) */
+    int coarse_enough;    /* stop coarsening at <= this many rows (1024; the coarsest level
+                           * gets a dense inverse, which takes at most 2048 rows) */
     int max_levels;       /* (12) */
     int npre, npost;      /* Jacobi/SPAI0 sweeps before and after the coarse correction (1, 1) */
     int precision;        /* 0: FP64 everywhere; 1: FP32 hierarchy and V-cycle under FP64 CG */

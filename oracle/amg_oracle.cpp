@@ -1048,7 +1048,7 @@ void ora_params_default(ora_params* p) {
     p->aggregation = 0;
     p->jacobi_omega = 0.72;
     p->eps_strong = 0.08;
-    p->coarse_enough = 128;
+    p->coarse_enough = 1024;
     p->max_levels = 12;
     p->npre = 1;
     p->npost = 1;

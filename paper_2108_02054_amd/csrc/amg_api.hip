@@ -585,13 +585,26 @@ void release_dia(amg_ctx* c) {
 // are checked on the device, and the solve switches to the symmetric read (half the
 // diagonals) once it has seen the result (c->dia.off.sym, set in the CG's first
 // residual read-back).
-void refresh_dia(amg_ctx* c) {
+// scatter = false: the values are already there (the level-0 A P kernel wrote them).
+void refresh_dia(amg_ctx* c, bool scatter = true) {
     if (c->dia.ndiag == 0) return;
     const Level& L0 = c->lv[0];
-    launch_dia_scatter<double>(L0.A, c->dia, L0.A.val, c->dia.val, c->stream);
-    if (c->dia.val32) launch_dia_scatter<float>(L0.A, c->dia, L0.A.val, c->dia.val32, c->stream);
+    if (scatter) {
+        launch_dia_scatter<double>(L0.A, c->dia, L0.A.val, c->dia.val, c->stream);
+        if (c->dia.val32) launch_dia_scatter<float>(L0.A, c->dia, L0.A.val, c->dia.val32, c->stream);
+    }
     c->dia.off.sym = 0;
     if (c->dia.symoff) launch_dia_symcheck(L0.A.nrows, c->dia, c->rs.scal(), c->stream);
+}
+
+// The CSR values of level 0 again equal to its diagonal storage (after partial updates
+// that wrote only the latter).
+void ensure_a0_csr(amg_ctx* c) {
+    if (!c->a0_csr_stale) return;
+    const Level& L0 = c->lv[0];
+    launch_dia_gather<double>(L0.A, c->dia, c->dia.val, L0.A.val, c->stream);
+    if (c->dia.val32 && L0.A.val32) launch_dia_gather<float>(L0.A, c->dia, c->dia.val32, L0.A.val32, c->stream);
+    c->a0_csr_stale = false;
 }
 
 // After a read-back of the scalar slots: use the symmetric read when the last refresh
@@ -665,6 +678,9 @@ void partial_rebuild(amg_ctx* c, const double* val) {
         if constexpr (std::is_same<T, float>::value) launch_cast_d2f(L0.A.nnz, L0.A.val, L0.A.val32, s);
         ingested = true;
     }
+    // with a diagonal storage of A_0 the A P kernel writes the new values there and not
+    // into the CSR copy, which is formed again only when it is read (ensure_a0_csr)
+    const bool direct = !ingested && c->dia.ndiag > 0;
     for (int l = 0; l + 1 < nlev; ++l) {
         const Level& L = c->lv[l];
         {
@@ -672,7 +688,8 @@ void partial_rebuild(amg_ctx* c, const double* val) {
             Trace tr(c, AMG_K_GALERKIN_AP, l);
             const bool fused = launch_galerkin_ap<T>(L.A, L.P, L.AP, L.gAP, L.galAP, c->prm.smoother,
                                                      c->prm.jacobi_omega, blocked ? nullptr : L.mv<T>(),
-                                                     (l == 0 && !ingested) ? val : nullptr, s);
+                                                     (l == 0 && !ingested) ? val : nullptr, s,
+                                                     (l == 0 && direct) ? &c->dia : nullptr);
             smoothed[(size_t)l] = fused && !blocked;
         }
         Trace tr(c, AMG_K_GALERKIN_RAP, l);
@@ -680,8 +697,9 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     }
     {
         Trace tr(c, AMG_K_CAST, 0);
-        refresh_dia(c);
+        refresh_dia(c, !direct);
     }
+    if (direct && val != L0.A.val) c->a0_csr_stale = true;
     HIP_CHECK(hipEventRecord(c->ev[1], s));
     for (int l = 0; l + 1 < nlev; ++l) {
         if (smoothed[(size_t)l]) continue;
@@ -696,7 +714,7 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     {
         Trace tr(c, AMG_K_COARSE_INV, nlev - 1);
         launch_densify<T>(c->lv.back().A, c->cinv, s);
-        launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), s);
+        launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), c->cwork, s);
     }
     HIP_CHECK(hipEventRecord(c->ev[3], s));
     c->phase_pending = true;
@@ -812,7 +830,9 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     c->lv.clear();
     c->outer_own = nullptr;
     c->cinv = nullptr;
+    c->cwork = nullptr;
     c->dia = Dia{};  // its arrays were hierarchy allocations
+    c->a0_csr_stale = false;
     c->tail = 0;
     c->lv.emplace_back();
     c->lv[0].A = A0;
@@ -954,8 +974,9 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     if (c->nL > COARSE_GLOBAL_MAX)
         throw Fail{AMG_ERR_ARG, "coarsest level has " + std::to_string(c->nL) + " rows; too many for a dense inverse"};
     c->cinv = halloc<double>(c, (size_t)c->nL * c->nL);
+    c->cwork = c->nL > COARSE_LDS_MAX ? halloc<double>(c, COARSE_WORK_DOUBLES) : nullptr;
     launch_densify<double>(c->lv.back().A, c->cinv, s);
-    launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), s);
+    launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), c->cwork, s);
     read_red(c);
     if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
     ph[5] += ms_since(t0);
@@ -995,6 +1016,7 @@ void repattern(amg_ctx* c) {
     release(c, c->outer_own);
     c->outer_own = nullptr;
     L0.A = A;
+    c->a0_csr_stale = false;
     c->outer_val = L0.A.val;
     dfree(c->pend_ptr, s);
     dfree(c->pend_col, s);
@@ -1732,7 +1754,7 @@ amg_status amg_params_default(amg_params* p) {
     p->aggregation = 0;
     p->jacobi_omega = 0.72;
     p->eps_strong = 0.08;
-    p->coarse_enough = 128;
+    p->coarse_enough = 1024;
     p->max_levels = 12;
     p->npre = 1;
     p->npost = 1;
@@ -2080,6 +2102,7 @@ amg_status amg_export_level(const amg_ctx* cc, int l, int32_t* agg, uint8_t* str
             }
         };
         const int32_t n = L.A.nrows;
+        if (l == 0) ensure_a0_csr(c);
         d2h(agg, L.agg, (size_t)n * sizeof(int32_t));
         d2h(strong, L.strong, (size_t)L.A.nnz);
         d2h(A_ptr, L.A.ptr, ((size_t)n + 1) * sizeof(int32_t));

@@ -305,6 +305,8 @@ template <typename T>
 void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, hipStream_t s);
 // scal[S_ASYM] = 0 when every stored sub-diagonal entry equals its mirror (bit for bit), 1
 // otherwise; needs D.symoff and the FP64 values just scattered.
+template <typename T>
+void launch_dia_gather(const Csr& A, const Dia& D, const T* dval, T* val, hipStream_t s);
 void launch_dia_symcheck(int n, const Dia& D, double* scal, hipStream_t s);
 template <typename T>
 void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T* u, T* r, hipStream_t s);
@@ -387,7 +389,7 @@ template <typename T>
 void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_t s);
 template <typename T>
 bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalShape gs, int kind, double omega, T* m,
-                        const double* ain, hipStream_t s);
+                        const double* ain, hipStream_t s, const Dia* dia = nullptr);
 template <typename T>
 void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s);
 GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen_c, int gforce);
@@ -444,10 +446,14 @@ int64_t max_i64(const int64_t* in, int64_t n, hipStream_t s);  // synchronises
 
 // ------------------------------------------------------------------ coarse solve
 constexpr int COARSE_LDS_MAX = 128;      // dense FP64 inverse held in one workgroup's LDS
-constexpr int COARSE_GLOBAL_MAX = 8192;  // larger coarsest levels work in global memory
+constexpr int COARSE_GLOBAL_MAX = 2048;  // larger coarsest levels: blocked, many workgroups
+constexpr size_t COARSE_WORK_DOUBLES = 2 * 64 * 64;  // scratch of the blocked inverse
 template <typename T>
 void launch_densify(const Csr& A, double* D, hipStream_t s);
-void launch_dense_inverse(int n, double* D, double* scal, hipStream_t s);
+// In-place inverse of the dense n x n coarsest operator (Gauss-Jordan, positive pivots;
+// scal[S_COARSE] = 1 when one is not).  work: COARSE_WORK_DOUBLES doubles, needed when
+// n > COARSE_LDS_MAX.
+void launch_dense_inverse(int n, double* D, double* scal, double* work, hipStream_t s);
 
 // ------------------------------------------------------------------ differentiable form
 void launch_logcoef7_assemble(int nx, int ny, int nz, const double* theta, double* val, hipStream_t s);
@@ -478,6 +484,7 @@ struct amg_ctx {
     int tail = 0;                 // first level of the fused coarse tail (0: none)
     amgmi::Dia dia;               // diagonal storage of A_0 (ndiag 0: CSR kernels)
     double* cinv = nullptr;       // dense inverse of the coarsest operator (FP64)
+    double* cwork = nullptr;      // scratch of its blocked inverse (more than COARSE_LDS_MAX rows)
     // CG state
     double *x = nullptr, *r = nullptr, *r2 = nullptr, *z = nullptr, *zold = nullptr, *pa = nullptr, *pb = nullptr,
            *q = nullptr;
@@ -522,6 +529,9 @@ struct amg_ctx {
     // set while a full setup or a pattern change replaces the hierarchy: a failure then
     // leaves the context unusable (broken)
     bool replacing = false;
+    // the partial update wrote A_0's new values straight into the diagonal storage: the CSR
+    // value arrays of level 0 are formed from it when they are read (exports)
+    bool a0_csr_stale = false;
     bool broken = false;
     std::string err;
 };

@@ -164,7 +164,8 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
     const uint16_t* __restrict__ Ltof, const T* __restrict__ Bval, const int* __restrict__ Cptr,
     T* __restrict__ Cval, const PT* __restrict__ pos, const int64_t* __restrict__ poff,
     const int* __restrict__ dpos, int kind, T omega, T* __restrict__ m, const double* __restrict__ lin,
-    double* __restrict__ lout64, T* __restrict__ loutT) {
+    double* __restrict__ lout64, T* __restrict__ loutT, const uint8_t* __restrict__ dslot, int64_t dn,
+    double* __restrict__ dout64, T* __restrict__ doutT) {
     extern __shared__ __align__(16) unsigned char wf_smem[];
     constexpr int NE = EPL * G;  // L entries per chunk
     const int g = threadIdx.x & (G - 1);
@@ -196,6 +197,11 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
                     const double x = lin[t];
                     if (lout64 != nullptr) lout64[t] = x;
                     if (loutT != nullptr) loutT[t] = (T)x;
+                    if (dslot != nullptr) {  // straight into the diagonal storage of L
+                        const size_t q = (size_t)dslot[t] * (size_t)dn + (size_t)row;
+                        dout64[q] = x;
+                        if (doutT != nullptr) doutT[q] = (T)x;
+                    }
                     lv = (T)x;
                 } else {
                     lv = Lval[t];
@@ -433,13 +439,19 @@ static size_t acc_smem(const GalShape& gs) {
 // Launches the position-map kernel for one product with the shape's template arguments.
 template <typename T>
 static void launch_pos(const Csr& L, const Csr& B, const Csr& C, const GalShape& gs, int kind, double omega, T* m,
-                       const double* lin, double* lout64, T* loutT, hipStream_t s) {
+                       const double* lin, double* lout64, T* loutT, hipStream_t s, const Dia* dia = nullptr) {
     const size_t sm = acc_smem<T>(gs);
     const int* dp = m != nullptr ? gs.dpos : nullptr;
+    const uint8_t* dslot = dia != nullptr ? dia->slot : nullptr;
+    double* d64 = dia != nullptr ? dia->val : nullptr;
+    T* dT = nullptr;
+    if constexpr (!std::is_same<T, double>::value)
+        if (dia != nullptr) dT = dia->val32;
 #define AMG_POS_LAUNCH(PT, EPL)                                                                           \
     AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, PT, EPL><<<row_blocks(L.nrows, GG), TPB, sm, s>>>(           \
                            L.nrows, gs.cap, L.ptr, L.v<T>(), gs.bst, gs.tof, B.v<T>(), C.ptr, C.v<T>(),     \
-                           (const PT*)gs.pos, gs.off, dp, kind, (T)omega, m, lin, lout64, loutT)))
+                           (const PT*)gs.pos, gs.off, dp, kind, (T)omega, m, lin, lout64, loutT, dslot,     \
+                           (int64_t)L.nrows, d64, dT)))
     if (gs.wide) {
         if (gs.epl == 4) AMG_POS_LAUNCH(uint16_t, 4);
         else AMG_POS_LAUNCH(uint16_t, 2);
@@ -458,16 +470,19 @@ void launch_smoother_diag(const Csr& A, int kind, double omega, T* m, hipStream_
 }
 
 // AP = A P; with m != nullptr also the smoother diagonal of A, and with ain != nullptr
-// the values of A are taken from ain (FP64) and stored into A's value arrays on the way.
-// Only the position-map form fuses these; it returns true when it did (m and A written).
+// the values of A are taken from ain (FP64) and stored on the way: into the diagonal
+// storage `dia` when one is given (its FP64 and, in mixed precision, FP32 arrays), else
+// into A's CSR value arrays.  Only the position-map form fuses these; it returns true when
+// it did (m and the values written).
 template <typename T>
 bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalShape gs, int kind, double omega, T* m,
-                        const double* ain, hipStream_t s) {
+                        const double* ain, hipStream_t s, const Dia* dia) {
     if (gs.g > 0) {
-        double* out64 = (ain != nullptr && ain != A.val) ? A.val : nullptr;
+        const bool to_dia = dia != nullptr && ain != nullptr;
+        double* out64 = (!to_dia && ain != nullptr && ain != A.val) ? A.val : nullptr;
         T* outT = nullptr;
-        if constexpr (!std::is_same<T, double>::value) outT = ain != nullptr ? A.v<T>() : nullptr;
-        launch_pos<T>(A, P, AP, gs, kind, omega, m, ain, out64, outT, s);
+        if constexpr (!std::is_same<T, double>::value) outT = (!to_dia && ain != nullptr) ? A.v<T>() : nullptr;
+        launch_pos<T>(A, P, AP, gs, kind, omega, m, ain, out64, outT, s, to_dia ? dia : nullptr);
         return true;
     }
     if (ain != nullptr) return false;  // the caller ingests the values first, then calls again
@@ -489,9 +504,9 @@ void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalS
 }
 
 template bool launch_galerkin_ap<double>(const Csr&, const Csr&, const Csr&, int, GalShape, int, double, double*,
-                                         const double*, hipStream_t);
+                                         const double*, hipStream_t, const Dia*);
 template bool launch_galerkin_ap<float>(const Csr&, const Csr&, const Csr&, int, GalShape, int, double, float*,
-                                        const double*, hipStream_t);
+                                        const double*, hipStream_t, const Dia*);
 template void launch_galerkin_rap<double>(const Csr&, const Csr&, const Csr&, int, GalShape, hipStream_t);
 template void launch_galerkin_rap<float>(const Csr&, const Csr&, const Csr&, int, GalShape, hipStream_t);
 template void launch_smoother_diag<double>(const Csr&, int, double, double*, hipStream_t);

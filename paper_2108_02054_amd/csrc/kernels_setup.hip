@@ -763,20 +763,15 @@ template void launch_densify<float>(const Csr&, double*, hipStream_t);
 
 // In-place inverse of an SPD matrix by Gauss-Jordan elimination without pivoting (the
 // pivots are the positive LDL^T pivots of an SPD matrix; a non-positive or non-finite
-// pivot reports "not SPD" in scal[S_COARSE]).  One workgroup; when n <= COARSE_LDS_MAX
-// the matrix is held in LDS (128 x 128 FP64 = 128 KiB of the 160 KiB available).
-template <bool IN_LDS>
+// pivot reports "not SPD" in scal[S_COARSE]).  One workgroup, n <= COARSE_LDS_MAX: the
+// matrix is held in LDS (128 x 128 FP64 = 128 KiB of the 160 KiB available).
 __global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restrict__ Mg, double* __restrict__ scal) {
-    constexpr int CAP = IN_LDS ? COARSE_LDS_MAX : COARSE_GLOBAL_MAX;
+    constexpr int CAP = COARSE_LDS_MAX;
     __shared__ double colk[CAP];
     __shared__ double rowk[CAP];
     __shared__ int bad;
-    double* M = Mg;
-    if constexpr (IN_LDS) {
-        __shared__ double sM[COARSE_LDS_MAX * COARSE_LDS_MAX];
-        M = sM;
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) sM[e] = Mg[e];
-    }
+    __shared__ double M[COARSE_LDS_MAX * COARSE_LDS_MAX];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = Mg[e];
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     for (int k = 0; k < n; ++k) {
@@ -805,19 +800,182 @@ __global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restric
         __syncthreads();
     }
     __syncthreads();
-    if constexpr (IN_LDS) {
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mg[e] = M[e];
-    }
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mg[e] = M[e];
     if (threadIdx.x == 0) scal[S_COARSE] = bad ? 1.0 : 0.0;
 }
 
-void launch_dense_inverse(int n, double* D, double* scal, hipStream_t s) {
+// ------------------------------------------------------------------ blocked Gauss-Jordan
+//
+// Coarsest levels larger than COARSE_LDS_MAX are inverted in place by the same Gauss-Jordan
+// elimination taken a block of BGJ pivots at a time.  With X = M_KK^{-1} for the pivot
+// block K, one block step maps
+//   M_KJ <- X M_KJ,   M_IJ <- M_IJ - M_IK X M_KJ,   M_IK <- -M_IK X,   M_KK <- X
+// (I, J != K), which is the composition of the scalar steps of K's pivots.  Step k runs as
+// two launches: k_bgj_pivot inverts M_KK (one workgroup, the scalar steps in LDS, every
+// pivot checked positive) while other workgroups finish step k-1 (its row block, column
+// block and diagonal block), then k_bgj_update applies the rank-BGJ update to every block
+// (I, J) outside row and column K, forming X M_KJ itself; a last k_bgj_pivot finishes the
+// last step.  X of two consecutive steps live in two slots of a scratch buffer.
+constexpr int BGJ = 64;
+constexpr int BGJ_THREADS = 256;
+
+__device__ __forceinline__ int bgj_size(int n, int b) { return min(BGJ, n - b * BGJ); }
+
+// The i-th block index other than kp.
+__device__ __forceinline__ int bgj_other(int i, int kp) { return i < kp ? i : i + 1; }
+
+// Block (I, J) of the row-major n x n M into s (row stride BGJ, zero outside the block).
+__device__ void bgj_load(const double* __restrict__ M, int n, int I, int J, double* s) {
+    const int bi = bgj_size(n, I), bj = bgj_size(n, J);
+    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) {
+        const int r = e / BGJ, q = e - r * BGJ;
+        s[e] = (r < bi && q < bj) ? M[(size_t)(I * BGJ + r) * n + (size_t)J * BGJ + q] : 0.0;
+    }
+}
+
+__device__ void bgj_store(double* __restrict__ M, int n, int I, int J, const double* s) {
+    const int bi = bgj_size(n, I), bj = bgj_size(n, J);
+    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) {
+        const int r = e / BGJ, q = e - r * BGJ;
+        if (r < bi && q < bj) M[(size_t)(I * BGJ + r) * n + (size_t)J * BGJ + q] = s[e];
+    }
+}
+
+// out = sign * (a b) for BGJ x BGJ tiles in LDS (zero-padded); thread t owns row t / 4 and
+// 16 consecutive columns; the sum runs over p in increasing order.
+__device__ void bgj_mul(const double* a, const double* b, double* out, double sign) {
+    const int r = threadIdx.x >> 2, q0 = (threadIdx.x & 3) * 16;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    for (int p = 0; p < BGJ; ++p) {
+        const double x = a[r * BGJ + p];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += x * b[p * BGJ + q0 + q];
+    }
+    __syncthreads();  // out may alias an operand
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[r * BGJ + q0 + q] = sign * acc[q];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(BGJ_THREADS) void k_bgj_pivot(int n, int k, double* __restrict__ M,
+                                                           double* __restrict__ X, double* __restrict__ scal) {
+    __shared__ double sa[BGJ * BGJ];
+    __shared__ double sb[BGJ * BGJ];
+    __shared__ double colk[BGJ], rowk[BGJ];
+    __shared__ int bad;
+    const int nb = (n + BGJ - 1) / BGJ;
+    const int w = blockIdx.x;
+    if (w == 0) {
+        if (k >= nb) return;
+        const int bk = bgj_size(n, k);
+        bgj_load(M, n, k, k, sa);
+        if (threadIdx.x == 0) bad = 0;
+        __syncthreads();
+        for (int p = 0; p < bk; ++p) {
+            const double piv = sa[p * BGJ + p];
+            if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
+                if (threadIdx.x == 0) bad = 1;
+                break;
+            }
+            const double pinv = 1.0 / piv;
+            for (int t = threadIdx.x; t < bk; t += BGJ_THREADS) {
+                colk[t] = sa[t * BGJ + p];
+                rowk[t] = (t == p) ? pinv : sa[p * BGJ + t] * pinv;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < bk * bk; e += BGJ_THREADS) {
+                const int i = e / bk, j = e - i * bk;
+                double v;
+                if (i == p)
+                    v = rowk[j];
+                else if (j == p)
+                    v = -colk[i] * pinv;
+                else
+                    v = sa[i * BGJ + j] - colk[i] * rowk[j];
+                sa[i * BGJ + j] = v;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        double* Xk = X + (size_t)(k & 1) * BGJ * BGJ;
+        for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) Xk[e] = sa[e];
+        if (threadIdx.x == 0 && (k == 0 || bad)) scal[S_COARSE] = bad ? 1.0 : 0.0;
+        return;
+    }
+    if (k == 0) return;
+    const int kp = k - 1;  // finish the block step of kp
+    const double* Xp = X + (size_t)(kp & 1) * BGJ * BGJ;
+    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) sa[e] = Xp[e];
+    __syncthreads();
+    if (w < nb) {  // row block: M_{kp J} <- X M_{kp J}
+        const int J = bgj_other(w - 1, kp);
+        bgj_load(M, n, kp, J, sb);
+        __syncthreads();
+        bgj_mul(sa, sb, sb, 1.0);
+        bgj_store(M, n, kp, J, sb);
+    } else if (w < 2 * nb - 1) {  // column block: M_{I kp} <- -M_{I kp} X
+        const int I = bgj_other(w - nb, kp);
+        bgj_load(M, n, I, kp, sb);
+        __syncthreads();
+        bgj_mul(sb, sa, sb, -1.0);
+        bgj_store(M, n, I, kp, sb);
+    } else {  // M_{kp kp} <- X
+        bgj_store(M, n, kp, kp, sa);
+    }
+}
+
+// M_IJ <- M_IJ - M_IK (X M_KJ) for I, J != K = k; one workgroup per block (I, J).
+__global__ __launch_bounds__(BGJ_THREADS) void k_bgj_update(int n, int k, double* __restrict__ M,
+                                                            const double* __restrict__ X) {
+    __shared__ double sx[BGJ * BGJ];
+    __shared__ double sb[BGJ * BGJ];
+    const int nb = (n + BGJ - 1) / BGJ;
+    const int w = blockIdx.x;
+    const int I = bgj_other(w / (nb - 1), k), J = bgj_other(w % (nb - 1), k);
+    const double* Xk = X + (size_t)(k & 1) * BGJ * BGJ;
+    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) sx[e] = Xk[e];
+    bgj_load(M, n, k, J, sb);
+    __syncthreads();
+    bgj_mul(sx, sb, sb, 1.0);   // T = X M_KJ
+    bgj_load(M, n, I, k, sx);   // M_IK
+    __syncthreads();
+    const int bi = bgj_size(n, I), bj = bgj_size(n, J);
+    const int r = threadIdx.x >> 2, q0 = (threadIdx.x & 3) * 16;
+    if (r < bi) {
+        double acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+        for (int p = 0; p < BGJ; ++p) {
+            const double x = sx[r * BGJ + p];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] += x * sb[p * BGJ + q0 + q];
+        }
+        double* row = M + (size_t)(I * BGJ + r) * n + (size_t)J * BGJ;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (q0 + q < bj) row[q0 + q] = row[q0 + q] - acc[q];
+    }
+}
+
+void launch_dense_inverse(int n, double* D, double* scal, double* work, hipStream_t s) {
     if (n > COARSE_GLOBAL_MAX) throw Fail{AMG_ERR_ARG, "coarsest level too large for the dense inverse"};
-    if (n <= COARSE_LDS_MAX)
-        k_dense_inverse<true><<<1, 1024, 0, s>>>(n, D, scal);
-    else
-        k_dense_inverse<false><<<1, 1024, 0, s>>>(n, D, scal);
-    HIP_LAUNCH_CHECK();
+    if (n <= COARSE_LDS_MAX) {
+        k_dense_inverse<<<1, 1024, 0, s>>>(n, D, scal);
+        HIP_LAUNCH_CHECK();
+        return;
+    }
+    if (work == nullptr) throw Fail{AMG_ERR_ARG, "blocked coarse inverse without its scratch"};
+    const int nb = (n + BGJ - 1) / BGJ;
+    for (int k = 0; k <= nb; ++k) {
+        k_bgj_pivot<<<k == 0 ? 1 : 2 * nb, BGJ_THREADS, 0, s>>>(n, k, D, work, scal);
+        HIP_LAUNCH_CHECK();
+        if (k < nb && nb > 1) {
+            k_bgj_update<<<(nb - 1) * (nb - 1), BGJ_THREADS, 0, s>>>(n, k, D, work);
+            HIP_LAUNCH_CHECK();
+        }
+    }
 }
 
 }  // namespace amgmi

@@ -593,6 +593,17 @@ __global__ __launch_bounds__(TPB) void k_dia_scatter_rows(int n, const int* __re
     for (int t = ptr[i]; t < ptr[i + 1]; ++t) dval[(size_t)slot[t] * n + i] = (T)val[t];
 }
 
+// The reverse: the CSR values of A_0 from its diagonal storage (the CSR copy is only
+// formed on demand once the partial update writes the diagonal storage directly).
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_dia_gather_rows(int n, const int* __restrict__ ptr,
+                                                         const uint8_t* __restrict__ slot,
+                                                         const T* __restrict__ dval, T* __restrict__ val) {
+    const int i = xcd_block() * TPB + threadIdx.x;
+    if (i >= n) return;
+    for (int t = ptr[i]; t < ptr[i + 1]; ++t) val[t] = dval[(size_t)slot[t] * n + i];
+}
+
 constexpr int SC_ROWS = 128;
 constexpr int SC_TILE_MIN_DIAG = 16;
 
@@ -1280,6 +1291,15 @@ void launch_dia_scatter(const Csr& A, const Dia& D, const double* val, T* dval, 
         timed_launch(k_dia_scatter_rows<T>, dia_blocks(A.nrows), TPB, 0, s, A.nrows, A.ptr, D.slot, val, dval);
     HIP_LAUNCH_CHECK();
 }
+
+template <typename T>
+void launch_dia_gather(const Csr& A, const Dia& D, const T* dval, T* val, hipStream_t s) {
+    timed_launch(k_dia_gather_rows<T>, dia_blocks(A.nrows), TPB, 0, s, A.nrows, (const int*)A.ptr,
+                 (const uint8_t*)D.slot, dval, val);
+    HIP_LAUNCH_CHECK();
+}
+template void launch_dia_gather<double>(const Csr&, const Dia&, const double*, double*, hipStream_t);
+template void launch_dia_gather<float>(const Csr&, const Dia&, const float*, float*, hipStream_t);
 
 void launch_dia_symcheck(int n, const Dia& D, double* scal, hipStream_t s) {
     timed_launch(k_dia_clear, 1, 64, 0, s, scal + S_ASYM);

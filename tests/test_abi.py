@@ -45,7 +45,7 @@ def test_host_side_argument_checks():
     assert L.amg_params_default(None) == -1
     p = AmgParams()
     assert L.amg_params_default(C.byref(p)) == 0
-    assert p.coarse_enough == 128 and p.npre == 1 and p.rtol == 1e-8
+    assert p.coarse_enough == 1024 and p.npre == 1 and p.rtol == 1e-8
     ctx = C.c_void_p()
     assert L.amg_setup(C.byref(ctx), 0, 10, None, None, None, None, None) == -1
     assert L.amg_setup(None, 10, 10, None, None, None, None, None) == -1

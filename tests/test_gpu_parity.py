@@ -346,7 +346,7 @@ def test_coarse_tail_matches_level_kernels(monkeypatch, npre, npost, precision):
     (Algorithm 2; the row sums differ only in their order), and both match the oracle."""
     p, c, v = two_fluid_7pt(32, 0.5)
     r = np.random.default_rng(7).standard_normal(32**3)
-    prm = dict(npre=npre, npost=npost, precision=precision)
+    prm = dict(npre=npre, npost=npost, precision=precision, coarse_enough=128)  # a 19-row coarsest level
     g = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), **prm)
     z_tail = g.vcycle(T(r)).cpu().numpy()
     monkeypatch.setenv("AMGMI_NO_TAIL", "1")
@@ -356,7 +356,7 @@ def test_coarse_tail_matches_level_kernels(monkeypatch, npre, npost, precision):
     assert rel_fro(z_tail, z_sep) <= tol
     if precision == 0:
         import oracle
-        o = oracle.OracleHierarchy(p, c, v, npre=npre, npost=npost)
+        o = oracle.OracleHierarchy(p, c, v, npre=npre, npost=npost, coarse_enough=128)
         assert rel_fro(z_tail, o.vcycle(r)) <= 1e-12
 
 
@@ -618,3 +618,37 @@ def test_host_mirror_matches_copy(monkeypatch, precision, flexible):
     for (im, cm, um), (ic, cc, uc) in zip(mapped, copied):
         assert cm and cc and im == ic
         assert np.array_equal(um, uc)
+
+
+
+@pytest.mark.parametrize("dims,precision", [((5, 5, 6), 0), ((9, 9, 9), 0), ((12, 12, 12), 0), ((8, 16, 16), 0),
+                                            ((9, 9, 9), 1)])
+def test_blocked_coarse_inverse(dims, precision):
+    """Coarsest levels above the 128 rows one workgroup's LDS holds are inverted by the
+    blocked Gauss-Jordan kernels (64-pivot blocks, ragged last block): a one-level hierarchy
+    (150 to 2048 rows) is a direct solve, one CG iteration, and its inverse matches NumPy's
+    (of the FP32-rounded operator in mixed precision)."""
+    from paper_2108_02054_amd import AMG
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    p, c, v = two_fluid_7pt(nx, 0.45, ny=ny, nz=nz)
+    print(f"case blocked coarse inverse n={n} precision {precision}", flush=True)
+    g = AMG(T(p), T(c), T(v), coarse_enough=2048, precision=precision)
+    assert g.num_levels == 1
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, c[p[i]:p[i + 1]]] = v[p[i]:p[i + 1]] if precision == 0 else v[p[i]:p[i + 1]].astype(np.float32)
+    assert rel_max(g.coarse_inverse(), np.linalg.inv(A)) <= 1e-11
+    f = rhs_uniform(n, 1, 0)
+    u, info = g.solve(T(f))
+    assert info["converged"] and info["iters"] <= (1 if precision == 0 else 3)
+    print(f"n={n}: coarse inverse {g.phase_times()['coarse']:.3f} ms at setup", flush=True)
+    g.close()
+
+
+def test_coarsest_level_too_large_for_the_dense_inverse():
+    from paper_2108_02054_amd import AMG, AmgError
+    p, c, v = two_fluid_7pt(13, 0.45)  # 2197 rows in one level
+    with pytest.raises(AmgError) as e:
+        AMG(T(p), T(c), T(v), coarse_enough=4096)
+    assert e.value.code == -1 and "dense inverse" in str(e.value)

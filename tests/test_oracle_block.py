@@ -237,7 +237,7 @@ def test_block_vcycle_two_grid_identity(ora, make):
     B = (I - E) A^{-1} with E = (I - M A)(I - P A_c^{-1} P^T A)(I - M A)."""
     p, c, v = make()
     n = len(p) - 1
-    h = ora.OracleHierarchy(p, c, v, aggregation=1, block_size=B, max_levels=2)
+    h = ora.OracleHierarchy(p, c, v, aggregation=1, block_size=B, max_levels=2, coarse_enough=4 * B)
     assert h.num_levels == 2
     A = dense(p, c, v)
     l0 = h.level(0)
