@@ -811,151 +811,222 @@ __global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restric
 // block K, one block step maps
 //   M_KJ <- X M_KJ,   M_IJ <- M_IJ - M_IK X M_KJ,   M_IK <- -M_IK X,   M_KK <- X
 // (I, J != K), which is the composition of the scalar steps of K's pivots.  Step k runs as
-// two launches: k_bgj_pivot inverts M_KK (one workgroup, the scalar steps in LDS, every
-// pivot checked positive) while other workgroups finish step k-1 (its row block, column
-// block and diagonal block), then k_bgj_update applies the rank-BGJ update to every block
-// (I, J) outside row and column K, forming X M_KJ itself; a last k_bgj_pivot finishes the
-// last step.  X of two consecutive steps live in two slots of a scratch buffer.
+// two launches: k_bgj_pivot inverts M_KK (one workgroup, the scalar steps in registers and
+// LDS, every pivot checked positive) while other workgroups finish step k-1 (its row block,
+// column block and diagonal block), then k_bgj_update applies the rank-BGJ update to every
+// block (I, J) outside row and column K, forming X M_KJ itself; a last k_bgj_pivot
+// finishes the last step.  X of two consecutive steps live in two slots of a scratch
+// buffer.  The 64 x 64 x 64 block products run on the FP64 matrix cores: each of the 16
+// waves of a workgroup owns one 16 x 16 tile of the product and accumulates it over 16
+// steps of V_MFMA_F64_16X16X4F64.
 constexpr int BGJ = 64;
-constexpr int BGJ_THREADS = 256;
+constexpr int BGJ_THREADS = 1024;
+constexpr int BGJ_RPT = BGJ * BGJ / BGJ_THREADS;  // tile elements per thread
+typedef double bgj_v4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int bgj_size(int n, int b) { return min(BGJ, n - b * BGJ); }
 
 // The i-th block index other than kp.
 __device__ __forceinline__ int bgj_other(int i, int kp) { return i < kp ? i : i + 1; }
 
-// Block (I, J) of the row-major n x n M into s (row stride BGJ, zero outside the block).
-__device__ void bgj_load(const double* __restrict__ M, int n, int I, int J, double* s) {
+// A BGJ x BGJ tile spread over the threads: thread t holds rows t / BGJ + (BGJ_THREADS /
+// BGJ) m (m < BGJ_RPT) of column t % BGJ.  Every global load of a tile is issued before any
+// is used.
+constexpr int BGJ_RSTEP = BGJ_THREADS / BGJ;
+
+// Block (I, J) of the row-major n x n M (zero outside the matrix).
+__device__ __forceinline__ void bgj_fetch(const double* __restrict__ M, int n, int I, int J, double (&v)[BGJ_RPT]) {
     const int bi = bgj_size(n, I), bj = bgj_size(n, J);
-    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) {
-        const int r = e / BGJ, q = e - r * BGJ;
-        s[e] = (r < bi && q < bj) ? M[(size_t)(I * BGJ + r) * n + (size_t)J * BGJ + q] : 0.0;
+    const int r = threadIdx.x / BGJ, q = threadIdx.x % BGJ;
+    const double* base = M + (size_t)(I * BGJ + r) * n + (size_t)J * BGJ + q;
+#pragma unroll
+    for (int m = 0; m < BGJ_RPT; ++m)
+        v[m] = (r + BGJ_RSTEP * m < bi && q < bj) ? base[(size_t)(BGJ_RSTEP * m) * n] : 0.0;
+}
+
+// A tile stored densely (row stride BGJ), as X is.
+__device__ __forceinline__ void bgj_fetch_dense(const double* __restrict__ X, double (&v)[BGJ_RPT]) {
+#pragma unroll
+    for (int m = 0; m < BGJ_RPT; ++m) v[m] = X[threadIdx.x + m * BGJ_THREADS];
+}
+
+// Into LDS s as stored (row stride BGJ), or transposed.
+__device__ __forceinline__ void bgj_put(double* s, const double (&v)[BGJ_RPT]) {
+#pragma unroll
+    for (int m = 0; m < BGJ_RPT; ++m) s[threadIdx.x + m * BGJ_THREADS] = v[m];
+}
+__device__ __forceinline__ void bgj_put_t(double* s, const double (&v)[BGJ_RPT]) {
+    const int r = threadIdx.x / BGJ, q = threadIdx.x % BGJ;
+#pragma unroll
+    for (int m = 0; m < BGJ_RPT; ++m) s[q * BGJ + r + BGJ_RSTEP * m] = v[m];
+}
+
+// Writes the tile of registers v to block (I, J) of M.
+__device__ __forceinline__ void bgj_store(double* __restrict__ M, int n, int I, int J, const double (&v)[BGJ_RPT]) {
+    const int bi = bgj_size(n, I), bj = bgj_size(n, J);
+    const int r = threadIdx.x / BGJ, q = threadIdx.x % BGJ;
+    double* base = M + (size_t)(I * BGJ + r) * n + (size_t)J * BGJ + q;
+#pragma unroll
+    for (int m = 0; m < BGJ_RPT; ++m)
+        if (r + BGJ_RSTEP * m < bi && q < bj) base[(size_t)(BGJ_RSTEP * m) * n] = v[m];
+}
+
+// The 16 x 16 tile of a b owned by this wave (tile row w / 4, tile column w % 4 for wave
+// w), for BGJ x BGJ tiles in LDS: at the transposed (at[k * BGJ + i] = a_ik), b as stored.
+// Lane l ends with entries (16 (w / 4) + l / 16 + 4 r, 16 (w % 4) + l % 16), r < 4 (the
+// instruction's result layout: entry r of lane l is row l / 16 + 4 r, column l % 16).
+__device__ __forceinline__ bgj_v4 bgj_mfma(const double* at, const double* b) {
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int i = 16 * (w >> 2) + (l & 15), j = 16 * (w & 3) + (l & 15), kk = l >> 4;
+    bgj_v4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < BGJ / 4; ++s)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[(4 * s + kk) * BGJ + i], b[(4 * s + kk) * BGJ + j], acc, 0, 0, 0);
+    return acc;
+}
+
+// Row and column of entry r of this lane's product tile.
+__device__ __forceinline__ int bgj_out_row(int r) {
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    return 16 * (w >> 2) + (l >> 4) + 4 * r;
+}
+__device__ __forceinline__ int bgj_out_col() {
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    return 16 * (w & 3) + (l & 15);
+}
+
+// Writes sign * (this lane's product entries) to block (I, J) of M.
+__device__ __forceinline__ void bgj_store_tile(double* __restrict__ M, int n, int I, int J, bgj_v4 acc, double sign) {
+    const int bi = bgj_size(n, I), bj = bgj_size(n, J), j = bgj_out_col();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = bgj_out_row(r);
+        if (i < bi && j < bj) M[(size_t)(I * BGJ + i) * n + (size_t)J * BGJ + j] = sign * acc[r];
     }
 }
 
-__device__ void bgj_store(double* __restrict__ M, int n, int I, int J, const double* s) {
-    const int bi = bgj_size(n, I), bj = bgj_size(n, J);
-    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) {
-        const int r = e / BGJ, q = e - r * BGJ;
-        if (r < bi && q < bj) M[(size_t)(I * BGJ + r) * n + (size_t)J * BGJ + q] = s[e];
+// Gauss-Jordan inverse of the bk x bk diagonal block K of M, written densely to Xk.
+// Thread t holds row t / 16, columns 4 (t % 16) + q (q < 4) of the block in registers; for
+// pivot p the threads of row p publish that row and the threads holding column p that
+// column through LDS (double-buffered, one barrier per pivot).  The pivot loop is not
+// unrolled: a straight-line body would be fetched instruction by instruction once per
+// launch.  A pivot that is not positive and finite stops the elimination and returns
+// false (the same value in every thread).
+__device__ bool bgj_invert_block(const double* __restrict__ M, int n, int K, double* __restrict__ Xk,
+                                 double (*rowbuf)[BGJ], double (*colbuf)[BGJ]) {
+    const int bk = bgj_size(n, K);
+    const int i = threadIdx.x >> 4, g = threadIdx.x & 15, c0 = g * 4;
+    const double* src = M + (size_t)(K * BGJ + i) * n + (size_t)K * BGJ + c0;
+    double e[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) e[q] = (i < bk && c0 + q < bk) ? src[q] : 0.0;
+    bool ok = true;
+#pragma nounroll
+    for (int p = 0; p < bk; ++p) {
+        const int par = p & 1;
+        if ((p >> 2) == g) {
+            const int q = p & 3;
+            colbuf[par][i] = q == 0 ? e[0] : q == 1 ? e[1] : q == 2 ? e[2] : e[3];
+        }
+        if (i == p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rowbuf[par][c0 + q] = e[q];
+        }
+        __syncthreads();
+        const double piv = rowbuf[par][p];
+        if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
+            ok = false;
+            break;
+        }
+        const double pinv = 1.0 / piv;
+        const double ci = colbuf[par][i];
+        const bool rowp = (i == p);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = c0 + q;
+            const double rj = rowbuf[par][j] * pinv;
+            double v = rowp ? rj : e[q] - ci * rj;
+            if (j == p) v = rowp ? pinv : -ci * pinv;
+            if (i < bk && j < bk) e[q] = v;
+        }
     }
-}
-
-// out = sign * (a b) for BGJ x BGJ tiles in LDS (zero-padded); thread t owns row t / 4 and
-// 16 consecutive columns; the sum runs over p in increasing order.
-__device__ void bgj_mul(const double* a, const double* b, double* out, double sign) {
-    const int r = threadIdx.x >> 2, q0 = (threadIdx.x & 3) * 16;
-    double acc[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    for (int p = 0; p < BGJ; ++p) {
-        const double x = a[r * BGJ + p];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += x * b[p * BGJ + q0 + q];
-    }
-    __syncthreads();  // out may alias an operand
-#pragma unroll
-    for (int q = 0; q < 16; ++q) out[r * BGJ + q0 + q] = sign * acc[q];
-    __syncthreads();
+    for (int q = 0; q < 4; ++q) Xk[i * BGJ + c0 + q] = e[q];
+    return ok;
 }
 
 __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_pivot(int n, int k, double* __restrict__ M,
                                                            double* __restrict__ X, double* __restrict__ scal) {
     __shared__ double sa[BGJ * BGJ];
     __shared__ double sb[BGJ * BGJ];
-    __shared__ double colk[BGJ], rowk[BGJ];
-    __shared__ int bad;
+    __shared__ double rowbuf[2][BGJ], colbuf[2][BGJ];
     const int nb = (n + BGJ - 1) / BGJ;
     const int w = blockIdx.x;
     if (w == 0) {
         if (k >= nb) return;
-        const int bk = bgj_size(n, k);
-        bgj_load(M, n, k, k, sa);
-        if (threadIdx.x == 0) bad = 0;
-        __syncthreads();
-        for (int p = 0; p < bk; ++p) {
-            const double piv = sa[p * BGJ + p];
-            if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
-                if (threadIdx.x == 0) bad = 1;
-                break;
-            }
-            const double pinv = 1.0 / piv;
-            for (int t = threadIdx.x; t < bk; t += BGJ_THREADS) {
-                colk[t] = sa[t * BGJ + p];
-                rowk[t] = (t == p) ? pinv : sa[p * BGJ + t] * pinv;
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < bk * bk; e += BGJ_THREADS) {
-                const int i = e / bk, j = e - i * bk;
-                double v;
-                if (i == p)
-                    v = rowk[j];
-                else if (j == p)
-                    v = -colk[i] * pinv;
-                else
-                    v = sa[i * BGJ + j] - colk[i] * rowk[j];
-                sa[i * BGJ + j] = v;
-            }
-            __syncthreads();
-        }
-        __syncthreads();
-        double* Xk = X + (size_t)(k & 1) * BGJ * BGJ;
-        for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) Xk[e] = sa[e];
-        if (threadIdx.x == 0 && (k == 0 || bad)) scal[S_COARSE] = bad ? 1.0 : 0.0;
+        const bool ok = bgj_invert_block(M, n, k, X + (size_t)(k & 1) * BGJ * BGJ, rowbuf, colbuf);
+        if (threadIdx.x == 0 && (k == 0 || !ok)) scal[S_COARSE] = ok ? 0.0 : 1.0;
         return;
     }
     if (k == 0) return;
     const int kp = k - 1;  // finish the block step of kp
-    const double* Xp = X + (size_t)(kp & 1) * BGJ * BGJ;
-    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) sa[e] = Xp[e];
-    __syncthreads();
-    if (w < nb) {  // row block: M_{kp J} <- X M_{kp J}
-        const int J = bgj_other(w - 1, kp);
-        bgj_load(M, n, kp, J, sb);
+    double vx[BGJ_RPT], vb[BGJ_RPT];
+    bgj_fetch_dense(X + (size_t)(kp & 1) * BGJ * BGJ, vx);
+    if (w == 2 * nb - 1) {  // M_{kp kp} <- X
+        bgj_store(M, n, kp, kp, vx);
+        return;
+    }
+    const bool row = w < nb;
+    const int O = bgj_other(row ? w - 1 : w - nb, kp);
+    if (row) {  // M_{kp O} <- X M_{kp O}
+        bgj_fetch(M, n, kp, O, vb);
+        bgj_put_t(sa, vx);
+        bgj_put(sb, vb);
         __syncthreads();
-        bgj_mul(sa, sb, sb, 1.0);
-        bgj_store(M, n, kp, J, sb);
-    } else if (w < 2 * nb - 1) {  // column block: M_{I kp} <- -M_{I kp} X
-        const int I = bgj_other(w - nb, kp);
-        bgj_load(M, n, I, kp, sb);
+        bgj_store_tile(M, n, kp, O, bgj_mfma(sa, sb), 1.0);
+    } else {  // M_{O kp} <- -M_{O kp} X
+        bgj_fetch(M, n, O, kp, vb);
+        bgj_put_t(sa, vb);
+        bgj_put(sb, vx);
         __syncthreads();
-        bgj_mul(sb, sa, sb, -1.0);
-        bgj_store(M, n, I, kp, sb);
-    } else {  // M_{kp kp} <- X
-        bgj_store(M, n, kp, kp, sa);
+        bgj_store_tile(M, n, O, kp, bgj_mfma(sa, sb), -1.0);
     }
 }
 
-// M_IJ <- M_IJ - M_IK (X M_KJ) for I, J != K = k; one workgroup per block (I, J).
+// M_IJ <- M_IJ - M_IK (X M_KJ) for I, J != K = k; one workgroup per block (I, J).  All four
+// operands are fetched at once; X M_KJ goes through LDS, M_IJ stays in registers.
 __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_update(int n, int k, double* __restrict__ M,
                                                             const double* __restrict__ X) {
-    __shared__ double sx[BGJ * BGJ];
-    __shared__ double sb[BGJ * BGJ];
+    __shared__ double sx[BGJ * BGJ];  // X^T, then (M_IK)^T
+    __shared__ double sb[BGJ * BGJ];  // M_KJ
+    __shared__ double st[BGJ * BGJ];  // X M_KJ
     const int nb = (n + BGJ - 1) / BGJ;
     const int w = blockIdx.x;
     const int I = bgj_other(w / (nb - 1), k), J = bgj_other(w % (nb - 1), k);
-    const double* Xk = X + (size_t)(k & 1) * BGJ * BGJ;
-    for (int e = threadIdx.x; e < BGJ * BGJ; e += BGJ_THREADS) sx[e] = Xk[e];
-    bgj_load(M, n, k, J, sb);
+    const int bi = bgj_size(n, I), bj = bgj_size(n, J), j = bgj_out_col();
+    double vx[BGJ_RPT], vk[BGJ_RPT], vi[BGJ_RPT], cur[4];
+    bgj_fetch_dense(X + (size_t)(k & 1) * BGJ * BGJ, vx);
+    bgj_fetch(M, n, k, J, vk);
+    bgj_fetch(M, n, I, k, vi);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = bgj_out_row(r);
+        cur[r] = (i < bi && j < bj) ? M[(size_t)(I * BGJ + i) * n + (size_t)J * BGJ + j] : 0.0;
+    }
+    bgj_put_t(sx, vx);
+    bgj_put(sb, vk);
     __syncthreads();
-    bgj_mul(sx, sb, sb, 1.0);   // T = X M_KJ
-    bgj_load(M, n, I, k, sx);   // M_IK
+    const bgj_v4 t = bgj_mfma(sx, sb);  // T = X M_KJ
+#pragma unroll
+    for (int r = 0; r < 4; ++r) st[bgj_out_row(r) * BGJ + j] = t[r];
     __syncthreads();
-    const int bi = bgj_size(n, I), bj = bgj_size(n, J);
-    const int r = threadIdx.x >> 2, q0 = (threadIdx.x & 3) * 16;
-    if (r < bi) {
-        double acc[16];
+    bgj_put_t(sx, vi);
+    __syncthreads();
+    const bgj_v4 acc = bgj_mfma(sx, st);  // M_IK T
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-        for (int p = 0; p < BGJ; ++p) {
-            const double x = sx[r * BGJ + p];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] += x * sb[p * BGJ + q0 + q];
-        }
-        double* row = M + (size_t)(I * BGJ + r) * n + (size_t)J * BGJ;
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            if (q0 + q < bj) row[q0 + q] = row[q0 + q] - acc[q];
+    for (int r = 0; r < 4; ++r) {
+        const int i = bgj_out_row(r);
+        if (i < bi && j < bj) M[(size_t)(I * BGJ + i) * n + (size_t)J * BGJ + j] = cur[r] - acc[r];
     }
 }
 

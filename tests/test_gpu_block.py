@@ -24,7 +24,7 @@ def test_block_setup_parity(N):
     """13^3 nodes = 8788 rows: several 256-row tiles and a ragged tail."""
     p, c, v = coupled4_7pt(N, 2)
     print(f"case coupled4 N={N}", flush=True)
-    g, o = both(p, c, v, **BLOCK)
+    g, o = both(p, c, v, coarse_enough=128, **BLOCK)
     compare_levels(g, o, tol=1e-10)
     assert g.num_levels >= 3
     g.close()
