@@ -362,9 +362,10 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
             return sum(ktl[l].get(gr[1], (0.0, 0))[0] for l in gr[2] if l < len(ktl))
         return max(groups, key=tot)
 
-    def series(mode, precision=0, diag=False):
+    def series(mode, precision=0, diag=False, snap=False):
         """Setup at t=0 (untimed), W warm-up steps, optionally a per-level kernel table
-        (untimed), K timed steps with the setup and solve of each step timed apart."""
+        (untimed), K timed steps with the setup and solve of each step timed apart; with
+        snap, host copies of the last step's level values, smoother and solution (untimed)."""
         torch.cuda.synchronize()
         t_setup = time.perf_counter()
         amg = AMG(ptr, col, vals[0], precision=precision, **amg_params)
@@ -412,6 +413,7 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
                 ev[5].record()
             if record:
                 log_["iters"].append(its)
+                log_["last_rel_res"] = info["rel_res_true"]
                 log_["missed"] += 0 if info["converged"] else 1
                 if mode != "reuse_paper":  # that series misses the limit by design
                     log_["converged"] &= bool(info["converged"])
@@ -454,10 +456,14 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         kt = amg.trace_read_levels() if traced else None
         amg.trace([], level=0)
         log_["kt_levels"], log_["kt"] = kt_levels, kt
+        if snap:
+            lv = [amg.level(l) for l in range(amg.num_levels)]
+            log_["snap"] = {"A": [x["A"][2] for x in lv], "m": [x["m"] for x in lv], "u": u.cpu().numpy()}
+            del lv
         return amg, (te - ts) * 1e3 / K, log_
 
     # ---------------------------------------------------------------- partial reuse (headline)
-    amg, ms_partial, info_p = series("partial", precision=head_prec, diag=True)
+    amg, ms_partial, info_p = series("partial", precision=head_prec, diag=True, snap=compare)
     bm = ByteModel.of(amg, block)
     L = bm.L
     dims = bm.dims
@@ -596,7 +602,7 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         plan = [("full", "full", 0), ("reuse", "reuse", 0), ("mixed", "partial", 1), ("policy", "policy", 0),
                 ("reuse_paper", "reuse_paper", 0)]
     for name, mode, prec in plan:
-        a, ms_x, info_x = series(mode, precision=prec)
+        a, ms_x, info_x = series(mode, precision=prec, snap=name in ("mixed", "fp64_partial"))
         a.close()
         del a
         runs[name] = (ms_x, info_x)
@@ -605,8 +611,38 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
             extra += f", solves past the iteration limit {info_x['missed']}"
         log(f"{name}: {ms_x:.3f} ms/step (setup {info_x['setup_ms_per_step']:.3f} + solve "
             f"{info_x['solve_ms_per_step']:.3f}), iters {info_x['iters']}{extra}")
+    for name in ("mixed", "fp64_partial"):
+        if name in runs:
+            mx, fp = (runs[name][1], info_p) if name == "mixed" else (info_p, runs[name][1])
+            res["mixed_vs_fp64"] = mixed_errors(mx, fp)
+            for r in (runs[name][1], info_p):
+                r.pop("snap", None)
     res["runs"] = runs
     return res
+
+
+def mixed_errors(mx, fp):
+    """Error of every result of the mixed-precision form against the FP64 form over the
+    same series, at its last step: per level ||dA_l||_F / ||A_l||_F and the largest
+    relative error of the smoother's diagonal, the solution's largest error over its
+    largest entry, the true relative residuals and the iterations of that step."""
+    import numpy as np
+    a, b = mx["snap"], fp["snap"]
+    levels = []
+    for l, (am, af) in enumerate(zip(a["A"], b["A"])):
+        e = {"level": l, "A_rel_fro": float(np.linalg.norm(am - af) / np.linalg.norm(af))}
+        if a["m"][l] is not None:
+            e["smoother_rel_max"] = float(np.abs(a["m"][l] - b["m"][l]).max() / np.abs(b["m"][l]).max())
+        levels.append(e)
+    return {
+        "reference": "the FP64 hierarchy on the device, which equals the FP64 oracle's bit for bit on the "
+                     "7-point series and within 1e-10 on the 27-point one (parity tests at these sizes)",
+        "step": "last timed step", "levels": levels,
+        "u_max_err_over_max": float(np.abs(a["u"] - b["u"]).max() / np.abs(b["u"]).max()),
+        "rel_res_true": {"mixed": mx["last_rel_res"], "fp64": fp["last_rel_res"]},
+        "iters_last_step": {"mixed": mx["iters"][-1], "fp64": fp["iters"][-1]},
+        "iters_mean": {"mixed": float(np.mean(mx["iters"])), "fp64": float(np.mean(fp["iters"]))},
+    }
 
 
 def table1(phases):
@@ -665,6 +701,8 @@ def leg_record(res):
     for name, (ms, inf) in res.get("runs", {}).items():
         rec[f"{name}_ms_per_step"] = ms
         rec[f"{name}_iters"] = inf["iters"]
+    if "mixed_vs_fp64" in res:
+        rec["mixed_vs_fp64"] = res["mixed_vs_fp64"]
     return rec
 
 
@@ -765,6 +803,8 @@ def main():
             result["iters_fp64"] = runs["fp64_partial"][1]["iters"]
             result["mixed_speedup_vs_fp64_pct"] = (runs["fp64_partial"][0] / res["ms_partial"] - 1.0) * 100.0
         result["table2_strategies"] = table2(res["ms_partial"], info_p, runs)
+    if "mixed_vs_fp64" in res:
+        result["mixed_vs_fp64"] = res["mixed_vs_fp64"]
 
     # ---------------------------------------------------------------- short legs beyond the MALL
     if cfg_id == 2 and not args.no_legs:
