@@ -822,6 +822,10 @@ __global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restric
 constexpr int BGJ = 64;
 constexpr int BGJ_THREADS = 1024;
 constexpr int BGJ_RPT = BGJ * BGJ / BGJ_THREADS;  // tile elements per thread
+// Row stride of a tile in LDS: 68 doubles put the 16 rows that an operand read of the
+// matrix instruction touches in different banks (2-way at most), where 64 would put
+// them all in one.
+constexpr int BGJ_LD = 68;
 typedef double bgj_v4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int bgj_size(int n, int b) { return min(BGJ, n - b * BGJ); }
@@ -850,15 +854,11 @@ __device__ __forceinline__ void bgj_fetch_dense(const double* __restrict__ X, do
     for (int m = 0; m < BGJ_RPT; ++m) v[m] = X[threadIdx.x + m * BGJ_THREADS];
 }
 
-// Into LDS s as stored (row stride BGJ), or transposed.
+// Into LDS s (row stride BGJ_LD).
 __device__ __forceinline__ void bgj_put(double* s, const double (&v)[BGJ_RPT]) {
-#pragma unroll
-    for (int m = 0; m < BGJ_RPT; ++m) s[threadIdx.x + m * BGJ_THREADS] = v[m];
-}
-__device__ __forceinline__ void bgj_put_t(double* s, const double (&v)[BGJ_RPT]) {
     const int r = threadIdx.x / BGJ, q = threadIdx.x % BGJ;
 #pragma unroll
-    for (int m = 0; m < BGJ_RPT; ++m) s[q * BGJ + r + BGJ_RSTEP * m] = v[m];
+    for (int m = 0; m < BGJ_RPT; ++m) s[(r + BGJ_RSTEP * m) * BGJ_LD + q] = v[m];
 }
 
 // Writes the tile of registers v to block (I, J) of M.
@@ -872,16 +872,16 @@ __device__ __forceinline__ void bgj_store(double* __restrict__ M, int n, int I, 
 }
 
 // The 16 x 16 tile of a b owned by this wave (tile row w / 4, tile column w % 4 for wave
-// w), for BGJ x BGJ tiles in LDS: at the transposed (at[k * BGJ + i] = a_ik), b as stored.
+// w), for BGJ x BGJ tiles a, b in LDS (row stride BGJ_LD).
 // Lane l ends with entries (16 (w / 4) + l / 16 + 4 r, 16 (w % 4) + l % 16), r < 4 (the
 // instruction's result layout: entry r of lane l is row l / 16 + 4 r, column l % 16).
-__device__ __forceinline__ bgj_v4 bgj_mfma(const double* at, const double* b) {
+__device__ __forceinline__ bgj_v4 bgj_mfma(const double* a, const double* b) {
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int i = 16 * (w >> 2) + (l & 15), j = 16 * (w & 3) + (l & 15), kk = l >> 4;
     bgj_v4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < BGJ / 4; ++s)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[(4 * s + kk) * BGJ + i], b[(4 * s + kk) * BGJ + j], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i * BGJ_LD + 4 * s + kk], b[(4 * s + kk) * BGJ_LD + j], acc, 0, 0, 0);
     return acc;
 }
 
@@ -905,66 +905,133 @@ __device__ __forceinline__ void bgj_store_tile(double* __restrict__ M, int n, in
     }
 }
 
-// Gauss-Jordan inverse of the bk x bk diagonal block K of M, written densely to Xk.
-// Thread t holds row t / 16, columns 4 (t % 16) + q (q < 4) of the block in registers; for
-// pivot p the threads of row p publish that row and the threads holding column p that
-// column through LDS (double-buffered, one barrier per pivot).  The pivot loop is not
-// unrolled: a straight-line body would be fetched instruction by instruction once per
-// launch.  A pivot that is not positive and finite stops the elimination and returns
-// false (the same value in every thread).
-__device__ bool bgj_invert_block(const double* __restrict__ M, int n, int K, double* __restrict__ Xk,
-                                 double (*rowbuf)[BGJ], double (*colbuf)[BGJ]) {
-    const int bk = bgj_size(n, K);
-    const int i = threadIdx.x >> 4, g = threadIdx.x & 15, c0 = g * 4;
-    const double* src = M + (size_t)(K * BGJ + i) * n + (size_t)K * BGJ + c0;
-    double e[4];
+// Value of v in lane `lane` (uniform) of the wavefront.
+__device__ __forceinline__ double bgj_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 16 x 16 tile product on the FP64 matrix cores: c + sign * (a b), a and b tiles of an LDS
+// matrix with row stride BGJ_LD, c and the result in the instruction's result layout (entry r
+// of lane l is row l / 16 + 4 r, column l % 16).
+__device__ __forceinline__ bgj_v4 bgj_tile_mm(const double* a, const double* b, bgj_v4 c, double sign) {
+    const int l = threadIdx.x % 64, i = l & 15, kk = l >> 4;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) e[q] = (i < bk && c0 + q < bk) ? src[q] : 0.0;
-    bool ok = true;
-#pragma nounroll
-    for (int p = 0; p < bk; ++p) {
-        const int par = p & 1;
-        if ((p >> 2) == g) {
-            const int q = p & 3;
-            colbuf[par][i] = q == 0 ? e[0] : q == 1 ? e[1] : q == 2 ? e[2] : e[3];
-        }
-        if (i == p) {
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * a[i * BGJ_LD + 4 * s + kk], b[(4 * s + kk) * BGJ_LD + i], c, 0, 0, 0);
+    return c;
+}
+
+__device__ __forceinline__ bgj_v4 bgj_tile_load(const double* t) {
+    const int l = threadIdx.x % 64;
+    bgj_v4 v;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) rowbuf[par][c0 + q] = e[q];
+    for (int r = 0; r < 4; ++r) v[r] = t[((l >> 4) + 4 * r) * BGJ_LD + (l & 15)];
+    return v;
+}
+
+__device__ __forceinline__ void bgj_tile_store(double* t, bgj_v4 v) {
+    const int l = threadIdx.x % 64;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t[((l >> 4) + 4 * r) * BGJ_LD + (l & 15)] = v[r];
+}
+
+// In-place inverse of the BGJ x BGJ matrix D in LDS (row stride BGJ_LD) by Gauss-Jordan
+// taken 16 pivots at a time, by the BGJ_THREADS = 16 wavefronts of the block.  For the
+// 16-block S, wavefront 0 inverts D_SS in registers (lane i % 16 holds row i; the pivot
+// row is read from its lane with readlane, so the 16 pivot steps need no barrier); then
+// wavefront w updates tile (w / 4, w % 4) of the 4 x 4 tiling on the matrix cores:
+//   D_SJ <- X D_SJ,   D_IS <- -D_IS X,   D_IJ <- D_IJ - D_IS (X D_SJ),   D_SS <- X.
+// Only the 16-blocks that hold one of the first bk pivots are eliminated (rows and
+// columns from bk on must be those of the identity).  A pivot that is not positive and
+// finite sets *bad; the elimination runs on (the values are then meaningless).
+__device__ void bgj_invert_lds(double* D, int bk, int* bad) {
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int TI = w >> 2, TJ = w & 3;
+    for (int S = 0; 16 * S < bk; ++S) {
+        double* X = D + 16 * S * BGJ_LD + 16 * S;
+        if (w == 0) {
+            const int i = l & 15;
+            double e[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) e[j] = X[i * BGJ_LD + j];
+            bool ok = true;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const double piv = bgj_lane(e[p], p);
+                ok = ok && piv > 0.0 && isfinite(piv);
+                const double pinv = 1.0 / piv;
+                // row p: e_pj / piv; other rows: e_ij - (e_ip / piv) e_pj
+                const double sc = (i == p) ? pinv : 1.0;
+                const double cf = (i == p) ? 0.0 : e[p] * pinv;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j == p) continue;
+                    const double rpj = bgj_lane(e[j], p);
+                    e[j] = fma(-cf, rpj, e[j] * sc);
+                }
+                e[p] = (i == p) ? pinv : -cf;
+            }
+            if (l < 16) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) X[i * BGJ_LD + j] = e[j];
+            }
+            if (!ok && l == 0) *bad = 1;
         }
         __syncthreads();
-        const double piv = rowbuf[par][p];
-        if (!(piv > 0.0) || !isfinite(piv)) {  // uniform: every thread reads the same pivot
-            ok = false;
-            break;
-        }
-        const double pinv = 1.0 / piv;
-        const double ci = colbuf[par][i];
-        const bool rowp = (i == p);
+        const bool own = TI != S || TJ != S;
+        bgj_v4 res = {0.0, 0.0, 0.0, 0.0};
+        if (TI == S && TJ != S) {
+            res = bgj_tile_mm(X, D + 16 * S * BGJ_LD + 16 * TJ, res, 1.0);
+        } else if (TJ == S && TI != S) {
+            res = bgj_tile_mm(D + 16 * TI * BGJ_LD + 16 * S, X, res, -1.0);
+        } else if (own) {
+            // T = X D_SJ in the result layout is the B operand of the next product as it
+            // stands: entry s of lane j + 16 k is T(4 s + k, j).
+            const bgj_v4 t = bgj_tile_mm(X, D + 16 * S * BGJ_LD + 16 * TJ, res, 1.0);
+            res = bgj_tile_load(D + 16 * TI * BGJ_LD + 16 * TJ);
+            const double* a = D + 16 * TI * BGJ_LD + 16 * S;
+            const int i = l & 15, kk = l >> 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = c0 + q;
-            const double rj = rowbuf[par][j] * pinv;
-            double v = rowp ? rj : e[q] - ci * rj;
-            if (j == p) v = rowp ? pinv : -ci * pinv;
-            if (i < bk && j < bk) e[q] = v;
+            for (int s = 0; s < 4; ++s) res = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i * BGJ_LD + 4 * s + kk], t[s], res, 0, 0, 0);
         }
+        __syncthreads();
+        if (own) bgj_tile_store(D + 16 * TI * BGJ_LD + 16 * TJ, res);
+        __syncthreads();
     }
+}
+
+// Inverse of the diagonal block K of M (bk x bk, padded with the identity), written
+// densely to Xk; false (in every thread) if a pivot was not positive and finite.
+__device__ bool bgj_invert_block(const double* __restrict__ M, int n, int K, double* __restrict__ Xk, double* D,
+                                 int* bad) {
+    const int bk = bgj_size(n, K);
+    double v[BGJ_RPT];
+    bgj_fetch(M, n, K, K, v);
+    const int r = threadIdx.x / BGJ, q = threadIdx.x % BGJ;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Xk[i * BGJ + c0 + q] = e[q];
-    return ok;
+    for (int m = 0; m < BGJ_RPT; ++m)
+        if (r + BGJ_RSTEP * m >= bk) v[m] = (r + BGJ_RSTEP * m == q) ? 1.0 : 0.0;
+    bgj_put(D, v);
+    if (threadIdx.x == 0) *bad = 0;
+    __syncthreads();
+    bgj_invert_lds(D, bk, bad);
+#pragma unroll
+    for (int m = 0; m < BGJ_RPT; ++m) Xk[threadIdx.x + m * BGJ_THREADS] = D[(r + BGJ_RSTEP * m) * BGJ_LD + q];
+    return *bad == 0;
 }
 
 __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_pivot(int n, int k, double* __restrict__ M,
                                                            double* __restrict__ X, double* __restrict__ scal) {
-    __shared__ double sa[BGJ * BGJ];
-    __shared__ double sb[BGJ * BGJ];
-    __shared__ double rowbuf[2][BGJ], colbuf[2][BGJ];
+    __shared__ double sa[BGJ * BGJ_LD];
+    __shared__ double sb[BGJ * BGJ_LD];
+    __shared__ int bad;
     const int nb = (n + BGJ - 1) / BGJ;
     const int w = blockIdx.x;
     if (w == 0) {
         if (k >= nb) return;
-        const bool ok = bgj_invert_block(M, n, k, X + (size_t)(k & 1) * BGJ * BGJ, rowbuf, colbuf);
+        const bool ok = bgj_invert_block(M, n, k, X + (size_t)(k & 1) * BGJ * BGJ, sa, &bad);
         if (threadIdx.x == 0 && (k == 0 || !ok)) scal[S_COARSE] = ok ? 0.0 : 1.0;
         return;
     }
@@ -980,13 +1047,13 @@ __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_pivot(int n, int k, double*
     const int O = bgj_other(row ? w - 1 : w - nb, kp);
     if (row) {  // M_{kp O} <- X M_{kp O}
         bgj_fetch(M, n, kp, O, vb);
-        bgj_put_t(sa, vx);
+        bgj_put(sa, vx);
         bgj_put(sb, vb);
         __syncthreads();
         bgj_store_tile(M, n, kp, O, bgj_mfma(sa, sb), 1.0);
     } else {  // M_{O kp} <- -M_{O kp} X
         bgj_fetch(M, n, O, kp, vb);
-        bgj_put_t(sa, vb);
+        bgj_put(sa, vb);
         bgj_put(sb, vx);
         __syncthreads();
         bgj_store_tile(M, n, O, kp, bgj_mfma(sa, sb), -1.0);
@@ -997,9 +1064,9 @@ __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_pivot(int n, int k, double*
 // operands are fetched at once; X M_KJ goes through LDS, M_IJ stays in registers.
 __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_update(int n, int k, double* __restrict__ M,
                                                             const double* __restrict__ X) {
-    __shared__ double sx[BGJ * BGJ];  // X^T, then (M_IK)^T
-    __shared__ double sb[BGJ * BGJ];  // M_KJ
-    __shared__ double st[BGJ * BGJ];  // X M_KJ
+    __shared__ double sx[BGJ * BGJ_LD];  // X, then M_IK
+    __shared__ double sb[BGJ * BGJ_LD];  // M_KJ
+    __shared__ double st[BGJ * BGJ_LD];  // X M_KJ
     const int nb = (n + BGJ - 1) / BGJ;
     const int w = blockIdx.x;
     const int I = bgj_other(w / (nb - 1), k), J = bgj_other(w % (nb - 1), k);
@@ -1013,14 +1080,14 @@ __global__ __launch_bounds__(BGJ_THREADS) void k_bgj_update(int n, int k, double
         const int i = bgj_out_row(r);
         cur[r] = (i < bi && j < bj) ? M[(size_t)(I * BGJ + i) * n + (size_t)J * BGJ + j] : 0.0;
     }
-    bgj_put_t(sx, vx);
+    bgj_put(sx, vx);
     bgj_put(sb, vk);
     __syncthreads();
     const bgj_v4 t = bgj_mfma(sx, sb);  // T = X M_KJ
 #pragma unroll
-    for (int r = 0; r < 4; ++r) st[bgj_out_row(r) * BGJ + j] = t[r];
+    for (int r = 0; r < 4; ++r) st[bgj_out_row(r) * BGJ_LD + j] = t[r];
     __syncthreads();
-    bgj_put_t(sx, vi);
+    bgj_put(sx, vi);
     __syncthreads();
     const bgj_v4 acc = bgj_mfma(sx, st);  // M_IK T
 #pragma unroll
