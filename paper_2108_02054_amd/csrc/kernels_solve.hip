@@ -98,9 +98,16 @@ __device__ __forceinline__ void rb_load_core(int row0, int row1, const int* __re
     for (int i = threadIdx.x; i <= nr; i += RB_THREADS) sptr[i] = ptr[row0 + i];
     const int k0 = ptr[row0];
     const int k1 = min(ptr[row1], k0 + RB_CAP);  // blocks are sized within RB_CAP
+    // as many load slots per thread as the block needs (a clamped slot still costs its
+    // loads): 5 passes are common (rows of 30-40 entries in blocks of 32 rows)
     const int passes = (k1 - k0 + RB_THREADS - 1) / RB_THREADS;
-    if (passes > 4)
-        rb_stage<RB_CAP / RB_THREADS>(k0, k1, colat, val, xget, sp);
+    static_assert(RB_CAP / RB_THREADS == 8, "stage variants cover 1 to 8 passes");
+    if (passes > 6)
+        rb_stage<8>(k0, k1, colat, val, xget, sp);
+    else if (passes > 5)
+        rb_stage<6>(k0, k1, colat, val, xget, sp);
+    else if (passes > 4)
+        rb_stage<5>(k0, k1, colat, val, xget, sp);
     else if (passes > 2)
         rb_stage<4>(k0, k1, colat, val, xget, sp);
     else if (passes > 0)
