@@ -441,12 +441,14 @@ bool lanes_only() {
 }
 
 // Galerkin form override (AMGMI_GALERKIN = pos | pos16 | lanes, optionally ":G" for the
-// position-map form's lanes per row; pos16 forces two-byte positions); used to exercise
-// every form and launch shape.  Default: the shape picker's choice.
+// position-map form's lanes per row and ":G:T" also for its B terms per lane and entry;
+// pos16 forces two-byte positions); used to exercise every form and launch shape.
+// Default: the shape picker's choice.
 struct GalForce {
     int lanes = 0;  // 1: lane-group kernels
     int wide = 0;   // 1: two-byte positions
     int g = 0;
+    int t = 0;      // B terms per lane and entry (1 or 2)
 };
 GalForce galerkin_force() {
     GalForce f;
@@ -454,7 +456,10 @@ GalForce galerkin_force() {
     if (e == nullptr) return f;
     if (std::strncmp(e, "lanes", 5) == 0) f.lanes = 1;
     if (std::strncmp(e, "pos16", 5) == 0) f.wide = 1;
-    if (const char* c = std::strchr(e, ':')) f.g = std::atoi(c + 1);
+    if (const char* c = std::strchr(e, ':')) {
+        f.g = std::atoi(c + 1);
+        if (const char* c2 = std::strchr(c + 1, ':')) f.t = std::atoi(c2 + 1);
+    }
     return f;
 }
 
@@ -518,7 +523,7 @@ GalShape make_posmap(amg_ctx* c, const Csr& L, const Csr& B, const Csr& C, bool 
     const auto Cp = to_host(C.ptr, (size_t)C.nrows + 1, s);
     int maxlen = 0;
     for (int32_t i = 0; i < C.nrows; ++i) maxlen = std::max(maxlen, Cp[(size_t)i + 1] - Cp[(size_t)i]);
-    GalShape gs = pick_galerkin_shape(L.nrows, L.nnz, terms, maxlen, f.g);
+    GalShape gs = pick_galerkin_shape(L.nrows, L.nnz, terms, maxlen, f.g, f.t);
     if (gs.g == 0 || !galerkin_terms_fit(max_row)) {
         release(c, off);
         return {};

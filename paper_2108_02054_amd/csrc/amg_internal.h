@@ -113,6 +113,7 @@ struct GalShape {
     int cap = 0;
     int epl = 2;                // L entries per lane per chunk
     int wide = 0;               // 1: two-byte positions
+    int tpl = 1;                // B terms per lane loaded per entry of a batch (1 or 2)
     // device arrays owned by the hierarchy
     void* pos = nullptr;        // position map, one entry per term
     int64_t* off = nullptr;     // nrows + 1 term offsets
@@ -392,7 +393,7 @@ bool launch_galerkin_ap(const Csr& A, const Csr& P, const Csr& AP, int g, GalSha
                         const double* ain, hipStream_t s, const Dia* dia = nullptr);
 template <typename T>
 void launch_galerkin_rap(const Csr& R, const Csr& AP, const Csr& Ac, int g, GalShape gs, hipStream_t s);
-GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen_c, int gforce);
+GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen_c, int gforce, int tforce);
 // count_galerkin_terms writes the term offsets gs.off (nrows + 1) and returns the number
 // of terms (and the most in one row); build_galerkin_posmap fills gs.pos, gs.bst, gs.tof
 // and, if allocated, gs.dpos (all allocated by the caller in between).

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(TPB) void k_galerkin_rap(int nc, const int* __restr
 // order), and can take A's values from a new FP64 array, storing the hierarchy's copies
 // on the way.
 
-constexpr int WF_AHEAD = 8;            // L entries whose terms are loaded together
+constexpr int WF_LOADS = 8;            // B terms per lane loaded together
 constexpr int WF_CAP_MAX = 4096;       // longest C row the form takes
 constexpr int64_t WF_TERMS_MAX = 65535;  // most terms in one C row (two-byte term offsets)
 constexpr size_t WF_SMEM_MAX = 65536;  // LDS per block
@@ -158,7 +158,7 @@ constexpr size_t wf_group_smem(int cap) {
     return (size_t)cap * sizeof(T) + (size_t)EPL * G * (sizeof(T) + sizeof(WfEnt));
 }
 
-template <typename T, int G, typename PT, int EPL>
+template <typename T, int G, typename PT, int EPL, int TPL>
 __global__ __launch_bounds__(TPB) void k_galerkin_pos(
     int nrows, int cap, const int* __restrict__ Lptr, const T* __restrict__ Lval, const int* __restrict__ Lbst,
     const uint16_t* __restrict__ Ltof, const T* __restrict__ Bval, const int* __restrict__ Cptr,
@@ -227,12 +227,16 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
                 ss = ss + a * a;
             }
         // Batches of WF_AHEAD entries, double-buffered: the terms of the next batch are
-        // loaded before the current batch is added.
-        int up[WF_AHEAD], ul[WF_AHEAD];
-        T bv[WF_AHEAD];
-        auto load = [&](int u0, int (&qp)[WF_AHEAD], int (&ql)[WF_AHEAD], T (&qv)[WF_AHEAD]) {
+        // loaded before the current batch is added.  Each lane loads TPL terms of every
+        // entry of a batch (g, and g + G with TPL = 2), so B rows of up to TPL G terms
+        // need no further round trip; TPL = 2 pays for it with half the entries per batch.
+        constexpr int WF_AHEAD = WF_LOADS / TPL;
+        int up[WF_AHEAD], ul[WF_AHEAD], uq[WF_AHEAD];
+        T bv[WF_AHEAD], bw[WF_AHEAD];
+        auto load = [&](int u0, int (&qp)[WF_AHEAD], int (&ql)[WF_AHEAD], T (&qv)[WF_AHEAD], int (&qq)[WF_AHEAD],
+                        T (&qw)[WF_AHEAD]) {
 #pragma unroll
-            for (int i = 0; i < WF_AHEAD; ++i) {  // first G terms of each entry, in flight together
+            for (int i = 0; i < WF_AHEAD; ++i) {  // first 2G terms of each entry, in flight together
                 const int u = u0 + i < nt ? u0 + i : nt - 1;
                 const WfEnt w = ent[u];
                 ql[i] = u0 + i < nt ? w.len : 0;
@@ -240,21 +244,26 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
                     qp[i] = (int)prow[w.to + g];
                     qv[i] = Bval[w.bs + g];
                 }
+                if (TPL > 1 && g + G < ql[i]) {
+                    qq[i] = (int)prow[w.to + g + G];
+                    qw[i] = Bval[w.bs + g + G];
+                }
             }
         };
-        load(0, up, ul, bv);
+        load(0, up, ul, bv, uq, bw);
         for (int u0 = 0; u0 < nt; u0 += WF_AHEAD) {
-            int up2[WF_AHEAD], ul2[WF_AHEAD];
-            T bv2[WF_AHEAD];
-            if (u0 + WF_AHEAD < nt) load(u0 + WF_AHEAD, up2, ul2, bv2);  // uniform across the group
+            int up2[WF_AHEAD], ul2[WF_AHEAD], uq2[WF_AHEAD];
+            T bv2[WF_AHEAD], bw2[WF_AHEAD];
+            if (u0 + WF_AHEAD < nt) load(u0 + WF_AHEAD, up2, ul2, bv2, uq2, bw2);  // uniform across the group
 #pragma unroll
             for (int i = 0; i < WF_AHEAD; ++i) {
                 if (ul[i] == 0) continue;  // uniform across the group
                 const T lv = elv[u0 + i];
                 if (g < ul[i] && up[i] < len) sacc[up[i]] = sacc[up[i]] + lv * bv[i];
-                if (ul[i] > G) {  // rows of B longer than G
+                if (TPL > 1 && g + G < ul[i] && uq[i] < len) sacc[uq[i]] = sacc[uq[i]] + lv * bw[i];
+                if (ul[i] > TPL * G) {  // rows of B longer than TPL G
                     const WfEnt w = ent[u0 + i];
-                    for (int k = g + G; k < ul[i]; k += G) {
+                    for (int k = g + TPL * G; k < ul[i]; k += G) {
                         const int p = (int)prow[w.to + k];
                         const T b = Bval[w.bs + k];
                         if (p < len) sacc[p] = sacc[p] + lv * b;
@@ -266,6 +275,8 @@ __global__ __launch_bounds__(TPB) void k_galerkin_pos(
                 up[i] = up2[i];
                 ul[i] = ul2[i];
                 bv[i] = bv2[i];
+                uq[i] = uq2[i];
+                bw[i] = bw2[i];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -401,20 +412,26 @@ void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalSh
     } while (0)
 
 // Launch shape of the position-map form for C = L B from its sizes (rows and entries of L,
-// terms, the longest C row): cap = the longest C row rounded up to a multiple of 8, and
-// G = the power of two in [4, 64] nearest above the mean number of terms per L entry (the
-// mean referenced B row length, so that most B rows take one pass of the group), or at
-// least an eighth of the mean L row length, raised until a block's LDS (TPB / G rows of
-// cap FP64 accumulators and the staged L entries) is within WF_SMEM_MAX.
-// {0, ...}: the rows are too long for the form (lane-group kernels).  gforce forces G
-// where the LDS allows.  The position map itself is built by the caller.
-GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen, int gforce) {
+// terms, the longest C row): cap = the longest C row rounded up to a multiple of 8; TPL =
+// 2 terms per lane and entry for products of at least TPL2_MIN_ROWS rows (more rows per
+// wavefront, fewer B rows left to a second round trip; measured at 128^3: level-0 A P
+// 286 against 315 us, R (A P) 215 against 241 us), else 1 (small products want every lane
+// on few rows); G = the power of two in [4, 64] nearest above the mean number of terms
+// per L entry over TPL (the mean referenced B row length, so that most B rows take one
+// pass of the group), or at least an eighth of the mean L row length, raised until a
+// block's LDS (TPB / G rows of cap FP64 accumulators and the staged L entries) is within
+// WF_SMEM_MAX.  {0, ...}: the rows are too long for the form (lane-group kernels).
+// gforce and tforce force G and TPL where the LDS allows.  The position map itself is
+// built by the caller.
+constexpr int32_t TPL2_MIN_ROWS = 1 << 16;
+GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int maxlen, int gforce, int tforce) {
     if (maxlen > WF_CAP_MAX) return {};
     const double mean_b = nnzL > 0 ? (double)terms / (double)nnzL : 1.0;
     const int cap = std::max(8, (maxlen + 7) / 8 * 8);
     const double mean_l = nrows > 0 ? (double)nnzL / (double)nrows : 1.0;
+    const int tpl = (tforce == 1 || tforce == 2) ? tforce : (nrows >= TPL2_MIN_ROWS ? 2 : 1);
     int G = 4;
-    while (G < 64 && G < mean_b) G <<= 1;
+    while (G < 64 && G * tpl < mean_b) G <<= 1;
     while (G < 64 && 8 * G <= mean_l) G <<= 1;  // long L rows: wider groups, fewer chunks
     if (gforce == 4 || gforce == 8 || gforce == 16 || gforce == 32 || gforce == 64) G = gforce;
     const int epl = mean_l > 2.0 * G ? 4 : 2;
@@ -428,6 +445,7 @@ GalShape pick_galerkin_shape(int32_t nrows, int64_t nnzL, int64_t terms, int max
     gs.cap = cap;
     gs.epl = epl;
     gs.wide = maxlen > 255 ? 1 : 0;
+    gs.tpl = tpl;
     return gs;
 }
 
@@ -447,18 +465,24 @@ static void launch_pos(const Csr& L, const Csr& B, const Csr& C, const GalShape&
     T* dT = nullptr;
     if constexpr (!std::is_same<T, double>::value)
         if (dia != nullptr) dT = dia->val32;
-#define AMG_POS_LAUNCH(PT, EPL)                                                                           \
-    AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, PT, EPL><<<row_blocks(L.nrows, GG), TPB, sm, s>>>(           \
+#define AMG_POS_LAUNCH(PT, EPL, TPL)                                                                      \
+    AMG_WITH_GS1(gs.g, (k_galerkin_pos<T, GG, PT, EPL, TPL><<<row_blocks(L.nrows, GG), TPB, sm, s>>>(      \
                            L.nrows, gs.cap, L.ptr, L.v<T>(), gs.bst, gs.tof, B.v<T>(), C.ptr, C.v<T>(),     \
                            (const PT*)gs.pos, gs.off, dp, kind, (T)omega, m, lin, lout64, loutT, dslot,     \
                            (int64_t)L.nrows, d64, dT)))
+#define AMG_POS_LAUNCH_T(PT, EPL)                  \
+    do {                                           \
+        if (gs.tpl == 2) AMG_POS_LAUNCH(PT, EPL, 2); \
+        else AMG_POS_LAUNCH(PT, EPL, 1);           \
+    } while (0)
     if (gs.wide) {
-        if (gs.epl == 4) AMG_POS_LAUNCH(uint16_t, 4);
-        else AMG_POS_LAUNCH(uint16_t, 2);
+        if (gs.epl == 4) AMG_POS_LAUNCH_T(uint16_t, 4);
+        else AMG_POS_LAUNCH_T(uint16_t, 2);
     } else {
-        if (gs.epl == 4) AMG_POS_LAUNCH(uint8_t, 4);
-        else AMG_POS_LAUNCH(uint8_t, 2);
+        if (gs.epl == 4) AMG_POS_LAUNCH_T(uint8_t, 4);
+        else AMG_POS_LAUNCH_T(uint8_t, 2);
     }
+#undef AMG_POS_LAUNCH_T
 #undef AMG_POS_LAUNCH
     HIP_LAUNCH_CHECK();
 }

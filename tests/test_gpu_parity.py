@@ -310,15 +310,16 @@ def test_lane_group_kernels_parity(monkeypatch):
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
 
 
-GALERKIN_FORMS = ["pos", "pos:4", "pos:16", "pos:64", "pos16", "lanes", "nodia"]
+GALERKIN_FORMS = ["pos", "pos:4", "pos:16", "pos:64", "pos:4:2", "pos:8:2", "pos:32:2", "pos16", "pos16:4:2",
+                  "lanes", "nodia"]
 
 
 @pytest.mark.parametrize("form", GALERKIN_FORMS)
 @pytest.mark.parametrize("smoother", [0, 1])
 def test_galerkin_forms_parity(monkeypatch, form, smoother):
-    """Every Galerkin form (the position-map form at several lanes per row and with one-
-    and two-byte positions, the lane-group kernels, and with level 0 in CSR rather than
-    diagonal storage) gives the oracle's FP64 hierarchy bit for bit after a partial
+    """Every Galerkin form (the position-map form at several lanes per row, with one or
+    two terms per lane and entry, with one- and two-byte positions, the lane-group kernels,
+    and with level 0 in CSR rather than diagonal storage) gives the oracle's FP64 hierarchy bit for bit after a partial
     rebuild, with the fused value ingest and smoother diagonal, on 7-point and 27-point
     patterns."""
     if form == "nodia":  # level 0 in CSR
