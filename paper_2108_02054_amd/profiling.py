@@ -13,7 +13,9 @@ Usage (after the rocprofv3 runs):
   python -m paper_2108_02054_amd.profiling traffic --kernel k_cg_pq --source csrc/kernels_solve.hip \\
       --fetch <dir>/run_counter_collection.csv --write <dir>/run_counter_collection.csv \\
       --copy-fetch <dir> --copy-write <dir> --copy-mib 256 --command "..." --out profiles/x.json \\
-      [--part REGEX:GRID ...]   (several kernels per unit, e.g. the Galerkin products of level 0)
+      [--part REGEX:GRID[:K/M] ...]   (several kernels per unit, e.g. the Galerkin products of
+      level 0; K/M keeps the K-th of every M matching dispatches, in dispatch order, for two
+      products that share a kernel and a grid size)
 """
 from __future__ import annotations
 
@@ -73,14 +75,23 @@ def write_stats(csv_path: str, out_txt: str, command: str, workload: str, top: i
         f.write("\n".join(lines) + "\n")
 
 
-def counter_per_dispatch(csv_path: str, counter: str, kernel_re: str, grid: int | None = None) -> list[float]:
+def counter_per_dispatch(csv_path: str, counter: str, kernel_re: str, grid: int | None = None,
+                         every: tuple[int, int] | None = None) -> list[float]:
     """Counter value (KiB) of every dispatch whose kernel name matches kernel_re (and whose
-    grid size is ``grid`` when given)."""
-    vals = []
+    grid size is ``grid`` when given), in dispatch order; with every = (k, m) only the k-th
+    of every m such dispatches (their count must be a multiple of m)."""
+    rows = []
     for r in csv.DictReader(open(csv_path)):
         if r["Counter_Name"] == counter and re.search(kernel_re, r["Kernel_Name"]):
             if grid is None or int(r["Grid_Size"]) == grid:
-                vals.append(float(r["Counter_Value"]))
+                rows.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    rows.sort()
+    vals = [v for _, v in rows]
+    if every is not None:
+        k, m = every
+        if len(vals) % m:
+            raise ValueError(f"{len(vals)} dispatches of {kernel_re} (grid {grid}), not a multiple of {m}")
+        vals = vals[k::m]
     return vals
 
 
@@ -94,7 +105,7 @@ def copy_kib(run_dir: str, counter: str) -> float:
 
 
 def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, copy_fetch_dir: str, copy_write_dir: str,
-            copy_mib: int, command: str, parts: list[tuple[str, int]] | None = None) -> dict:
+            copy_mib: int, command: str, parts: list[tuple] | None = None) -> dict:
     """HBM bytes per launch of ``kernel``; with ``parts`` (kernel regex, grid size) the
     per-dispatch averages of each part are added (one unit = one dispatch of every part,
     e.g. the two Galerkin products of one level per rebuild)."""
@@ -103,9 +114,10 @@ def traffic(kernel: str, source: str, fetch_csv: str, write_csv: str, copy_fetch
     w_scale = known / (copy_kib(copy_write_dir, "WRITE_SIZE") * 1024.0)
     fb = wb = 0.0
     nd = 0
-    for rx, grid in (parts or [(kernel, None)]):
-        f = counter_per_dispatch(fetch_csv, "FETCH_SIZE", rx, grid)
-        w = counter_per_dispatch(write_csv, "WRITE_SIZE", rx, grid)
+    for part in (parts or [(kernel, None, None)]):
+        rx, grid, every = part
+        f = counter_per_dispatch(fetch_csv, "FETCH_SIZE", rx, grid, every)
+        w = counter_per_dispatch(write_csv, "WRITE_SIZE", rx, grid, every)
         if not f or not w:
             raise ValueError(f"no dispatches of {rx} (grid {grid})")
         fb += sum(f) / len(f) * 1024.0 * f_scale
@@ -137,6 +149,16 @@ def load_traffic(json_path: str) -> dict | None:
     return rec
 
 
+def parse_part(spec: str) -> tuple:
+    """REGEX:GRID or REGEX:GRID:K/M -> (regex, grid, (k, m) or None)."""
+    head, last = spec.rsplit(":", 1)
+    if "/" in last:
+        rx, grid = head.rsplit(":", 1)
+        k, m = last.split("/")
+        return rx, int(grid), (int(k), int(m))
+    return head, int(last), None
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -155,13 +177,14 @@ def main():
     b.add_argument("--copy-mib", type=int, required=True)
     b.add_argument("--command", required=True)
     b.add_argument("--out", required=True)
-    b.add_argument("--part", action="append", default=[], metavar="REGEX:GRID",
-                   help="add the per-dispatch traffic of the dispatches of REGEX with grid size GRID")
+    b.add_argument("--part", action="append", default=[], metavar="REGEX:GRID[:K/M]",
+                   help="add the per-dispatch traffic of the dispatches of REGEX with grid size GRID "
+                        "(only the K-th of every M of them)")
     args = ap.parse_args()
     if args.cmd == "stats":
         write_stats(args.csv, args.out, args.command, args.workload)
     else:
-        parts = [(p.rsplit(":", 1)[0], int(p.rsplit(":", 1)[1])) for p in args.part] or None
+        parts = [parse_part(p) for p in args.part] or None
         rec = traffic(args.kernel, args.source, args.fetch, args.write, args.copy_fetch, args.copy_write,
                       args.copy_mib, args.command, parts)
         with open(args.out, "w") as f:
