@@ -327,6 +327,7 @@ bool mixed(const amg_ctx* c) { return c->prm.precision == 1; }
 struct Trace {
     amg_ctx* c;
     int cls, level;
+    hipStream_t ts;  // the stream the bracketing events are recorded on
     hipEvent_t a = nullptr, b = nullptr;
     static hipEvent_t take(amg_ctx* c) {
         if (c->ev_pool.empty()) {
@@ -348,7 +349,7 @@ struct Trace {
                k == AMG_K_COARSE_GEMV || k == AMG_K_TAIL;
     }
     bool own = false;
-    Trace(amg_ctx* cc, int k, int lvl) : c(cc), cls(k), level(lvl) {
+    Trace(amg_ctx* cc, int k, int lvl, hipStream_t st = nullptr) : c(cc), cls(k), level(lvl), ts(st ? st : cc->stream) {
         if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == lvl)) {
             a = take(c);
             b = take(c);
@@ -356,14 +357,14 @@ struct Trace {
                 own = true;
                 g_kernel_events = KernelEvents{a, b};
             } else {
-                HIP_CHECK(hipEventRecord(a, c->stream));
+                HIP_CHECK(hipEventRecord(a, ts));
             }
         }
     }
     ~Trace() {
         if (!a) return;
         if (!own) {
-            (void)hipEventRecord(b, c->stream);
+            (void)hipEventRecord(b, ts);
         } else if (g_kernel_events.start == a) {  // the scope launched nothing: not a launch
             g_kernel_events = KernelEvents{};
             c->ev_pool.push_back(a);
@@ -379,6 +380,14 @@ void read_red(amg_ctx* c) {
     HIP_CHECK(hipMemcpyAsync(c->h_red, c->rs.scal(), RedScratch::host_doubles(c->rs.cap) * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
     HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+// The context's stream waits for the coarsest inverse of the last partial update (run on
+// the side stream) before anything on it uses the inverse or its pivot flag.
+void wait_coarse(amg_ctx* c) {
+    if (!c->cinv_pending) return;
+    HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_inv, 0));
+    c->cinv_pending = false;
 }
 
 // Queue the copy of the scalar slots and the first nrr ||r||^2 partials (the CG loop's
@@ -669,6 +678,7 @@ template <typename T>
 void partial_rebuild(amg_ctx* c, const double* val) {
     hipStream_t s = c->stream;
     Level& L0 = c->lv[0];
+    wait_coarse(c);  // the last update's inverse reads A_L, which this update rewrites
     HIP_CHECK(hipEventRecord(c->ev[0], s));
     c->outer_val = L0.A.val;
     const int nlev = (int)c->lv.size();
@@ -716,12 +726,24 @@ void partial_rebuild(amg_ctx* c, const double* val) {
             launch_smoother_diag<T>(L.A, c->prm.smoother, c->prm.jacobi_omega, L.mv<T>(), s);
     }
     HIP_CHECK(hipEventRecord(c->ev[2], s));
-    {
-        Trace tr(c, AMG_K_COARSE_INV, nlev - 1);
-        launch_densify<T>(c->lv.back().A, c->cinv, s);
-        launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), c->cwork, s);
+    // the blocked inverse (one workgroup per pivot block on its critical path) runs beside
+    // the start of the next solve, which needs it only at the bottom of its first cycle
+    const bool side = c->side != nullptr && c->nL > COARSE_LDS_MAX && c->tail == 0;
+    hipStream_t cs = side ? c->side : s;
+    if (side) {
+        HIP_CHECK(hipEventRecord(c->ev_fork, s));
+        HIP_CHECK(hipStreamWaitEvent(cs, c->ev_fork, 0));
     }
-    HIP_CHECK(hipEventRecord(c->ev[3], s));
+    {
+        Trace tr(c, AMG_K_COARSE_INV, nlev - 1, cs);
+        launch_densify<T>(c->lv.back().A, c->cinv, cs);
+        launch_dense_inverse(c->nL, c->cinv, c->rs.scal(), c->cwork, cs);
+    }
+    HIP_CHECK(hipEventRecord(c->ev[3], cs));
+    if (side) {
+        HIP_CHECK(hipEventRecord(c->ev_inv, cs));
+        c->cinv_pending = true;
+    }
     c->phase_pending = true;
 }
 
@@ -809,6 +831,7 @@ struct Transfer {
 
 void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, const int32_t* col,
                      const double* val, const Transfer* tr) {
+    wait_coarse(c);  // the old hierarchy's arrays are freed on the context's stream
     c->pol_updates = 0;
     c->pol_iters_ref = 0;
     c->pol_last_iters = 0;
@@ -989,6 +1012,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     if (mixed(c)) {
         alloc_shadow(c);
         partial_rebuild<float>(c, c->lv[0].A.val);
+        wait_coarse(c);
         read_red(c);
         if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest FP32 operator is not SPD"};
         c->phase_pending = false;
@@ -1007,6 +1031,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
 // New pattern with the same number of rows: keep P_l and R_l, recompute the Galerkin
 // patterns level by level (values follow in the partial update).
 void repattern(amg_ctx* c) {
+    wait_coarse(c);
     hipStream_t s = c->stream;
     Level& L0 = c->lv[0];
     Csr A;
@@ -1225,7 +1250,8 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep, int
     if (l == nlev - 1) {
         T* u = out ? out : (T*)L.u;
         Trace tr(c, AMG_K_COARSE_GEMV, l);
-        launch_coarse_gemv<T>(c->nL, c->cinv, f, u, s);
+        wait_coarse(c);
+        launch_coarse_gemv<T>(c->nL, c->cinv, f, u, c->rs.scal() + S_COARSE, s);
         if (ep) {
             Trace tr2(c, AMG_K_CG_RZ, 0);
             if (ep->flexible) throw Fail{AMG_ERR_ARG, "flexible CG needs at least one post-smoothing sweep"};
@@ -1377,10 +1403,23 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         return nb;
     };
     launch_copy(n, u, c->x, s);
+    // with the inverse still running beside, its pivot flag is read after the first cycle
+    // (a failed inverse makes that cycle's output NaN, hence a breakdown, checked below)
+    const bool coarse_known = !c->cinv_pending;
     int nb = true_residual();
-    if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
+    auto coarse_failed = [&]() {
+        if (!coarse_known) {
+            wait_coarse(c);
+            read_red(c);
+        }
+        return host_scal(c, S_COARSE) != 0.0;
+    };
+    if (coarse_known && coarse_failed())
+        throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
     const double ff = host_sum(c, P_FF, nb);
     if (ff == 0.0) {
+        if (!coarse_known && coarse_failed())
+            throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
         HIP_CHECK(hipMemsetAsync(u, 0, (size_t)n * sizeof(double), s));
         HIP_CHECK(hipStreamSynchronize(s));
         inf.converged = 1;
@@ -1390,6 +1429,8 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
     const double nf = std::sqrt(ff);
     double res = std::sqrt(host_sum(c, P_RR, nb)) / nf;
     if (res <= p.rtol) {
+        if (!coarse_known && coarse_failed())
+            throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
         inf.converged = 1;
         inf.rel_res_true = res;
         if (info) *info = inf;
@@ -1456,8 +1497,11 @@ amg_status pcg(amg_ctx* c, const double* f, double* u, amg_solve_info* info) {
         if (speculate) precondition(0, ready);
         HIP_CHECK(hipEventSynchronize(c->ev_read));
         if (host_scal(c, S_FLAG) != 0.0) {
+            wait_coarse(c);
+            read_red(c);  // a coarsest operator that is not SPD shows as a breakdown
+            if (host_scal(c, S_COARSE) != 0.0)
+                throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
             c->err = "CG breakdown (p.Ap <= 0 or a non-finite scalar)";
-            HIP_CHECK(hipStreamSynchronize(s));
             if (info) {
                 inf.iters = it;
                 *info = inf;
@@ -1583,8 +1627,12 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
         return false;
     };
     auto breakdown = [&](const char* what) {
-        c->err = std::string("BiCGStab breakdown: ") + what;
         HIP_CHECK(hipStreamSynchronize(s));
+        wait_coarse(c);
+        read_red(c);  // a coarsest operator that is not SPD shows as a breakdown
+        if (host_scal(c, S_COARSE) != 0.0)
+            throw Fail{AMG_ERR_NOT_SPD, "coarsest operator of the last rebuild is not SPD"};
+        c->err = std::string("BiCGStab breakdown: ") + what;
         if (info) {
             inf.iters = it;
             *info = inf;
@@ -1669,6 +1717,7 @@ amg_status check_params(const amg_params& p) {
 void destroy_ctx(amg_ctx* c) {
     if (!c) return;
     hipStream_t s = c->stream;
+    if (c->side) (void)hipStreamSynchronize(c->side);
     (void)hipStreamSynchronize(s);
     {
         MemScope scope(&c->mem);
@@ -1685,6 +1734,9 @@ void destroy_ctx(amg_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->ev_read) (void)hipEventDestroy(c->ev_read);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_inv) (void)hipEventDestroy(c->ev_inv);
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (auto& t : c->traced) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -1704,6 +1756,9 @@ amg_ctx* create_ctx(const amg_params& p, void* stream) {
         HIP_CHECK(hipHostMalloc((void**)&c->h_flags, F_COUNT * sizeof(int), hipHostMallocDefault));
         for (hipEvent_t& e : c->ev) HIP_CHECK(hipEventCreate(&e));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_read, hipEventDisableTiming));
+        HIP_CHECK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&c->ev_inv, hipEventDisableTiming));
     } catch (...) {
         destroy_ctx(c);
         throw;
@@ -2128,6 +2183,7 @@ amg_status amg_export_coarse_inverse(const amg_ctx* cc, double* inv) {
     amg_ctx* c = const_cast<amg_ctx*>(cc);
     if (!c || !inv) return AMG_ERR_ARG;
     return guard(c, [&] {
+        wait_coarse(c);
         HIP_CHECK(hipMemcpyAsync(inv, c->cinv, (size_t)c->nL * c->nL * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
         HIP_CHECK(hipStreamSynchronize(c->stream));

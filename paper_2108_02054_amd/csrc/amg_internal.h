@@ -365,7 +365,7 @@ template <typename T>
 void launch_vcycle_tail(const TailArgs<T>& a, hipStream_t s);
 
 template <typename T>
-void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s);
+void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, const double* bad, hipStream_t s);
 void launch_cast_d2f(int64_t n, const double* a, float* b, hipStream_t s);
 void launch_cast_f2d(int64_t n, const float* a, double* b, hipStream_t s);
 void launch_copy(int64_t n, const double* a, double* b, hipStream_t s);
@@ -517,6 +517,14 @@ struct amg_ctx {
     bool phase_pending = false;   // partial rebuild: times still to be read from ev[]
     hipEvent_t ev[4]{};
     hipEvent_t ev_read = nullptr;  // completion of the per-iteration scalar read
+    // The blocked inverse of the coarsest operator (more than COARSE_LDS_MAX rows) of a
+    // partial update runs on a stream of the context's own (side, default priority),
+    // ordered after the update's Galerkin products by ev_fork, so that it overlaps the
+    // start of the next solve; every use of the inverse, or of its pivot flag, on the
+    // context's stream first waits for ev_inv (wait_coarse).
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_inv = nullptr;
+    bool cinv_pending = false;
     // per-kernel tracing (amg_trace)
     unsigned trace_mask = 0;
     int trace_level = -1;

@@ -414,10 +414,12 @@ __global__ __launch_bounds__(TPB) void k_lg(int n, const int* __restrict__ ptr, 
     if constexpr (KIND == 4) y[row] += s;                                 // u += P uc
 }
 
-// u = A^{-1} f on the coarsest level: one wavefront per row of the dense FP64 inverse.
+// u = A^{-1} f on the coarsest level: one wavefront per row of the dense FP64 inverse; a
+// NaN solution when the inverse's pivot flag *bad is set (a coarsest operator that is not
+// SPD then surfaces as a breakdown of the Krylov method that applies the cycle).
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_coarse_gemv(int n, const double* __restrict__ inv, const T* __restrict__ f,
-                                                     T* __restrict__ u) {
+                                                     T* __restrict__ u, const double* __restrict__ bad) {
     const int lane = threadIdx.x & 63;
     const int row = (blockIdx.x * TPB + (int)threadIdx.x) >> 6;
     if (row >= n) return;
@@ -425,7 +427,7 @@ __global__ __launch_bounds__(TPB) void k_coarse_gemv(int n, const double* __rest
     double s = 0.0;
     for (int j = lane; j < n; j += 64) s += a[j] * (double)f[j];
     s = wave_sum(s);
-    if (lane == 0) u[row] = (T)s;
+    if (lane == 0) u[row] = (*bad != 0.0) ? (T)__builtin_nan("") : (T)s;
 }
 
 __global__ void k_cast_d2f(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
@@ -501,8 +503,8 @@ void launch_prolong_add(const Csr& P, const T* uc, T* u, hipStream_t s) {
     HIP_LAUNCH_CHECK();
 }
 template <typename T>
-void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, hipStream_t s) {
-    timed_launch(k_coarse_gemv<T>, grid_for((int64_t)n * 64, TPB), TPB, 0, s, n, inv, f, u);
+void launch_coarse_gemv(int n, const double* inv, const T* f, T* u, const double* bad, hipStream_t s) {
+    timed_launch(k_coarse_gemv<T>, grid_for((int64_t)n * 64, TPB), TPB, 0, s, n, inv, f, u, bad);
     HIP_LAUNCH_CHECK();
 }
 void launch_cast_d2f(int64_t n, const double* a, float* b, hipStream_t s) {
@@ -1646,7 +1648,7 @@ void launch_vcycle_tail(const TailArgs<T>& a, hipStream_t s) {
     template void launch_jacobi<T>(const Csr&, const T*, const T*, const T*, T*, hipStream_t);      \
     template void launch_smooth0_residual<T>(const Csr&, const T*, const T*, T*, T*, hipStream_t);  \
     template void launch_prolong_add<T>(const Csr&, const T*, T*, hipStream_t);                     \
-    template void launch_coarse_gemv<T>(int, const double*, const T*, T*, hipStream_t);             \
+    template void launch_coarse_gemv<T>(int, const double*, const T*, T*, const double*, hipStream_t); \
     template void launch_vcycle_tail<T>(const TailArgs<T>&, hipStream_t);                          \
     template void launch_dia_scatter<T>(const Csr&, const Dia&, const double*, T*, hipStream_t);    \
     template void launch_dia_smooth0_residual<T>(int, const Dia&, const T*, const T*, T*, T*, hipStream_t); \

@@ -647,6 +647,49 @@ def test_blocked_coarse_inverse(dims, precision):
     g.close()
 
 
+def test_coarse_inverse_beside_the_solve(monkeypatch):
+    """The blocked inverse of a partial update runs on the context's side stream: exported
+    right after the update it is the inverse of the new coarsest operator; two updates in a
+    row followed by a solve give the oracle's iterations; a NaN value makes the next CG and
+    BiCGStab solves report a coarsest operator that is not SPD."""
+    import oracle
+    from paper_2108_02054_amd import AMG, AmgError
+    monkeypatch.setenv("AMGMI_NO_TAIL", "1")  # the side stream serves only levels outside a tail
+    p, c, v0 = two_fluid_7pt(32, front_c1(0))
+    _, _, v1 = two_fluid_7pt(32, front_c1(2))
+    _, _, v2 = two_fluid_7pt(32, front_c1(4))
+    print("case coarse inverse beside the solve (32^3)", flush=True)
+    g = AMG(T(p), T(c), T(v0))
+    nL = g.dims(g.num_levels - 1)[0]
+    assert nL > 128, nL  # the blocked inverse
+    g.rebuild(T(v1))
+    L = g.level(g.num_levels - 1)
+    Ap, Ac, Av = L["A"]
+    A = np.zeros((nL, nL))
+    for i in range(nL):
+        A[i, Ac[Ap[i]:Ap[i + 1]]] = Av[Ap[i]:Ap[i + 1]]
+    assert rel_max(g.coarse_inverse(), np.linalg.inv(A)) <= 1e-11
+    g.rebuild(T(v2))
+    o = oracle.OracleHierarchy(p, c, v0)
+    o.rebuild(v2, 0)
+    f = rhs_uniform(32**3, 1, 4)
+    u, info = g.solve(T(f))
+    uo, io = o.solve(f)
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1
+    assert rel_max(u.cpu().numpy(), uo) <= 1e-6
+    vn = v2.copy()
+    vn[7] = np.nan
+    for solver in ("solve", "solve_bicgstab"):
+        g.rebuild(T(vn))
+        with pytest.raises(AmgError) as e:
+            getattr(g, solver)(T(f))
+        assert e.value.code == -5, (solver, e.value)
+    g.rebuild(T(v2))  # the context stays usable
+    u, info = g.solve(T(f))
+    assert info["converged"]
+    g.close()
+
+
 def test_coarsest_level_too_large_for_the_dense_inverse():
     from paper_2108_02054_amd import AMG, AmgError
     p, c, v = two_fluid_7pt(13, 0.45)  # 2197 rows in one level
