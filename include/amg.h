@@ -19,7 +19,11 @@
  *  - Pointers are DEVICE pointers unless marked (host).  Inputs are borrowed for the
  *    duration of the call; the library copies what it keeps.
  *  - All device work is enqueued on the HIP stream given to amg_setup (NULL: the null
- *    stream).  The caller's buffers must be ready on that stream.
+ *    stream), except the blocked inverse of a coarsest level of more than 128 rows after a
+ *    partial update, which runs on a stream the context owns (ordered after the update's
+ *    work on the given stream) so that it overlaps the start of the next solve; every later
+ *    use of the hierarchy on the given stream waits for it, and amg_destroy for all of the
+ *    context's work.  The caller's buffers must be ready on the given stream.
  *  - Every call returns an amg_status and never throws across the interface.  After a
  *    HIP runtime error, and after any failure of a call that replaces the hierarchy (a full
  *    rebuild, AMG_FULL or a size change; a pattern change), the context is unusable: every
