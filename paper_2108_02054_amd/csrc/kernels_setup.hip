@@ -811,11 +811,11 @@ __global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restric
 // block K, one block step maps
 //   M_KJ <- X M_KJ,   M_IJ <- M_IJ - M_IK X M_KJ,   M_IK <- -M_IK X,   M_KK <- X
 // (I, J != K), which is the composition of the scalar steps of K's pivots.  Step k runs as
-// two launches: k_bgj_pivot inverts M_KK (one workgroup, the scalar steps in registers and
-// LDS, every pivot checked positive) while other workgroups finish step k-1 (its row block,
-// column block and diagonal block), then k_bgj_update applies the rank-BGJ update to every
-// block (I, J) outside row and column K, forming X M_KJ itself; a last k_bgj_pivot
-// finishes the last step.  X of two consecutive steps live in two slots of a scratch
+// two launches: k_bgj_pivot inverts M_KK (one workgroup, by the same block steps 16 pivots
+// at a time: see bgj_invert_lds; every pivot checked positive) while other workgroups
+// finish step k-1 (its row block, column block and diagonal block), then k_bgj_update
+// applies the rank-BGJ update to every block (I, J) outside row and column K, forming
+// X M_KJ itself; a last k_bgj_pivot finishes the last step.  X of two consecutive steps live in two slots of a scratch
 // buffer.  The 64 x 64 x 64 block products run on the FP64 matrix cores: each of the 16
 // waves of a workgroup owns one 16 x 16 tile of the product and accumulates it over 16
 // steps of V_MFMA_F64_16X16X4F64.
@@ -919,7 +919,9 @@ __device__ __forceinline__ double bgj_lane(double v, int lane) {
 __device__ __forceinline__ bgj_v4 bgj_tile_mm(const double* a, const double* b, bgj_v4 c, double sign) {
     const int l = threadIdx.x % 64, i = l & 15, kk = l >> 4;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * a[i * BGJ_LD + 4 * s + kk], b[(4 * s + kk) * BGJ_LD + i], c, 0, 0, 0);
+    for (int s = 0; s < 4; ++s)
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * a[i * BGJ_LD + 4 * s + kk], b[(4 * s + kk) * BGJ_LD + i], c, 0,
+                                                  0, 0);
     return c;
 }
 
