@@ -2227,6 +2227,7 @@ static amg_status trace_collect(amg_ctx* c, int nlev, double* ms, int64_t* launc
             launches[k] = 0;
         }
         HIP_CHECK(hipStreamSynchronize(c->stream));
+        if (c->side) HIP_CHECK(hipStreamSynchronize(c->side));  // the coarsest inverse's events
         for (auto& t : c->traced) {
             float x = 0.f;
             HIP_CHECK(hipEventElapsedTime(&x, t.a, t.b));

@@ -648,8 +648,9 @@ def test_blocked_coarse_inverse(dims, precision):
 
 
 def test_coarse_inverse_beside_the_solve(monkeypatch):
-    """The blocked inverse of a partial update runs on the context's side stream: exported
-    right after the update it is the inverse of the new coarsest operator; two updates in a
+    """The blocked inverse of a partial update runs on the context's side stream: its traced
+    time reads right after the update; exported then it is the inverse of the new coarsest
+    operator; two updates in a
     row followed by a solve give the oracle's iterations; a NaN value makes the next CG and
     BiCGStab solves report a coarsest operator that is not SPD."""
     import oracle
@@ -662,7 +663,11 @@ def test_coarse_inverse_beside_the_solve(monkeypatch):
     g = AMG(T(p), T(c), T(v0))
     nL = g.dims(g.num_levels - 1)[0]
     assert nL > 128, nL  # the blocked inverse
+    g.trace(["coarse_inv"], level=-1)
     g.rebuild(T(v1))
+    t = g.trace_read()  # its events were recorded on the side stream: read before any solve
+    assert t["coarse_inv"][1] == 1 and t["coarse_inv"][0] > 0, t
+    g.trace([], level=0)
     L = g.level(g.num_levels - 1)
     Ap, Ac, Av = L["A"]
     A = np.zeros((nL, nL))
