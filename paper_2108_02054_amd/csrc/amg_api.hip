@@ -654,6 +654,7 @@ void configure_dia(amg_ctx* c) {
     if (D.march_a == 0 && std::getenv("AMGMI_NO_WIN") == nullptr) {
         D.win = win_plan(offs);
         D.win.all = std::getenv("AMGMI_WIN_ALL") != nullptr;
+        if (std::getenv("AMGMI_NO_WIN2") != nullptr) D.win.two = false;
     }
     if (std::getenv("AMGMI_NO_DIA_SYM") != nullptr) D.symoff = false;
     D.slot = halloc<uint8_t>(c, (size_t)A.nnz);

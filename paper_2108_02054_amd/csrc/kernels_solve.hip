@@ -1111,6 +1111,7 @@ WinPlan win_plan(const std::vector<int>& offs) {
     if (total > WIN_CAP) return WinPlan{};
     w.ncl = k;
     w.total = total;
+    w.two = nd == 27 && total + k * TPB <= WIN_CAP;
     return w;
 }
 
@@ -1166,39 +1167,140 @@ __device__ __forceinline__ void win_rows(int n, int nd_rt, const DiaOff& o, cons
     epi((int)i, s, xc);
 }
 
-template <int ND, bool SYM, typename T>
+// Two rows per thread (27 diagonals): a workgroup of TPB threads owns 2 TPB consecutive
+// rows, thread t the rows i and i + 1 with i = i0 + 2t, and fetches each diagonal's
+// entries of both rows with one load of two values (16 bytes in FP64, 8 in FP32): the
+// own-row pair (i, i + 1) and, for a mirrored sub-diagonal entry, the pair
+// (i + off, i + off + 1) of the super-diagonal, aligned to one value for any parity of
+// off.  The windows are TPB entries longer.  Each row adds the same terms in the same
+// order with the same fused multiply-adds as win_rows, so the results are equal bit for
+// bit.  A workgroup whose pairs all lie inside [0, n) loads them whole (the offsets are
+// sorted, so the first and last bound them); the others load entry by entry.
+template <typename T>
+struct WPair;
+template <>
+struct WPair<double> {
+    typedef double v __attribute__((ext_vector_type(2)));
+    typedef v u __attribute__((aligned(8)));
+};
+template <>
+struct WPair<float> {
+    typedef float v __attribute__((ext_vector_type(2)));
+    typedef v u __attribute__((aligned(4)));
+};
+
+// entries j and j + 1 of the diagonal array p; an entry outside [0, n) reads entry 0 and
+// is not used
+template <typename T>
+__device__ __forceinline__ typename WPair<T>::v wp_pair_edge(const T* __restrict__ p, int64_t j, int n) {
+    typename WPair<T>::v r;
+    r.x = p[(j >= 0 && j < n) ? j : 0];
+    r.y = p[(j + 1 >= 0 && j + 1 < n) ? j + 1 : 0];
+    return r;
+}
+
+template <int ND, bool SYM, typename T, typename XG, typename EP>
+__device__ __forceinline__ void win_rows2(int n, const DiaOff& o, const WinPlan& w, const T* __restrict__ v,
+                                          XG xget, EP epi) {
+    static_assert(ND > 0, "two rows per thread need the diagonal count at compile time");
+    typedef typename WPair<T>::v P2;
+    typedef typename WPair<T>::u P2u;
+    extern __shared__ __align__(16) unsigned char win_smem[];  // w.total + w.ncl * TPB entries
+    T* X = reinterpret_cast<T*>(win_smem);
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)xcd_block() * (2 * TPB);
+    for (int k = 0; k < w.ncl; ++k)
+        for (int e = t; e < w.len[k] + TPB; e += TPB) {
+            const int64_t j = i0 + w.lo[k] + e;
+            X[w.base[k] + k * TPB + e] = (j >= 0 && j < n) ? xget((int)j) : T(0);
+        }
+    const int64_t i = i0 + 2 * t;
+    const size_t sn = (size_t)n;
+    const bool inner = i0 + min(o.off[0], 0) >= 0 && i0 + 2 * TPB + max(o.off[ND - 1], 0) <= n;
+    P2 A[ND];
+    if (inner) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int off = o.off[d];
+            A[d] = *reinterpret_cast<const P2u*>((SYM && off < 0) ? v + (size_t)(ND - 1 - d) * sn + (i + off)
+                                                                 : v + (size_t)d * sn + i);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const int off = o.off[d];
+            A[d] = (SYM && off < 0) ? wp_pair_edge(v + (size_t)(ND - 1 - d) * sn, i + off, n)
+                                    : wp_pair_edge(v + (size_t)d * sn, i, n);
+        }
+    }
+    __syncthreads();
+    if (i >= n) return;
+    T s0 = 0, s1 = 0, xc0 = 0, xc1 = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int off = o.off[d];
+        const int k = w.cl[d];
+        const T* xp = X + w.base[k] + k * TPB + (off - w.lo[k]) + 2 * t;
+        const T x0 = xp[0], x1 = xp[1];
+        if (off == 0) {
+            xc0 = x0;
+            xc1 = x1;
+        }
+        const int64_t j = i + off;
+        s0 = (j >= 0 && j < n) ? fmadd(A[d].x, x0, s0) : s0;
+        s1 = (j + 1 >= 0 && j + 1 < n) ? fmadd(A[d].y, x1, s1) : s1;
+        // both sums step together: without this point the scheduler runs the first row's
+        // chain through all diagonals first and holds the second row's 27 window values
+        // (FP64: 226 VGPRs against 125, and half the waves per SIMD)
+        asm volatile("" : "+v"(s0), "+v"(s1));
+    }
+    epi((int)i, s0, xc0);
+    if (i + 1 < n) epi((int)i + 1, s1, xc1);
+}
+
+// The windowed row loop with R rows per thread (R = 2: win_rows2, ND > 0).
+template <int R, int ND, bool SYM, typename T, typename XG, typename EP>
+__device__ __forceinline__ void win_any(int n, int nd, const DiaOff& o, const WinPlan& w, const T* __restrict__ v,
+                                        XG xget, EP epi) {
+    if constexpr (R == 2)
+        win_rows2<ND, SYM, T>(n, o, w, v, xget, epi);
+    else
+        win_rows<ND, SYM, T>(n, nd, o, w, v, xget, epi);
+}
+
+template <int ND, bool SYM, int R, typename T>
 __global__ __launch_bounds__(TPB) void k_w_smooth0_residual(int n, int nd, DiaOff o, WinPlan w,
                                                             const T* __restrict__ v, const T* __restrict__ m,
                                                             const T* __restrict__ f, T* __restrict__ u,
                                                             T* __restrict__ r) {
-    win_rows<ND, SYM, T>(n, nd, o, w, v, [&](int j) { return m[j] * f[j]; }, [&](int i, T s, T xc) {
+    win_any<R, ND, SYM, T>(n, nd, o, w, v, [&](int j) { return m[j] * f[j]; }, [&](int i, T s, T xc) {
         u[i] = xc;
         r[i] = f[i] - s;
     });
 }
 
-template <int ND, bool SYM, typename T>
+template <int ND, bool SYM, int R, typename T>
 __global__ __launch_bounds__(TPB) void k_w_residual(int n, int nd, DiaOff o, WinPlan w, const T* __restrict__ v,
                                                     const T* __restrict__ f, const T* __restrict__ u,
                                                     T* __restrict__ r) {
-    win_rows<ND, SYM, T>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, T s, T) { r[i] = f[i] - s; });
+    win_any<R, ND, SYM, T>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, T s, T) { r[i] = f[i] - s; });
 }
 
-template <int ND, bool SYM, typename T>
+template <int ND, bool SYM, int R, typename T>
 __global__ __launch_bounds__(TPB) void k_w_jacobi(int n, int nd, DiaOff o, WinPlan w, const T* __restrict__ v,
                                                   const T* __restrict__ m, const T* __restrict__ f,
                                                   const T* __restrict__ u, T* __restrict__ uout) {
-    win_rows<ND, SYM, T>(n, nd, o, w, v, [&](int j) { return u[j]; },
+    win_any<R, ND, SYM, T>(n, nd, o, w, v, [&](int j) { return u[j]; },
                          [&](int i, T s, T xc) { uout[i] = xc + m[i] * (f[i] - s); });
 }
 
-template <int ND, bool SYM>
+template <int ND, bool SYM, int R>
 __global__ __launch_bounds__(TPB) void k_w_jacobi_rz(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
                                                      const double* __restrict__ m, const double* __restrict__ r,
                                                      const double* __restrict__ u, double* __restrict__ z,
                                                      int flexible, RedScratch rs) {
     double loc[2] = {0.0, 0.0};
-    win_rows<ND, SYM, double>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, double s, double xc) {
+    win_any<R, ND, SYM, double>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, double s, double xc) {
         const double ri = r[i];
         const double zi = xc + m[i] * (ri - s);
         if (flexible) loc[1] += ri * z[i];
@@ -1209,13 +1311,13 @@ __global__ __launch_bounds__(TPB) void k_w_jacobi_rz(int n, int nd, DiaOff o, Wi
     block_store<2>(loc, dst, xcd_block());
 }
 
-template <int ND, bool SYM, bool FIRST>
+template <int ND, bool SYM, int R, bool FIRST>
 __global__ __launch_bounds__(TPB) void k_w_cg_pq(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
                                                  const double* __restrict__ z, const double* __restrict__ pold,
                                                  double* __restrict__ pnew, double* __restrict__ q, RedScratch rs) {
     const double beta = FIRST ? 0.0 : rs.scal()[S_BETA];
     double loc[1] = {0.0};
-    win_rows<ND, SYM, double>(
+    win_any<R, ND, SYM, double>(
         n, nd, o, w, v, [&](int j) { return FIRST ? z[j] : __builtin_fma(beta, pold[j], z[j]); },
         [&](int i, double s, double xc) {
             pnew[i] = xc;
@@ -1226,7 +1328,7 @@ __global__ __launch_bounds__(TPB) void k_w_cg_pq(int n, int nd, DiaOff o, WinPla
     block_store<1>(loc, dst, xcd_block());
 }
 
-template <int ND, bool SYM>
+template <int ND, bool SYM, int R>
 __global__ __launch_bounds__(TPB) void k_w_update_smooth0(int n, int nd, DiaOff o, WinPlan w,
                                                           const double* __restrict__ v, const double* __restrict__ p,
                                                           const double* __restrict__ q, double* __restrict__ x,
@@ -1238,7 +1340,7 @@ __global__ __launch_bounds__(TPB) void k_w_update_smooth0(int n, int nd, DiaOff 
     const double alpha = sc[S_ALPHA];
     const double step = bad ? 0.0 : alpha;
     double loc[1] = {0.0};
-    win_rows<ND, SYM, double>(
+    win_any<R, ND, SYM, double>(
         n, nd, o, w, v, [&](int j) { return m[j] * __builtin_fma(-step, q[j], r[j]); },
         [&](int i, double s, double xc) {
             const double ri = __builtin_fma(-step, q[i], r[i]);
@@ -1252,26 +1354,43 @@ __global__ __launch_bounds__(TPB) void k_w_update_smooth0(int n, int nd, DiaOff 
     block_store<1>(loc, dst, xcd_block());
 }
 
-template <typename T>
-inline unsigned win_bytes(const Dia& D) {
-    return (unsigned)((size_t)D.win.total * sizeof(T));
+// Two rows per thread in the windowed kernels: 27 diagonals and room for windows TPB
+// entries longer (WinPlan::two, off with AMGMI_NO_WIN2).
+inline bool win_two(const Dia& D) { return D.win.ncl > 0 && D.win.two && D.ndiag == 27; }
+
+inline int win_blocks(int n, const Dia& D) {
+    return win_two(D) ? (int)(((int64_t)n + 2 * TPB - 1) / (2 * TPB)) : (int)dia_blocks(n);
 }
 
-// Runs f(std::integral_constant<int, ND>, std::bool_constant<SYM>) for the windowed form
-// when D has one (ND = 27 for the 27-point stencil, else 0).
+template <typename T>
+inline unsigned win_bytes(const Dia& D) {
+    return (unsigned)((size_t)(D.win.total + (win_two(D) ? D.win.ncl * TPB : 0)) * sizeof(T));
+}
+
+// Runs f(std::integral_constant<int, ND>, std::bool_constant<SYM>,
+// std::integral_constant<int, R>) for the windowed form when D has one (ND = 27 for the
+// 27-point stencil, else 0; R rows per thread, launched on win_blocks(n, D) workgroups
+// with win_bytes(D) of LDS).
 // `gains`: the kernel reads two or more FP64 vectors per neighbour (the Krylov SpMV, the
-// CG update fused with the first sweep, the FP64 first sweep): the windows win there; the
-// sweeps that read one vector per neighbour, and the FP32 ones, measured faster with one
-// row per thread (27-point, 160^3: last sweep 176 against 231 us), so they use the
-// windows only when D.win.all is set.
+// CG update fused with the first sweep, the FP64 first sweep).  With one row per thread
+// the windows win only there: the sweeps that read one vector per neighbour, and the FP32
+// ones, measured faster without them (27-point, 160^3: last sweep 176 against 231 us), so
+// they use one-row windows only when D.win.all is set.  With two rows per thread every
+// windowed kernel is faster than one row per thread (27-point, 160^3: FP32 first sweep +
+// residual 89 against 106 us, FP32 sweep 82 against 96, FP64 last sweep + r.z 157
+// against 172), so the windows are then used for all.
 template <typename F>
 inline bool win_call(const Dia& D, F&& f, bool gains = false) {
-    if (D.win.ncl == 0 || !(gains || D.win.all)) return false;
+    if (D.win.ncl == 0 || !(gains || D.win.all || win_two(D))) return false;
     auto with_nd = [&](auto S) {
-        if (D.ndiag == 27)
-            f(std::integral_constant<int, 27>{}, S);
-        else
-            f(std::integral_constant<int, 0>{}, S);
+        if (D.ndiag == 27) {
+            if (win_two(D))
+                f(std::integral_constant<int, 27>{}, S, std::integral_constant<int, 2>{});
+            else
+                f(std::integral_constant<int, 27>{}, S, std::integral_constant<int, 1>{});
+        } else {
+            f(std::integral_constant<int, 0>{}, S, std::integral_constant<int, 1>{});
+        }
     };
     if (D.off.sym)
         with_nd(std::true_type{});
@@ -1326,8 +1445,8 @@ void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T*
         HIP_LAUNCH_CHECK();
         return;
     }
-    if (win_call(D, [&](auto K, auto S) {
-            timed_launch(k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, T>, dia_blocks(n), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
+    if (win_call(D, [&](auto K, auto S, auto R) {
+            timed_launch(k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
         }, std::is_same<T, double>::value)) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1345,8 +1464,8 @@ void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipS
         HIP_LAUNCH_CHECK();
         return;
     }
-    if (win_call(D, [&](auto K, auto S) {
-            timed_launch(k_w_residual<decltype(K)::value, decltype(S)::value, T>, dia_blocks(n), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
+    if (win_call(D, [&](auto K, auto S, auto R) {
+            timed_launch(k_w_residual<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
         })) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1364,8 +1483,8 @@ void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, 
         HIP_LAUNCH_CHECK();
         return;
     }
-    if (win_call(D, [&](auto K, auto S) {
-            timed_launch(k_w_jacobi<decltype(K)::value, decltype(S)::value, T>, dia_blocks(n), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
+    if (win_call(D, [&](auto K, auto S, auto R) {
+            timed_launch(k_w_jacobi<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
         })) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1396,14 +1515,16 @@ int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, 
         HIP_LAUNCH_CHECK();
         return nb;
     }
-    const int nb = (int)dia_blocks(n);
-    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    if (win_call(D, [&](auto K, auto S) {
-            timed_launch(k_w_jacobi_rz<decltype(K)::value, decltype(S)::value>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, m, r, u, z, flexible, rs);
+    const int nbw = win_blocks(n, D);
+    if (win_call(D, [&](auto K, auto S, auto R) {
+            if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+            timed_launch(k_w_jacobi_rz<decltype(K)::value, decltype(S)::value, decltype(R)::value>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, m, r, u, z, flexible, rs);
         })) {
         HIP_LAUNCH_CHECK();
-        return nb;
+        return nbw;
     }
+    const int nb = (int)dia_blocks(n);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     dia_nd(D.ndiag, [&](auto K) {
         timed_launch(k_dia_jacobi_rz<decltype(K)::value>, nb, TPB, 0, s, n, D.ndiag, D.off, D.val, m, r, u, z, flexible, rs);
     });
@@ -1427,21 +1548,24 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
         HIP_LAUNCH_CHECK();
         return nb;
     }
-    const int nb = (int)dia_blocks(n);
-    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    if (win_call(D, [&](auto K, auto S) {
+    const int nbw = win_blocks(n, D);
+    if (win_call(D, [&](auto K, auto S, auto R) {
             constexpr int NDK = decltype(K)::value;
             constexpr bool SYM = decltype(S)::value;
+            constexpr int RK = decltype(R)::value;
+            if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
             if (first)
-                timed_launch(k_w_cg_pq<NDK, SYM, true>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, (const double*)D.val,
+                timed_launch(k_w_cg_pq<NDK, SYM, RK, true>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, (const double*)D.val,
                              z, pold, pnew, q, rs);
             else
-                timed_launch(k_w_cg_pq<NDK, SYM, false>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, (const double*)D.val,
+                timed_launch(k_w_cg_pq<NDK, SYM, RK, false>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, (const double*)D.val,
                              z, pold, pnew, q, rs);
         }, true)) {
         HIP_LAUNCH_CHECK();
-        return nb;
+        return nbw;
     }
+    const int nb = (int)dia_blocks(n);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     dia_nd(D.ndiag, [&](auto K) {
         if (first)
             timed_launch(k_dia_cg_pq<decltype(K)::value, true>, nb, TPB, 0, s, n, D.ndiag, D.off, (const double*)D.val,
@@ -1467,14 +1591,16 @@ int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double
         HIP_LAUNCH_CHECK();
         return nb;
     }
-    const int nb = (int)dia_blocks(n);
-    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    if (win_call(D, [&](auto K, auto S) {
-            timed_launch(k_w_update_smooth0<decltype(K)::value, decltype(S)::value>, nb, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, p, q, x, r, rn, m, u, rv, rs);
+    const int nbw = win_blocks(n, D);
+    if (win_call(D, [&](auto K, auto S, auto R) {
+            if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+            timed_launch(k_w_update_smooth0<decltype(K)::value, decltype(S)::value, decltype(R)::value>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, p, q, x, r, rn, m, u, rv, rs);
         }, true)) {
         HIP_LAUNCH_CHECK();
-        return nb;
+        return nbw;
     }
+    const int nb = (int)dia_blocks(n);
+    if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
     dia_nd(D.ndiag, [&](auto K) {
         timed_launch(k_dia_update_smooth0<decltype(K)::value>, nb, TPB, 0, s, n, D.ndiag, D.off, D.val, p, q, x, r, rn, m, u, rv, rs);
     });

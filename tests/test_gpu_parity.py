@@ -542,6 +542,51 @@ def test_windowed_kernels_match_row_kernels(monkeypatch, case, precision):
     assert rel_fro(uw, ur) <= 1e-7
 
 
+@pytest.mark.parametrize("N", [16, 17, 20])
+def test_two_row_krylov_spmv_is_exact(monkeypatch, N):
+    """The 27-point Krylov SpMV with two rows per thread (one 16-byte load per diagonal for
+    both rows' entries, windows of 512 rows) gives y = A x equal bit for bit to the one-row
+    windowed kernel's and the one-row-per-thread kernel's, with the full read and with the
+    symmetric read, for an even row count, an odd one (17^3, whose last thread has one row)
+    and counts that are not a multiple of 512; y also agrees with a host product."""
+    import scipy.sparse as sp
+
+    from paper_2108_02054_amd import AMG
+
+    p, c, v0 = lognormal_27pt(N, 0)
+    v1 = lognormal_27pt(N, 2)[2]
+    n = len(p) - 1
+    x = np.random.default_rng(16).standard_normal(n)
+    f = rhs_uniform(n, 1, 3)
+    print(f"N {N} n {n}", flush=True)
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), eps_strong=0.02)
+        g.rebuild(T(v1))
+        y_full = g.apply_operator(T(x)).cpu().numpy()
+        u, info = g.solve(T(f))
+        y_sym = g.apply_operator(T(x)).cpu().numpy()
+        out = (y_full, y_sym, g.diagonals_read(0), u.cpu().numpy(), info)
+        g.close()
+        return out
+
+    two = run()
+    monkeypatch.setenv("AMGMI_NO_WIN2", "1")
+    one = run()
+    monkeypatch.setenv("AMGMI_NO_WIN", "1")
+    row = run()
+    assert two[2] == 14 and one[2] == 14 and row[2] == 14
+    for other in (one, row):
+        assert np.array_equal(two[0], other[0])
+        assert np.array_equal(two[1], other[1])
+        assert abs(two[4]["iters"] - other[4]["iters"]) <= 1
+        assert rel_fro(two[3], other[3]) <= 1e-7
+    assert np.array_equal(two[0], two[1])
+    A = sp.csr_matrix((v1, c, p), shape=(n, n))
+    assert rel_max(two[0], A @ x) <= 1e-13
+    assert two[4]["converged"]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_two_byte_columns_change_nothing(monkeypatch, precision):
     """The row-block kernels reading two-byte block-relative column indices (64^3: level 0's
