@@ -235,7 +235,7 @@ struct WinPlan {
     int base[WIN_MAX_CL] = {0, 0, 0, 0};  // start of the window in LDS
     int total = 0;                        // LDS entries of all windows
     bool all = false;                     // also the V-cycle kernels (else the Krylov SpMV only)
-    bool two = false;                     // Krylov SpMV with two rows per thread (27 diagonals)
+    bool two = false;                     // two rows per thread fit (27 diagonals)
     unsigned char cl[DIA_MAX] = {};       // cluster of each diagonal
 };
 struct Dia {

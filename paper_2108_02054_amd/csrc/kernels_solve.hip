@@ -1111,6 +1111,7 @@ WinPlan win_plan(const std::vector<int>& offs) {
     if (total > WIN_CAP) return WinPlan{};
     w.ncl = k;
     w.total = total;
+    // two rows per thread: windows TPB entries longer
     w.two = nd == 27 && total + k * TPB <= WIN_CAP;
     return w;
 }
@@ -1167,103 +1168,108 @@ __device__ __forceinline__ void win_rows(int n, int nd_rt, const DiaOff& o, cons
     epi((int)i, s, xc);
 }
 
-// Two rows per thread (27 diagonals): a workgroup of TPB threads owns 2 TPB consecutive
-// rows, thread t the rows i and i + 1 with i = i0 + 2t, and fetches each diagonal's
-// entries of both rows with one load of two values (16 bytes in FP64, 8 in FP32): the
-// own-row pair (i, i + 1) and, for a mirrored sub-diagonal entry, the pair
-// (i + off, i + off + 1) of the super-diagonal, aligned to one value for any parity of
-// off.  The windows are TPB entries longer.  Each row adds the same terms in the same
-// order with the same fused multiply-adds as win_rows, so the results are equal bit for
-// bit.  A workgroup whose pairs all lie inside [0, n) loads them whole (the offsets are
-// sorted, so the first and last bound them); the others load entry by entry.
-template <typename T>
-struct WPair;
-template <>
-struct WPair<double> {
-    typedef double v __attribute__((ext_vector_type(2)));
-    typedef v u __attribute__((aligned(8)));
-};
-template <>
-struct WPair<float> {
-    typedef float v __attribute__((ext_vector_type(2)));
-    typedef v u __attribute__((aligned(4)));
+// R rows per thread (27 diagonals, R = 2): a workgroup of TPB threads owns R TPB
+// consecutive rows, thread t the rows i .. i + R - 1 with i = i0 + R t, and fetches each
+// diagonal's entries of its rows with one load (16 bytes in FP64, 8 in FP32): the own-row run
+// (i .. i + R - 1) and, for a mirrored sub-diagonal entry, the run (i + off ..
+// i + off + R - 1) of the super-diagonal, aligned to one value for any off.  The windows
+// are (R - 1) TPB entries longer.  Each row adds the same terms in the same order with the
+// same fused multiply-adds as win_rows, so the results are equal bit for bit.  A
+// workgroup whose runs all lie inside [0, n) loads them whole (the offsets are sorted, so
+// the first and last bound them); the others load entry by entry.  (Four FP32 rows per
+// thread, one 16-byte load per diagonal, measured slower: 160^3 first sweep + residual
+// 106 against 90 us, sweep 94 against 84; the longer windows and 130 VGPRs cost more than
+// the loads saved.)
+template <typename T, int R>
+struct WRun {
+    typedef T v __attribute__((ext_vector_type(R)));
+    typedef v u __attribute__((aligned(sizeof(T))));
 };
 
-// entries j and j + 1 of the diagonal array p; an entry outside [0, n) reads entry 0 and
-// is not used
-template <typename T>
-__device__ __forceinline__ typename WPair<T>::v wp_pair_edge(const T* __restrict__ p, int64_t j, int n) {
-    typename WPair<T>::v r;
-    r.x = p[(j >= 0 && j < n) ? j : 0];
-    r.y = p[(j + 1 >= 0 && j + 1 < n) ? j + 1 : 0];
+// entries j .. j + R - 1 of the diagonal array p; an entry outside [0, n) reads entry 0
+// and is not used
+template <int R, typename T>
+__device__ __forceinline__ typename WRun<T, R>::v wp_run_edge(const T* __restrict__ p, int64_t j, int n) {
+    typename WRun<T, R>::v r;
+#pragma unroll
+    for (int q = 0; q < R; ++q) r[q] = p[(j + q >= 0 && j + q < n) ? j + q : 0];
     return r;
 }
 
-template <int ND, bool SYM, typename T, typename XG, typename EP>
-__device__ __forceinline__ void win_rows2(int n, const DiaOff& o, const WinPlan& w, const T* __restrict__ v,
-                                          XG xget, EP epi) {
-    static_assert(ND > 0, "two rows per thread need the diagonal count at compile time");
-    typedef typename WPair<T>::v P2;
-    typedef typename WPair<T>::u P2u;
-    extern __shared__ __align__(16) unsigned char win_smem[];  // w.total + w.ncl * TPB entries
+// the R row sums step together: without this point the scheduler runs the first row's
+// chain through all diagonals first and keeps the other rows' window values live (FP64,
+// two rows: 226 VGPRs against 125, and half the waves per SIMD)
+template <int R, typename T>
+__device__ __forceinline__ void wp_step(T (&s)[R]) {
+    static_assert(R == 2, "two row sums");
+    asm volatile("" : "+v"(s[0]), "+v"(s[1]));
+}
+
+template <int R, int ND, bool SYM, typename T, typename XG, typename EP>
+__device__ __forceinline__ void win_rows_r(int n, const DiaOff& o, const WinPlan& w, const T* __restrict__ v,
+                                           XG xget, EP epi) {
+    static_assert(ND > 0, "several rows per thread need the diagonal count at compile time");
+    static_assert(R == 2, "two rows per thread");
+    typedef typename WRun<T, R>::v PR;
+    typedef typename WRun<T, R>::u PRu;
+    extern __shared__ __align__(16) unsigned char win_smem[];  // w.total + (R - 1) w.ncl TPB entries
     T* X = reinterpret_cast<T*>(win_smem);
     const int t = threadIdx.x;
-    const int64_t i0 = (int64_t)xcd_block() * (2 * TPB);
+    const int64_t i0 = (int64_t)xcd_block() * (R * TPB);
     for (int k = 0; k < w.ncl; ++k)
-        for (int e = t; e < w.len[k] + TPB; e += TPB) {
+        for (int e = t; e < w.len[k] + (R - 1) * TPB; e += TPB) {
             const int64_t j = i0 + w.lo[k] + e;
-            X[w.base[k] + k * TPB + e] = (j >= 0 && j < n) ? xget((int)j) : T(0);
+            X[w.base[k] + k * (R - 1) * TPB + e] = (j >= 0 && j < n) ? xget((int)j) : T(0);
         }
-    const int64_t i = i0 + 2 * t;
+    const int64_t i = i0 + R * t;
     const size_t sn = (size_t)n;
-    const bool inner = i0 + min(o.off[0], 0) >= 0 && i0 + 2 * TPB + max(o.off[ND - 1], 0) <= n;
-    P2 A[ND];
+    const bool inner = i0 + min(o.off[0], 0) >= 0 && i0 + R * TPB + max(o.off[ND - 1], 0) <= n;
+    PR A[ND];
     if (inner) {
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int off = o.off[d];
-            A[d] = *reinterpret_cast<const P2u*>((SYM && off < 0) ? v + (size_t)(ND - 1 - d) * sn + (i + off)
+            A[d] = *reinterpret_cast<const PRu*>((SYM && off < 0) ? v + (size_t)(ND - 1 - d) * sn + (i + off)
                                                                  : v + (size_t)d * sn + i);
         }
     } else {
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
             const int off = o.off[d];
-            A[d] = (SYM && off < 0) ? wp_pair_edge(v + (size_t)(ND - 1 - d) * sn, i + off, n)
-                                    : wp_pair_edge(v + (size_t)d * sn, i, n);
+            A[d] = (SYM && off < 0) ? wp_run_edge<R>(v + (size_t)(ND - 1 - d) * sn, i + off, n)
+                                    : wp_run_edge<R>(v + (size_t)d * sn, i, n);
         }
     }
     __syncthreads();
     if (i >= n) return;
-    T s0 = 0, s1 = 0, xc0 = 0, xc1 = 0;
+    T sum[R], xc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) sum[q] = xc[q] = T(0);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         const int off = o.off[d];
         const int k = w.cl[d];
-        const T* xp = X + w.base[k] + k * TPB + (off - w.lo[k]) + 2 * t;
-        const T x0 = xp[0], x1 = xp[1];
-        if (off == 0) {
-            xc0 = x0;
-            xc1 = x1;
-        }
+        const T* xp = X + w.base[k] + k * (R - 1) * TPB + (off - w.lo[k]) + R * t;
         const int64_t j = i + off;
-        s0 = (j >= 0 && j < n) ? fmadd(A[d].x, x0, s0) : s0;
-        s1 = (j + 1 >= 0 && j + 1 < n) ? fmadd(A[d].y, x1, s1) : s1;
-        // both sums step together: without this point the scheduler runs the first row's
-        // chain through all diagonals first and holds the second row's 27 window values
-        // (FP64: 226 VGPRs against 125, and half the waves per SIMD)
-        asm volatile("" : "+v"(s0), "+v"(s1));
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const T x = xp[q];
+            if (off == 0) xc[q] = x;
+            sum[q] = (j + q >= 0 && j + q < n) ? fmadd(A[d][q], x, sum[q]) : sum[q];
+        }
+        wp_step<R>(sum);
     }
-    epi((int)i, s0, xc0);
-    if (i + 1 < n) epi((int)i + 1, s1, xc1);
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        if (i + q < n) epi((int)i + q, sum[q], xc[q]);
 }
 
-// The windowed row loop with R rows per thread (R = 2: win_rows2, ND > 0).
+// The windowed row loop with R rows per thread (R > 1: win_rows_r, ND > 0).
 template <int R, int ND, bool SYM, typename T, typename XG, typename EP>
 __device__ __forceinline__ void win_any(int n, int nd, const DiaOff& o, const WinPlan& w, const T* __restrict__ v,
                                         XG xget, EP epi) {
-    if constexpr (R == 2)
-        win_rows2<ND, SYM, T>(n, o, w, v, xget, epi);
+    if constexpr (R > 1)
+        win_rows_r<R, ND, SYM, T>(n, o, w, v, xget, epi);
     else
         win_rows<ND, SYM, T>(n, nd, o, w, v, xget, epi);
 }
@@ -1354,37 +1360,44 @@ __global__ __launch_bounds__(TPB) void k_w_update_smooth0(int n, int nd, DiaOff 
     block_store<1>(loc, dst, xcd_block());
 }
 
-// Two rows per thread in the windowed kernels: 27 diagonals and room for windows TPB
-// entries longer (WinPlan::two, off with AMGMI_NO_WIN2).
-inline bool win_two(const Dia& D) { return D.win.ncl > 0 && D.win.two && D.ndiag == 27; }
+// Rows per thread of the windowed kernels: two with 27 diagonals and room for the longer
+// windows (WinPlan::two, off with AMGMI_NO_WIN2), else one.
+template <typename T>
+inline int win_rows_per_thread(const Dia& D) {
+    return (D.win.ncl > 0 && D.ndiag == 27 && D.win.two) ? 2 : 1;
+}
 
+template <typename T>
 inline int win_blocks(int n, const Dia& D) {
-    return win_two(D) ? (int)(((int64_t)n + 2 * TPB - 1) / (2 * TPB)) : (int)dia_blocks(n);
+    const int r = win_rows_per_thread<T>(D);
+    return (int)(((int64_t)n + r * TPB - 1) / (r * TPB));
 }
 
 template <typename T>
 inline unsigned win_bytes(const Dia& D) {
-    return (unsigned)((size_t)(D.win.total + (win_two(D) ? D.win.ncl * TPB : 0)) * sizeof(T));
+    const int r = win_rows_per_thread<T>(D);
+    return (unsigned)((size_t)(D.win.total + (r - 1) * D.win.ncl * TPB) * sizeof(T));
 }
 
 // Runs f(std::integral_constant<int, ND>, std::bool_constant<SYM>,
-// std::integral_constant<int, R>) for the windowed form when D has one (ND = 27 for the
-// 27-point stencil, else 0; R rows per thread, launched on win_blocks(n, D) workgroups
-// with win_bytes(D) of LDS).
+// std::integral_constant<int, R>) for the windowed form of a kernel in T when D has one
+// (ND = 27 for the 27-point stencil, else 0; R = win_rows_per_thread<T>(D), launched on
+// win_blocks<T>(n, D) workgroups with win_bytes<T>(D) of LDS).
 // `gains`: the kernel reads two or more FP64 vectors per neighbour (the Krylov SpMV, the
 // CG update fused with the first sweep, the FP64 first sweep).  With one row per thread
 // the windows win only there: the sweeps that read one vector per neighbour, and the FP32
 // ones, measured faster without them (27-point, 160^3: last sweep 176 against 231 us), so
-// they use one-row windows only when D.win.all is set.  With two rows per thread every
-// windowed kernel is faster than one row per thread (27-point, 160^3: FP32 first sweep +
-// residual 89 against 106 us, FP32 sweep 82 against 96, FP64 last sweep + r.z 157
-// against 172), so the windows are then used for all.
-template <typename F>
+// they use one-row windows only when D.win.all is set.  With several rows per thread
+// every windowed kernel is faster than one row per thread (27-point, 160^3, two rows:
+// FP32 first sweep + residual 89 against 106 us, FP32 sweep 82 against 96, FP64 last
+// sweep + r.z 157 against 172), so the windows are then used for all.
+template <typename T, typename F>
 inline bool win_call(const Dia& D, F&& f, bool gains = false) {
-    if (D.win.ncl == 0 || !(gains || D.win.all || win_two(D))) return false;
+    const int rows = win_rows_per_thread<T>(D);
+    if (D.win.ncl == 0 || !(gains || D.win.all || rows > 1)) return false;
     auto with_nd = [&](auto S) {
         if (D.ndiag == 27) {
-            if (win_two(D))
+            if (rows == 2)
                 f(std::integral_constant<int, 27>{}, S, std::integral_constant<int, 2>{});
             else
                 f(std::integral_constant<int, 27>{}, S, std::integral_constant<int, 1>{});
@@ -1445,8 +1458,8 @@ void launch_dia_smooth0_residual(int n, const Dia& D, const T* m, const T* f, T*
         HIP_LAUNCH_CHECK();
         return;
     }
-    if (win_call(D, [&](auto K, auto S, auto R) {
-            timed_launch(k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
+    if (win_call<T>(D, [&](auto K, auto S, auto R) {
+            timed_launch(k_w_smooth0_residual<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks<T>(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, r);
         }, std::is_same<T, double>::value)) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1464,8 +1477,8 @@ void launch_dia_residual(int n, const Dia& D, const T* f, const T* u, T* r, hipS
         HIP_LAUNCH_CHECK();
         return;
     }
-    if (win_call(D, [&](auto K, auto S, auto R) {
-            timed_launch(k_w_residual<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
+    if (win_call<T>(D, [&](auto K, auto S, auto R) {
+            timed_launch(k_w_residual<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks<T>(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), f, u, r);
         })) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1483,8 +1496,8 @@ void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, 
         HIP_LAUNCH_CHECK();
         return;
     }
-    if (win_call(D, [&](auto K, auto S, auto R) {
-            timed_launch(k_w_jacobi<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
+    if (win_call<T>(D, [&](auto K, auto S, auto R) {
+            timed_launch(k_w_jacobi<decltype(K)::value, decltype(S)::value, decltype(R)::value, T>, win_blocks<T>(n, D), TPB, win_bytes<T>(D), s, n, D.ndiag, D.off, D.win, D.v<T>(), m, f, u, uout);
         })) {
         HIP_LAUNCH_CHECK();
         return;
@@ -1515,8 +1528,8 @@ int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, 
         HIP_LAUNCH_CHECK();
         return nb;
     }
-    const int nbw = win_blocks(n, D);
-    if (win_call(D, [&](auto K, auto S, auto R) {
+    const int nbw = win_blocks<double>(n, D);
+    if (win_call<double>(D, [&](auto K, auto S, auto R) {
             if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
             timed_launch(k_w_jacobi_rz<decltype(K)::value, decltype(S)::value, decltype(R)::value>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, m, r, u, z, flexible, rs);
         })) {
@@ -1548,8 +1561,8 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
         HIP_LAUNCH_CHECK();
         return nb;
     }
-    const int nbw = win_blocks(n, D);
-    if (win_call(D, [&](auto K, auto S, auto R) {
+    const int nbw = win_blocks<double>(n, D);
+    if (win_call<double>(D, [&](auto K, auto S, auto R) {
             constexpr int NDK = decltype(K)::value;
             constexpr bool SYM = decltype(S)::value;
             constexpr int RK = decltype(R)::value;
@@ -1591,8 +1604,8 @@ int launch_dia_update_smooth0(int n, const Dia& D, const double* p, const double
         HIP_LAUNCH_CHECK();
         return nb;
     }
-    const int nbw = win_blocks(n, D);
-    if (win_call(D, [&](auto K, auto S, auto R) {
+    const int nbw = win_blocks<double>(n, D);
+    if (win_call<double>(D, [&](auto K, auto S, auto R) {
             if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
             timed_launch(k_w_update_smooth0<decltype(K)::value, decltype(S)::value, decltype(R)::value>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, p, q, x, r, rn, m, u, rv, rs);
         }, true)) {

@@ -498,13 +498,15 @@ def test_marching_kernels_match_row_kernels(monkeypatch, shape, precision):
     assert rel_fro(um, ur) <= 1e-7
 
 
-@pytest.mark.parametrize("case", ["ln27_16", "ln27_20", "tf7_nomarch"])
+@pytest.mark.parametrize("case", ["ln27_16", "ln27_17", "ln27_20", "tf7_nomarch"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_windowed_kernels_match_row_kernels(monkeypatch, case, precision):
     """The windowed diagonal-storage kernels (vector entries of each offset cluster staged
-    in LDS per workgroup) give every row the one-row-per-thread result bit for bit: the
-    27-point operator on grids whose plane is and is not a multiple of a workgroup, and a
-    7-point operator with the marching kernels switched off."""
+    in LDS per workgroup; with 27 diagonals two FP64 or four FP32 rows per thread) give
+    every row the one-row-per-thread result bit for bit: the 27-point operator on grids
+    whose plane is and is not a multiple of a workgroup and whose row count is odd (17^3:
+    the last thread has one row), and a 7-point operator with the marching kernels
+    switched off."""
     from paper_2108_02054_amd import AMG
 
     if case.startswith("ln27"):
