@@ -2082,7 +2082,7 @@ amg_status amg_apply_operator_noalloc(amg_ctx* c, const double* x, double* y) {
                                         std::to_string(NOALLOC_ROWS) + "-row scratch"};
         double* sp = scratch_on(dev);
         RedScratch rs;
-        rs.cap = (int)((NOALLOC_PART - S_COUNT - RED_BLOCKS) / 4);
+        rs.cap = (int)((NOALLOC_PART - S_COUNT) / 5);
         rs.part = sp + NOALLOC_ROWS;
         rs.host = nullptr;
         double* w = sp;  // the p copy

@@ -166,15 +166,15 @@ enum Scal {
 };
 
 // Reductions store one partial per block into a region; the consumer adds them in block
-// order.  Regions P_RZ, P_RZOLD, P_PQ hold up to `cap` partials (full grids of the level-0
-// kernels); P_RR, P_FF hold at most RED_BLOCKS (bounded grids) and sit right before the
-// scalars so the host reads them, and the scalars, with one copy.
+// order.  Every region holds up to `cap` partials (full grids of the level-0 kernels;
+// bounded grids use at most RED_BLOCKS <= cap); P_RR and P_FF sit right after the scalars
+// so the host reads them, and the scalars, with one copy.
 enum PartRegion { P_RZ = 0, P_RZOLD = 1, P_PQ = 2, P_RR = 3, P_FF = 4 };
 constexpr int RED_BLOCKS = 1024;
 
 struct RedScratch {
-    // [P_RZ cap][P_RZOLD cap][P_PQ cap][scalars S_COUNT][P_RR cap][P_FF RED_BLOCKS]: the
-    // scalars and the ||r||^2 partials are adjacent, so one copy brings both to the host
+    // [P_RZ cap][P_RZOLD cap][P_PQ cap][scalars S_COUNT][P_RR cap][P_FF cap]: the scalars
+    // and the ||r||^2 and ||f||^2 partials are adjacent, so one copy brings them to the host
     double* part = nullptr;
     int cap = 0;
     // device address of the host mirror (mapped, coherent pinned memory): the CG update
@@ -186,9 +186,9 @@ struct RedScratch {
         return part + 4 * (size_t)cap + S_COUNT;
     }
     __host__ __device__ double* scal() const { return part + 3 * (size_t)cap; }
-    static size_t doubles(int cap) { return 4 * (size_t)cap + S_COUNT + (size_t)RED_BLOCKS; }
+    static size_t doubles(int cap) { return 5 * (size_t)cap + S_COUNT; }
     // the host mirror of [scalars, P_RR, P_FF]
-    static size_t host_doubles(int cap) { return S_COUNT + (size_t)cap + (size_t)RED_BLOCKS; }
+    static size_t host_doubles(int cap) { return S_COUNT + 2 * (size_t)cap; }
 };
 
 // Row-block kernels: RB_THREADS threads, at most RB_CAP nonzeros staged in LDS per block.

@@ -1317,6 +1317,23 @@ __global__ __launch_bounds__(TPB) void k_w_jacobi_rz(int n, int nd, DiaOff o, Wi
     block_store<2>(loc, dst, xcd_block());
 }
 
+// k_dia_cg_init in the windowed form: r = f - A x, partials of r.r and f.f.
+template <int ND, bool SYM, int R>
+__global__ __launch_bounds__(TPB) void k_w_cg_init(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
+                                                   const double* __restrict__ f, const double* __restrict__ x,
+                                                   double* __restrict__ r, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    win_any<R, ND, SYM, double>(n, nd, o, w, v, [&](int j) { return x[j]; }, [&](int i, double s, double) {
+        const double fi = f[i];
+        const double ri = fi - s;
+        r[i] = ri;
+        loc[0] += ri * ri;
+        loc[1] += fi * fi;
+    });
+    double* const dst[2] = {rs.region(P_RR), rs.region(P_FF)};
+    block_store<2>(loc, dst, xcd_block());
+}
+
 template <int ND, bool SYM, int R, bool FIRST>
 __global__ __launch_bounds__(TPB) void k_w_cg_pq(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
                                                  const double* __restrict__ z, const double* __restrict__ pold,
@@ -1509,6 +1526,14 @@ void launch_dia_jacobi(int n, const Dia& D, const T* m, const T* f, const T* u, 
 }
 int launch_dia_cg_init(int n, const Dia& D, const double* f, const double* x, double* r, const RedScratch& rs,
                        hipStream_t s) {
+    const int nbw = win_blocks<double>(n, D);
+    if (win_call<double>(D, [&](auto K, auto S, auto R) {
+            if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+            timed_launch(k_w_cg_init<decltype(K)::value, decltype(S)::value, decltype(R)::value>, nbw, TPB, win_bytes<double>(D), s, n, D.ndiag, D.off, D.win, D.val, f, x, r, rs);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return nbw;
+    }
     const int nb = red_grid_elems(n);
     dia_nd(D.ndiag, [&](auto K) {
         timed_launch(k_dia_cg_init<decltype(K)::value>, nb, TPB, 0, s, n, D.ndiag, D.off, D.val, f, x, r, rs);

@@ -544,13 +544,15 @@ def test_windowed_kernels_match_row_kernels(monkeypatch, case, precision):
     assert rel_fro(uw, ur) <= 1e-7
 
 
-@pytest.mark.parametrize("N", [16, 17, 20])
+@pytest.mark.parametrize("N", [16, 17, 20, 84])
 def test_two_row_krylov_spmv_is_exact(monkeypatch, N):
     """The 27-point Krylov SpMV with two rows per thread (one 16-byte load per diagonal for
     both rows' entries, windows of 512 rows) gives y = A x equal bit for bit to the one-row
     windowed kernel's and the one-row-per-thread kernel's, with the full read and with the
     symmetric read, for an even row count, an odd one (17^3, whose last thread has one row)
-    and counts that are not a multiple of 512; y also agrees with a host product."""
+    and counts that are not a multiple of 512; y also agrees with a host product.  At 84^3
+    the windowed initial and final residual runs on 1158 workgroups, more than the 1024
+    partials of the bounded grids, and its true residual agrees with the row kernel's."""
     import scipy.sparse as sp
 
     from paper_2108_02054_amd import AMG
@@ -587,6 +589,8 @@ def test_two_row_krylov_spmv_is_exact(monkeypatch, N):
     A = sp.csr_matrix((v1, c, p), shape=(n, n))
     assert rel_max(two[0], A @ x) <= 1e-13
     assert two[4]["converged"]
+    res = np.linalg.norm(f - A @ two[3]) / np.linalg.norm(f)
+    assert abs(two[4]["rel_res_true"] - res) <= 1e-3 * res, (two[4]["rel_res_true"], res)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
