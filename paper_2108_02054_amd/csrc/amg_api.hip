@@ -657,6 +657,7 @@ void configure_dia(amg_ctx* c) {
         if (std::getenv("AMGMI_NO_WIN2") != nullptr) D.win.two = false;
     }
     if (std::getenv("AMGMI_NO_DIA_SYM") != nullptr) D.symoff = false;
+    c->rz32 = std::getenv("AMGMI_NO_RZ32") == nullptr;
     D.slot = halloc<uint8_t>(c, (size_t)A.nnz);
     launch_dia_slots(A, D, s);
     const size_t nv = (size_t)nd * (size_t)A.nrows;
@@ -1104,6 +1105,11 @@ void repattern(amg_ctx* c) {
 struct RzEpilogue {
     int flexible;
     mutable int nb;  // partials written (set by the kernel that formed r.z)
+    // mixed precision: the CG's FP64 r and z; the FP32 cycle's last level-0 sweep writes z
+    // and forms r.z itself when it can (z_done), else the caller widens the cycle's output
+    const double* r64 = nullptr;
+    double* z64 = nullptr;
+    mutable bool z_done = false;
 };
 
 // Algorithm 2 on level l from a zero initial guess; returns the buffer holding u_l.
@@ -1336,6 +1342,14 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep, int
                 sweep(cur, dst);
             }
         } else {
+            if (last && ep && ep->z64 && dia && c->rz32) {
+                const int nb = launch_dia_jacobi_rz32(n, c->dia, m, f, cur, ep->r64, ep->z64, ep->flexible, c->rs, s);
+                if (nb > 0) {  // z is the FP64 result; the FP32 one is not written
+                    ep->nb = nb;
+                    ep->z_done = true;
+                    break;
+                }
+            }
             sweep(cur, dst);
         }
         if (dst == other)
@@ -1347,10 +1361,12 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep, int
         d2d(out, cur, (size_t)L.A.nrows * sizeof(T), s);
         cur = out;
     }
-    if (ep && !fused) {
-        if (ep->flexible) throw Fail{AMG_ERR_ARG, "flexible CG needs at least one post-smoothing sweep"};
-        Trace tr(c, AMG_K_CG_RZ, 0);
-        ep->nb = launch_cg_rz(L.A.nrows, (const double*)f, (const double*)cur, c->rs, s);
+    if constexpr (std::is_same<T, double>::value) {
+        if (ep && !fused) {
+            if (ep->flexible) throw Fail{AMG_ERR_ARG, "flexible CG needs at least one post-smoothing sweep"};
+            Trace tr(c, AMG_K_CG_RZ, 0);
+            ep->nb = launch_cg_rz(L.A.nrows, (const double*)f, (const double*)cur, c->rs, s);
+        }
     }
     return cur;
 }
@@ -1366,7 +1382,12 @@ void vcycle_apply(amg_ctx* c, const double* r, double* z, const RzEpilogue* ep =
             Trace tr(c, AMG_K_CAST, 0);
             launch_cast_d2f(L0.A.nrows, r, (float*)L0.f, c->stream);
         }
-        const float* res = vcycle_level<float>(c, 0, (const float*)L0.f, nullptr);
+        RzEpilogue e32{ep ? ep->flexible : 0, 0, r, z};
+        const float* res = vcycle_level<float>(c, 0, (const float*)L0.f, nullptr, ep ? &e32 : nullptr);
+        if (e32.z_done) {
+            ep->nb = e32.nb;
+            return;
+        }
         Trace tr(c, AMG_K_CAST, 0);
         if (ep)
             ep->nb = launch_cast_rz(L0.A.nrows, res, r, z, ep->flexible, c->rs, c->stream);

@@ -325,6 +325,11 @@ int launch_dia_cg_init(int n, const Dia& D, const double* f, const double* x, do
                        hipStream_t s);
 int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, const double* u, double* z,
                          int flexible, const RedScratch& rs, hipStream_t s);
+// Mixed precision: the last FP32 sweep u + M (f - A u) written to z in FP64, with the r.z
+// partials of the FP64 residual r; returns the partial count, or 0 when D has no marching
+// or windowed form for it (nothing launched).
+int launch_dia_jacobi_rz32(int n, const Dia& D, const float* m, const float* f, const float* u, const double* r,
+                           double* z, int flexible, const RedScratch& rs, hipStream_t s);
 int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,
                      const RedScratch& rs, hipStream_t s);
 
@@ -542,6 +547,9 @@ struct amg_ctx {
     // the partial update wrote A_0's new values straight into the diagonal storage: the CSR
     // value arrays of level 0 are formed from it when they are read (exports)
     bool a0_csr_stale = false;
+    // mixed precision: the last level-0 sweep writes z in FP64 with r.z (off with
+    // AMGMI_NO_RZ32: a separate widening pass)
+    bool rz32 = true;
     bool broken = false;
     std::string err;
 };

@@ -1037,6 +1037,26 @@ __global__ __launch_bounds__(TPB) void k_m7_jacobi_rz(int n, int a, int b, const
     block_store<2>(loc, dst, xcd_block());
 }
 
+// Mixed precision: the last FP32 sweep of level 0 writes z in FP64 (its FP32 value widened,
+// as k_cast_rz does) and forms the CG's r.z with the FP64 residual r in the same pass.
+template <bool SYM>
+__global__ __launch_bounds__(TPB) void k_m7_jacobi_rz32(int n, int a, int b, const float* __restrict__ v,
+                                                        const float* __restrict__ m, const float* __restrict__ f,
+                                                        const float* __restrict__ u, const double* __restrict__ r,
+                                                        double* __restrict__ z, int flexible, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    march7<SYM, float>(n, a, b, v, [&](int j) { return u[j]; }, [&](int i, float s, float xc) {
+        const float z32 = xc + m[i] * (f[i] - s);
+        const double ri = r[i];
+        const double zi = (double)z32;
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    });
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, xcd_block());
+}
+
 template <bool SYM, bool FIRST>
 __global__ __launch_bounds__(TPB) void k_m7_cg_pq(int n, int a, int b, const double* __restrict__ v,
                                                   const double* __restrict__ z, const double* __restrict__ pold,
@@ -1317,6 +1337,25 @@ __global__ __launch_bounds__(TPB) void k_w_jacobi_rz(int n, int nd, DiaOff o, Wi
     block_store<2>(loc, dst, xcd_block());
 }
 
+// k_m7_jacobi_rz32 in the windowed form.
+template <int ND, bool SYM, int R>
+__global__ __launch_bounds__(TPB) void k_w_jacobi_rz32(int n, int nd, DiaOff o, WinPlan w, const float* __restrict__ v,
+                                                       const float* __restrict__ m, const float* __restrict__ f,
+                                                       const float* __restrict__ u, const double* __restrict__ r,
+                                                       double* __restrict__ z, int flexible, RedScratch rs) {
+    double loc[2] = {0.0, 0.0};
+    win_any<R, ND, SYM, float>(n, nd, o, w, v, [&](int j) { return u[j]; }, [&](int i, float s, float xc) {
+        const float z32 = xc + m[i] * (f[i] - s);
+        const double ri = r[i];
+        const double zi = (double)z32;
+        if (flexible) loc[1] += ri * z[i];
+        z[i] = zi;
+        loc[0] += ri * zi;
+    });
+    double* const dst[2] = {rs.region(P_RZ), rs.region(P_RZOLD)};
+    block_store<2>(loc, dst, xcd_block());
+}
+
 // k_dia_cg_init in the windowed form: r = f - A x, partials of r.r and f.f.
 template <int ND, bool SYM, int R>
 __global__ __launch_bounds__(TPB) void k_w_cg_init(int n, int nd, DiaOff o, WinPlan w, const double* __restrict__ v,
@@ -1568,6 +1607,29 @@ int launch_dia_jacobi_rz(int n, const Dia& D, const double* m, const double* r, 
     });
     HIP_LAUNCH_CHECK();
     return nb;
+}
+int launch_dia_jacobi_rz32(int n, const Dia& D, const float* m, const float* f, const float* u, const double* r,
+                           double* z, int flexible, const RedScratch& rs, hipStream_t s) {
+    if (D.march_a > 0) {
+        const int nb = march_blocks(n, D.march_a);
+        if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+        march_call(D, [&](auto S) {
+            timed_launch(k_m7_jacobi_rz32<decltype(S)::value>, nb, TPB, 0, s, n, D.march_a, D.march_b, D.val32, m, f, u,
+                         r, z, flexible, rs);
+        });
+        HIP_LAUNCH_CHECK();
+        return nb;
+    }
+    const int nbw = win_blocks<float>(n, D);
+    if (win_call<float>(D, [&](auto K, auto S, auto R) {
+            if (nbw > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
+            timed_launch(k_w_jacobi_rz32<decltype(K)::value, decltype(S)::value, decltype(R)::value>, nbw, TPB,
+                         win_bytes<float>(D), s, n, D.ndiag, D.off, D.win, D.val32, m, f, u, r, z, flexible, rs);
+        })) {
+        HIP_LAUNCH_CHECK();
+        return nbw;
+    }
+    return 0;
 }
 int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, double* pnew, double* q, int first,
                      const RedScratch& rs, hipStream_t s) {

@@ -37,6 +37,50 @@ def test_mixed_precision_solve(N, flex):
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-5
 
 
+@pytest.mark.parametrize("case,flex", [("tf7", 0), ("tf7", 1), ("ln27", 0), ("ln27", 1)])
+def test_mixed_last_sweep_writes_fp64_z(monkeypatch, case, flex):
+    """In mixed precision the last FP32 sweep of level 0 (plane marching for the 7-point
+    operator, two-row windows for the 27-point one) writes z widened to FP64 and forms the
+    CG's r.z (and, flexible, r.z_old) itself; the solve agrees with the form that widens z
+    in a separate pass, and its true residual is confirmed on the host."""
+    import scipy.sparse as sp
+
+    from paper_2108_02054_amd import AMG
+
+    if case == "tf7":
+        N = 48
+        p, c, v0 = two_fluid_7pt(N, front_moving(N, 0))
+        v1 = two_fluid_7pt(N, front_moving(N, 2))[2]
+        prm = dict()
+    else:
+        from workloads import lognormal_27pt
+        N = 40
+        p, c, v0 = lognormal_27pt(N, 0)
+        v1 = lognormal_27pt(N, 2)[2]
+        prm = dict(eps_strong=0.02)
+    n = len(p) - 1
+    f = rhs_uniform(n, 3, 2)
+    print(f"case {case} flexible {flex}", flush=True)
+
+    def run():
+        g = AMG(T(p), T(c), T(v0), precision=1, flexible_cg=flex, **prm)
+        g.rebuild(T(v1))
+        u, info = g.solve(T(f))
+        g.close()
+        return u.cpu().numpy(), info
+
+    uf, inf_f = run()
+    monkeypatch.setenv("AMGMI_NO_RZ32", "1")
+    us, inf_s = run()
+    A = sp.csr_matrix((v1, c, p), shape=(n, n))
+    for u, info in ((uf, inf_f), (us, inf_s)):
+        assert info["converged"]
+        res = np.linalg.norm(f - A @ u) / np.linalg.norm(f)
+        assert res <= 1.01e-8, res
+    assert abs(inf_f["iters"] - inf_s["iters"]) <= 1
+    assert rel_fro(uf, us) <= 1e-6, rel_fro(uf, us)
+
+
 def test_logcoef_assembly_parity():
     import oracle
     from paper_2108_02054_amd import logcoef7_assemble
