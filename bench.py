@@ -550,6 +550,8 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         dom_traffic = load_traffic_rec(f"{dom_file}_two_fluid_128_traffic.json")
         pq_traffic = load_traffic_rec("cg_pq_two_fluid_128_traffic.json")
         rap_traffic = load_traffic_rec("galerkin_two_fluid_128_traffic.json")
+    elif cfg_id == 5 and N == 160:
+        pq_traffic = load_traffic_rec("cg_pq_lognormal27_160_traffic.json")
     elif cfg_id == 7:
         pq_traffic = load_traffic_rec("cg_pq_coupled4_56_traffic.json")
     dom_rec = roof(f"{dom_name}: levels {sorted(dom_levels)} (the kernel with the step's largest time)",
