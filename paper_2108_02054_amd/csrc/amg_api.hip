@@ -1242,9 +1242,11 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
         d2d(out, cur, (size_t)n * sizeof(T), s);
         cur = out;
     }
-    if (ep && !fused) {
-        Trace tr(c, AMG_K_CG_RZ, 0);
-        ep->nb = launch_cg_rz(n, (const double*)f, (const double*)cur, c->rs, s);
+    if constexpr (std::is_same<T, double>::value) {  // (an FP32 cycle's r.z is formed by its caller)
+        if (ep && !fused) {
+            Trace tr(c, AMG_K_CG_RZ, 0);
+            ep->nb = launch_cg_rz(n, (const double*)f, (const double*)cur, c->rs, s);
+        }
     }
     return cur;
 }
@@ -1259,7 +1261,7 @@ T* vcycle_level(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* ep, int
         Trace tr(c, AMG_K_COARSE_GEMV, l);
         wait_coarse(c);
         launch_coarse_gemv<T>(c->nL, c->cinv, f, u, c->rs.scal() + S_COARSE, s);
-        if (ep) {
+        if (std::is_same<T, double>::value && ep) {  // (an FP32 cycle's r.z is formed by its caller)
             Trace tr2(c, AMG_K_CG_RZ, 0);
             if (ep->flexible) throw Fail{AMG_ERR_ARG, "flexible CG needs at least one post-smoothing sweep"};
             ep->nb = launch_cg_rz(L.A.nrows, (const double*)f, (const double*)u, c->rs, s);
@@ -1382,8 +1384,11 @@ void vcycle_apply(amg_ctx* c, const double* r, double* z, const RzEpilogue* ep =
             Trace tr(c, AMG_K_CAST, 0);
             launch_cast_d2f(L0.A.nrows, r, (float*)L0.f, c->stream);
         }
+        // the FP32 cycle forms z and r.z itself only in the level-0 diagonal-storage sweep;
+        // every other FP32 path leaves them to the widening pass below
+        const bool fuse = ep && c->rz32 && c->prm.block_size == 1 && c->dia.ndiag > 0 && c->lv.size() > 1;
         RzEpilogue e32{ep ? ep->flexible : 0, 0, r, z};
-        const float* res = vcycle_level<float>(c, 0, (const float*)L0.f, nullptr, ep ? &e32 : nullptr);
+        const float* res = vcycle_level<float>(c, 0, (const float*)L0.f, nullptr, fuse ? &e32 : nullptr);
         if (e32.z_done) {
             ep->nb = e32.nb;
             return;
