@@ -33,6 +33,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "per-step setup+solve ms, partial vs full rebuild at 1e-8 rel res; RAP/SpMV GB/s"
 HBM_PEAK_GBS = 8000.0
+# the timed steps time every TRACE_EVERY-th launch of the dominant kernel class per level
+TRACE_EVERY = 8
+# untimed steps after the timed ones that time every launch of the Krylov SpMV and the
+# Galerkin products
+XSTEPS = 3
 
 
 def log(*a):
@@ -435,9 +440,12 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
             amg.trace([], level=0)
         traced = None
         if diag:
+            # the timed steps bracket only every TRACE_EVERY-th launch of the dominant
+            # kernel class per level with events: each bracketed launch holds the stream for
+            # its timestamps (tracing all launches of four classes cost 0.8 ms per 128^3 step)
             dom = dominant(kt_levels, groups_of(amg))
-            traced = sorted({spmv_cls, "galerkin_ap", "galerkin_rap", dom[1]})
-            amg.trace(traced, level=-1)
+            traced = [dom[1]]
+            amg.trace(traced, level=-1, every=TRACE_EVERY)
             amg.trace_read()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
         torch.cuda.synchronize()
@@ -455,7 +463,17 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         log_["setup_ms_per_step"], log_["solve_ms_per_step"] = setup_ms, solve_ms
         kt = amg.trace_read_levels() if traced else None
         amg.trace([], level=0)
-        log_["kt_levels"], log_["kt"] = kt_levels, kt
+        kx = None
+        if diag:
+            # untimed instrumented steps (the last step's values again): every launch of the
+            # Krylov SpMV and of the Galerkin products bracketed
+            amg.trace(sorted({spmv_cls, "galerkin_ap", "galerkin_rap"}), level=-1)
+            amg.trace_read()
+            for _ in range(XSTEPS):
+                step(W + K, False)
+            kx = amg.trace_read_levels()
+            amg.trace([], level=0)
+        log_["kt_levels"], log_["kt"], log_["kx"] = kt_levels, kt, kx
         if snap:
             lv = [amg.level(l) for l in range(amg.num_levels)]
             log_["snap"] = {"A": [x["A"][2] for x in lv], "m": [x["m"] for x in lv], "u": u.cpu().numpy()}
@@ -487,15 +505,18 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
     log("kernel time per partial step (ms, launches), all levels: "
         + ", ".join(f"{k}={v[0]:.3f}/{v[1]}" for k, v in sorted(totals.items(), key=lambda kv: -kv[1][0])))
 
-    # live records over the timed region
+    # live records: the dominant class over the timed region (sampled launches), the
+    # Krylov SpMV and the Galerkin products over the instrumented steps after it
     kt = info_p["kt"]
+    kx = info_p["kx"]
 
-    def class_live(cls, levels=None):
+    def class_live(cls, levels=None, src=None):
+        src = kt if src is None else src
         ms = cnt = 0
         byt = 0.0
         ok = True
         for l in (range(L) if levels is None else levels):
-            m_, c_ = kt[l].get(cls, (0.0, 0))
+            m_, c_ = src[l].get(cls, (0.0, 0))
             if not c_:
                 continue
             b = bm.bytes(cls, l)
@@ -516,18 +537,18 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         cnt_ = sum(ktl[l].get(cls, (0.0, 0))[1] for l in lvls if l < L)
         if cnt_:
             by_kernel[name] = [round(ms_, 4), cnt_]
-    pq_ms, pq_cnt, _ = class_live(spmv_cls, [0])
+    pq_ms, pq_cnt, _ = class_live(spmv_cls, [0], kx)
     if bicg:
         spmv_bytes = pq_cnt * (bm.krylov_A() + 16 * n)
     elif block > 1:
         spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0)
     else:
-        spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0) - K * 8 * n  # first iteration reads no p_old
-    g_ms = kt[0].get("galerkin_ap", (0.0, 0))[0] + kt[0].get("galerkin_rap", (0.0, 0))[0]
-    g_cnt = kt[0].get("galerkin_rap", (0.0, 0))[1]
-    rap_all_ms = sum(kt[l].get("galerkin_ap", (0.0, 0))[0] + kt[l].get("galerkin_rap", (0.0, 0))[0]
+        spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0) - XSTEPS * 8 * n  # first iteration reads no p_old
+    g_ms = kx[0].get("galerkin_ap", (0.0, 0))[0] + kx[0].get("galerkin_rap", (0.0, 0))[0]
+    g_cnt = kx[0].get("galerkin_rap", (0.0, 0))[1]
+    rap_all_ms = sum(kx[l].get("galerkin_ap", (0.0, 0))[0] + kx[l].get("galerkin_rap", (0.0, 0))[0]
                      for l in range(L))
-    rap_all_bytes = sum(bm.galerkin(l) * kt[l].get("galerkin_rap", (0.0, 0))[1] for l in range(L - 1))
+    rap_all_bytes = sum(bm.galerkin(l) * kx[l].get("galerkin_rap", (0.0, 0))[1] for l in range(L - 1))
 
     if plane:
         pq_kernel = "k_m7_cg_pq"
@@ -567,6 +588,11 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
                     pq_traffic if (pq_traffic and pq_traffic["kernel"] == pq_kernel) else None)
     rap_rec = roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
                    g_cnt * bm.galerkin(0), rap_traffic)
+    dom_rec["timing"] = (f"HIP events attached to every {TRACE_EVERY}th launch per level, on the library's "
+                         f"stream, over the {K} timed steps")
+    for r_ in (spmv_rec, rap_rec):
+        r_["timing"] = (f"HIP events attached to every launch, on the library's stream, over {XSTEPS} untimed "
+                        f"steps after the timed ones")
 
     res = {
         "ms_partial": ms_partial, "n": n, "nnz": nnz, "work": work, "head_prec": head_prec,

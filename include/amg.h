@@ -301,6 +301,12 @@ typedef enum {
  * stream.  mask = 0 turns tracing off. */
 amg_status amg_trace(amg_ctx* c, unsigned mask, int level);
 
+/* Bracket only every `every`-th launch (1, 1 + every, ...) of each traced class on each
+ * level; the others run with no events, so a timing of live launches adds little to the
+ * work it times (each bracketed launch holds the stream for its timestamps).  Counts start
+ * again at this call and at amg_trace.  AMG_ERR_ARG for every < 1.  Default 1. */
+amg_status amg_trace_every(amg_ctx* c, int every);
+
 /* Milliseconds and launch counts per class (host arrays of AMG_K_COUNT) accumulated since
  * the previous read; resets them.  Synchronises the stream. */
 amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches);

@@ -24,7 +24,7 @@ EXPORTED = [
     "amg_params_default", "amg_setup", "amg_setup_transfer", "amg_rebuild", "amg_set_pattern",
     "amg_rebuild_ex", "amg_solve", "amg_vcycle", "amg_destroy", "amg_last_error", "amg_num_levels",
     "amg_level_dims", "amg_level_format", "amg_export_level", "amg_export_coarse_inverse", "amg_phase_times",
-    "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_read", "amg_policy_pick",
+    "amg_logcoef7_assemble", "amg_logcoef7_adjoint", "amg_trace", "amg_trace_every", "amg_trace_read", "amg_policy_pick",
     "amg_rebuild_auto", "amg_solve_bicgstab", "amg_apply_operator", "amg_trace_read_levels", "amg_level_storage",
     "amg_apply_operator_noalloc",
 ]
@@ -144,6 +144,7 @@ def lib():
         L.amg_logcoef7_assemble.argtypes = [I32, I32, I32, V, V, V]
         L.amg_logcoef7_adjoint.argtypes = [I32, I32, I32, V, V, V, V, V]
         L.amg_trace.argtypes = [V, C.c_uint, I]
+        L.amg_trace_every.argtypes = [V, I]
         L.amg_trace_read.argtypes = [V, C.POINTER(D), C.POINTER(I64)]
         L.amg_trace_read_levels.argtypes = [V, I, C.POINTER(D), C.POINTER(I64)]
         L.amg_level_storage.argtypes = [V, I, C.POINTER(I)]
@@ -374,12 +375,14 @@ class AMG:
         self._check(lib().amg_export_coarse_inverse(self.ctx, C.c_void_p(M.ctypes.data)))
         return M
 
-    def trace(self, classes, level: int = 0):
-        """Time every launch of the named kernel classes on `level` with HIP events."""
+    def trace(self, classes, level: int = 0, every: int = 1):
+        """Time the launches of the named kernel classes on `level` with HIP events: every
+        launch, or with `every` > 1 only each every-th one per class and level."""
         mask = 0
         for name in classes:
             mask |= 1 << KERNEL_CLASSES.index(name)
         self._check(lib().amg_trace(self.ctx, mask, level))
+        self._check(lib().amg_trace_every(self.ctx, every))
 
     def trace_read(self) -> dict:
         """{class: (total ms, launches)} since the previous read."""

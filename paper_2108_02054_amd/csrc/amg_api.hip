@@ -350,7 +350,8 @@ struct Trace {
     }
     bool own = false;
     Trace(amg_ctx* cc, int k, int lvl, hipStream_t st = nullptr) : c(cc), cls(k), level(lvl), ts(st ? st : cc->stream) {
-        if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == lvl)) {
+        if (((c->trace_mask >> k) & 1u) && (c->trace_level < 0 || c->trace_level == lvl) && k >= 0 && k < 16 &&
+            c->trace_seen[(size_t)k][(size_t)std::min(std::max(lvl, 0), 63)]++ % c->trace_every == 0) {
             a = take(c);
             b = take(c);
             if (single_launch(k)) {
@@ -2242,6 +2243,14 @@ amg_status amg_trace(amg_ctx* c, unsigned mask, int level) {
     if (!c) return AMG_ERR_ARG;
     c->trace_mask = mask;
     c->trace_level = level;
+    for (auto& row : c->trace_seen) row.fill(0);
+    return AMG_OK;
+}
+
+amg_status amg_trace_every(amg_ctx* c, int every) {
+    if (!c || every < 1) return AMG_ERR_ARG;
+    c->trace_every = every;
+    for (auto& row : c->trace_seen) row.fill(0);
     return AMG_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -531,9 +532,12 @@ struct amg_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_inv = nullptr;
     bool cinv_pending = false;
-    // per-kernel tracing (amg_trace)
+    // per-kernel tracing (amg_trace): every trace_every-th launch of a traced class on a
+    // level is bracketed (trace_seen counts them per class and level, levels above 63 as 63)
     unsigned trace_mask = 0;
     int trace_level = -1;
+    int trace_every = 1;
+    std::array<std::array<int64_t, 64>, 16> trace_seen{};
     std::vector<hipEvent_t> ev_pool;
     struct Traced {
         int cls;

@@ -752,3 +752,31 @@ def test_coarsest_level_too_large_for_the_dense_inverse():
     with pytest.raises(AmgError) as e:
         AMG(T(p), T(c), T(v), coarse_enough=4096)
     assert e.value.code == -1 and "dense inverse" in str(e.value)
+
+
+def test_trace_every_brackets_a_sample():
+    """amg_trace_every: with every = 4 only launches 1, 5, 9, ... of a traced class on a
+    level are timed (each solve of k iterations launches the Krylov SpMV k times), the
+    counts start again at each amg_trace call, and the solution does not change."""
+    from paper_2108_02054_amd import AMG
+
+    p, c, v0 = two_fluid_7pt(32, front_c1(0))
+    _, _, v1 = two_fluid_7pt(32, front_c1(2))
+    f = rhs_uniform(32**3, 1, 2)
+    g = AMG(T(p), T(c), T(v0))
+    g.rebuild(T(v1))
+    g.trace(["cg_pq"], level=0)
+    u1, i1 = g.solve(T(f))
+    all_ = g.trace_read()["cg_pq"]
+    assert all_[1] == i1["iters"] and all_[0] > 0
+    g.trace(["cg_pq"], level=0, every=4)
+    u2, i2 = g.solve(T(f))
+    u3, i3 = g.solve(T(f))
+    some = g.trace_read()["cg_pq"]
+    assert some[1] == (i2["iters"] + i3["iters"] + 3) // 4, (some, i2["iters"], i3["iters"])
+    assert some[0] > 0
+    g.trace([], level=0)
+    assert torch.equal(u1, u2) and torch.equal(u2, u3)
+    with pytest.raises(Exception):
+        g.trace(["cg_pq"], level=0, every=0)
+    g.close()
