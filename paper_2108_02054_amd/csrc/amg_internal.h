@@ -291,17 +291,28 @@ int march_blocks(int n, int a);
 WinPlan win_plan(const std::vector<int>& offs);
 
 // BiCGStab vector kernels (kernels_krylov.hip).  Partials: part[q * nb + workgroup].
+// The step's scalars live on the device (BiScal slots, formed by launch_bi_scal from the
+// partials of the kernel before), so a step runs with one host round trip: the update
+// copies the slots and the r.r partials to the host mirror (host[0..nb) partials,
+// host[2 RED_BLOCKS + k] slot k).
+enum BiScal { BS_RHO = 0, BS_ALPHA = 1, BS_OMEGA = 2, BS_BETA = 3, BS_HALF = 4, BS_BAD = 5, BS_COUNT = 8 };
+// launch_bi_scal stages: RESET (rho = value, alpha = omega = 1, flags cleared); BETA (from
+// the r^.r partials: beta, then rho); ALPHA (from r^.v: alpha = rho / r^.v); HALF (from s.s:
+// the half step has converged when ||s|| <= tol); OMEGA (from t.s and t.t: omega)
+enum BiStage { BI_RESET = 0, BI_BETA = 1, BI_ALPHA = 2, BI_HALF = 3, BI_OMEGA = 4 };
+// BS_BAD bits: a zero or non-finite r^.r, r^.v, t.t or omega
+enum BiBad { BI_BAD_RHO = 1, BI_BAD_RV = 2, BI_BAD_TT = 4, BI_BAD_OMEGA = 8 };
 int bi_grid(int64_t n);
 void launch_bi_residual(int64_t n, const double* f, const double* y, double* r, double* part, int nb, hipStream_t s);
 void launch_bi_dots(int64_t n, const double* a, const double* b, const double* c, const double* d, double* part,
                     int nb, hipStream_t s);
-void launch_bi_direction(int64_t n, const double* r, const double* v, double beta, double omega, int first, double* p,
+void launch_bi_scal(int stage, double* sc, const double* part, int nb, double value, double tol, hipStream_t s);
+void launch_bi_direction(int64_t n, const double* r, const double* v, const double* sc, int first, double* p,
                          hipStream_t s);
-void launch_bi_half(int64_t n, const double* r, const double* v, double alpha, double* sv, double* part, int nb,
+void launch_bi_half(int64_t n, const double* r, const double* v, const double* sc, double* sv, double* part, int nb,
                     hipStream_t s);
-void launch_bi_xhalf(int64_t n, const double* ph, double alpha, double* x, hipStream_t s);
 void launch_bi_update(int64_t n, const double* ph, const double* sh, const double* sv, const double* t,
-                      const double* rh, double alpha, double omega, double* x, double* r, double* part, int nb,
+                      const double* rh, const double* sc, double* x, double* r, double* rho_part, double* host, int nb,
                       hipStream_t s);
 void launch_dia_slots(const Csr& A, const Dia& D, hipStream_t s);
 template <typename T>
@@ -500,6 +511,8 @@ struct amg_ctx {
     double* h_red = nullptr;      // pinned host mirror of the scalars and the P_RR, P_FF partials
     // BiCGStab: one more vector (the hierarchy's) and mapped host memory for its partials
     double* bi_t = nullptr;
+    double* bi_sc = nullptr;      // BiCGStab's device scalars (BS_COUNT)
+    double* bi_part = nullptr;    // its device partials (5 regions of RED_BLOCKS)
     double* bi_w = nullptr;       // the p copy the diagonal-storage SpMV writes (unused here)
     double* h_bi = nullptr;
     double* d_bi = nullptr;
