@@ -91,3 +91,27 @@ def test_bicgstab_full_reuse_matches_oracle():
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
     g.close()
     o.close()
+
+
+def test_bicgstab_single_level_converges_at_the_half_step():
+    """With one level the preconditioner is the exact inverse, so the first step's half
+    step already solves the system (alpha = 1, s = 0): the device-side test of ||s|| ends
+    the solve there with x = alpha p^ only, after one iteration, as the oracle does; the
+    solution matches a dense solve of the non-symmetric system."""
+    p, c, v = convdiff_7pt(6, 2, ny=6, nz=6)
+    n = len(p) - 1
+    g, o = both(p, c, v, coarse_enough=400)
+    assert g.num_levels == 1
+    f = rhs_uniform(n, 6, 1)
+    u, info = g.solve_bicgstab(T(f))
+    uo, io = o.solve_bicgstab(f)
+    assert info["converged"] and info["iters"] == 1, info
+    assert io["iters"] == 1
+    A = np.zeros((n, n))
+    for i in range(n):
+        A[i, c[p[i]:p[i + 1]]] = v[p[i]:p[i + 1]]
+    ud = np.linalg.solve(A, f)
+    assert np.abs(u.cpu().numpy() - ud).max() <= 1e-12 * np.abs(ud).max()
+    assert rel_fro(u.cpu().numpy(), uo) <= 1e-12
+    g.close()
+    o.close()
