@@ -1585,7 +1585,7 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
     const amg_params& prm = c->prm;
     if (!c->bi_t) c->bi_t = halloc<double>(c, (size_t)n);
     if (!c->bi_sc) c->bi_sc = halloc<double>(c, (size_t)BS_COUNT);
-    if (!c->bi_part) c->bi_part = halloc<double>(c, 5 * (size_t)RED_BLOCKS);
+    if (!c->bi_part) c->bi_part = halloc<double>(c, 6 * (size_t)RED_BLOCKS);
     if (!c->h_bi) {
         HIP_CHECK(hipHostMalloc((void**)&c->h_bi, (2 * (size_t)RED_BLOCKS + BS_COUNT) * sizeof(double),
                                 hipHostMallocMapped | hipHostMallocCoherent));
@@ -1609,11 +1609,12 @@ amg_status bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info
            *t = c->bi_t;
     const int nb = bi_grid(n);
     double* sc = c->bi_sc;
-    // device partials: r^.v, s.s, (t.s, t.t), r^.r
+    // device partials, each region within its own RED_BLOCKS slots: r^.v (and the unused
+    // second region the dot kernel writes), s.s, (t.s, t.t), r^.r
     double* p_rv = c->bi_part;
-    double* p_ss = c->bi_part + RED_BLOCKS;
-    double* p_tt = c->bi_part + 2 * RED_BLOCKS;
-    double* p_rho = c->bi_part + 4 * RED_BLOCKS;
+    double* p_ss = c->bi_part + 2 * RED_BLOCKS;
+    double* p_tt = c->bi_part + 3 * RED_BLOCKS;
+    double* p_rho = c->bi_part + 5 * RED_BLOCKS;
     const double* hp = c->h_bi;
     const double* hsc = c->h_bi + 2 * RED_BLOCKS;  // the scalars as the last update saw them
     auto sum = [&](int q) {

@@ -512,7 +512,7 @@ struct amg_ctx {
     // BiCGStab: one more vector (the hierarchy's) and mapped host memory for its partials
     double* bi_t = nullptr;
     double* bi_sc = nullptr;      // BiCGStab's device scalars (BS_COUNT)
-    double* bi_part = nullptr;    // its device partials (5 regions of RED_BLOCKS)
+    double* bi_part = nullptr;    // its device partials (6 regions of RED_BLOCKS)
     double* bi_w = nullptr;       // the p copy the diagonal-storage SpMV writes (unused here)
     double* h_bi = nullptr;
     double* d_bi = nullptr;
