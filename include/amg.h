@@ -195,8 +195,9 @@ amg_status amg_solve(amg_ctx* c, const double* f, double* u, amg_solve_info* inf
  * paper's Krylov method, for non-symmetric operators (Section 4).  Arguments, stopping
  * rule (true relative residual, maxiter, restart from the true residual when the
  * recursive one reached rtol but the true one did not) and info as for amg_solve; each
- * iteration applies the V-cycle and the Krylov operator twice and reads dot-product
- * partials back three times.  A zero or non-finite r^.r, r^.v, t.t or omega returns
+ * iteration applies the V-cycle and the Krylov operator twice, forms its scalars (alpha,
+ * omega, beta, the half-step test) on the device and reads the ||r||^2 partials and the
+ * breakdown flags back once.  A zero or non-finite r^.r, r^.v, t.t or omega returns
  * AMG_ERR_BREAKDOWN.  The coarsest level's inverse is formed without pivoting and needs
  * positive elimination pivots (diagonally dominant M-matrices have them). */
 amg_status amg_solve_bicgstab(amg_ctx* c, const double* f, double* u, amg_solve_info* info);
