@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-legs", action="store_true", help="skip the short 192^3 and 160^3 legs")
     ap.add_argument("--leg-steps", type=int, default=2, help="timed steps of each short leg")
     ap.add_argument("--cpu-steps", type=int, default=12, help="oracle partial steps in the CPU sample")
+    ap.add_argument("--aggregation", type=int, default=None, choices=[0, 1],
+                    help="transfer operators: 0 = smoothed aggregation, 1 = plain aggregation (P = P_tent, the "
+                         "paper's own form); default: the series' own")
     ap.add_argument("--allocator", default="torch", choices=["torch", "library"],
                     help="device memory of the hierarchy: PyTorch's caching allocator or the library's pool")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -68,7 +71,7 @@ def parse():
     return ap.parse_args()
 
 
-def workload_name(cfg_id, N, n, nnz, prec):
+def workload_name(cfg_id, N, n, nnz, prec, plain=False):
     series = {2: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               3: "two-fluid 7-point Poisson, rho ratio 1000, interface +1 cell/step",
               5: "27-point lognormal-coefficient Poisson (sigma 1.5) with smooth drift per step",
@@ -77,7 +80,8 @@ def workload_name(cfg_id, N, n, nnz, prec):
                  "face weights, SPD couplings turning 9 degrees per step, interface +1 cell/step)"}[cfg_id]
     form = "FP32 hierarchy and V-cycle under FP64 CG" if prec == 1 else "FP64"
     krylov = "BiCGStab" if cfg_id == 6 else "PCG"
-    amg = ("plain aggregation of nodes on block norms, damped block Jacobi; " if cfg_id == 7 else "")
+    amg = ("plain aggregation of nodes on block norms, damped block Jacobi; " if cfg_id == 7
+           else "plain aggregation (P = P_tent); " if plain else "")
     return (f"{series}, {N}^3 {'nodes' if cfg_id == 7 else 'cells'} (n={n}, nnz={nnz}); {amg}partial reuse "
             f"(numeric-only cached RAP + smoother), {form}, {krylov} to 1e-8 true rel res")
 
@@ -335,6 +339,8 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
     for key in ("block_size", "aggregation"):
         if key in cfg:
             amg_params[key] = cfg[key]
+    if args.aggregation is not None:
+        amg_params["aggregation"] = args.aggregation
 
     def solve(amg, f, x):
         return amg.solve_bicgstab(f, x) if bicg else amg.solve(f, x)
@@ -561,8 +567,9 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
     first_kernel = pq_kernel if not pq_kernel.startswith("k_rb") else "k_cg_pq"
     spmv_first_bytes = (bm.bytes("cg_pq", 0) - 8 * n) if not block > 1 else bm.bytes("cg_pq", 0)
 
-    work = workload_name(cfg_id, N, n, nnz, head_prec)
-    is_headline = cfg_id == 2 and N == 128 and head_prec == 0
+    plain = args.aggregation == 1 and cfg_id != 7
+    work = workload_name(cfg_id, N, n, nnz, head_prec, plain)
+    is_headline = cfg_id == 2 and N == 128 and head_prec == 0 and not plain
     dom_traffic = None
     pq_traffic = None
     rap_traffic = None
