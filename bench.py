@@ -49,11 +49,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20, help="timed time steps")
     ap.add_argument("--warmup", type=int, default=3, help="untimed time steps before the timed ones")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 5, 6, 7],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7],
                     help="matrix series: 2 = two-fluid 7-point 128^3 FP64 (the headline), 3 = two-fluid "
-                         "7-point 192^3, 5 = lognormal 27-point 160^3 with the FP32 hierarchy, 6 = non-symmetric "
-                         "convection-diffusion 7-point 128^3 solved by BiCGStab, 7 = coupled system with 4x4 "
-                         "blocks on 56^3 nodes (node aggregation, block Jacobi)")
+                         "7-point 192^3, 4 = the differentiable solve on the 7-point log-coefficient operator "
+                         "(128^3; forward and adjoint solves on the reused hierarchy), 5 = lognormal 27-point "
+                         "160^3 with the FP32 hierarchy, 6 = non-symmetric convection-diffusion 7-point 128^3 "
+                         "solved by BiCGStab, 7 = coupled system with 4x4 blocks on 56^3 nodes (node "
+                         "aggregation, block Jacobi)")
     ap.add_argument("--n", type=int, default=0, help="grid size N (N^3 nodes); 0: the series' own")
     ap.add_argument("--no-compare", action="store_true", help="skip the full-rebuild/full-reuse/mixed runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -741,6 +743,83 @@ def leg_record(res):
     return rec
 
 
+def run_grad(N, K, W, args):
+    """Series 4, the differentiable solve: per step the log-coefficients theta_t move (an
+    outer optimisation's update), u = A(theta_t)^{-1} f by AMGSolve (assembly of A(theta)
+    on the device, the partial update of the hierarchy, PCG), the loss 0.5 ||u - u_t||^2
+    and its gradient by the adjoint solve on the same hierarchy and the -lambda (dA/dtheta)
+    u scatter.  Every theta_t is uploaded before the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_2108_02054_amd import AMG, AMGSolve, logcoef7_assemble
+    from workloads import logcoef_inputs, logcoef_theta, pattern_7pt
+
+    dev = torch.device("cuda")
+
+    def T(a):
+        return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+    _, f, ut, _ = logcoef_inputs(N)
+    p, c, _ = pattern_7pt(N)
+    thetas = [T(logcoef_theta(N, t)) for t in range(W + K + 1)]
+    F, UT = T(f), T(ut)
+    amg = AMG(T(p), T(c), logcoef7_assemble(thetas[0], N, N, N), allocator=args.allocator, maxiter=300)
+    grid = (N, N, N)
+    dom_cls = "cg_pq"
+
+    def step(t):
+        theta = thetas[t].clone().requires_grad_(True)
+        u = AMGSolve.apply(theta, F, amg, grid)
+        loss = 0.5 * torch.sum((u - UT) ** 2)
+        loss.backward()
+        return theta.grad
+
+    for t in range(1, W + 1):
+        step(t)
+    amg.trace([dom_cls], level=0, every=TRACE_EVERY)
+    amg.trace_read()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ts = time.perf_counter()
+    ev[0].record()
+    for t in range(W + 1, W + K + 1):
+        g = step(t)
+    ev[1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - ts) * 1e3 / K
+    ms = ev[0].elapsed_time(ev[1]) / K
+    kt = amg.trace_read_levels()
+    amg.trace([], level=0)
+    pq_ms, pq_cnt = kt[0].get(dom_cls, (0.0, 0))
+    n = N ** 3
+    # the Krylov SpMV (7-point marching form, symmetric read): 4 diagonals, z and p_old read,
+    # p_new and q written (the first iteration of each solve reads no p_old)
+    nnz = int(p[-1])
+    spmv_bytes = pq_cnt * (4.0 * (nnz + n) + 32.0 * n)
+    rec = roof("k_m7_cg_pq (Krylov operator SpMV with p = z + beta p and p.q, level 0; forward and adjoint "
+               "solves)", pq_ms, pq_cnt, spmv_bytes)
+    rec["timing"] = (f"HIP events attached to every {TRACE_EVERY}th launch, on the library's stream, over "
+                     f"the {K} timed steps")
+    log(f"differentiable solve {N}^3: {ms:.3f} ms/step (events), {wall:.3f} ms/step (host clock); "
+        f"gradient norm {float(torch.linalg.norm(g)):.4e}")
+    result = {
+        "metric": METRIC, "value": ms, "unit": "ms/step", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"differentiable solve on the 7-point log-coefficient Poisson operator, {N}^3 cells "
+                               f"(n={n}, nnz={nnz}): theta_t = theta_0 + 0.02 t d (theta_0 ~ N(0, 0.5^2), d ~ "
+                               f"N(0, 1)); per step the assembly of A(theta_t), the partial update, PCG to 1e-8, "
+                               f"the loss 0.5||u - u_t||^2 and its gradient by the adjoint PCG on the same "
+                               f"hierarchy", "grid": N, "n": n, "nnz": nnz, "levels": amg.num_levels,
+                   "parallelism": "single GPU"},
+        "host_ms_per_step": wall,
+        "roofline": rec,
+    }
+    amg.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -755,6 +834,9 @@ def main():
     from workloads import CONFIGS, rhs_uniform, series_matrix
 
     cfg_id = args.config
+    if cfg_id == 4:
+        run_grad(args.n or 128, args.steps, args.warmup, args)
+        return
     cfg = CONFIGS[cfg_id]
     N = args.n or cfg["N"]
     K, W = args.steps, args.warmup

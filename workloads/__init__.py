@@ -20,6 +20,7 @@ from .poisson import (  # noqa: F401
     front_moving,
     lognormal_27pt,
     logcoef_inputs,
+    logcoef_theta,
     rhs_uniform,
     neumann_7pt,
     CONFIGS,

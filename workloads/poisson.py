@@ -189,6 +189,17 @@ def logcoef_inputs(N: int, cfg_id: int = 4, n_cells: int = 16):
     return theta, f, u_t, np.sort(cells)
 
 
+def logcoef_theta(N: int, t: int, cfg_id: int = 4, step: float = 0.02) -> np.ndarray:
+    """Log-coefficients of step t of the differentiable series: theta_0 of logcoef_inputs
+    moved t steps along one seeded N(0, 1) direction (``step`` per step), as an outer
+    optimisation would move them; the pattern stays."""
+    theta0 = logcoef_inputs(N, cfg_id)[0]
+    if t == 0:
+        return theta0
+    d = rng(cfg_id, 0, STREAM_DRIFT).standard_normal(N ** 3)
+    return theta0 + (step * t) * d
+
+
 def rhs_uniform(n: int, cfg_id: int, t: int) -> np.ndarray:
     """Right-hand side of step t: U[-1, 1]."""
     return rng(cfg_id, t, STREAM_RHS).uniform(-1.0, 1.0, size=n)
