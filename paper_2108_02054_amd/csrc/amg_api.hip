@@ -439,6 +439,7 @@ void node_pattern(amg_ctx* c, Level& L) {
     build_node_matrix(pat, c->prm.block_size, Nm, c->d_flags, c->h_flags, c->stream);
     L.nptr = Nm.ptr;
     L.ncol = Nm.col;
+    L.node_pairs = std::getenv("AMGMI_NO_NODE_PAIRS") == nullptr;
     c->hier_allocs.push_back(L.nptr);
     c->hier_allocs.push_back(L.ncol);
 }
@@ -567,13 +568,18 @@ void set_groups(amg_ctx* c, Level& L, const Csr* Ac, hipStream_t s) {
 // The fused coarse tail starts at the first level t >= 1 from which every level down to
 // the coarsest fits the one-workgroup kernel: their rows together (LDS), their stored
 // entries together with the restriction into level t (a single CU reads them all, so
-// only the smallest levels gain from the fusion) and the level count.  0: no tail.
+// only the smallest levels gain from the fusion) and the level count.  A tail of the
+// coarsest level alone replaces two launches (the restriction into it and the dense solve)
+// by one on a single CU, whose dense solve reads the whole inverse: it is kept only for a
+// coarsest level of at most TAIL_SOLO_ROWS rows.  0: no tail.
 void configure_tail(amg_ctx* c) {
     const int nlev = (int)c->lv.size();
     c->tail = 0;
     if (nlev < 2 || std::getenv("AMGMI_NO_TAIL") != nullptr) return;
     int64_t max_nnz = TAIL_MAX_NNZ;
     if (const char* e = std::getenv("AMGMI_TAIL_NNZ")) max_nnz = std::atoll(e);
+    int64_t solo = TAIL_SOLO_ROWS;
+    if (const char* e = std::getenv("AMGMI_TAIL_SOLO")) solo = std::atoll(e);
     int64_t rows = 0, nnz = 0;
     for (int t = nlev - 1; t >= 1; --t) {
         const Level& L = c->lv[(size_t)t];
@@ -583,6 +589,7 @@ void configure_tail(amg_ctx* c) {
         if (rows > TAIL_MAX_ROWS || nnz + in > max_nnz || nlev - t > TAIL_MAX_LEVELS) break;
         c->tail = t;
     }
+    if (c->tail == nlev - 1 && c->lv.back().A.nrows > solo) c->tail = 0;
 }
 
 // Diagonal storage of A_0 when its pattern has at most DIA_MAX distinct column offsets

@@ -133,6 +133,7 @@ struct Level {
     // node-group kernels in place of A_l's own index arrays
     int32_t* nptr = nullptr;
     int32_t* ncol = nullptr;
+    bool node_pairs = true;      // node-group kernels take two adjacent positions per lane (even B)
     uint8_t* strong = nullptr;   // strength flag per stored entry of A_l
     double* m = nullptr;         // smoother diagonal
     float* m32 = nullptr;
@@ -350,6 +351,7 @@ int launch_dia_cg_pq(int n, const Dia& D, const double* z, const double* pold, d
 constexpr int TAIL_MAX_LEVELS = 6;
 constexpr int TAIL_MAX_ROWS = 2048;        // rows of all tail levels together
 constexpr int64_t TAIL_MAX_NNZ = 16384;    // stored entries the tail reads (A, P, R and R_{t-1})
+constexpr int TAIL_SOLO_ROWS = 64;         // largest coarsest level that a tail may hold alone
 constexpr size_t TAIL_SMEM_MAX = 3 * TAIL_MAX_ROWS * sizeof(double);
 template <typename T>
 struct TailLevel {

@@ -125,10 +125,10 @@ constexpr int NODES_PER_WG = TPB_B / NG;
 __device__ __forceinline__ double bfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float bfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
-template <int B, typename T, typename X>
+template <int B, typename T>
 __device__ __forceinline__ void node_rowsums(int I, int lane, const int* __restrict__ nptr,
-                                             const int* __restrict__ ncol, const T* __restrict__ val, X x,
-                                             T (&s)[B]) {
+                                             const int* __restrict__ ncol, const T* __restrict__ val,
+                                             const T* __restrict__ x, T (&s)[B]) {
     const int nb = nptr[I];
     const int len = B * (nptr[I + 1] - nb);
     const T* v = val + (size_t)B * B * nb;
@@ -144,12 +144,12 @@ __device__ __forceinline__ void node_rowsums(int I, int lane, const int* __restr
             v1[a] = v[a * len + k];
             v2[a] = v[a * len + k2];
         }
-        const T x1 = x(j1), x2 = x(j2);
+        const T x1 = x[j1], x2 = x[j2];
 #pragma unroll
         for (int a = 0; a < B; ++a) s[a] = bfma(v2[a], x2, bfma(v1[a], x1, s[a]));
     }
     if (k < len) {
-        const T xj = x(B * ncol[nb + k / B] + k % B);
+        const T xj = x[B * ncol[nb + k / B] + k % B];
 #pragma unroll
         for (int a = 0; a < B; ++a) s[a] = bfma(v[a * len + k], xj, s[a]);
     }
@@ -158,6 +158,63 @@ __device__ __forceinline__ void node_rowsums(int I, int lane, const int* __restr
 #pragma unroll
         for (int a = 0; a < B; ++a) s[a] += __shfl_xor(s[a], o, NG);
     }
+}
+
+// The same row sums with each lane taking two adjacent positions (k, k + 1), k even (B
+// even): both lie in one block column, so one node column, one 2-element load of x and
+// one 2-element load per row serve them, against two of each.  Rows of a node and the
+// node's first entry start at even offsets, so every pair load is aligned to its size.
+template <int B, typename T>
+__device__ __forceinline__ void node_rowsums_pairs(int I, int lane, const int* __restrict__ nptr,
+                                                   const int* __restrict__ ncol, const T* __restrict__ val,
+                                                   const T* __restrict__ x, T (&s)[B]) {
+    static_assert(B % 2 == 0, "pairs of positions need an even block size");
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    const int nb = nptr[I];
+    const int len = B * (nptr[I + 1] - nb);
+    const T* v = val + (size_t)B * B * nb;
+#pragma unroll
+    for (int a = 0; a < B; ++a) s[a] = 0;
+    const int np = len / 2;
+    int h = lane;
+    for (; h + NG < np; h += 2 * NG) {  // two pairs per pass: their loads in flight together
+        const int k1 = 2 * h, k2 = 2 * (h + NG);
+        const int j1 = B * ncol[nb + k1 / B] + k1 % B, j2 = B * ncol[nb + k2 / B] + k2 % B;
+        T2 v1[B], v2[B];
+#pragma unroll
+        for (int a = 0; a < B; ++a) {
+            v1[a] = *reinterpret_cast<const T2*>(v + a * len + k1);
+            v2[a] = *reinterpret_cast<const T2*>(v + a * len + k2);
+        }
+        const T2 x1 = *reinterpret_cast<const T2*>(x + j1), x2 = *reinterpret_cast<const T2*>(x + j2);
+#pragma unroll
+        for (int a = 0; a < B; ++a)
+            s[a] = bfma(v2[a].y, x2.y, bfma(v2[a].x, x2.x, bfma(v1[a].y, x1.y, bfma(v1[a].x, x1.x, s[a]))));
+    }
+    if (h < np) {
+        const int k1 = 2 * h;
+        const T2 x1 = *reinterpret_cast<const T2*>(x + B * ncol[nb + k1 / B] + k1 % B);
+#pragma unroll
+        for (int a = 0; a < B; ++a) {
+            const T2 v1 = *reinterpret_cast<const T2*>(v + a * len + k1);
+            s[a] = bfma(v1.y, x1.y, bfma(v1.x, x1.x, s[a]));
+        }
+    }
+#pragma unroll
+    for (int o = NG / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < B; ++a) s[a] += __shfl_xor(s[a], o, NG);
+    }
+}
+
+// PR: pairs of positions (even B only)
+template <int B, bool PR, typename T>
+__device__ __forceinline__ void node_sums(int I, int lane, const int* __restrict__ nptr, const int* __restrict__ ncol,
+                                          const T* __restrict__ val, const T* __restrict__ x, T (&s)[B]) {
+    if constexpr (PR && B % 2 == 0)
+        node_rowsums_pairs<B>(I, lane, nptr, ncol, val, x, s);
+    else
+        node_rowsums<B>(I, lane, nptr, ncol, val, x, s);
 }
 
 // s[lane] for lane < B, by selects (the array stays in registers)
@@ -170,7 +227,7 @@ __device__ __forceinline__ T pick(const T (&s)[B], int lane) {
 }
 
 // r = f - A u
-template <int B, typename T>
+template <int B, bool PR, typename T>
 __global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __restrict__ nptr,
                                                          const int* __restrict__ ncol, const T* __restrict__ val,
                                                          const T* __restrict__ f, const T* __restrict__ u,
@@ -179,7 +236,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __re
     const int lane = threadIdx.x & (NG - 1);
     if (I >= nn) return;
     T s[B];
-    node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return u[j]; }, s);
+    node_sums<B, PR>(I, lane, nptr, ncol, val, u, s);
     if (lane < B) {
         const int i = I * B + lane;
         r[i] = f[i] - pick<B>(s, lane);
@@ -187,7 +244,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_residual(int nn, const int* __re
 }
 
 // uout = uin + M (f - A uin): a residual and the block-diagonal product in one pass
-template <int B, typename T>
+template <int B, bool PR, typename T>
 __global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restrict__ nptr, const int* __restrict__ ncol,
                                                       const T* __restrict__ val, const T* __restrict__ m,
                                                       const T* __restrict__ f, const T* __restrict__ uin,
@@ -196,7 +253,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restr
     const int lane = threadIdx.x & (NG - 1);
     if (I >= nn) return;
     T s[B];
-    node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return uin[j]; }, s);
+    node_sums<B, PR>(I, lane, nptr, ncol, val, uin, s);
     if (lane < B) {
         const int i = I * B + lane;
         const T* mi = m + (size_t)i * B;
@@ -209,7 +266,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_sweep(int nn, const int* __restr
 
 // The last post-sweep of a block system's level 0 with the CG's r.z partials (FP64): z =
 // uin + M (r - A uin), one partial of r.z per workgroup (the full node grid).
-template <int B>
+template <int B, bool PR>
 __global__ __launch_bounds__(TPB_B) void k_node_sweep_rz(int nn, const int* __restrict__ nptr,
                                                          const int* __restrict__ ncol, const double* __restrict__ val,
                                                          const double* __restrict__ m, const double* __restrict__ r,
@@ -220,7 +277,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_sweep_rz(int nn, const int* __re
     double loc = 0.0;
     if (I < nn) {
         double s[B];
-        node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return uin[j]; }, s);
+        node_sums<B, PR>(I, lane, nptr, ncol, val, uin, s);
         if (lane < B) {
             const int i = I * B + lane;
             const double* mi = m + (size_t)i * B;
@@ -255,7 +312,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_pupdate(int n, const double* __r
 }
 
 // q = A p and p.q partials (FP64), p formed by k_node_pupdate: one gathered vector per
-// block column.  Bounded grid, nodes by grid stride: one partial per workgroup, in a
+// block column, one position per lane (the pair form measured slower here).  Bounded grid, nodes by grid stride: one partial per workgroup, in a
 // fixed order.
 template <int B>
 __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restrict__ nptr,
@@ -266,7 +323,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restr
     double loc = 0.0;
     for (int I = blockIdx.x * NODES_PER_WG + (int)threadIdx.x / NG; I < nn; I += gridDim.x * NODES_PER_WG) {
         double s[B];
-        node_rowsums<B>(I, lane, nptr, ncol, val, [&](int j) { return p[j]; }, s);
+        node_rowsums<B>(I, lane, nptr, ncol, val, p, s);
         if (lane < B) {
             const int i = I * B + lane;
             const double qi = pick<B>(s, lane);
@@ -328,7 +385,12 @@ void launch_node_residual(const Level& L, int B_, const T* f, const T* u, T* r, 
     need_nodes(L);
     const int nn = L.A.nrows / B_;
     const unsigned nb = (unsigned)std::max(1, node_grid(nn));
-    AMG_WITH_B(B_, timed_launch(k_node_residual<B, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r));
+    AMG_WITH_B(B_, {
+        if (L.node_pairs)
+            timed_launch(k_node_residual<B, true, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r);
+        else
+            timed_launch(k_node_residual<B, false, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), f, u, r);
+    });
     HIP_LAUNCH_CHECK();
 }
 
@@ -337,8 +399,12 @@ void launch_node_sweep(const Level& L, int B_, const T* m, const T* f, const T* 
     need_nodes(L);
     const int nn = L.A.nrows / B_;
     const unsigned nb = (unsigned)std::max(1, node_grid(nn));
-    AMG_WITH_B(B_, timed_launch(k_node_sweep<B, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin,
-                                                                          uout));
+    AMG_WITH_B(B_, {
+        if (L.node_pairs)
+            timed_launch(k_node_sweep<B, true, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin, uout);
+        else
+            timed_launch(k_node_sweep<B, false, T>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.v<T>(), m, f, uin, uout);
+    });
     HIP_LAUNCH_CHECK();
 }
 
@@ -356,14 +422,15 @@ int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z
     timed_launch(k_node_pupdate, bgrid(n), TPB_B, 0, s, n, z, pold, pnew, first, rs);
     HIP_LAUNCH_CHECK();
     const double* p = pnew;
-    AMG_WITH_B(B_, {
+    auto go = [&](auto kern) {
         if (e.start != nullptr)
-            hipExtLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, e.start, e.stop, 0, nn,
-                                  (const int*)L.nptr, (const int*)L.ncol, val, p, q, rs);
+            hipExtLaunchKernelGGL(kern, dim3(nb), dim3(TPB_B), 0, s, e.start, e.stop, 0, nn, (const int*)L.nptr,
+                                  (const int*)L.ncol, val, p, q, rs);
         else
-            hipLaunchKernelGGL(k_node_cg_pq<B>, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)L.nptr,
-                               (const int*)L.ncol, val, p, q, rs);
-    });
+            hipLaunchKernelGGL(kern, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)L.nptr, (const int*)L.ncol, val, p,
+                               q, rs);
+    };
+    AMG_WITH_B(B_, go(k_node_cg_pq<B>));
     HIP_LAUNCH_CHECK();
     return nb;
 }
@@ -374,7 +441,12 @@ int launch_node_sweep_rz(const Level& L, int B_, const double* m, const double* 
     const int nn = L.A.nrows / B_;
     const int nb = std::max(1, node_grid(nn));
     if (nb > rs.cap) throw Fail{AMG_ERR_ARG, "reduction scratch too small"};
-    AMG_WITH_B(B_, timed_launch(k_node_sweep_rz<B>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.val, m, r, uin, z, rs));
+    AMG_WITH_B(B_, {
+        if (L.node_pairs)
+            timed_launch(k_node_sweep_rz<B, true>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.val, m, r, uin, z, rs);
+        else
+            timed_launch(k_node_sweep_rz<B, false>, nb, TPB_B, 0, s, nn, L.nptr, L.ncol, L.A.val, m, r, uin, z, rs);
+    });
     HIP_LAUNCH_CHECK();
     return nb;
 }

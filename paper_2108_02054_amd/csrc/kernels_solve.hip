@@ -414,6 +414,28 @@ __global__ __launch_bounds__(TPB) void k_lg(int n, const int* __restrict__ ptr, 
     if constexpr (KIND == 4) y[row] += s;                                 // u += P uc
 }
 
+// s = sum of a[j] * x[j] over j = j0, j0 + G, ... < n, added in that order; U pairs are
+// loaded before they are added, so that a row of a few hundred entries costs a few round
+// trips to memory rather than one per entry.
+template <int G, typename T>
+__device__ __forceinline__ double strided_dot(const double* __restrict__ a, const T* x, int j0, int n) {
+    constexpr int U = 8;
+    double s = 0.0;
+    for (int jb = j0; jb < n; jb += U * G) {
+        double av[U], xv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int j = jb + k * G;
+            av[k] = j < n ? a[j] : 0.0;
+            xv[k] = j < n ? (double)x[j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (jb + k * G < n) s += av[k] * xv[k];
+    }
+    return s;
+}
+
 // u = A^{-1} f on the coarsest level: one wavefront per row of the dense FP64 inverse; a
 // NaN solution when the inverse's pivot flag *bad is set (a coarsest operator that is not
 // SPD then surfaces as a breakdown of the Krylov method that applies the cycle).
@@ -423,9 +445,7 @@ __global__ __launch_bounds__(TPB) void k_coarse_gemv(int n, const double* __rest
     const int lane = threadIdx.x & 63;
     const int row = (blockIdx.x * TPB + (int)threadIdx.x) >> 6;
     if (row >= n) return;
-    const double* a = inv + (size_t)row * n;
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64) s += a[j] * (double)f[j];
+    double s = strided_dot<64>(inv + (size_t)row * n, f, lane, n);
     s = wave_sum(s);
     if (lane == 0) u[row] = (*bad != 0.0) ? (T)__builtin_nan("") : (T)s;
 }
@@ -1825,9 +1845,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_vcycle_tail(TailArgs<T> a) {
         const T* f = sm + L.soff;
         T* u = sm + L.soff + nc;
         for (int i = r0; i < nc; i += RS) {
-            double s = 0.0;
-            const double* row = a.cinv + (size_t)i * nc;
-            for (int j = g; j < nc; j += TAIL_G) s += row[j] * (double)f[j];
+            double s = strided_dot<TAIL_G>(a.cinv + (size_t)i * nc, f, g, nc);
             s = group_sum<TAIL_G, double>(s);
             if (g == 0) u[i] = (T)s;
         }

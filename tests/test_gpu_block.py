@@ -9,7 +9,7 @@ import pytest
 import scipy.sparse as sp
 
 from tests.dense import random_spd_graph
-from tests.gpu_util import T, both, compare_levels, rel_fro
+from tests.gpu_util import T, both, compare_levels, rel_fro, rel_max
 from workloads import rhs_uniform, two_fluid_7pt
 from workloads.poisson import coupled4_7pt
 
@@ -45,6 +45,43 @@ def test_block_kronecker_random_graph(seed):
     compare_levels(g, o, tol=1e-10)
     g.close()
     o.close()
+
+
+@pytest.mark.parametrize("bs", [2, 3, 4, 6])
+def test_node_pair_loads(monkeypatch, bs):
+    """The node-group residual and sweeps with two adjacent positions per lane (even block
+    sizes; odd ones keep one position per lane) form the row sums of the one-position form
+    in another order: the V-cycle and the solve match those of the one-position kernels and
+    the oracle's V-cycle, and the Krylov product (one position per lane) matches SciPy's."""
+    pp, cc, vv = random_spd_graph(300, 5, 3)
+    rg = np.random.default_rng(bs)
+    M = rg.uniform(-1.0, 1.0, size=(bs, bs))
+    K = M @ M.T + bs * np.eye(bs)
+    A = sp.kron(sp.csr_matrix((vv, cc, pp), shape=(300, 300)), sp.csr_matrix(K), format="csr")
+    A.sort_indices()
+    p, c, v = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+    prm = dict(block_size=bs, aggregation=1, coarse_enough=64)
+    print(f"case kron bs={bs}", flush=True)
+    g, o = both(p, c, v, **prm)
+    x = np.random.default_rng(1).standard_normal(A.shape[0])
+    y = g.apply_operator(T(x)).cpu().numpy()
+    assert rel_max(y, A @ x) <= 1e-14
+    r = np.random.default_rng(2).standard_normal(A.shape[0])
+    z = g.vcycle(T(r)).cpu().numpy()
+    u, info = g.solve(T(r))
+    monkeypatch.setenv("AMGMI_NO_NODE_PAIRS", "1")
+    h = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), **prm)
+    z1 = h.vcycle(T(r)).cpu().numpy()
+    u1, info1 = h.solve(T(r))
+    if bs % 2:
+        assert np.array_equal(z, z1) and np.array_equal(u.cpu().numpy(), u1.cpu().numpy())
+    else:
+        assert rel_fro(z, z1) <= 1e-13
+        assert rel_fro(u.cpu().numpy(), u1.cpu().numpy()) <= 1e-9
+    assert rel_fro(z, o.vcycle(r)) <= 1e-10
+    assert info["converged"] and abs(info["iters"] - info1["iters"]) <= 1, (info, info1)
+    for m in (g, h, o):
+        m.close()
 
 
 def test_block_partial_series_and_solves():
@@ -89,6 +126,34 @@ def test_block_mixed_precision():
     assert rel_fro(u.cpu().numpy(), uo) <= 1e-6
     g.close()
     o.close()
+
+
+@pytest.mark.parametrize("env,first", [({}, 0), ({"AMGMI_TAIL_SOLO": "128"}, 2), ({"AMGMI_TAIL_NNZ": "200000"}, 1)])
+def test_block_coarse_tail(monkeypatch, env, first):
+    """The one-workgroup coarse tail on a block system.  A coarsest level alone goes to it only
+    up to 64 rows (this system's has 88); forced onto that level (the restriction into it and
+    the dense solve), or onto the last two levels (the block smoother applied from LDS as well),
+    it computes the V-cycle of the separate launches (row sums in another order) and of the
+    oracle (Algorithm 2)."""
+    N = 13
+    p, c, v = coupled4_7pt(N, 1)
+    for k, x in env.items():
+        monkeypatch.setenv(k, x)
+    print(f"case coupled4 N=13 tail env={env}", flush=True)
+    g, o = both(p, c, v, coarse_enough=128, **BLOCK)
+    L = g.num_levels
+    assert L == 3 and g.dims(L - 1)[0] == 88
+    assert [g.level_storage(l)["tail"] for l in range(L)] == [int(first > 0 and l >= first) for l in range(L)]
+    r = np.random.default_rng(11).standard_normal(len(p) - 1)
+    z = g.vcycle(T(r)).cpu().numpy()
+    monkeypatch.setenv("AMGMI_NO_TAIL", "1")
+    h = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), coarse_enough=128, **BLOCK)
+    assert h.level_storage(L - 1)["tail"] == 0
+    z_sep = h.vcycle(T(r)).cpu().numpy()
+    assert rel_fro(z, z_sep) <= 1e-12
+    assert rel_fro(z, o.vcycle(r)) <= 1e-10
+    for x in (g, h, o):
+        x.close()
 
 
 @pytest.mark.parametrize("kernels,npre,npost", [("default", 2, 2), ("default", 0, 2), ("lanes", 1, 1)])

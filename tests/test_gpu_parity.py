@@ -349,9 +349,11 @@ def test_coarse_tail_matches_level_kernels(monkeypatch, npre, npost, precision):
     r = np.random.default_rng(7).standard_normal(32**3)
     prm = dict(npre=npre, npost=npost, precision=precision, coarse_enough=128)  # a 19-row coarsest level
     g = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), **prm)
+    assert g.level_storage(g.num_levels - 1)["tail"] == 1  # the coarsest level (27 rows) runs in the tail
     z_tail = g.vcycle(T(r)).cpu().numpy()
     monkeypatch.setenv("AMGMI_NO_TAIL", "1")
     h = __import__("paper_2108_02054_amd").AMG(T(p), T(c), T(v), **prm)
+    assert h.level_storage(h.num_levels - 1)["tail"] == 0
     z_sep = h.vcycle(T(r)).cpu().numpy()
     tol = 1e-12 if precision == 0 else 1e-5
     assert rel_fro(z_tail, z_sep) <= tol
