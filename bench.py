@@ -223,10 +223,15 @@ class ByteModel:
 
     def galerkin(self, l):
         """A_l, P_l, R_l read once, A_{l+1} written once with its cached columns read once
-        (the A_l P_l intermediate and the cached plan are implementation costs)."""
+        (the A_l P_l intermediate and the cached plan are implementation costs).  The node
+        form of a block system: A_l's values read and A_{l+1}'s written once, P_l and R_l as
+        one aggregate index per node, A_{l+1}'s node pattern read once."""
         n, nnzA, nc, nnzP, _ = self.dims[l]
         nnzAc = self.dims[l + 1][1]
         s = self.s
+        if self.st[l].get("node_galerkin"):
+            B = self.block
+            return s * (nnzA + nnzAc) + 8 * (n // B) + 4 * (nc // B + 1) + 4 * (nnzAc // (B * B))
         ind = lambda rows, nnz: 4 * (rows + 1) + 4 * nnz  # noqa: E731
         return (ind(n, nnzA) + s * nnzA + 2 * (ind(n, nnzP) + s * nnzP) - 4 * (n + 1) + 4 * (nc + 1)
                 + ind(nc, nnzAc) + s * nnzAc)
@@ -552,11 +557,15 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0)
     else:
         spmv_bytes = pq_cnt * bm.bytes("cg_pq", 0) - XSTEPS * 8 * n  # first iteration reads no p_old
+
+    def gal_cnt(l):  # products per level (the node form of a block system is one launch, traced as A P)
+        return kx[l].get("galerkin_rap", (0.0, 0))[1] or kx[l].get("galerkin_ap", (0.0, 0))[1]
+
     g_ms = kx[0].get("galerkin_ap", (0.0, 0))[0] + kx[0].get("galerkin_rap", (0.0, 0))[0]
-    g_cnt = kx[0].get("galerkin_rap", (0.0, 0))[1]
+    g_cnt = gal_cnt(0)
     rap_all_ms = sum(kx[l].get("galerkin_ap", (0.0, 0))[0] + kx[l].get("galerkin_rap", (0.0, 0))[0]
                      for l in range(L))
-    rap_all_bytes = sum(bm.galerkin(l) * kx[l].get("galerkin_rap", (0.0, 0))[1] for l in range(L - 1))
+    rap_all_bytes = sum(bm.galerkin(l) * gal_cnt(l) for l in range(L - 1))
 
     if plane:
         pq_kernel = "k_m7_cg_pq"
@@ -595,8 +604,9 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
                                  if block > 1 else " (Krylov operator SpMV with p = z + beta p and p.q, level 0)"),
                     pq_ms, pq_cnt, spmv_bytes,
                     pq_traffic if (pq_traffic and pq_traffic["kernel"] == pq_kernel) else None)
-    rap_rec = roof("k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0), per rebuild (level 0)", g_ms, g_cnt,
-                   g_cnt * bm.galerkin(0), rap_traffic)
+    rap_name = ("k_node_rap R_0 A_0 P_0 in one pass over the BxB blocks" if bm.st[0].get("node_galerkin")
+                else "k_galerkin_pos A_0 P_0 then R_0 (A_0 P_0)")
+    rap_rec = roof(f"{rap_name}, per rebuild (level 0)", g_ms, g_cnt, g_cnt * bm.galerkin(0), rap_traffic)
     dom_rec["timing"] = (f"HIP events attached to every {TRACE_EVERY}th launch per level, on the library's "
                          f"stream, over the {K} timed steps")
     for r_ in (spmv_rec, rap_rec):

@@ -521,6 +521,57 @@ void release_posmaps(amg_ctx* c, Level& L) {
     release_posmap(c, L.galRAP);
 }
 
+void release_node_gal(amg_ctx* c, NodeGal& g) {
+    for (void* q : {(void*)g.tptr, (void*)g.toff, (void*)g.tlen, (void*)g.cout, (void*)g.clen}) release(c, q);
+    g = NodeGal{};
+}
+
+// Node Galerkin plans of a block system (every level's node pattern built): a level whose
+// P is P_node (x) I_B with unit values gets one, and its partial rebuild forms A_{l+1} in
+// one pass over A_l's blocks; other levels (user transfer operators of another form) keep
+// the scalar position-map product.  AMGMI_NO_NODE_GAL keeps the scalar product everywhere.
+void configure_node_gal(amg_ctx* c) {
+    for (Level& L : c->lv) release_node_gal(c, L.ngal);
+    const int B = c->prm.block_size;
+    if (B < 2 || std::getenv("AMGMI_NO_NODE_GAL") != nullptr) return;
+    hipStream_t s = c->stream;
+    const int nlev = (int)c->lv.size();
+    for (int l = 0; l + 1 < nlev; ++l) {
+        Level& L = c->lv[(size_t)l];
+        const Level& N = c->lv[(size_t)l + 1];
+        if (L.P.nrows == 0 || L.nptr == nullptr || N.nptr == nullptr) continue;
+        const int nn = L.A.nrows / B;
+        const int64_t nb_fine = L.A.nnz / ((int64_t)B * B);
+        const int64_t ncb = N.A.nnz / ((int64_t)B * B);
+        Temps tmp(s);
+        int32_t* nagg = tmp.make<int32_t>((size_t)std::max(nn, 1));
+        int32_t* tpos = tmp.make<int32_t>((size_t)std::max<int64_t>(nb_fine, 1));
+        int32_t* cnt = tmp.make<int32_t>((size_t)ncb + 1);
+        HIP_CHECK(hipMemsetAsync(cnt, 0, ((size_t)ncb + 1) * sizeof(int32_t), s));
+        clear_flags(c);
+        launch_node_gal_agg(L.P, B, nagg, c->d_flags, s);
+        launch_node_gal_count(L, N, B, nagg, tpos, cnt, c->d_flags, s);
+        read_flags(c);
+        if (c->h_flags[F_NODEGAL]) continue;
+        NodeGal g;
+        g.nblk = ncb;
+        g.complete = c->h_flags[F_NODEPART] == 0;
+        g.tptr = halloc<int32_t>(c, (size_t)ncb + 1);
+        exclusive_scan_i32(cnt, g.tptr, ncb + 1, s);
+        g.nterm = to_host(g.tptr + ncb, 1, s)[0];
+        const size_t nt = (size_t)std::max<int64_t>(g.nterm, 1);
+        g.toff = halloc<int32_t>(c, nt);
+        g.tlen = halloc<int32_t>(c, nt);
+        g.cout = halloc<int32_t>(c, (size_t)std::max<int64_t>(ncb, 1));
+        g.clen = halloc<int32_t>(c, (size_t)std::max<int64_t>(ncb, 1));
+        int32_t* cur = tmp.make<int32_t>((size_t)std::max<int64_t>(ncb, 1));
+        int32_t* last = tmp.make<int32_t>((size_t)std::max<int64_t>(ncb, 1));
+        launch_node_gal_fill(L, N, B, tpos, g, cur, last, s);
+        HIP_CHECK(hipStreamSynchronize(s));
+        L.ngal = g;
+    }
+}
+
 // The launch shape and position map of C = L B (allocated with the hierarchy); with
 // diag, also the diagonal index of every row of L (for the smoother).  Rows with more
 // terms than the form takes, or C rows too long for it, leave the product to the
@@ -698,7 +749,8 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     // array and stores the hierarchy's copies (FP64, and FP32 in mixed precision) as it
     // reads them; otherwise they are copied first.
     bool ingested = false;
-    if (nlev == 1 || L0.galAP.g == 0) {
+    const bool node0 = nlev > 1 && L0.ngal.nblk > 0;
+    if (nlev == 1 || (node0 ? !L0.ngal.complete : L0.galAP.g == 0)) {
         if (val != L0.A.val) d2d(L0.A.val, val, (size_t)L0.A.nnz * sizeof(double), s);
         if constexpr (std::is_same<T, float>::value) launch_cast_d2f(L0.A.nnz, L0.A.val, L0.A.val32, s);
         ingested = true;
@@ -708,6 +760,15 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     const bool direct = !ingested && c->dia.ndiag > 0;
     for (int l = 0; l + 1 < nlev; ++l) {
         const Level& L = c->lv[l];
+        if (L.ngal.nblk > 0) {  // block system: R A P in one pass over A_l's blocks
+            Trace tr(c, AMG_K_GALERKIN_AP, l);
+            const bool in = l == 0 && !ingested;
+            float* a32 = nullptr;
+            if constexpr (std::is_same<T, float>::value) a32 = in ? L0.A.val32 : nullptr;
+            launch_node_rap<T>(L.ngal, c->prm.block_size, L.A.v<T>(), in ? val : nullptr, in ? L0.A.val : nullptr,
+                               a32, c->lv[l + 1].A.v<T>(), s);
+            continue;
+        }
         {
             // the staged A P kernel also forms this level's smoother diagonal
             Trace tr(c, AMG_K_GALERKIN_AP, l);
@@ -1018,6 +1079,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     read_red(c);
     if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
     ph[5] += ms_since(t0);
+    configure_node_gal(c);
 
     if (mixed(c)) {
         alloc_shadow(c);
@@ -1094,6 +1156,7 @@ void repattern(amg_ctx* c) {
     if (mixed(c)) L0.A.val32 = halloc<float>(c, (size_t)L0.A.nnz);
     if (c->prm.block_size > 1)
         for (int l = 1; l < nlev; ++l) node_pattern(c, c->lv[(size_t)l]);
+    configure_node_gal(c);
     set_groups(c, c->lv.back(), nullptr, s);
     release(c, c->rs.part);
     alloc_reduction(c);
@@ -2318,6 +2381,7 @@ amg_status amg_level_storage(const amg_ctx* c, int l, int* out) {
     out[5] = L.R.rpb;
     out[6] = (c->tail > 0 && l >= c->tail) ? 1 : 0;
     out[7] = mixed(c) ? 4 : 8;
+    out[8] = L.ngal.nblk > 0 ? 1 : 0;
     return AMG_OK;
 }
 

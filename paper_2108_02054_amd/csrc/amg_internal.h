@@ -124,6 +124,22 @@ struct GalShape {
     int64_t terms = 0;
 };
 
+// Galerkin product of a block system whose transfer operator is P_l = P_node (x) I_B with
+// unit values (node aggregation, plain): block (J, L) of A_{l+1} is the sum, over the fine
+// nodes I of aggregate J in ascending order, of the sum of the blocks (I, K) of A_l with K
+// in aggregate L in ascending K -- the row-by-row product's order, so the result is that
+// product's bit for bit.  One term per block of A_l, grouped by the coarse block it feeds.
+struct NodeGal {
+    int32_t* tptr = nullptr;  // per coarse block (+1): its first term
+    int32_t* toff = nullptr;  // per term: index of the fine block's (0, 0) value
+    int32_t* tlen = nullptr;  // per term: 2 * the fine rows' length, + 1 when it starts a new fine node
+    int32_t* cout = nullptr;  // per coarse block: index of its (0, 0) value
+    int32_t* clen = nullptr;  // per coarse block: the coarse rows' length
+    int64_t nblk = 0;         // coarse blocks (0: no plan, the scalar product runs)
+    int64_t nterm = 0;
+    bool complete = false;    // every block of A_l is some term's (the product can ingest values)
+};
+
 struct Level {
     Csr A;       // A_l
     Csr P, R;    // P_l and R_l = P_l^T (empty on the coarsest level)
@@ -134,6 +150,7 @@ struct Level {
     int32_t* nptr = nullptr;
     int32_t* ncol = nullptr;
     bool node_pairs = true;      // node-group kernels take two adjacent positions per lane (even B)
+    NodeGal ngal;                // block systems: node Galerkin plan of A_{l+1} = R_l A_l P_l
     uint8_t* strong = nullptr;   // strength flag per stored entry of A_l
     double* m = nullptr;         // smoother diagonal
     float* m32 = nullptr;
@@ -423,7 +440,17 @@ void build_galerkin_posmap(const Csr& L, const Csr& B, const Csr& C, const GalSh
 
 // ------------------------------------------------------------------ setup
 // flags: device int[8], see SetupFlag.
-enum SetupFlag { F_ARG = 0, F_PATTERN = 1, F_NOT_SPD = 2, F_UNDECIDED = 3, F_NOAGG = 4, F_BLOCK = 5, F_COUNT = 8 };
+enum SetupFlag {
+    F_ARG = 0,
+    F_PATTERN = 1,
+    F_NOT_SPD = 2,
+    F_UNDECIDED = 3,
+    F_NOAGG = 4,
+    F_BLOCK = 5,
+    F_NODEGAL = 6,   // block system: P_l is not P_node (x) I_B with unit values (no node Galerkin plan)
+    F_NODEPART = 7,  // block system: some node belongs to no aggregate
+    F_COUNT = 8
+};
 
 void launch_validate(const Csr& A, int32_t* diag_pos, int* flags, hipStream_t s);
 void launch_strength(const Csr& A, const int32_t* diag_pos, double eps2, uint8_t* strong, int32_t* tpos,
@@ -462,6 +489,21 @@ int launch_node_sweep_rz(const Level& L, int B, const double* m, const double* r
                          const RedScratch& rs, hipStream_t s);
 void launch_node_expand(const Csr& A, int B, const Csr& Nm, const uint8_t* nstrong, const int32_t* nagg,
                         uint8_t* strong, int32_t* agg, hipStream_t s);
+// Node Galerkin plan of levels L -> N (block size B; N's node pattern built): the aggregate
+// of every fine node from P (flags[F_NODEGAL] when P is not of the unit Kronecker form,
+// flags[F_NODEPART] for a node outside every aggregate), then per coarse node the terms'
+// coarse positions (tpos per block of A_l) and counts (cnt per coarse block), then, with
+// g.tptr formed from the counts, the terms themselves (cur, last: scratch per coarse block).
+void launch_node_gal_agg(const Csr& P, int B, int32_t* nagg, int* flags, hipStream_t s);
+void launch_node_gal_count(const Level& L, const Level& N, int B, const int32_t* nagg, int32_t* tpos, int32_t* cnt,
+                           int* flags, hipStream_t s);
+void launch_node_gal_fill(const Level& L, const Level& N, int B, const int32_t* tpos, const NodeGal& g, int32_t* cur,
+                          int32_t* last, hipStream_t s);
+// A_{l+1} = R_l A_l P_l by the node plan: the values of A_l from aval, or, with lin, from
+// the caller's FP64 array, stored into a64 (and a32 when given) as they are read.
+template <typename T>
+void launch_node_rap(const NodeGal& g, int B, const T* aval, const double* lin, double* a64, float* a32, T* cval,
+                     hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 int64_t max_i64(const int64_t* in, int64_t n, hipStream_t s);  // synchronises
 

@@ -1,7 +1,8 @@
 // kernels_block.hip -- systems with B unknowns per node (the paper's 4x4-block systems,
 // Section 4, where every matrix value is a block): damped block Jacobi, whose smoother
-// holds omega * D_I^{-1} for every node I (row-major, B*B values per node), and the
-// node-group products (residual, sweep, Krylov SpMV) that read the level's node pattern.
+// holds omega * D_I^{-1} for every node I (row-major, B*B values per node), the
+// node-group products (residual, sweep, Krylov SpMV) that read the level's node pattern,
+// and the Galerkin product of a partial update formed block by block.
 // Unknown b of node I is row I*B + b; every stored entry belongs to a full B x B block.
 //
 // The inverse is Gauss-Jordan elimination with partial pivoting on [D_I | I], in the
@@ -343,6 +344,189 @@ __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restr
     }
 }
 
+// ------------------------------------------------------------------ node Galerkin product
+//
+// With P_l = P_node (x) I_B and unit values, row I*B + a of A_l P_l sums, per aggregate L,
+// the entries (a, c) of the blocks (I, K), K in L, in ascending K, and row J*B + a of
+// R_l (A_l P_l) sums those row sums over the fine nodes I of aggregate J in ascending I.
+// The plan lists, per block (J, L) of A_{l+1}, its terms -- the blocks (I, K) -- in the
+// order (I, K), marking where a new fine node starts; lane (a, c) of the block's group adds
+// the terms' entries (a, c) in that order, closing each fine node's sum before it adds the
+// next one's: the products by the unit values are exact, so this is the row-by-row
+// product's arithmetic.  The values are read once, in whole blocks of B consecutive
+// entries per row.
+
+// Aggregate of each fine node from P's rows, checking the unit Kronecker form.
+template <int B>
+__global__ __launch_bounds__(TPB_B) void k_ngal_agg(int nn, const int* __restrict__ Pptr, const int* __restrict__ Pcol,
+                                                    const double* __restrict__ Pval, int* __restrict__ nagg,
+                                                    int* __restrict__ flags) {
+    const int I = blockIdx.x * TPB_B + threadIdx.x;
+    if (I >= nn) return;
+    const int c0 = Pptr[I * B + 1] - Pptr[I * B];
+    bool ok = c0 == 0 || c0 == 1;
+    int J = -1;
+    if (ok && c0 == 1) {
+        const int col0 = Pcol[Pptr[I * B]];
+        ok = col0 % B == 0;
+        J = col0 / B;
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int k = Pptr[I * B + b];
+        const int cnt = Pptr[I * B + b + 1] - k;
+        if (cnt != c0) ok = false;
+        else if (ok && cnt == 1 && (Pcol[k] != J * B + b || Pval[k] != 1.0)) ok = false;
+    }
+    if (!ok) flags[F_NODEGAL] = 1;
+    if (ok && J < 0) flags[F_NODEPART] = 1;
+    nagg[I] = ok ? J : -1;
+}
+
+// One thread per coarse node J: the fine nodes of aggregate J are the columns / B of R's
+// row J*B; each of their blocks (I, K) gets the position of aggregate(K) in J's coarse row.
+template <int B>
+__global__ __launch_bounds__(TPB_B) void k_ngal_count(int ncn, const int* __restrict__ Rptr,
+                                                      const int* __restrict__ Rcol, const int* __restrict__ nptr,
+                                                      const int* __restrict__ ncol, const int* __restrict__ nagg,
+                                                      const int* __restrict__ cnptr, const int* __restrict__ cncol,
+                                                      int* __restrict__ tpos, int* __restrict__ cnt,
+                                                      int* __restrict__ flags) {
+    const int J = blockIdx.x * TPB_B + threadIdx.x;
+    if (J >= ncn) return;
+    const int c0 = cnptr[J], c1 = cnptr[J + 1];
+    for (int t = Rptr[J * B]; t < Rptr[J * B + 1]; ++t) {
+        const int I = Rcol[t] / B;
+        if (Rcol[t] % B != 0 || nagg[I] != J) flags[F_NODEGAL] = 1;
+        for (int e = nptr[I]; e < nptr[I + 1]; ++e) {
+            const int L = nagg[ncol[e]];
+            int p = -1;
+            if (L >= 0) {
+                int lo = c0, hi = c1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (cncol[mid] < L)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo < c1 && cncol[lo] == L)
+                    p = lo - c0;
+                else
+                    flags[F_NODEGAL] = 1;  // the coarse pattern lacks a block the product forms
+            } else {
+                flags[F_NODEPART] = 1;
+            }
+            tpos[e] = p;
+            if (p >= 0) cnt[c0 + p] += 1;  // coarse row J is this thread's alone
+        }
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(TPB_B) void k_ngal_fill(int ncn, const int* __restrict__ Rptr,
+                                                     const int* __restrict__ Rcol, const int* __restrict__ nptr,
+                                                     const int* __restrict__ cnptr, const int* __restrict__ tpos,
+                                                     const int* __restrict__ tptr, int* __restrict__ toff,
+                                                     int* __restrict__ tlen, int* __restrict__ cout,
+                                                     int* __restrict__ clen, int* __restrict__ cur,
+                                                     int* __restrict__ last) {
+    const int J = blockIdx.x * TPB_B + threadIdx.x;
+    if (J >= ncn) return;
+    const int c0 = cnptr[J], c1 = cnptr[J + 1];
+    for (int g = c0; g < c1; ++g) {
+        cur[g] = tptr[g];
+        last[g] = -1;
+        cout[g] = B * B * c0 + (g - c0) * B;
+        clen[g] = B * (c1 - c0);
+    }
+    for (int t = Rptr[J * B]; t < Rptr[J * B + 1]; ++t) {
+        const int I = Rcol[t] / B;
+        const int nb = nptr[I], len = B * (nptr[I + 1] - nb);
+        for (int e = nb; e < nptr[I + 1]; ++e) {
+            const int p = tpos[e];
+            if (p < 0) continue;
+            const int g = c0 + p;
+            const int slot = cur[g]++;
+            toff[slot] = B * B * nb + (e - nb) * B;
+            tlen[slot] = 2 * len + (last[g] != I ? 1 : 0);
+            last[g] = I;
+        }
+    }
+}
+
+// One lane per entry (a, c) of a coarse block, NGB >= B*B lanes per block.  The terms go
+// in batches of U: a lane issues a batch's U value loads, then the next batch's plan loads,
+// then adds the batch's values in order -- a coarse block's list (some forty terms for the
+// block on the diagonal, two or three for the others) costs about one round trip to memory
+// per batch.  lin, a64, a32 may be one array (the caller's values may be the hierarchy's
+// own); each index is read and written by one lane only.
+template <int B, int NGB, typename T>
+__global__ __launch_bounds__(TPB_B) void k_node_rap(int64_t nblk, const int* __restrict__ tptr,
+                                                    const int* __restrict__ toff, const int* __restrict__ tlen,
+                                                    const int* __restrict__ cout, const int* __restrict__ clen,
+                                                    const T* aval, const double* lin, double* a64, float* a32,
+                                                    T* __restrict__ cval) {
+    constexpr int U = 8;
+    const int64_t t = (int64_t)xcd_block() * TPB_B + threadIdx.x;
+    const int64_t g = t / NGB;
+    const int q = (int)(t % NGB);
+    if (g >= nblk || q >= B * B) return;
+    const int a = q / B, c = q % B;
+    const int k0 = tptr[g], k1 = tptr[g + 1];
+    int o[U], lf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool in = k0 + u < k1;
+        o[u] = in ? toff[k0 + u] : 0;
+        lf[u] = in ? tlen[k0 + u] : 0;
+    }
+    T acc = 0, part = 0;
+    for (int k = k0; k < k1; k += U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = 0;
+            if (k + u < k1) {
+                const int64_t idx = (int64_t)o[u] + (int64_t)a * (lf[u] >> 1) + c;
+                if (lin != nullptr) {
+                    const double x = lin[idx];
+                    a64[idx] = x;
+                    if (a32 != nullptr) a32[idx] = (float)x;
+                    v[u] = (T)x;
+                } else {
+                    v[u] = aval[idx];
+                }
+            }
+        }
+        int on[U], ln[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kk = k + U + u;
+            const bool in = kk < k1;
+            on[u] = in ? toff[kk] : 0;
+            ln[u] = in ? tlen[kk] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (k + u < k1) {
+                if ((lf[u] & 1) && k + u > k0) {  // a new fine node: its predecessor's sum is complete
+                    acc = acc + part;
+                    part = 0;
+                }
+                part = part + v[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            o[u] = on[u];
+            lf[u] = ln[u];
+        }
+    }
+    acc = acc + part;
+    cval[(int64_t)cout[g] + (int64_t)a * clen[g] + c] = acc;
+}
+
 static unsigned bgrid(int64_t n) {
     const int64_t b = (n + TPB_B - 1) / TPB_B;
     return (unsigned)(b > 0 ? b : 1);
@@ -451,6 +635,57 @@ int launch_node_sweep_rz(const Level& L, int B_, const double* m, const double* 
     return nb;
 }
 
+void launch_node_gal_agg(const Csr& P, int B_, int32_t* nagg, int* flags, hipStream_t s) {
+    const int nn = P.nrows / B_;
+    AMG_WITH_B(B_, timed_launch(k_ngal_agg<B>, bgrid(nn), TPB_B, 0, s, nn, P.ptr, P.col, P.val, nagg, flags));
+    HIP_LAUNCH_CHECK();
+}
+
+void launch_node_gal_count(const Level& L, const Level& N, int B_, const int32_t* nagg, int32_t* tpos, int32_t* cnt,
+                           int* flags, hipStream_t s) {
+    need_nodes(L);
+    need_nodes(N);
+    const int ncn = N.A.nrows / B_;
+    AMG_WITH_B(B_, timed_launch(k_ngal_count<B>, bgrid(ncn), TPB_B, 0, s, ncn, L.R.ptr, L.R.col, L.nptr, L.ncol,
+                                nagg, N.nptr, N.ncol, tpos, cnt, flags));
+    HIP_LAUNCH_CHECK();
+}
+
+void launch_node_gal_fill(const Level& L, const Level& N, int B_, const int32_t* tpos, const NodeGal& g, int32_t* cur,
+                          int32_t* last, hipStream_t s) {
+    const int ncn = N.A.nrows / B_;
+    AMG_WITH_B(B_, timed_launch(k_ngal_fill<B>, bgrid(ncn), TPB_B, 0, s, ncn, L.R.ptr, L.R.col, L.nptr, N.nptr, tpos,
+                                g.tptr, g.toff, g.tlen, g.cout, g.clen, cur, last));
+    HIP_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_node_rap(const NodeGal& g, int B_, const T* aval, const double* lin, double* a64, float* a32, T* cval,
+                     hipStream_t s) {
+    if (g.nblk <= 0) return;
+    auto go = [&](auto kern, int ngb) {
+        const int64_t threads = g.nblk * ngb;
+        timed_launch(kern, (unsigned)((threads + TPB_B - 1) / TPB_B), TPB_B, 0, s, g.nblk, (const int*)g.tptr,
+                     (const int*)g.toff, (const int*)g.tlen, (const int*)g.cout, (const int*)g.clen, aval, lin, a64,
+                     a32, cval);
+    };
+    switch (B_) {
+        case 2: go(k_node_rap<2, 4, T>, 4); break;
+        case 3: go(k_node_rap<3, 16, T>, 16); break;
+        case 4: go(k_node_rap<4, 16, T>, 16); break;
+        case 5: go(k_node_rap<5, 32, T>, 32); break;
+        case 6: go(k_node_rap<6, 64, T>, 64); break;
+        case 7: go(k_node_rap<7, 64, T>, 64); break;
+        case 8: go(k_node_rap<8, 64, T>, 64); break;
+        default: throw Fail{AMG_ERR_ARG, "block_size must be 1 .. 8"};
+    }
+    HIP_LAUNCH_CHECK();
+}
+
+template void launch_node_rap<double>(const NodeGal&, int, const double*, const double*, double*, float*, double*,
+                                      hipStream_t);
+template void launch_node_rap<float>(const NodeGal&, int, const float*, const double*, double*, float*, float*,
+                                     hipStream_t);
 template void launch_node_residual<double>(const Level&, int, const double*, const double*, double*, hipStream_t);
 template void launch_node_residual<float>(const Level&, int, const float*, const float*, float*, hipStream_t);
 template void launch_node_sweep<double>(const Level&, int, const double*, const double*, const double*, double*,

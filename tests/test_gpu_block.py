@@ -84,6 +84,77 @@ def test_node_pair_loads(monkeypatch, bs):
         m.close()
 
 
+def _kron_system(n, deg, seed, bs, isolate=()):
+    pp, cc, vv = random_spd_graph(n, deg, seed)
+    G = sp.csr_matrix((vv, cc, pp), shape=(n, n)).tolil()
+    for i in isolate:  # a node with its diagonal block only: it joins no aggregate
+        d = G[i, i]
+        G[i, :] = 0
+        G[:, i] = 0
+        G[i, i] = d
+    G = G.tocsr()
+    G.eliminate_zeros()
+    rg = np.random.default_rng(seed + bs)
+    M = rg.uniform(-1.0, 1.0, size=(bs, bs))
+    K = M @ M.T + bs * np.eye(bs)
+    A = sp.kron(G, sp.csr_matrix(K), format="csr")
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.copy()
+
+
+@pytest.mark.parametrize("case", ["coupled4", "kron3", "kron2_isolated", "mixed"])
+def test_node_galerkin_product(monkeypatch, case):
+    """A partial update of a block system forms A_{l+1} = R_l A_l P_l in one pass over A_l's
+    B x B blocks (Section 4's block values; Alg. 4): bit for bit the scalar position-map
+    product's and the oracle's row-by-row product's coarse operators and block smoothers,
+    also when a node joins no aggregate (its values then reach the hierarchy by a copy) and
+    in the FP32 hierarchy (same solve as the scalar product's)."""
+    from paper_2108_02054_amd import AMG
+    if case in ("coupled4", "mixed"):
+        p, c, v0 = coupled4_7pt(12, 0)
+        v1 = coupled4_7pt(12, 3)[2]
+        prm = dict(block_size=4, aggregation=1, coarse_enough=128, precision=1 if case == "mixed" else 0)
+    else:
+        bs = 3 if case == "kron3" else 2
+        p, c, v0 = _kron_system(400, 5, 4, bs, isolate=(7, 123) if "isolated" in case else ())
+        rg = np.random.default_rng(9)
+        v1 = v0 * (1.0 + 0.1 * rg.uniform(size=v0.shape))
+        v1 = 0.5 * (v1 + sp.csr_matrix((v1, c, p)).T.tocsr().sorted_indices().data)  # still symmetric
+        prm = dict(block_size=bs, aggregation=1, coarse_enough=32)
+    print(f"case node galerkin {case}", flush=True)
+    g = AMG(T(p), T(c), T(v0), **prm)
+    L = g.num_levels
+    assert L >= 2
+    assert [g.level_storage(l)["node_galerkin"] for l in range(L - 1)] == [1] * (L - 1)
+    g.rebuild(T(v1))
+    monkeypatch.setenv("AMGMI_NO_NODE_GAL", "1")
+    h = AMG(T(p), T(c), T(v0), **prm)
+    assert h.level_storage(0)["node_galerkin"] == 0
+    h.rebuild(T(v1))
+    f = rhs_uniform(len(p) - 1, 7, 2)
+    u, info = g.solve(T(f))
+    uh, ih = h.solve(T(f))
+    assert info["converged"] and info["iters"] == ih["iters"], (info, ih)
+    assert np.array_equal(u.cpu().numpy(), uh.cpu().numpy())
+    if case == "mixed":
+        g.close()
+        h.close()
+        return
+    for l in range(L):
+        a, b = g.level(l), h.level(l)
+        assert np.array_equal(a["A"][2], b["A"][2]), l
+        if a["P"] is not None:
+            assert np.array_equal(a["m"], b["m"]), l
+    import oracle
+    o = oracle.OracleHierarchy(p, c, v0, **{k: x for k, x in prm.items() if k != "precision"})
+    o.rebuild(v1, 0)
+    assert o.num_levels == L
+    for l in range(L):
+        assert np.array_equal(g.level(l)["A"][2], o.level(l)["A"][2]), l
+    for m in (g, h, o):
+        m.close()
+
+
 def test_block_partial_series_and_solves():
     N = 14
     p, c, v0 = coupled4_7pt(N, 0)
