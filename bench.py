@@ -591,8 +591,10 @@ def run_config(cfg_id, N, K, W, args, headline_prec=None, compare=True, legs_mod
         rap_traffic = load_traffic_rec("galerkin_two_fluid_128_traffic.json")
     elif cfg_id == 5 and N == 160:
         pq_traffic = load_traffic_rec("cg_pq_lognormal27_160_traffic.json")
-    elif cfg_id == 7:
+    elif cfg_id == 7 and N == 56:
         pq_traffic = load_traffic_rec("cg_pq_coupled4_56_traffic.json")
+        if bm.st[0].get("node_galerkin"):
+            rap_traffic = load_traffic_rec("node_rap_coupled4_56_traffic.json")
     dom_rec = roof(f"{dom_name}: levels {sorted(dom_levels)} (the kernel with the step's largest time)",
                    d_ms, d_cnt, d_bytes or 0.0, dom_traffic)
     dom_rec["per_level"] = [{"level": l, "launches": kt[l].get(dom, (0, 0))[1],

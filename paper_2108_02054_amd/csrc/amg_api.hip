@@ -526,10 +526,11 @@ void release_node_gal(amg_ctx* c, NodeGal& g) {
     g = NodeGal{};
 }
 
-// Node Galerkin plans of a block system (every level's node pattern built): a level whose
-// P is P_node (x) I_B with unit values gets one, and its partial rebuild forms A_{l+1} in
-// one pass over A_l's blocks; other levels (user transfer operators of another form) keep
-// the scalar position-map product.  AMGMI_NO_NODE_GAL keeps the scalar product everywhere.
+// Node Galerkin plans of a block system (every level's node pattern built), formed by the
+// first partial update after a setup or a pattern change: a level whose P is
+// P_node (x) I_B with unit values gets one, and its partial updates form A_{l+1} in one
+// pass over A_l's blocks; other levels (user transfer operators of another form) keep the
+// scalar position-map product.  AMGMI_NO_NODE_GAL keeps the scalar product everywhere.
 void configure_node_gal(amg_ctx* c) {
     for (Level& L : c->lv) release_node_gal(c, L.ngal);
     const int B = c->prm.block_size;
@@ -740,6 +741,10 @@ void partial_rebuild(amg_ctx* c, const double* val) {
     hipStream_t s = c->stream;
     Level& L0 = c->lv[0];
     wait_coarse(c);  // the last update's inverse reads A_L, which this update rewrites
+    if (!c->ngal_ready) {
+        configure_node_gal(c);
+        c->ngal_ready = true;
+    }
     HIP_CHECK(hipEventRecord(c->ev[0], s));
     c->outer_val = L0.A.val;
     const int nlev = (int)c->lv.size();
@@ -1079,7 +1084,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     read_red(c);
     if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
     ph[5] += ms_since(t0);
-    configure_node_gal(c);
+    c->ngal_ready = false;
 
     if (mixed(c)) {
         alloc_shadow(c);
@@ -1156,7 +1161,8 @@ void repattern(amg_ctx* c) {
     if (mixed(c)) L0.A.val32 = halloc<float>(c, (size_t)L0.A.nnz);
     if (c->prm.block_size > 1)
         for (int l = 1; l < nlev; ++l) node_pattern(c, c->lv[(size_t)l]);
-    configure_node_gal(c);
+    for (Level& L : c->lv) release_node_gal(c, L.ngal);
+    c->ngal_ready = false;
     set_groups(c, c->lv.back(), nullptr, s);
     release(c, c->rs.part);
     alloc_reduction(c);

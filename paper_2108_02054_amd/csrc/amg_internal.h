@@ -608,6 +608,9 @@ struct amg_ctx {
     // the partial update wrote A_0's new values straight into the diagonal storage: the CSR
     // value arrays of level 0 are formed from it when they are read (exports)
     bool a0_csr_stale = false;
+    // block systems: the node Galerkin plans are built by the first partial update after a
+    // setup or a pattern change (a series of full setups never needs them)
+    bool ngal_ready = false;
     // mixed precision: the last level-0 sweep writes z in FP64 with r.z (off with
     // AMGMI_NO_RZ32: a separate widening pass)
     bool rz32 = true;
