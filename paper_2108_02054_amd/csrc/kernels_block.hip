@@ -313,24 +313,27 @@ __global__ __launch_bounds__(TPB_B) void k_node_pupdate(int n, const double* __r
 }
 
 // q = A p and p.q partials (FP64), p formed by k_node_pupdate: one gathered vector per
-// block column, one position per lane (the pair form measured slower here).  Bounded grid, nodes by grid stride: one partial per workgroup, in a
-// fixed order.
-template <int B>
+// block column.  One node group per node, workgroups in XCD order like the sweeps', one
+// partial per workgroup at its logical index; GS: a grid smaller than that (a reduction
+// scratch with fewer slots than workgroups) takes the other nodes by grid stride.
+template <int B, bool PR, bool GS>
 __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restrict__ nptr,
                                                       const int* __restrict__ ncol, const double* __restrict__ val,
                                                       const double* __restrict__ p, double* __restrict__ q,
                                                       RedScratch rs) {
+    const int lb = xcd_block();
     const int lane = threadIdx.x & (NG - 1);
     double loc = 0.0;
-    for (int I = blockIdx.x * NODES_PER_WG + (int)threadIdx.x / NG; I < nn; I += gridDim.x * NODES_PER_WG) {
+    for (int I = lb * NODES_PER_WG + (int)threadIdx.x / NG; I < nn; I += gridDim.x * NODES_PER_WG) {
         double s[B];
-        node_rowsums<B>(I, lane, nptr, ncol, val, p, s);
+        node_sums<B, PR>(I, lane, nptr, ncol, val, p, s);
         if (lane < B) {
             const int i = I * B + lane;
             const double qi = pick<B>(s, lane);
             q[i] = qi;
             loc += p[i] * qi;
         }
+        if constexpr (!GS) break;
     }
     __shared__ double sm[TPB_B / 64];
 #pragma unroll
@@ -340,7 +343,7 @@ __global__ __launch_bounds__(TPB_B) void k_node_cg_pq(int nn, const int* __restr
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < TPB_B / 64; ++w) t += sm[w];
-        rs.region(P_PQ)[blockIdx.x] = t;
+        rs.region(P_PQ)[lb] = t;
     }
 }
 
@@ -600,7 +603,8 @@ int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z
                       double* q, int first, const RedScratch& rs, hipStream_t s) {
     need_nodes(L);
     const int n = L.A.nrows, nn = n / B_;
-    const int nb = std::max(1, std::min(node_grid(nn), rs.cap));
+    const int full = std::max(1, node_grid(nn));
+    const int nb = std::min(full, rs.cap);
     const KernelEvents e = g_kernel_events;
     g_kernel_events = KernelEvents{};
     timed_launch(k_node_pupdate, bgrid(n), TPB_B, 0, s, n, z, pold, pnew, first, rs);
@@ -614,7 +618,14 @@ int launch_node_cg_pq(const Level& L, int B_, const double* val, const double* z
             hipLaunchKernelGGL(kern, dim3(nb), dim3(TPB_B), 0, s, nn, (const int*)L.nptr, (const int*)L.ncol, val, p,
                                q, rs);
     };
-    AMG_WITH_B(B_, go(k_node_cg_pq<B>));
+    AMG_WITH_B(B_, {
+        if (nb < full)
+            go(k_node_cg_pq<B, false, true>);
+        else if (L.node_pairs)
+            go(k_node_cg_pq<B, true, false>);
+        else
+            go(k_node_cg_pq<B, false, false>);
+    });
     HIP_LAUNCH_CHECK();
     return nb;
 }

@@ -49,10 +49,10 @@ def test_block_kronecker_random_graph(seed):
 
 @pytest.mark.parametrize("bs", [2, 3, 4, 6])
 def test_node_pair_loads(monkeypatch, bs):
-    """The node-group residual and sweeps with two adjacent positions per lane (even block
-    sizes; odd ones keep one position per lane) form the row sums of the one-position form
-    in another order: the V-cycle and the solve match those of the one-position kernels and
-    the oracle's V-cycle, and the Krylov product (one position per lane) matches SciPy's."""
+    """The node-group residual, sweeps and Krylov product with two adjacent positions per
+    lane (even block sizes; odd ones keep one position per lane) form the row sums of the
+    one-position form in another order: the product matches SciPy's, and the V-cycle and
+    the solve match those of the one-position kernels and the oracle's V-cycle."""
     pp, cc, vv = random_spd_graph(300, 5, 3)
     rg = np.random.default_rng(bs)
     M = rg.uniform(-1.0, 1.0, size=(bs, bs))
