@@ -317,13 +317,15 @@ amg_status amg_trace_read(amg_ctx* c, double* ms, int64_t* launches);
  * AMG_ERR_ARG for NULL arrays or nlev <= 0.  Synchronises the stream. */
 amg_status amg_trace_read_levels(amg_ctx* c, int nlev, double* ms, int64_t* launches);
 
-/* How level l is stored for the solve kernels (host out[9]): {A_l, P_l, R_l read with
+/* How level l is stored for the solve kernels (host out[10]): {A_l, P_l, R_l read with
  * two-byte column offsets (1) or int32 columns (0) by the row-block kernels; rows per
  * LDS-staged block of A_l, P_l, R_l (0: lane-group kernels); 1 when the level is part of the
  * one-workgroup coarse tail; value bytes of the hierarchy (8 FP64, 4 FP32); 1 when a
  * partial update forms A_{l+1} from A_l's B x B blocks in one pass (block systems whose
  * P_l is the node aggregation's, Section 4's block value type; known once the first
- * partial update after a setup or a pattern change has run), 0 otherwise}.  For reports of the bytes the kernels move.  AMG_ERR_ARG for NULL
+ * partial update after a setup or a pattern change has run), 0 otherwise; 1 when the
+ * V-cycle's prolongation from level l + 1 reads one aggregate index per node instead of
+ * P_l's row pointers, columns and values (the same block systems)}.  For reports of the bytes the kernels move.  AMG_ERR_ARG for NULL
  * out or l out of range. */
 amg_status amg_level_storage(const amg_ctx* c, int l, int* out);
 

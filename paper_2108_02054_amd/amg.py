@@ -403,10 +403,10 @@ class AMG:
 
     def level_storage(self, l: int) -> dict:
         """Column format and launch shape of level l's operators in the solve kernels."""
-        out = (C.c_int * 9)()
+        out = (C.c_int * 10)()
         self._check(lib().amg_level_storage(self.ctx, l, out))
         return dict(A_c16=out[0], P_c16=out[1], R_c16=out[2], A_rpb=out[3], P_rpb=out[4], R_rpb=out[5],
-                    tail=out[6], value_bytes=out[7], node_galerkin=out[8])
+                    tail=out[6], value_bytes=out[7], node_galerkin=out[8], node_transfer=out[9])
 
     def phase_times(self) -> dict:
         out = (C.c_double * 8)()

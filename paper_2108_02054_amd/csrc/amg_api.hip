@@ -526,6 +526,33 @@ void release_node_gal(amg_ctx* c, NodeGal& g) {
     g = NodeGal{};
 }
 
+// Node transfer maps of a block system, at setup: a level whose P is P_node (x) I_B with
+// unit values keeps the aggregate of every node, and its V-cycle prolongation reads that
+// map instead of P's row pointers, columns and values.  AMGMI_NO_NODE_TRANSFER keeps the
+// CSR prolongation.
+void configure_node_transfer(amg_ctx* c) {
+    for (Level& L : c->lv) {
+        release(c, L.nagg);
+        L.nagg = nullptr;
+    }
+    const int B = c->prm.block_size;
+    if (B < 2 || std::getenv("AMGMI_NO_NODE_TRANSFER") != nullptr) return;
+    hipStream_t s = c->stream;
+    for (size_t l = 0; l + 1 < c->lv.size(); ++l) {
+        Level& L = c->lv[l];
+        if (L.P.nrows == 0) continue;
+        int32_t* nagg = halloc<int32_t>(c, (size_t)std::max(L.A.nrows / B, 1));
+        clear_flags(c);
+        launch_node_gal_agg(L.P, B, nagg, c->d_flags, s);
+        read_flags(c);
+        if (c->h_flags[F_NODEGAL]) {
+            release(c, nagg);
+            continue;
+        }
+        L.nagg = nagg;
+    }
+}
+
 // Node Galerkin plans of a block system (every level's node pattern built), formed by the
 // first partial update after a setup or a pattern change: a level whose P is
 // P_node (x) I_B with unit values gets one, and its partial updates form A_{l+1} in one
@@ -1085,6 +1112,7 @@ void build_hierarchy(amg_ctx* c, int32_t n, int64_t nnz, const int32_t* ptr, con
     if (host_scal(c, S_COARSE) != 0.0) throw Fail{AMG_ERR_NOT_SPD, "coarsest operator is not SPD"};
     ph[5] += ms_since(t0);
     c->ngal_ready = false;
+    configure_node_transfer(c);
 
     if (mixed(c)) {
         alloc_shadow(c);
@@ -1294,7 +1322,10 @@ T* vcycle_level_block(amg_ctx* c, int l, const T* f, T* out, const RzEpilogue* e
     }
     {
         Trace tr(c, AMG_K_PROLONG, l);
-        launch_prolong_add<T>(L.P, uc, cur, s);
+        if (L.nagg != nullptr)
+            launch_node_prolong<T>(L, B, uc, cur, s);
+        else
+            launch_prolong_add<T>(L.P, uc, cur, s);
     }
     bool fused = false;
     for (int it = 0; it < p.npost; ++it) {
@@ -2388,6 +2419,7 @@ amg_status amg_level_storage(const amg_ctx* c, int l, int* out) {
     out[6] = (c->tail > 0 && l >= c->tail) ? 1 : 0;
     out[7] = mixed(c) ? 4 : 8;
     out[8] = L.ngal.nblk > 0 ? 1 : 0;
+    out[9] = L.nagg != nullptr ? 1 : 0;
     return AMG_OK;
 }
 

@@ -151,6 +151,9 @@ struct Level {
     int32_t* ncol = nullptr;
     bool node_pairs = true;      // node-group kernels take two adjacent positions per lane (even B)
     NodeGal ngal;                // block systems: node Galerkin plan of A_{l+1} = R_l A_l P_l
+    // block systems whose P_l is P_node (x) I_B with unit values: the aggregate of every
+    // node (-1: none), for the node prolongation (null: the CSR prolongation runs)
+    int32_t* nagg = nullptr;
     uint8_t* strong = nullptr;   // strength flag per stored entry of A_l
     double* m = nullptr;         // smoother diagonal
     float* m32 = nullptr;
@@ -499,6 +502,10 @@ void launch_node_gal_count(const Level& L, const Level& N, int B, const int32_t*
                            int* flags, hipStream_t s);
 void launch_node_gal_fill(const Level& L, const Level& N, int B, const int32_t* tpos, const NodeGal& g, int32_t* cur,
                           int32_t* last, hipStream_t s);
+// Prolongation of a block system with P_l = P_node (x) I_B (L.nagg set): u_l += P_l uc,
+// one thread per fine row.
+template <typename T>
+void launch_node_prolong(const Level& L, int B, const T* uc, T* u, hipStream_t s);
 // A_{l+1} = R_l A_l P_l by the node plan: the values of A_l from aval, or, with lin, from
 // the caller's FP64 array, stored into a64 (and a32 when given) as they are read.
 template <typename T>

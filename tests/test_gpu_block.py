@@ -155,6 +155,44 @@ def test_node_galerkin_product(monkeypatch, case):
         m.close()
 
 
+@pytest.mark.parametrize("case", ["coupled4", "kron3", "kron2_isolated", "mixed"])
+def test_node_transfers(monkeypatch, case):
+    """The block V-cycle's prolongation through the aggregate of each node (P_l =
+    P_node (x) I_B with unit values, Section 4's node aggregation) gives the V-cycle of the
+    CSR prolongation bit for bit, the oracle's V-cycle and the same solve, also with nodes
+    outside every aggregate and in FP32."""
+    from paper_2108_02054_amd import AMG
+    if case in ("coupled4", "mixed"):
+        p, c, v = coupled4_7pt(12, 1)
+        prm = dict(block_size=4, aggregation=1, coarse_enough=128, precision=1 if case == "mixed" else 0)
+    else:
+        bs = 3 if case == "kron3" else 2
+        p, c, v = _kron_system(400, 5, 4, bs, isolate=(7, 123) if "isolated" in case else ())
+        prm = dict(block_size=bs, aggregation=1, coarse_enough=32)
+    print(f"case node transfers {case}", flush=True)
+    g = AMG(T(p), T(c), T(v), **prm)
+    L = g.num_levels
+    assert [g.level_storage(l)["node_transfer"] for l in range(L - 1)] == [1] * (L - 1)
+    monkeypatch.setenv("AMGMI_NO_NODE_TRANSFER", "1")
+    h = AMG(T(p), T(c), T(v), **prm)
+    assert h.level_storage(0)["node_transfer"] == 0
+    r = np.random.default_rng(3).standard_normal(len(p) - 1)
+    z, zh = g.vcycle(T(r)).cpu().numpy(), h.vcycle(T(r)).cpu().numpy()
+    assert np.array_equal(z, zh)
+    f = rhs_uniform(len(p) - 1, 7, 5)
+    u, info = g.solve(T(f))
+    uh, ih = h.solve(T(f))
+    assert info["converged"] and info["iters"] == ih["iters"], (info, ih)
+    assert np.array_equal(u.cpu().numpy(), uh.cpu().numpy())
+    if case != "mixed":
+        import oracle
+        o = oracle.OracleHierarchy(p, c, v, **{k: x for k, x in prm.items() if k != "precision"})
+        assert rel_fro(z, o.vcycle(r)) <= 1e-10
+        o.close()
+    g.close()
+    h.close()
+
+
 def test_block_partial_series_and_solves():
     N = 14
     p, c, v0 = coupled4_7pt(N, 0)
